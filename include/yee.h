@@ -1,0 +1,196 @@
+/*
+ * yee.h -- C ABI of the MI355X (gfx950) Yee FDTD time-step library.
+ *
+ * The library advances a 3-D staggered-grid (Yee) electromagnetic field in
+ * time: per step one H half-update (forward differences of E) and one E
+ * half-update (backward differences of H) with per-cell lossy material
+ * coefficients, convolutional PML (CPML) layers, PEC faces and PEC masks,
+ * soft point sources, and probes with an FP64 running DFT.
+ *
+ * Source of the definitions.  The paper this library accompanies (radar
+ * ray-meta-data simulation; Sections II.A-II.E, Eqs. 1-7) contains no
+ * full-wave solver: no grid, field update or time-stepping scheme.  The
+ * operation is therefore the textbook one, and each entry point below names
+ * it:  Yee, IEEE Trans. Antennas Propag. 14(3), 1966 (staggering, leapfrog);
+ * Taflove & Hagness, "Computational Electrodynamics: The FDTD Method",
+ * ch. 3 (lossy Ca/Cb form) and ch. 7 (CPML); Roden & Gedney, Microwave Opt.
+ * Technol. Lett. 27(5), 2000 (CPML recursion).
+ *
+ * Conventions shared by every call
+ *  - Return value: YEE_OK (0) or a negative yee_status.  No call aborts or
+ *    throws; yee_last_error() returns a thread-local message for the last
+ *    failing call on this thread.
+ *  - Device memory: the caller owns it.  yee_footprint() says how many bytes
+ *    one context needs; the caller allocates one device buffer of at least
+ *    that size (256-byte aligned) and hands it to yee_bind_workspace().  The
+ *    library never allocates device memory and never frees the caller's.
+ *  - Host arrays passed in are copied before the call returns.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that launch work are asynchronous on that stream unless
+ *    documented as synchronizing.
+ *  - Grid indices: cell (i, j, k), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz.
+ *    Components sit at the Yee positions
+ *        Ex ((i+1/2)dx, j dy, k dz)    Hx (i dx, (j+1/2)dy, (k+1/2)dz)
+ *        Ey (i dx, (j+1/2)dy, k dz)    Hy ((i+1/2)dx, j dy, (k+1/2)dz)
+ *        Ez (i dx, j dy, (k+1/2)dz)    Hz ((i+1/2)dx, (j+1/2)dy, k dz)
+ *    Host field arrays are [nz][ny][nx] doubles (x fastest) covering the
+ *    samples with 0 <= i < nx, 0 <= j < ny, 0 <= k < nz.  Every Yee sample
+ *    outside that range is a PEC-wall E sample or a wall-normal H sample that
+ *    is identically zero.
+ *  - A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef YEE_H_
+#define YEE_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define YEE_API_VERSION 1
+
+typedef enum {
+    YEE_OK = 0,
+    YEE_EINVAL = -1,     /* invalid argument or configuration */
+    YEE_ENOMEM = -2,     /* workspace too small */
+    YEE_EHIP = -3,       /* a HIP runtime call failed */
+    YEE_ESTATE = -4,     /* call not valid in the context's current state */
+    YEE_ENUMERIC = -5,   /* non-finite value detected */
+    YEE_EAGAIN = -6,     /* resource busy (serving: no slot or memory) */
+    YEE_EOVERFLOW = -7   /* value outside the storage format's range */
+} yee_status;
+
+typedef enum {
+    YEE_F64 = 0,         /* FP64 storage and arithmetic */
+    YEE_F32 = 1,         /* FP32 storage and arithmetic */
+    YEE_F16S = 2         /* FP16 storage x 2^s per component, FP32 arithmetic */
+} yee_precision;
+
+typedef enum { YEE_EX = 0, YEE_EY, YEE_EZ, YEE_HX, YEE_HY, YEE_HZ } yee_component;
+
+typedef enum {
+    YEE_GAUSS_DERIV = 0, /* w(t) = -2 u exp(-u^2),                    u = (t - t0)/tau */
+    YEE_MOD_GAUSS = 1    /* w(t) = sin(2 pi f0 (t - t0)) exp(-u^2)                    */
+} yee_waveform;
+
+/* Grid description (Yee 1966 grid; CPML per Roden & Gedney 2000). */
+typedef struct {
+    int32_t nx, ny, nz;        /* cells; 2 <= n; nx <= 512 (nx <= 256 for YEE_F64) */
+    double dx, dy, dz;         /* cell sizes in metres, > 0 */
+    double courant;            /* S in (0, 1]: dt = S / (c0 sqrt(dx^-2 + dy^-2 + dz^-2)) */
+    int32_t precision;         /* yee_precision */
+    int32_t cpml_cells[3];     /* CPML thickness L per axis (both faces); 0 = bare PEC face;
+                                  2 L <= n on that axis */
+    double cpml_m;             /* grading order m >= 0 (sigma, kappa ~ x^m) */
+    double cpml_sigma_max;     /* < 0: 0.8 (m + 1)/(eta0 dw) per axis; >= 0: used as given */
+    double cpml_kappa_max;     /* >= 1 */
+    double cpml_alpha_max;     /* >= 0 (S/m) */
+    int32_t fp16_exp[6];       /* YEE_F16S: component c is stored as fp16(x * 2^fp16_exp[c]) */
+    int32_t series_len;        /* probe samples kept per probe (ring of the last series_len
+                                  steps); >= 1 */
+} yee_grid_desc;
+
+/* Soft point source (additive, not scaled by the update coefficient): after
+ * the E half-update of step n (n = 0, 1, ...), the E sample (component, i, j, k)
+ * gains amp * w((n + 1) dt).  Times in seconds, f0 in Hz, tau > 0. */
+typedef struct {
+    int32_t component;         /* YEE_EX, YEE_EY or YEE_EZ */
+    int32_t i, j, k;
+    int32_t waveform;          /* yee_waveform */
+    double amp, t0, tau, f0;
+} yee_source;
+
+typedef struct yee_ctx yee_ctx;
+
+/* Thread-local message describing the last failing call ("" if none). */
+const char* yee_last_error(void);
+int32_t yee_api_version(void);
+
+/* Validate the description (sizes, Courant number, CPML thickness) and
+ * create a context.  No device work.  *out is set to NULL on failure. */
+yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out);
+void yee_destroy(yee_ctx* ctx);
+
+/* The time step dt the context uses (seconds). */
+yee_status yee_time_step(const yee_ctx* ctx, double* dt);
+
+/* Materials on a rectilinear block lattice (Taflove & Hagness ch. 3 lossy
+ * update).  seg_x[nx], seg_y[ny], seg_z[nz] give each cell's block index
+ * along each axis (0 <= seg < ns*); eps_r and sigma (S/m) are indexed
+ * [(bz * nsy + by) * nsx + bx], eps_r >= 1e-3, sigma >= 0.  The E samples of
+ * cell (i, j, k) use that cell's block:
+ *     Ca = (1 - s)/(1 + s),  Cb = (dt/(eps0 eps_r))/(1 + s),  s = sigma dt/(2 eps0 eps_r).
+ * Before yee_bind_workspace() any lattice is accepted; afterwards only one
+ * with the same (nsx, nsy, nsz) (it is re-uploaded by the next yee_reset()
+ * or yee_upload_materials()).  Default: vacuum (one block, eps_r 1, sigma 0). */
+yee_status yee_set_materials(yee_ctx* ctx, int32_t nsx, int32_t nsy, int32_t nsz,
+                             const int32_t* seg_x, const int32_t* seg_y, const int32_t* seg_z,
+                             const double* eps_r, const double* sigma);
+/* Upload the current material table to the bound workspace (stream-ordered). */
+yee_status yee_upload_materials(yee_ctx* ctx, void* stream);
+
+/* PEC mask on the z-plane k (0 < k < nz): mask[j * nx + i] bit 0 holds Ex,
+ * bit 1 Ey, bit 2 Ez of sample (i, j, k) at Ca = Cb = 0 (the sample stays 0).
+ * Only before yee_bind_workspace(). */
+yee_status yee_add_pec_plane(yee_ctx* ctx, int32_t k, const uint8_t* mask);
+
+/* Soft source (see yee_source).  Only before yee_bind_workspace(). */
+yee_status yee_add_source(yee_ctx* ctx, const yee_source* src);
+
+/* Probe recording component `component` (0..5) at (i, j, k) after every
+ * step: E^{n+1} for E components, H^{n+1/2} for H components, as stored (in
+ * YEE_F16S: the decoded fp16 value).  *id receives the probe index.  Only
+ * before yee_bind_workspace(). */
+yee_status yee_add_probe(yee_ctx* ctx, int32_t component, int32_t i, int32_t j, int32_t k,
+                         int32_t* id);
+
+/* Frequencies (Hz) of the running DFT shared by all probes:
+ * X_p(f) = sum_{n >= 1} y_p[n] exp(-i 2 pi f n dt) dt, accumulated in FP64.
+ * Only before yee_bind_workspace(); nf may be 0. */
+yee_status yee_set_dft_freqs(yee_ctx* ctx, const double* freqs, int32_t nf);
+
+/* Device bytes one context needs for its current configuration. */
+yee_status yee_footprint(const yee_ctx* ctx, int64_t* bytes);
+
+/* Hand the caller-owned device buffer to the context (>= footprint bytes,
+ * 256-byte aligned).  Freezes sources, probes, PEC planes and DFT
+ * frequencies.  The buffer must outlive the context's use of it. */
+yee_status yee_bind_workspace(yee_ctx* ctx, void* device_ptr, int64_t bytes);
+
+/* Zero every field, CPML auxiliary, probe ring and DFT accumulator, set the
+ * step counter to 0 and upload all tables.  Stream-ordered. */
+yee_status yee_reset(yee_ctx* ctx, void* stream);
+
+/* Overwrite one component (initial E^0 or H^{-1/2}) from host[nz][ny][nx].
+ * Synchronizes the stream.  In YEE_F16S the values are rounded to storage. */
+yee_status yee_set_field(yee_ctx* ctx, int32_t component, const double* host, void* stream);
+
+/* Advance n_steps leapfrog steps (E^n, H^{n-1/2}) -> (E^{n+1}, H^{n+1/2}).
+ * Asynchronous on `stream`; probe samples and DFT sums are folded on the
+ * same stream. */
+yee_status yee_step(yee_ctx* ctx, int64_t n_steps, void* stream);
+
+/* Steps taken since the last yee_reset(). */
+yee_status yee_steps_done(const yee_ctx* ctx, int64_t* n);
+
+/* Copy one component to host[nz][ny][nx] (doubles).  Synchronizes. */
+yee_status yee_read_field(yee_ctx* ctx, int32_t component, double* host, void* stream);
+
+/* Probe samples y_p[n] for n = first .. first+count-1 (n = 1 is the value
+ * after the first step) into host[count][n_probes].  The samples must still
+ * be in the ring (the last series_len steps).  Synchronizes. */
+yee_status yee_read_series(yee_ctx* ctx, int64_t first, int64_t count, double* host, void* stream);
+
+/* DFT accumulators into re[n_probes][nf], im[n_probes][nf].  Synchronizes. */
+yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
+
+/* Launch shape of the fused step kernel: rows per workgroup tile (1..15)
+ * and planes per z-chunk (>= 1); 0 keeps the automatic choice. */
+yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YEE_H_ */

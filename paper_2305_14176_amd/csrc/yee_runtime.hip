@@ -1,0 +1,680 @@
+// Host side of the Yee FDTD library: context, validation, workspace carving,
+// table construction and kernel launches behind the C ABI of include/yee.h.
+//
+// Definitions (the paper defines no full-wave solver; textbook operations):
+//   dt  = S / (c0 sqrt(dx^-2 + dy^-2 + dz^-2))                  (Courant limit)
+//   Ca  = (1 - s)/(1 + s), Cb = (dt/eps)/(1 + s), s = sigma dt/(2 eps)
+//                                                  (Taflove & Hagness ch. 3)
+//   CPML: x = depth/L, sigma = sigma_max x^m, kappa = 1 + (kappa_max - 1) x^m,
+//         alpha = alpha_max (1 - x), b = exp(-(sigma/kappa + alpha) dt/eps0),
+//         a = sigma (b - 1)/(kappa (sigma + kappa alpha))     (Roden & Gedney 2000)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/yee.h"
+#include "yee_kernels.hpp"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+const double kMu0 = 4.0e-7 * kPi;
+const double kEps0 = 1.0 / (kMu0 * kC0 * kC0);
+const double kEta0 = std::sqrt(kMu0 / kEps0);
+
+thread_local std::string g_err;
+
+yee_status fail(yee_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(YEE_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+}  // namespace
+
+struct yee_ctx {
+  yee_grid_desc d{};
+  double dt = 0.0;
+  int V = 1;        // x samples per lane
+  int px = 0;       // x pitch in elements
+  size_t tsize = 0; // storage element size
+  size_t csize = 0; // compute element size
+  int ty = 0, kz = 0;
+  size_t lds_limit = 65536;  // per-workgroup LDS, queried at bind time
+
+  // host-side configuration
+  int nsx = 1, nsy = 1, nsz = 1;
+  std::vector<int32_t> segx, segy, segz;
+  std::vector<double> eps, sig;
+  std::vector<int32_t> pec_k;
+  std::vector<std::vector<uint8_t>> pec_masks;
+  std::vector<yee::SrcDev> src;
+  std::vector<int4> probes;
+  std::vector<double> freqs;
+
+  // workspace
+  bool bound = false;
+  unsigned char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  Region fields[2], psi_e, psi_h[2], series, dft, segxr, segyr, segzr, coef, prof, pecplane,
+      pecmask, rowflag, srcr, prober, freqr;
+  size_t comp_bytes = 0;   // one component array
+  size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
+  size_t prof_len = 0;     // elements of one profile array (max axis length)
+  int64_t n = 0;           // steps taken
+  int64_t folded = 0;      // steps folded into the DFT
+};
+
+namespace {
+
+int choose_v(const yee_grid_desc& d) {
+  const int vmax = d.precision == YEE_F64 ? 4 : 8;
+  for (int v = 1; v <= vmax; v *= 2)
+    if (d.nx <= yee::kWave * v) return v;
+  return 0;
+}
+
+size_t storage_size(int prec) { return prec == YEE_F64 ? 8 : prec == YEE_F32 ? 4 : 2; }
+size_t compute_size(int prec) { return prec == YEE_F64 ? 8 : 4; }
+
+void psi_lengths(const yee_ctx* c, size_t out[6]) {
+  const auto& d = c->d;
+  const size_t px = c->px, ny = d.ny, nz = d.nz;
+  const size_t lx = d.cpml_cells[0], ly = d.cpml_cells[1], lz = d.cpml_cells[2];
+  // order: (comp, axis) = xy, xz, yz, yx, zx, zy  (same for E and H side)
+  const size_t yl = nz * 2 * ly * px, zl = 2 * lz * ny * px, xl = nz * ny * 2 * lx;
+  out[0] = yl; out[1] = zl; out[2] = zl; out[3] = xl; out[4] = xl; out[5] = yl;
+}
+
+void layout(yee_ctx* c) {
+  const auto& d = c->d;
+  size_t off = 0;
+  auto take = [&](Region& r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += align256(std::max<size_t>(bytes, 1));
+  };
+  c->comp_bytes = align256((size_t)d.nz * d.ny * c->px * c->tsize);
+  for (int s = 0; s < 2; ++s) take(c->fields[s], 6 * c->comp_bytes);
+  psi_lengths(c, c->psi_len);
+  size_t psib = 0;
+  for (int q = 0; q < 6; ++q) psib += align256(c->psi_len[q] * c->csize);
+  take(c->psi_e, psib);
+  take(c->psi_h[0], psib);
+  take(c->psi_h[1], psib);
+  const size_t np = c->probes.size(), nf = c->freqs.size();
+  take(c->series, (size_t)d.series_len * np * sizeof(double));
+  take(c->dft, np * nf * 2 * sizeof(double));
+  take(c->segxr, (size_t)c->px * 4);
+  take(c->segyr, (size_t)d.ny * 4);
+  take(c->segzr, (size_t)d.nz * 4);
+  take(c->coef, (size_t)c->nsx * c->nsy * c->nsz * 2 * c->csize);
+  c->prof_len = std::max({d.nx, d.ny, d.nz}) + 1;
+  take(c->prof, 2 * 3 * 3 * c->prof_len * c->csize);
+  take(c->pecplane, (size_t)d.nz * 4);
+  take(c->pecmask, c->pec_k.size() * (size_t)d.ny * c->px);
+  take(c->rowflag, (size_t)d.nz * d.ny);
+  take(c->srcr, c->src.size() * sizeof(yee::SrcDev));
+  take(c->prober, np * sizeof(int4));
+  take(c->freqr, nf * sizeof(double));
+  c->ws_bytes = (int64_t)off;
+}
+
+// Roden-Gedney profile along one axis of n cells with a layer of L cells.
+// side 0: E (positions 0..n-1 integer), side 1: H (positions i + 1/2).
+void cpml_profile(const yee_grid_desc& d, double dw, double dt, int n, int L, int side,
+                  std::vector<double>& b, std::vector<double>& a, std::vector<double>& kinv) {
+  b.assign(n, 1.0);
+  a.assign(n, 0.0);
+  kinv.assign(n, 1.0);
+  if (L <= 0) return;
+  const double m = d.cpml_m;
+  const double smax = d.cpml_sigma_max < 0.0 ? 0.8 * (m + 1.0) / (kEta0 * dw) : d.cpml_sigma_max;
+  for (int i = 0; i < n; ++i) {
+    const double p = i + (side ? 0.5 : 0.0);
+    const double x = std::max(std::max((double)L - p, p - (double)(n - L)), 0.0) / L;
+    const double xm = std::pow(x, m);
+    const double sg = smax * xm;
+    const double kp = 1.0 + (d.cpml_kappa_max - 1.0) * xm;
+    const double al = d.cpml_alpha_max * (1.0 - x);
+    const double bb = std::exp(-(sg / kp + al) * dt / kEps0);
+    const double den = kp * (sg + kp * al);
+    b[i] = bb;
+    a[i] = (sg > 0.0 && den > 0.0) ? sg * (bb - 1.0) / den : 0.0;
+    kinv[i] = 1.0 / kp;
+  }
+}
+
+template <class C>
+void put(std::vector<unsigned char>& buf, size_t byte_off, const std::vector<double>& v) {
+  C* p = reinterpret_cast<C*>(buf.data() + byte_off);
+  for (size_t i = 0; i < v.size(); ++i) p[i] = static_cast<C>(v[i]);
+}
+
+yee_status upload(yee_ctx* c, const Region& r, const void* host, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return YEE_OK;
+  HIP_TRY(hipMemcpyAsync(c->ws + r.off, host, bytes, hipMemcpyHostToDevice, s));
+  return YEE_OK;
+}
+
+yee_status upload_materials_impl(yee_ctx* c, hipStream_t s) {
+  const size_t nb = (size_t)c->nsx * c->nsy * c->nsz;
+  std::vector<double> cab(2 * nb);
+  for (size_t b = 0; b < nb; ++b) {
+    const double eps = kEps0 * c->eps[b];
+    const double sg = c->sig[b] * c->dt / (2.0 * eps);
+    cab[2 * b] = (1.0 - sg) / (1.0 + sg);
+    cab[2 * b + 1] = (c->dt / eps) / (1.0 + sg);
+  }
+  std::vector<unsigned char> buf(2 * nb * c->csize);
+  if (c->csize == 8) put<double>(buf, 0, cab); else put<float>(buf, 0, cab);
+  yee_status st = upload(c, c->coef, buf.data(), buf.size(), s);
+  if (st) return st;
+  std::vector<int32_t> sx(c->px, 0);
+  std::copy(c->segx.begin(), c->segx.end(), sx.begin());
+  if ((st = upload(c, c->segxr, sx.data(), sx.size() * 4, s))) return st;
+  if ((st = upload(c, c->segyr, c->segy.data(), c->segy.size() * 4, s))) return st;
+  if ((st = upload(c, c->segzr, c->segz.data(), c->segz.size() * 4, s))) return st;
+  // pageable source buffers: make sure the copies are done before they go away
+  HIP_TRY(hipStreamSynchronize(s));
+  return YEE_OK;
+}
+
+size_t step_lds_bytes(const yee_ctx* c, int ty) {
+  return (size_t)((ty + 2) + (ty + 1)) * 2 * yee::kWave * c->V * c->csize;
+}
+
+template <class T, class C, int V>
+yee_status launch_step(yee_ctx* c, hipStream_t s) {
+  using namespace yee;
+  const auto& d = c->d;
+  StepArgs<T, C> a{};
+  const int cur = (int)(c->n & 1), nxt = cur ^ 1;
+  for (int q = 0; q < 3; ++q) {
+    a.e_in[q] = reinterpret_cast<const T*>(c->ws + c->fields[cur].off + q * c->comp_bytes);
+    a.h_in[q] = reinterpret_cast<const T*>(c->ws + c->fields[cur].off + (3 + q) * c->comp_bytes);
+    a.e_out[q] = reinterpret_cast<T*>(c->ws + c->fields[nxt].off + q * c->comp_bytes);
+    a.h_out[q] = reinterpret_cast<T*>(c->ws + c->fields[nxt].off + (3 + q) * c->comp_bytes);
+  }
+  size_t po = 0;
+  for (int q = 0; q < 6; ++q) {
+    a.psi_e[q] = reinterpret_cast<C*>(c->ws + c->psi_e.off + po);
+    a.psi_h_in[q] = reinterpret_cast<const C*>(c->ws + c->psi_h[cur].off + po);
+    a.psi_h_out[q] = reinterpret_cast<C*>(c->ws + c->psi_h[nxt].off + po);
+    po += align256(c->psi_len[q] * sizeof(C));
+  }
+  const C* prof = reinterpret_cast<const C*>(c->ws + c->prof.off);
+  for (int side = 0; side < 2; ++side)
+    for (int ax = 0; ax < 3; ++ax) {
+      const size_t base = ((size_t)(side * 3 + ax) * 3) * c->prof_len;
+      a.pb[side][ax] = prof + base;
+      a.pa[side][ax] = prof + base + c->prof_len;
+      a.pk[side][ax] = prof + base + 2 * c->prof_len;
+    }
+  a.segx = reinterpret_cast<const int32_t*>(c->ws + c->segxr.off);
+  a.segy = reinterpret_cast<const int32_t*>(c->ws + c->segyr.off);
+  a.segz = reinterpret_cast<const int32_t*>(c->ws + c->segzr.off);
+  a.coef = reinterpret_cast<const Coef2<C>*>(c->ws + c->coef.off);
+  a.nsx = c->nsx;
+  a.nsxy = c->nsx * c->nsy;
+  a.pec_plane = reinterpret_cast<const int32_t*>(c->ws + c->pecplane.off);
+  a.pec_mask = reinterpret_cast<const uint8_t*>(c->ws + c->pecmask.off);
+  a.rowflag = reinterpret_cast<const uint8_t*>(c->ws + c->rowflag.off);
+  a.src = reinterpret_cast<const SrcDev*>(c->ws + c->srcr.off);
+  a.nsrc = (int32_t)c->src.size();
+  a.probe = reinterpret_cast<const int4*>(c->ws + c->prober.off);
+  a.nprobe = (int32_t)c->probes.size();
+  a.series = reinterpret_cast<double*>(c->ws + c->series.off);
+  a.series_len = d.series_len;
+  a.nx = d.nx; a.ny = d.ny; a.nz = d.nz; a.px = c->px;
+  for (int q = 0; q < 3; ++q) a.L[q] = d.cpml_cells[q];
+  a.inv_d[0] = static_cast<C>(1.0 / d.dx);
+  a.inv_d[1] = static_cast<C>(1.0 / d.dy);
+  a.inv_d[2] = static_cast<C>(1.0 / d.dz);
+  a.dt_mu = static_cast<C>(c->dt / kMu0);
+  a.dt = c->dt;
+  a.n = c->n;
+  for (int q = 0; q < 6; ++q) {
+    const int e = d.precision == YEE_F16S ? d.fp16_exp[q] : 0;
+    a.enc[q] = std::ldexp(1.0f, e);
+    a.dec[q] = std::ldexp(1.0f, -e);
+  }
+  a.ty = c->ty;
+  a.kz = c->kz;
+  a.ny_tiles = (d.ny + c->ty - 1) / c->ty;
+  const int nchunks = (d.nz + c->kz - 1) / c->kz;
+  a.ntiles = a.ny_tiles * nchunks;
+  const int grid = ((a.ntiles + 7) / 8) * 8;
+  const size_t lds = step_lds_bytes(c, c->ty);
+  if (lds > c->lds_limit) return fail(YEE_EINVAL, "tile of %d rows needs %zu bytes of LDS (limit %zu)", c->ty, lds, c->lds_limit);
+  hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * (c->ty + 1)), lds, s, a);
+  HIP_TRY(hipGetLastError());
+  return YEE_OK;
+}
+
+template <class T, class C>
+yee_status launch_step_v(yee_ctx* c, hipStream_t s) {
+  switch (c->V) {
+    case 1: return launch_step<T, C, 1>(c, s);
+    case 2: return launch_step<T, C, 2>(c, s);
+    case 4: return launch_step<T, C, 4>(c, s);
+    default: return launch_step<T, C, 8>(c, s);
+  }
+}
+
+yee_status launch_one_step(yee_ctx* c, hipStream_t s) {
+  switch (c->d.precision) {
+    case YEE_F64: {
+      switch (c->V) {  // FP64 is limited to V <= 4
+        case 1: return launch_step<double, double, 1>(c, s);
+        case 2: return launch_step<double, double, 2>(c, s);
+        default: return launch_step<double, double, 4>(c, s);
+      }
+    }
+    case YEE_F32: return launch_step_v<float, float>(c, s);
+    default: return launch_step_v<_Float16, float>(c, s);
+  }
+}
+
+yee_status fold_dft(yee_ctx* c, hipStream_t s) {
+  const int64_t count = c->n - c->folded;
+  if (count <= 0) return YEE_OK;
+  const int np = (int)c->probes.size(), nf = (int)c->freqs.size();
+  if (np > 0 && nf > 0) {
+    const int waves = np * nf;
+    const int blocks = (waves * yee::kWave + 255) / 256;
+    hipLaunchKernelGGL(yee::dft_fold_kernel, dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const double*>(c->ws + c->series.off), np, c->d.series_len,
+                       c->folded + 1, (int)count, reinterpret_cast<const double*>(c->ws + c->freqr.off),
+                       nf, c->dt, reinterpret_cast<double2*>(c->ws + c->dft.off));
+    HIP_TRY(hipGetLastError());
+  }
+  c->folded = c->n;
+  return YEE_OK;
+}
+
+void default_launch(yee_ctx* c) {
+  const auto& d = c->d;
+  if (c->ty == 0) c->ty = std::min(7, d.ny);
+  // keep the LDS rows within the device's per-workgroup limit
+  while (c->ty > 1 && step_lds_bytes(c, c->ty) > c->lds_limit) --c->ty;
+  if (c->kz == 0) {
+    // enough workgroups to fill 256 CUs several times over, but keep the
+    // per-chunk warm-up plane a small fraction of the march
+    const int ny_tiles = (d.ny + c->ty - 1) / c->ty;
+    int kz = d.nz;
+    while (kz > 8 && (long)ny_tiles * ((d.nz + kz - 1) / kz) < 1024) kz = (kz + 1) / 2;
+    c->kz = std::max(1, kz);
+  }
+}
+
+template <class T>
+void host_to_storage(const double* in, std::vector<unsigned char>& out, const yee_grid_desc& d,
+                     int px, float enc) {
+  T* o = reinterpret_cast<T*>(out.data());
+  for (size_t k = 0; k < (size_t)d.nz; ++k)
+    for (size_t j = 0; j < (size_t)d.ny; ++j)
+      for (size_t i = 0; i < (size_t)d.nx; ++i)
+        o[(k * d.ny + j) * px + i] = static_cast<T>(static_cast<float>(in[(k * d.ny + j) * d.nx + i]) * enc);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* yee_last_error(void) { return g_err.c_str(); }
+int32_t yee_api_version(void) { return YEE_API_VERSION; }
+
+yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out) {
+  if (!out) return fail(YEE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(YEE_EINVAL, "desc is NULL");
+  const yee_grid_desc& d = *desc;
+  if (d.nx < 2 || d.ny < 2 || d.nz < 2) return fail(YEE_EINVAL, "grid must have >= 2 cells per axis");
+  if (d.precision < YEE_F64 || d.precision > YEE_F16S) return fail(YEE_EINVAL, "bad precision %d", d.precision);
+  if (!(d.dx > 0) || !(d.dy > 0) || !(d.dz > 0)) return fail(YEE_EINVAL, "cell sizes must be > 0");
+  if (!(d.courant > 0.0) || d.courant > 1.0) return fail(YEE_EINVAL, "Courant number %g not in (0, 1]", d.courant);
+  if (d.series_len < 1) return fail(YEE_EINVAL, "series_len must be >= 1");
+  const int n3[3] = {d.nx, d.ny, d.nz};
+  for (int q = 0; q < 3; ++q)
+    if (d.cpml_cells[q] < 0 || 2 * d.cpml_cells[q] > n3[q])
+      return fail(YEE_EINVAL, "CPML thickness %d invalid for axis of %d cells", d.cpml_cells[q], n3[q]);
+  if (d.cpml_m < 0 || d.cpml_kappa_max < 1.0 || d.cpml_alpha_max < 0)
+    return fail(YEE_EINVAL, "CPML grading parameters out of range");
+  for (int q = 0; q < 6; ++q)
+    if (d.fp16_exp[q] < -30 || d.fp16_exp[q] > 30) return fail(YEE_EINVAL, "fp16 exponent out of range");
+  auto* c = new (std::nothrow) yee_ctx();
+  if (!c) return fail(YEE_ENOMEM, "host allocation failed");
+  c->d = d;
+  c->V = choose_v(d);
+  if (c->V == 0) {
+    delete c;
+    return fail(YEE_EINVAL, "nx = %d exceeds the row limit (%d)", d.nx, d.precision == YEE_F64 ? 256 : 512);
+  }
+  c->tsize = storage_size(d.precision);
+  c->csize = compute_size(d.precision);
+  const int line = 128 / (int)c->tsize;
+  const int q = std::max(c->V, line);
+  c->px = ((d.nx + q - 1) / q) * q;
+  c->dt = d.courant / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz)));
+  c->segx.assign(d.nx, 0);
+  c->segy.assign(d.ny, 0);
+  c->segz.assign(d.nz, 0);
+  c->eps.assign(1, 1.0);
+  c->sig.assign(1, 0.0);
+  *out = c;
+  return YEE_OK;
+}
+
+void yee_destroy(yee_ctx* ctx) { delete ctx; }
+
+yee_status yee_time_step(const yee_ctx* c, double* dt) {
+  if (!c || !dt) return fail(YEE_EINVAL, "NULL argument");
+  *dt = c->dt;
+  return YEE_OK;
+}
+
+yee_status yee_set_materials(yee_ctx* c, int32_t nsx, int32_t nsy, int32_t nsz, const int32_t* seg_x,
+                             const int32_t* seg_y, const int32_t* seg_z, const double* eps_r,
+                             const double* sigma) {
+  if (!c || !seg_x || !seg_y || !seg_z || !eps_r || !sigma) return fail(YEE_EINVAL, "NULL argument");
+  if (nsx < 1 || nsy < 1 || nsz < 1) return fail(YEE_EINVAL, "lattice must have >= 1 block per axis");
+  if (c->bound && (nsx != c->nsx || nsy != c->nsy || nsz != c->nsz))
+    return fail(YEE_ESTATE, "lattice shape is fixed once the workspace is bound");
+  const auto& d = c->d;
+  for (int i = 0; i < d.nx; ++i) if (seg_x[i] < 0 || seg_x[i] >= nsx) return fail(YEE_EINVAL, "seg_x[%d] out of range", i);
+  for (int i = 0; i < d.ny; ++i) if (seg_y[i] < 0 || seg_y[i] >= nsy) return fail(YEE_EINVAL, "seg_y[%d] out of range", i);
+  for (int i = 0; i < d.nz; ++i) if (seg_z[i] < 0 || seg_z[i] >= nsz) return fail(YEE_EINVAL, "seg_z[%d] out of range", i);
+  const size_t nb = (size_t)nsx * nsy * nsz;
+  for (size_t b = 0; b < nb; ++b)
+    if (!(eps_r[b] >= 1e-3) || !(sigma[b] >= 0.0) || !std::isfinite(eps_r[b]) || !std::isfinite(sigma[b]))
+      return fail(YEE_EINVAL, "material %zu out of range (eps_r %g, sigma %g)", b, eps_r[b], sigma[b]);
+  c->nsx = nsx; c->nsy = nsy; c->nsz = nsz;
+  c->segx.assign(seg_x, seg_x + d.nx);
+  c->segy.assign(seg_y, seg_y + d.ny);
+  c->segz.assign(seg_z, seg_z + d.nz);
+  c->eps.assign(eps_r, eps_r + nb);
+  c->sig.assign(sigma, sigma + nb);
+  return YEE_OK;
+}
+
+yee_status yee_upload_materials(yee_ctx* c, void* stream) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  return upload_materials_impl(c, (hipStream_t)stream);
+}
+
+yee_status yee_add_pec_plane(yee_ctx* c, int32_t k, const uint8_t* mask) {
+  if (!c || !mask) return fail(YEE_EINVAL, "NULL argument");
+  if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
+  if (k <= 0 || k >= c->d.nz) return fail(YEE_EINVAL, "PEC plane k = %d not in (0, nz)", k);
+  if (std::find(c->pec_k.begin(), c->pec_k.end(), k) != c->pec_k.end())
+    return fail(YEE_EINVAL, "PEC plane %d given twice", k);
+  c->pec_k.push_back(k);
+  std::vector<uint8_t> m((size_t)c->d.ny * c->px, 0);
+  for (int j = 0; j < c->d.ny; ++j)
+    for (int i = 0; i < c->d.nx; ++i) m[(size_t)j * c->px + i] = mask[(size_t)j * c->d.nx + i] & 7;
+  c->pec_masks.push_back(std::move(m));
+  return YEE_OK;
+}
+
+yee_status yee_add_source(yee_ctx* c, const yee_source* s) {
+  if (!c || !s) return fail(YEE_EINVAL, "NULL argument");
+  if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
+  const auto& d = c->d;
+  if (s->component < 0 || s->component > 2) return fail(YEE_EINVAL, "source component must be an E component");
+  if (s->i < 0 || s->i >= d.nx || s->j < 0 || s->j >= d.ny || s->k < 0 || s->k >= d.nz)
+    return fail(YEE_EINVAL, "source (%d,%d,%d) outside the grid", s->i, s->j, s->k);
+  if (s->waveform != YEE_GAUSS_DERIV && s->waveform != YEE_MOD_GAUSS) return fail(YEE_EINVAL, "bad waveform");
+  if (!(s->tau > 0)) return fail(YEE_EINVAL, "tau must be > 0");
+  yee::SrcDev sd{};
+  sd.comp = s->component; sd.i = s->i; sd.j = s->j; sd.k = s->k; sd.kind = s->waveform;
+  sd.amp = s->amp; sd.t0 = s->t0; sd.tau = s->tau; sd.f0 = s->f0;
+  c->src.push_back(sd);
+  return YEE_OK;
+}
+
+yee_status yee_add_probe(yee_ctx* c, int32_t comp, int32_t i, int32_t j, int32_t k, int32_t* id) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
+  const auto& d = c->d;
+  if (comp < 0 || comp > 5) return fail(YEE_EINVAL, "probe component %d not in 0..5", comp);
+  if (i < 0 || i >= d.nx || j < 0 || j >= d.ny || k < 0 || k >= d.nz)
+    return fail(YEE_EINVAL, "probe (%d,%d,%d) outside the grid", i, j, k);
+  c->probes.push_back(int4{comp, i, j, k});
+  if (id) *id = (int32_t)c->probes.size() - 1;
+  return YEE_OK;
+}
+
+yee_status yee_set_dft_freqs(yee_ctx* c, const double* freqs, int32_t nf) {
+  if (!c || (nf > 0 && !freqs) || nf < 0) return fail(YEE_EINVAL, "bad argument");
+  if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
+  c->freqs.assign(freqs, freqs + nf);
+  return YEE_OK;
+}
+
+yee_status yee_footprint(const yee_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return fail(YEE_EINVAL, "NULL argument");
+  yee_ctx tmp = *c;
+  layout(&tmp);
+  *bytes = tmp.ws_bytes;
+  return YEE_OK;
+}
+
+yee_status yee_bind_workspace(yee_ctx* c, void* dev, int64_t bytes) {
+  if (!c || !dev) return fail(YEE_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(YEE_EINVAL, "workspace must be 256-byte aligned");
+  layout(c);
+  if (bytes < c->ws_bytes) return fail(YEE_ENOMEM, "workspace has %lld bytes, needs %lld", (long long)bytes, (long long)c->ws_bytes);
+  int dev_id = 0, lds = 0;
+  HIP_TRY(hipGetDevice(&dev_id));
+  HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev_id));
+  if (lds > 0) c->lds_limit = (size_t)lds;
+  c->ws = static_cast<unsigned char*>(dev);
+  c->bound = true;
+  default_launch(c);
+  return YEE_OK;
+}
+
+yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (tile_rows < 0 || tile_rows > yee::kMaxTileRows || chunk_planes < 0)
+    return fail(YEE_EINVAL, "tile_rows must be in 0..%d, chunk_planes >= 0", yee::kMaxTileRows);
+  c->ty = tile_rows;
+  c->kz = chunk_planes;
+  if (c->bound) default_launch(c);
+  return YEE_OK;
+}
+
+yee_status yee_reset(yee_ctx* c, void* stream) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  hipStream_t s = (hipStream_t)stream;
+  const auto& d = c->d;
+  // state: both field sets, psi, series, dft (one contiguous run) -- zeroed
+  const size_t state_end = c->dft.off + align256(std::max<size_t>(c->dft.bytes, 1));
+  HIP_TRY(hipMemsetAsync(c->ws, 0, state_end, s));
+  yee_status st = upload_materials_impl(c, s);
+  if (st) return st;
+  // CPML profiles
+  std::vector<unsigned char> pbuf(c->prof.bytes, 0);
+  const int n3[3] = {d.nx, d.ny, d.nz};
+  const double dw[3] = {d.dx, d.dy, d.dz};
+  for (int side = 0; side < 2; ++side)
+    for (int ax = 0; ax < 3; ++ax) {
+      std::vector<double> b, a, k;
+      cpml_profile(d, dw[ax], c->dt, n3[ax], d.cpml_cells[ax], side, b, a, k);
+      b.resize(c->prof_len, 1.0); a.resize(c->prof_len, 0.0); k.resize(c->prof_len, 1.0);
+      const size_t base = ((size_t)(side * 3 + ax) * 3) * c->prof_len * c->csize;
+      if (c->csize == 8) {
+        put<double>(pbuf, base, b); put<double>(pbuf, base + c->prof_len * 8, a); put<double>(pbuf, base + 2 * c->prof_len * 8, k);
+      } else {
+        put<float>(pbuf, base, b); put<float>(pbuf, base + c->prof_len * 4, a); put<float>(pbuf, base + 2 * c->prof_len * 4, k);
+      }
+    }
+  if ((st = upload(c, c->prof, pbuf.data(), pbuf.size(), s))) return st;
+  // PEC planes
+  std::vector<int32_t> plane(d.nz, -1);
+  std::vector<uint8_t> masks(c->pecmask.bytes, 0);
+  for (size_t p = 0; p < c->pec_k.size(); ++p) {
+    plane[c->pec_k[p]] = (int32_t)p;
+    std::copy(c->pec_masks[p].begin(), c->pec_masks[p].end(), masks.begin() + p * (size_t)d.ny * c->px);
+  }
+  if ((st = upload(c, c->pecplane, plane.data(), plane.size() * 4, s))) return st;
+  if ((st = upload(c, c->pecmask, masks.data(), masks.size(), s))) return st;
+  // row flags, sources, probes, frequencies
+  std::vector<uint8_t> flags((size_t)d.nz * d.ny, 0);
+  for (auto& sd : c->src) flags[(size_t)sd.k * d.ny + sd.j] |= 1;
+  for (auto& p : c->probes) flags[(size_t)p.w * d.ny + p.z] |= 2;
+  if ((st = upload(c, c->rowflag, flags.data(), flags.size(), s))) return st;
+  if ((st = upload(c, c->srcr, c->src.data(), c->src.size() * sizeof(yee::SrcDev), s))) return st;
+  if ((st = upload(c, c->prober, c->probes.data(), c->probes.size() * sizeof(int4), s))) return st;
+  if ((st = upload(c, c->freqr, c->freqs.data(), c->freqs.size() * sizeof(double), s))) return st;
+  HIP_TRY(hipStreamSynchronize(s));
+  c->n = 0;
+  c->folded = 0;
+  return YEE_OK;
+}
+
+yee_status yee_set_field(yee_ctx* c, int32_t comp, const double* host, void* stream) {
+  if (!c || !host) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  if (comp < 0 || comp > 5) return fail(YEE_EINVAL, "component %d not in 0..5", comp);
+  const auto& d = c->d;
+  std::vector<unsigned char> buf((size_t)d.nz * d.ny * c->px * c->tsize, 0);
+  const float enc = d.precision == YEE_F16S ? std::ldexp(1.0f, d.fp16_exp[comp]) : 1.0f;
+  if (d.precision == YEE_F64) {
+    double* o = reinterpret_cast<double*>(buf.data());
+    for (size_t k = 0; k < (size_t)d.nz; ++k)
+      for (size_t j = 0; j < (size_t)d.ny; ++j)
+        for (size_t i = 0; i < (size_t)d.nx; ++i) o[(k * d.ny + j) * c->px + i] = host[(k * d.ny + j) * d.nx + i];
+  } else if (d.precision == YEE_F32) {
+    host_to_storage<float>(host, buf, d, c->px, 1.0f);
+  } else {
+    // round from double directly to fp16 (nearest even) after exact scaling
+    _Float16* o = reinterpret_cast<_Float16*>(buf.data());
+    for (size_t k = 0; k < (size_t)d.nz; ++k)
+      for (size_t j = 0; j < (size_t)d.ny; ++j)
+        for (size_t i = 0; i < (size_t)d.nx; ++i)
+          o[(k * d.ny + j) * c->px + i] = static_cast<_Float16>(host[(k * d.ny + j) * d.nx + i] * (double)enc);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const int cur = (int)(c->n & 1);
+  HIP_TRY(hipMemcpyAsync(c->ws + c->fields[cur].off + comp * c->comp_bytes, buf.data(), buf.size(),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return YEE_OK;
+}
+
+yee_status yee_step(yee_ctx* c, int64_t n_steps, void* stream) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  if (n_steps < 0) return fail(YEE_EINVAL, "n_steps < 0");
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t q = 0; q < n_steps; ++q) {
+    yee_status st = launch_one_step(c, s);
+    if (st) return st;
+    c->n += 1;
+    if (c->n - c->folded >= c->d.series_len) {
+      if ((st = fold_dft(c, s))) return st;
+    }
+  }
+  return fold_dft(c, s);
+}
+
+yee_status yee_steps_done(const yee_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(YEE_EINVAL, "NULL argument");
+  *n = c->n;
+  return YEE_OK;
+}
+
+yee_status yee_read_field(yee_ctx* c, int32_t comp, double* host, void* stream) {
+  if (!c || !host) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  if (comp < 0 || comp > 5) return fail(YEE_EINVAL, "component %d not in 0..5", comp);
+  const auto& d = c->d;
+  std::vector<unsigned char> buf((size_t)d.nz * d.ny * c->px * c->tsize);
+  hipStream_t s = (hipStream_t)stream;
+  const int cur = (int)(c->n & 1);
+  HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->fields[cur].off + comp * c->comp_bytes, buf.size(),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double dec = d.precision == YEE_F16S ? std::ldexp(1.0, -d.fp16_exp[comp]) : 1.0;
+  for (size_t k = 0; k < (size_t)d.nz; ++k)
+    for (size_t j = 0; j < (size_t)d.ny; ++j)
+      for (size_t i = 0; i < (size_t)d.nx; ++i) {
+        const size_t src = (k * d.ny + j) * c->px + i;
+        double v;
+        if (d.precision == YEE_F64) v = reinterpret_cast<const double*>(buf.data())[src];
+        else if (d.precision == YEE_F32) v = reinterpret_cast<const float*>(buf.data())[src];
+        else v = (double)reinterpret_cast<const _Float16*>(buf.data())[src] * dec;
+        host[(k * d.ny + j) * d.nx + i] = v;
+      }
+  return YEE_OK;
+}
+
+yee_status yee_read_series(yee_ctx* c, int64_t first, int64_t count, double* host, void* stream) {
+  if (!c || (count > 0 && !host)) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  if (count < 0 || first < 1 || first + count - 1 > c->n || first <= c->n - c->d.series_len)
+    return fail(YEE_EINVAL, "samples %lld..%lld not in the ring (steps done %lld, ring %d)",
+                (long long)first, (long long)(first + count - 1), (long long)c->n, c->d.series_len);
+  const size_t np = c->probes.size();
+  if (np == 0 || count == 0) return YEE_OK;
+  std::vector<double> ring((size_t)c->d.series_len * np);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(ring.data(), c->ws + c->series.off, ring.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int64_t q = 0; q < count; ++q) {
+    const int64_t n = first + q;
+    const size_t slot = (size_t)((n - 1) % c->d.series_len);
+    std::memcpy(host + q * np, ring.data() + slot * np, np * sizeof(double));
+  }
+  return YEE_OK;
+}
+
+yee_status yee_read_dft(yee_ctx* c, double* re, double* im, void* stream) {
+  if (!c || !re || !im) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  const size_t cnt = c->probes.size() * c->freqs.size();
+  if (cnt == 0) return YEE_OK;
+  std::vector<double> buf(2 * cnt);
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->dft.off, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (size_t q = 0; q < cnt; ++q) {
+    re[q] = buf[2 * q];
+    im[q] = buf[2 * q + 1];
+  }
+  return YEE_OK;
+}
+
+}  // extern "C"

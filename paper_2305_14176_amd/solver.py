@@ -1,0 +1,169 @@
+"""Python binding of one Yee FDTD context (argument marshalling only).
+
+PyTorch provides the device memory (one workspace tensor per context) and the
+stream; every step of the update runs in ``libyee.so``.  Field arrays on the
+Python side use index order (i, j, k) and shape (nx, ny, nz): the stored Yee
+samples with i < nx, j < ny, k < nz (the samples outside are PEC-wall E or
+wall-normal H samples and are identically zero).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from .workloads import COMP_INDEX, Workload
+
+_dp = C.POINTER(C.c_double)
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class YeeSolver:
+    """A configured, bound and reset context for one workload on one device."""
+
+    def __init__(self, wl: Workload, device: str = "cuda:0", series_len: Optional[int] = None,
+                 tile_rows: int = 0, chunk_planes: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = _lib.load()
+        self.wl = wl
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("YeeSolver needs a GPU device (the HIP library has no CPU path)")
+        d = _lib.GridDesc()
+        d.nx, d.ny, d.nz = wl.nx, wl.ny, wl.nz
+        d.dx, d.dy, d.dz = wl.dx, wl.dy, wl.dz
+        d.courant = wl.courant
+        d.precision = _lib.PRECISIONS[wl.precision]
+        for q in range(3):
+            d.cpml_cells[q] = int(wl.cpml_cells[q])
+        d.cpml_m = wl.cpml_m
+        d.cpml_sigma_max = -1.0 if wl.cpml_sigma_max is None else float(wl.cpml_sigma_max)
+        d.cpml_kappa_max = wl.cpml_kappa_max
+        d.cpml_alpha_max = wl.cpml_alpha_max
+        for q in range(6):
+            d.fp16_exp[q] = int(wl.fp16_exp[q])
+        d.series_len = int(series_len if series_len is not None else max(1, wl.steps))
+        self.desc = d
+        ctx = C.c_void_p()
+        _lib.check(self.lib.yee_create(C.byref(d), C.byref(ctx)), "yee_create")
+        self.ctx = ctx
+        dt = C.c_double()
+        _lib.check(self.lib.yee_time_step(ctx, C.byref(dt)), "yee_time_step")
+        self.dt = dt.value
+        self._configure()
+        nbytes = C.c_int64()
+        _lib.check(self.lib.yee_footprint(ctx, C.byref(nbytes)), "yee_footprint")
+        self.footprint = nbytes.value
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(self.footprint + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        _lib.check(self.lib.yee_bind_workspace(ctx, C.c_void_p(aligned), self.footprint), "yee_bind_workspace")
+        if tile_rows or chunk_planes:
+            _lib.check(self.lib.yee_set_launch(ctx, tile_rows, chunk_planes), "yee_set_launch")
+        self.stream = stream
+        self.reset()
+
+    # -- configuration ---------------------------------------------------------
+    def _configure(self):
+        wl, lib, ctx = self.wl, self.lib, self.ctx
+        segx = np.ascontiguousarray(wl.seg_x, np.int32)
+        segy = np.ascontiguousarray(wl.seg_y, np.int32)
+        segz = np.ascontiguousarray(wl.seg_z, np.int32)
+        eps = np.ascontiguousarray(wl.eps_blk, np.float64)
+        sig = np.ascontiguousarray(wl.sig_blk, np.float64)
+        _lib.check(lib.yee_set_materials(ctx, wl.nsx, wl.nsy, wl.nsz, _ptr(segx, C.c_int32), _ptr(segy, C.c_int32),
+                                         _ptr(segz, C.c_int32), _ptr(eps, C.c_double), _ptr(sig, C.c_double)),
+                   "yee_set_materials")
+        for k, mask in wl.pec_planes:
+            m = np.ascontiguousarray(mask, np.uint8)
+            _lib.check(lib.yee_add_pec_plane(ctx, int(k), _ptr(m, C.c_uint8)), "yee_add_pec_plane")
+        for s in wl.sources:
+            t0, tau = s.times(self.dt)
+            sd = _lib.SourceDesc(s.comp, s.i, s.j, s.k, _lib.WAVEFORMS[s.kind], s.amp, t0, tau, s.f0)
+            _lib.check(lib.yee_add_source(ctx, C.byref(sd)), "yee_add_source")
+        for (comp, i, j, k) in wl.probes:
+            pid = C.c_int32()
+            _lib.check(lib.yee_add_probe(ctx, comp, i, j, k, C.byref(pid)), "yee_add_probe")
+        f = np.ascontiguousarray(wl.freqs, np.float64)
+        _lib.check(lib.yee_set_dft_freqs(ctx, _ptr(f, C.c_double) if f.size else None, int(f.size)),
+                   "yee_set_dft_freqs")
+
+    def _s(self):
+        if self.stream is not None:
+            return C.c_void_p(self.stream.cuda_stream)
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    # -- state -----------------------------------------------------------------
+    def reset(self):
+        _lib.check(self.lib.yee_reset(self.ctx, self._s()), "yee_reset")
+
+    def set_materials(self, eps_blk: np.ndarray, sig_blk: Optional[np.ndarray] = None):
+        """Replace the block values (same lattice) and upload them."""
+        wl = self.wl
+        eps = np.ascontiguousarray(eps_blk, np.float64)
+        sig = np.ascontiguousarray(wl.sig_blk if sig_blk is None else sig_blk, np.float64)
+        segx = np.ascontiguousarray(wl.seg_x, np.int32)
+        segy = np.ascontiguousarray(wl.seg_y, np.int32)
+        segz = np.ascontiguousarray(wl.seg_z, np.int32)
+        _lib.check(self.lib.yee_set_materials(self.ctx, wl.nsx, wl.nsy, wl.nsz, _ptr(segx, C.c_int32),
+                                              _ptr(segy, C.c_int32), _ptr(segz, C.c_int32),
+                                              _ptr(eps, C.c_double), _ptr(sig, C.c_double)), "yee_set_materials")
+        _lib.check(self.lib.yee_upload_materials(self.ctx, self._s()), "yee_upload_materials")
+
+    def set_field(self, comp, arr: np.ndarray):
+        ci = COMP_INDEX[comp] if isinstance(comp, str) else int(comp)
+        a = np.ascontiguousarray(np.transpose(np.asarray(arr, np.float64), (2, 1, 0)))
+        _lib.check(self.lib.yee_set_field(self.ctx, ci, _ptr(a, C.c_double), self._s()), "yee_set_field")
+
+    def step(self, n: int):
+        _lib.check(self.lib.yee_step(self.ctx, int(n), self._s()), "yee_step")
+
+    @property
+    def steps_done(self) -> int:
+        v = C.c_int64()
+        _lib.check(self.lib.yee_steps_done(self.ctx, C.byref(v)), "yee_steps_done")
+        return v.value
+
+    def field(self, comp) -> np.ndarray:
+        ci = COMP_INDEX[comp] if isinstance(comp, str) else int(comp)
+        wl = self.wl
+        out = np.empty((wl.nz, wl.ny, wl.nx), np.float64)
+        _lib.check(self.lib.yee_read_field(self.ctx, ci, _ptr(out, C.c_double), self._s()), "yee_read_field")
+        return np.ascontiguousarray(np.transpose(out, (2, 1, 0)))
+
+    def series(self, first: int = 1, count: Optional[int] = None) -> np.ndarray:
+        """Probe samples y[n], n = first .. first+count-1, as [count, n_probes]."""
+        count = self.steps_done - first + 1 if count is None else count
+        out = np.empty((max(count, 0), len(self.wl.probes)), np.float64)
+        _lib.check(self.lib.yee_read_series(self.ctx, int(first), int(count),
+                                            _ptr(out, C.c_double) if out.size else None, self._s()),
+                   "yee_read_series")
+        return out
+
+    def dft(self) -> np.ndarray:
+        npr, nf = len(self.wl.probes), len(self.wl.freqs)
+        re = np.zeros((npr, nf))
+        im = np.zeros((npr, nf))
+        if npr and nf:
+            _lib.check(self.lib.yee_read_dft(self.ctx, _ptr(re, C.c_double), _ptr(im, C.c_double), self._s()),
+                       "yee_read_dft")
+        return re + 1j * im
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.yee_destroy(self.ctx)
+            self.ctx = None
+            self.workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,147 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid configurations before any device work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2305_14176_amd import _lib
+from paper_2305_14176_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "yee.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(yee_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    decl = _declared()
+    assert set(decl) == set(_lib.EXPORTED), set(decl) ^ set(_lib.EXPORTED)
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert lib.yee_api_version() == 1
+
+
+def _desc(**kw):
+    d = _lib.GridDesc()
+    d.nx, d.ny, d.nz = kw.get("n", (16, 16, 16))
+    d.dx = d.dy = d.dz = 1e-3
+    d.courant = kw.get("courant", 0.99)
+    d.precision = kw.get("precision", 1)
+    for q, v in enumerate(kw.get("cpml", (0, 0, 0))):
+        d.cpml_cells[q] = v
+    d.cpml_m = 3.0
+    d.cpml_sigma_max = -1.0
+    d.cpml_kappa_max = 1.0
+    d.cpml_alpha_max = 0.0
+    d.series_len = kw.get("series_len", 8)
+    return d
+
+
+@pytest.mark.parametrize("kw,ok", [
+    ({}, True),
+    ({"courant": 1.2}, False),
+    ({"courant": 0.0}, False),
+    ({"n": (1, 16, 16)}, False),
+    ({"n": (513, 16, 16)}, False),
+    ({"n": (300, 16, 16), "precision": 0}, False),      # FP64 rows limited to 256
+    ({"n": (512, 16, 16)}, True),
+    ({"cpml": (9, 0, 0)}, False),                      # 2 L > n
+    ({"cpml": (8, 8, 8)}, True),
+    ({"series_len": 0}, False),
+    ({"precision": 7}, False),
+])
+def test_create_validates(kw, ok):
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    d = _desc(**kw)
+    ctx = C.c_void_p()
+    st = lib.yee_create(C.byref(d), C.byref(ctx))
+    assert (st == 0) == ok, lib.yee_last_error()
+    if ok:
+        nb = C.c_int64()
+        assert lib.yee_footprint(ctx, C.byref(nb)) == 0
+        assert nb.value > 0
+        lib.yee_destroy(ctx)
+    else:
+        assert st == -1 and not ctx.value
+        assert lib.yee_last_error()
+
+
+def test_configuration_errors_before_device_work():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    d = _desc()
+    ctx = C.c_void_p()
+    assert lib.yee_create(C.byref(d), C.byref(ctx)) == 0
+    pid = C.c_int32()
+    assert lib.yee_add_probe(ctx, 6, 1, 1, 1, C.byref(pid)) == -1
+    assert lib.yee_add_probe(ctx, 2, 16, 1, 1, C.byref(pid)) == -1
+    assert lib.yee_add_probe(ctx, 2, 3, 4, 5, C.byref(pid)) == 0 and pid.value == 0
+    s = _lib.SourceDesc(3, 1, 1, 1, 0, 1.0, 0.0, 1e-12, 0.0)   # H component: rejected
+    assert lib.yee_add_source(ctx, C.byref(s)) == -1
+    s = _lib.SourceDesc(2, 1, 1, 1, 0, 1.0, 0.0, 0.0, 0.0)     # tau = 0: rejected
+    assert lib.yee_add_source(ctx, C.byref(s)) == -1
+    seg = np.zeros(16, np.int32)
+    bad = np.array([5.0, 1.0])
+    eps = np.array([0.0])
+    sig = np.array([0.0])
+    p32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int32))
+    pd = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.yee_set_materials(ctx, 1, 1, 1, p32(seg), p32(seg), p32(seg), pd(eps), pd(sig)) == -1
+    seg2 = seg.copy(); seg2[3] = 2
+    assert lib.yee_set_materials(ctx, 2, 1, 1, p32(seg2), p32(seg), p32(seg), pd(bad), pd(np.zeros(2))) == -1
+    # calls that need a bound workspace
+    assert lib.yee_step(ctx, 1, None) == -4
+    assert lib.yee_reset(ctx, None) == -4
+    mask = np.zeros(256, np.uint8)
+    assert lib.yee_add_pec_plane(ctx, 0, mask.ctypes.data_as(C.POINTER(C.c_uint8))) == -1
+    assert lib.yee_add_pec_plane(ctx, 5, mask.ctypes.data_as(C.POINTER(C.c_uint8))) == 0
+    lib.yee_destroy(ctx)
+
+
+def test_time_step_matches_courant_definition():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    d = _desc()
+    ctx = C.c_void_p()
+    assert lib.yee_create(C.byref(d), C.byref(ctx)) == 0
+    dt = C.c_double()
+    assert lib.yee_time_step(ctx, C.byref(dt)) == 0
+    assert abs(dt.value - 0.99e-3 / (299792458.0 * np.sqrt(3.0))) < 1e-27
+    lib.yee_destroy(ctx)
+
+
+def test_workloads_are_seeded_and_consistent():
+    a, b = W.cpml_block_lattice(n=64, steps=10), W.cpml_block_lattice(n=64, steps=10)
+    np.testing.assert_array_equal(a.eps_blk, b.eps_blk)
+    assert a.probes == b.probes
+    eps, sig = a.cell_materials()
+    assert eps.shape == (64, 64, 64)
+    assert eps[0, 0, 0] == a.eps_blk[0] and eps[8, 0, 0] == a.eps_blk[1] and eps[0, 8, 0] == a.eps_blk[a.nsx]
+    assert 1.0 <= eps.min() and eps.max() < 10.0 and 0.0 <= sig.min() and sig.max() < 0.1
+    c1 = W.plain_pec_box()
+    e1, _ = c1.cell_materials()
+    assert e1[12:20, 12:20, 12:20].min() == 4.0 and e1.sum() == 32 ** 3 + 3 * 8 ** 3
+    for (_, i, j, k) in c1.probes:
+        assert 1 <= i < 31 and (i, j, k) != (16, 16, 16)
+    f = W.fp16_substrate(128, 128, 64, steps=10)
+    m = f.pec_component_masks()
+    assert m["Ex"].any() and not m["Ez"].any()
+    ad = W.adjoint_design(n=40, design=(12, 28), steps=8, cpml=4)
+    e, _ = ad.cell_materials()
+    assert np.all(e[:12] == 1.0) and np.all(e[12:28, 12:28, 12:28] >= 1.0) and e[12:28, 12:28, 12:28].std() > 0.5
+    for (_, i, j, k) in ad.probes:
+        assert not (12 <= i < 28 and 12 <= j < 28 and 12 <= k < 28)

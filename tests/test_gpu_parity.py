@@ -1,0 +1,164 @@
+"""GPU parity: the HIP step (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (relative L2 per output: each probe series, each probe's DFT
+vector, each final field component):
+  * FP64 mode  : 1e-12  (only rounding order and FMA contraction differ);
+  * FP32 mode  : 1e-5   against the FP64 oracle;
+  * FP16 storage: 1e-3  against the oracle emulating FP16 storage.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_14176_amd import workloads as W
+from _helpers import oracle_from_workload, rel_l2, stored
+
+pytestmark = pytest.mark.gpu
+
+COMPS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16": 1e-3}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver_cls():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_14176_amd.solver import YeeSolver
+    return YeeSolver
+
+
+def _run_both(solver_cls, wl, steps, init_seed=None, **kw):
+    init = W.random_initial_fields(wl, init_seed) if init_seed is not None else None
+    _say(f"[gpu] {wl.name} prec={wl.precision} steps={steps} init={init_seed} kw={kw}")
+    s = solver_cls(wl, series_len=max(steps, 1), **kw)
+    if init is not None:
+        for c, a in init.items():
+            s.set_field(c, a)
+    s.step(steps)
+    sim = oracle_from_workload(wl, initial=init)
+    assert sim.dt == s.dt
+    sim.run(steps)
+    return s, sim
+
+
+def _check_fields(s, sim, tol):
+    for c in COMPS:
+        ref = stored(sim, c)
+        got = s.field(c)
+        err = rel_l2(got, ref)
+        assert err <= tol, (c, err)
+
+
+def _check_probes(s, sim, tol, steps):
+    if not sim.probes:
+        return
+    got = s.series(1, steps)
+    ref = sim.series_array()
+    for p in range(len(sim.probes)):
+        err = rel_l2(got[:, p], ref[:, p])
+        assert err <= tol, ("series", p, err)
+    if len(s.wl.freqs):
+        gd = s.dft()
+        for p in range(len(sim.probes)):
+            err = rel_l2(gd[p], sim.dft[p])
+            assert err <= tol, ("dft", p, err)
+
+
+def test_plain_pec_box_fp64_full():
+    """The 32^3 FP64 PEC box, full size and step count."""
+    import torch  # noqa
+    from paper_2305_14176_amd.solver import YeeSolver
+    wl = W.plain_pec_box()
+    s, sim = _run_both(YeeSolver, wl, wl.steps)
+    _check_probes(s, sim, TOL["f64"], wl.steps)
+    _check_fields(s, sim, TOL["f64"])
+    assert np.abs(s.series()).max() > 1e-3
+
+
+@pytest.mark.parametrize("shape,cpml,v", [
+    ((37, 29, 23), (4, 3, 5), "ragged V=1"),
+    ((100, 21, 18), (6, 2, 0), "V=2, no z layer"),
+    ((200, 12, 30), (10, 5, 7), "V=4"),
+    ((2, 2, 2), (0, 0, 0), "smallest grid"),
+])
+def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
+    nx, ny, nz = shape
+    wl = W.cpml_block_lattice(n=nx, ny=ny, nz=nz, steps=12, precision="f64", cpml=0, nprobes=0, nfreq=0,
+                              block=4)
+    wl.cpml_cells = cpml
+    wl.cpml_kappa_max = 2.0
+    wl.cpml_alpha_max = 0.05
+    wl.sources = [] if min(shape) < 4 else wl.sources
+    s, sim = _run_both(solver_cls, wl, 12, init_seed=11)
+    _check_fields(s, sim, TOL["f64"])
+
+
+@pytest.mark.parametrize("shape,ty,kz", [
+    ((256, 40, 33), 0, 0),
+    ((256, 40, 33), 3, 5),
+    ((300, 17, 26), 7, 4),     # V = 8
+    ((160, 48, 48), 5, 16),
+    ((512, 9, 12), 1, 1),      # widest rows, one row per tile, one plane per chunk
+])
+def test_random_init_fp32_launch_shapes(solver_cls, shape, ty, kz):
+    nx, ny, nz = shape
+    wl = W.cpml_block_lattice(n=nx, ny=ny, nz=nz, steps=10, precision="f32", cpml=1, nprobes=6, nfreq=8)
+    wl.cpml_cells = (min(6, nx // 2), min(4, ny // 2), min(5, nz // 2))
+    s, sim = _run_both(solver_cls, wl, 10, init_seed=12, tile_rows=ty, chunk_planes=kz)
+    _check_fields(s, sim, TOL["f32"])
+
+
+def test_cpml_lattice_fp32_probes_and_dft(solver_cls):
+    """The CPML block-lattice workload at 64^3 for 400 steps (probes + DFT)."""
+    wl = W.cpml_block_lattice(n=64, steps=400)
+    s, sim = _run_both(solver_cls, wl, wl.steps)
+    _check_probes(s, sim, TOL["f32"], wl.steps)
+    _check_fields(s, sim, TOL["f32"])
+
+
+def test_cpml_lattice_full_size_fp32_few_steps(solver_cls):
+    """256^3 in the benchmark's launch shape, 3 steps from a random state."""
+    wl = W.cpml_block_lattice(n=256, steps=3, nprobes=16)
+    s, sim = _run_both(solver_cls, wl, 3, init_seed=21)
+    _check_fields(s, sim, TOL["f32"])
+    _check_probes(s, sim, TOL["f32"], 3)
+
+
+def test_fp16_storage_substrate(solver_cls):
+    """FP16 storage with a PEC strip mask, against the FP16-emulating oracle."""
+    # long enough for the pulse (peak at t0 = 4 tau, about 210 steps) to reach the probes
+    wl = W.fp16_substrate(64, 64, 40, steps=500, cpml=6)
+    s, sim = _run_both(solver_cls, wl, wl.steps)
+    _check_probes(s, sim, TOL["f16"], wl.steps)
+    _check_fields(s, sim, TOL["f16"])
+    # the FP64 (no storage rounding) error is reported, not gated
+    sim64 = oracle_from_workload(wl, storage="f64")
+    sim64.run(wl.steps)
+    errs = [rel_l2(s.series()[:, p], sim64.series_array()[:, p]) for p in range(len(wl.probes))]
+    _say(f"[gpu] fp16 storage vs pure FP64 oracle: max series rel L2 = {max(errs):.3e}")
+
+
+def test_series_ring_and_dft_chunking(solver_cls):
+    """A ring shorter than the run: the DFT is folded chunk by chunk."""
+    wl = W.cpml_block_lattice(n=48, steps=150, nprobes=5, nfreq=16)
+    s = solver_cls(wl, series_len=32)
+    s.step(100)
+    s.step(50)
+    sim = oracle_from_workload(wl)
+    sim.run(150)
+    got = s.series(150 - 31, 32)
+    ref = sim.series_array()[150 - 32:]
+    for p in range(5):
+        assert rel_l2(got[:, p], ref[:, p]) <= TOL["f32"]
+    gd = s.dft()
+    for p in range(5):
+        assert rel_l2(gd[p], sim.dft[p]) <= TOL["f32"]
+    with pytest.raises(Exception):
+        s.series(1, 10)   # no longer in the ring
