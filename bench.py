@@ -1,0 +1,158 @@
+"""Benchmark of the Yee FDTD step on one MI355X.
+
+Workload: the 256^3 FP32 grid with a 10-cell CPML on all faces, an 8^3-cell
+block lattice (eps_r ~ U[1, 10), sigma ~ U[0, 0.1) S/m), a modulated-Gaussian
+Ez source, 16 probes and a 64-frequency FP64 running DFT.  One "step" is one
+full leapfrog step (H and E half-updates, CPML, source, probes; the DFT fold
+runs on the same stream inside the timed region).
+
+Prints one JSON line: Mcell-updates/s, the HBM roofline of the fused step
+kernel (algorithmic bytes per launch over its measured duration), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak (AMD public spec)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_cpml256_fp32_traffic.json")
+
+
+def algorithmic_bytes_per_step(wl, elem_bytes=4, psi_bytes=4):
+    """Bytes one step must move at minimum: every field component read and
+    written once (12 component accesses per cell) plus every CPML auxiliary
+    read and written once.  The material table (32^3 blocks) stays in cache."""
+    nx, ny, nz = wl.nx, wl.ny, wl.nz
+    fields = 12 * elem_bytes * nx * ny * nz
+    lx, ly, lz = wl.cpml_cells
+    psi_elems = 2 * (nz * ny * 2 * lx) + 2 * (nz * 2 * ly * nx) + 2 * (2 * lz * ny * nx)  # per side
+    psi = 2 * 2 * psi_bytes * psi_elems     # E side + H side, read + write
+    return fields + psi, fields, psi
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("yee_kernels.hpp", "yee_runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2305_14176_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """Counter-measured HBM bytes per launch, if taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, budget_s=15.0, max_steps=5):
+    """The FP64 oracle (numpy, single thread) on the same 256^3 workload, a few steps."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _helpers import oracle_from_workload
+    sim = oracle_from_workload(wl)
+    sim.step()  # first step pays page faults of the large arrays
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps:
+        sim.step()
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": wl.cells * n / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} steps of the same {wl.nx}x{wl.ny}x{wl.nz} workload after 1 untimed step "
+                      f"(numpy FP64, single-threaded elementwise), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=256, help="grid side (256 is the benchmark workload)")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--chunk-planes", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; no multi-GPU path exists (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.solver import YeeSolver
+
+    wl = W.cpml_block_lattice(n=args.n, steps=args.steps)
+    solver = YeeSolver(wl, device="cuda:0", series_len=max(1000, args.steps),
+                       tile_rows=args.tile_rows, chunk_planes=args.chunk_planes)
+    stream = torch.cuda.current_stream()
+    solver.step(args.warmup)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ev0.record(stream)
+    solver.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    ms = ev0.elapsed_time(ev1)
+    ms_per_step = ms / args.steps
+
+    cells = wl.cells
+    value = cells * args.steps / (ms / 1e3) / 1e6
+    alg, fields_b, psi_b = algorithmic_bytes_per_step(wl)
+    achieved = alg / (ms_per_step / 1e3) / 1e9
+    traffic = load_traffic()
+
+    out = {
+        "metric": "Mcell-updates/s (FP32 Yee step, 256^3, CPML 10)",
+        "value": round(value, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": cells, "cpml_cells": list(wl.cpml_cells),
+                   "materials": "8^3-cell block lattice, eps_r~U[1,10), sigma~U[0,0.1)",
+                   "probes": len(wl.probes), "dft_freqs": len(wl.freqs),
+                   "tile_rows": args.tile_rows or "auto", "chunk_planes": args.chunk_planes or "auto",
+                   "parallelism": "single GPU"},
+        "hbm_gbs_algorithmic": round(achieved, 1),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg,
+                     "kernel": "yee::step_kernel<float,float,4>",
+                     "kernel_ms_avg": round(ms_per_step, 5)},
+        "wall_s_timed": round(t_wall, 4),
+    }
+    if not args.no_cpu_baseline:
+        del solver
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -76,7 +76,7 @@ typedef enum {
 
 /* Grid description (Yee 1966 grid; CPML per Roden & Gedney 2000). */
 typedef struct {
-    int32_t nx, ny, nz;        /* cells; 2 <= n; nx <= 512 (nx <= 256 for YEE_F64) */
+    int32_t nx, ny, nz;        /* cells; 2 <= n; nx <= 512 */
     double dx, dy, dz;         /* cell sizes in metres, > 0 */
     double courant;            /* S in (0, 1]: dt = S / (c0 sqrt(dx^-2 + dy^-2 + dz^-2)) */
     int32_t precision;         /* yee_precision */
@@ -185,9 +185,11 @@ yee_status yee_read_series(yee_ctx* ctx, int64_t first, int64_t count, double* h
 /* DFT accumulators into re[n_probes][nf], im[n_probes][nf].  Synchronizes. */
 yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
 
-/* Launch shape of the fused step kernel: rows per workgroup tile (1..15)
- * and planes per z-chunk (>= 1); 0 keeps the automatic choice. */
-yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes);
+/* Launch shape of the fused step kernel: y-rows per workgroup tile, planes
+ * per z-chunk and x samples per lane (1, 2 or 4); 0 keeps the automatic
+ * choice.  A workgroup holds (tile_rows + 1) * ceil(nx / (64 * samples))
+ * waves, at most 16.  Results do not depend on the launch shape. */
+yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane);
 
 #ifdef __cplusplus
 }

@@ -92,7 +92,7 @@ def load():
         "yee_read_field": (I32, [VP, I32, P(D), VP]),
         "yee_read_series": (I32, [VP, I64, I64, P(D), VP]),
         "yee_read_dft": (I32, [VP, P(D), P(D), VP]),
-        "yee_set_launch": (I32, [VP, I32, I32]),
+        "yee_set_launch": (I32, [VP, I32, I32, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -6,17 +6,25 @@
 // absorbing layers (Roden & Gedney 2000).  The paper defines no full-wave
 // solver; these are the textbook operations.
 //
-// Fused single pass.  A workgroup owns a tile of TY consecutive y-rows (full
-// x extent: one wave per row, V consecutive x samples per lane) and a chunk
-// of z-planes, and marches upward in z.  At plane k it
-//   1. computes H^{n+1/2}(k) for its rows plus the halo row j0-1 (wave 0),
-//      from E^n(k), E^n(k+1) and H^{n-1/2}(k);
-//   2. computes E^{n+1}(k) from H^{n+1/2}(k) (rows j, j-1 via LDS; x-1 via a
-//      lane shuffle) and H^{n+1/2}(k-1) (kept in registers);
+// Fused single pass.  A workgroup owns a tile of TY consecutive y-rows over
+// the full x extent and a chunk of z-planes, and marches upward in z.  Each
+// row is covered by WPR waves, each lane holding V consecutive x samples; the
+// first WPR waves carry the halo row j0-1 (whose H the tile recomputes).  At
+// plane k the workgroup
+//   1. publishes E^n(k) of its rows in LDS and computes H^{n+1/2}(k) from
+//      E^n(k) (x+1 and y+1 neighbours from LDS), E^n(k+1) and H^{n-1/2}(k);
+//   2. publishes H^{n+1/2}(k) in LDS and computes E^{n+1}(k) from it (x-1 and
+//      y-1 neighbours from LDS) and H^{n+1/2}(k-1) (kept in registers);
 //   3. stores both.
-// y-neighbours move through LDS, x-neighbours through lane shuffles, z-
-// neighbours stay in registers.  E, H and the H-side psi are ping-ponged so a
-// tile that recomputes its neighbour's halo row reads the old values.
+// E, H and the H-side psi are ping-ponged, so a tile that recomputes its
+// neighbour's halo row reads old values only.
+//
+// Memory pipelining.  gfx9 counts outstanding vector loads in one in-order
+// counter, so waiting for any load also waits for every load issued before
+// it.  Each iteration therefore issues its small loads (CPML auxiliaries,
+// material and mask data) first and the plane prefetches (E^n(k+2),
+// H^{n-1/2}(k+1)) last; waits for the small loads then leave the prefetches
+// in flight for a whole iteration.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +33,12 @@
 namespace yee {
 
 constexpr int kWave = 64;
-constexpr int kMaxTileRows = 7;
+constexpr int kMaxBlockWaves = 16;   // 1024 threads
+
+// Waves a workgroup may hold at V samples per lane (bounds the registers the
+// compiler may give each lane).
+__host__ __device__ constexpr int max_block_waves(int V) { return V >= 4 ? 8 : 16; }
+constexpr int kMaxSources = 8;
 
 // psi array order (E side in place; H side ping-ponged)
 enum { PEXY = 0, PEXZ, PEYZ, PEYX, PEZX, PEZY };
@@ -41,46 +54,38 @@ struct Coef2 {
   C ca, cb;
 };
 
+// Kernel arguments.  Few base pointers (element offsets are derived in the
+// kernel) keep the scalar register file from spilling.
 template <class T, class C>
 struct StepArgs {
-  const T* e_in[3];
-  const T* h_in[3];
-  T* e_out[3];
-  T* h_out[3];
-  C* psi_e[6];
-  const C* psi_h_in[6];
-  C* psi_h_out[6];
-  // CPML profiles per side (0 = E, 1 = H) and axis: b, a, 1/kappa over the axis
-  const C* pb[2][3];
-  const C* pa[2][3];
-  const C* pk[2][3];
-  // materials
-  const int32_t* segx;  // [px]
-  const int32_t* segy;  // [ny]
-  const int32_t* segz;  // [nz]
-  const Coef2<C>* coef; // [nsz][nsy][nsx]
+  const T* fin;             // E^n, H^{n-1/2}: component c (Ex..Hz) at fin + c * cstride
+  T* fout;                  // E^{n+1}, H^{n+1/2}
+  uint64_t cstride;         // elements between components
+  C* pse;                   // E-side psi, updated in place
+  const C* psh_in;          // H-side psi, old
+  C* psh_out;               // H-side psi, new
+  uint32_t psoff[6];        // element offset of each psi array inside its region
+  const C* prof;            // CPML profiles [side E,H][axis][b | a | 1/kappa][plen]
+  int32_t plen;
+  const int32_t* seg;       // block index per cell: x [px] | y [ny] | z [nz]
+  const Coef2<C>* coef;     // (Ca, Cb) per block [nsz][nsy][nsx]
   int32_t nsx, nsxy;
-  // PEC planes
-  const int32_t* pec_plane;  // [nz], -1 = none
-  const uint8_t* pec_mask;   // [nplanes][ny][px]
-  // sources / probes
-  const uint8_t* rowflag;    // [nz][ny] bit0 source, bit1 probe
-  const SrcDev* src;
+  const int32_t* pec_plane; // [nz], -1 = none
+  const uint8_t* pec_mask;  // [nplanes][ny][px], bit 0 Ex, 1 Ey, 2 Ez
+  const uint8_t* rowflag;   // [nz][ny], bit 0 source, bit 1 probe
+  const int4* probe;        // (comp, i, j, k)
+  double* series;           // probe ring [series_len][nprobe]
+  int32_t nprobe, series_slot;
+  const SrcDev* src;        // soft sources
   int32_t nsrc;
-  const int4* probe;         // (comp, i, j, k)
-  int32_t nprobe;
-  double* series;            // [series_len][nprobe]
-  int32_t series_len;
-  // geometry
+  int64_t n;                // index of the step being taken
+  double dt;
   int32_t nx, ny, nz, px;
   int32_t L[3];
   C inv_d[3];
   C dt_mu;
-  double dt;
-  int64_t n;                 // index of the step being taken
-  float enc[6], dec[6];      // FP16 storage scales (2^s, 2^-s)
-  // launch shape
-  int32_t ty, kz, ny_tiles, ntiles;
+  float enc[6], dec[6];     // FP16 storage scales (2^s, 2^-s)
+  int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, planes per chunk, waves per row
 };
 
 // ---------------------------------------------------------------------------
@@ -103,9 +108,10 @@ struct alignas(sizeof(T) * V) VecT {
 };
 
 template <class T, class C, int V>
-__device__ __forceinline__ void load_row(const T* __restrict__ p, bool ok, C (&out)[V], float dec) {
+__device__ __forceinline__ void load_row(const T* __restrict__ base, uint32_t off, bool ok, C (&out)[V],
+                                         float dec) {
   if (ok) {
-    const VecT<T, V> r = *reinterpret_cast<const VecT<T, V>*>(p);
+    const VecT<T, V> r = *reinterpret_cast<const VecT<T, V>*>(base + off);
 #pragma unroll
     for (int e = 0; e < V; ++e) out[e] = Conv<T, C>::ld(r.v[e], dec);
   } else {
@@ -115,11 +121,11 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, bool ok, C (&o
 }
 
 template <class T, class C, int V>
-__device__ __forceinline__ void store_row(T* __restrict__ p, const C (&in)[V], float enc) {
+__device__ __forceinline__ void store_row(T* __restrict__ base, uint32_t off, const C (&in)[V], float enc) {
   VecT<T, V> r;
 #pragma unroll
   for (int e = 0; e < V; ++e) r.v[e] = Conv<T, C>::st(in[e], enc);
-  *reinterpret_cast<VecT<T, V>*>(p) = r;
+  *reinterpret_cast<VecT<T, V>*>(base + off) = r;
 }
 
 // Round a computed value to what storage would hold (identity unless FP16).
@@ -128,35 +134,36 @@ __device__ __forceinline__ C to_storage(C v, float enc, float dec) {
   return Conv<T, C>::ld(Conv<T, C>::st(v, enc), dec);
 }
 
-// Source waveform in FP64 (same definitions as the header documents).
-__device__ __forceinline__ double waveform(const SrcDev& s, double t) {
+// Source waveform in FP64: w(t) = -2u exp(-u^2) or sin(2 pi f0 (t - t0)) exp(-u^2).
+__device__ __noinline__ double waveform(const SrcDev s, double t) {
   const double u = (t - s.t0) / s.tau;
   const double g = exp(-u * u);
   if (s.kind == 0) return -2.0 * u * g;
   return sin(2.0 * M_PI * s.f0 * (t - s.t0)) * g;
 }
 
-template <class C>
-__device__ __forceinline__ C shfl_down1(C v, int lane) {
-  C r = __shfl_down(v, 1, kWave);
-  return lane == kWave - 1 ? C(0) : r;
-}
-template <class C>
-__device__ __forceinline__ C shfl_up1(C v, int lane) {
-  C r = __shfl_up(v, 1, kWave);
-  return lane == 0 ? C(0) : r;
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// LDS footprint of one workgroup (elements of C): E rows j0-1..j0+ty, H rows
+// j0-1..j0+ty-1, each with three components of RL = wpr * 64 * V samples,
+// plus the source values.
+__host__ __device__ inline size_t step_lds_elems(int ty, int wpr, int V) {
+  const size_t rl = (size_t)wpr * kWave * V;
+  return (size_t)(ty + 2) * 3 * rl + (size_t)(ty + 1) * 3 * rl + kMaxSources;
 }
 
 // ---------------------------------------------------------------------------
 // The fused step kernel
 // ---------------------------------------------------------------------------
 template <class T, class C, int V>
-__global__ void __launch_bounds__(kWave * (kMaxTileRows + 1))
+__global__ void __launch_bounds__(kWave * max_block_waves(V))
 step_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
-  constexpr int RW = kWave * V;
-  C* ldsE = reinterpret_cast<C*>(smem_raw);      // [(ty+2)][2][RW]: Ez, Ex at plane k
-  C* ldsH = ldsE + (a.ty + 2) * 2 * RW;           // [(ty+1)][2][RW]: Hz, Hx at plane k
+  const int wpr = a.wpr;
+  const int RL = wpr * kWave * V;                 // LDS row length
+  C* ldsE = reinterpret_cast<C*>(smem_raw);      // [(ty+2)][3][RL]: E^n(k) rows j0-1..j0+ty
+  C* ldsH = ldsE + (a.ty + 2) * 3 * RL;           // [(ty+1)][3][RL]: H^{n+1/2}(k) rows j0-1..j0+ty-1
+  C* ldsS = ldsH + (a.ty + 1) * 3 * RL;           // [kMaxSources]: amp * w((n+1) dt)
 
   // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
   // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
@@ -167,225 +174,378 @@ step_kernel(const StepArgs<T, C> a) {
   const int ytile = t % a.ny_tiles;
   const int chunk = t / a.ny_tiles;
 
-  const int w = threadIdx.x >> 6;
+  if ((int)threadIdx.x < a.nsrc) {
+    const SrcDev sd = a.src[threadIdx.x];
+    ldsS[threadIdx.x] = static_cast<C>(sd.amp * waveform(sd, (double)(a.n + 1) * a.dt));
+  }
+  // (the first barrier of the march orders these writes before any use)
+
+  const int wv = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int j0 = ytile * a.ty;
-  const int j = j0 - 1 + w;          // w = 0: halo row j0-1
-  const bool halo = (w == 0);
-  const bool row_ok = (j >= 0) && (j < a.ny);
-  const int k0 = chunk * a.kz;
-  const int k1 = min(a.nz, k0 + a.kz);
-  const int kstart = k0 > 0 ? k0 - 1 : 0;
-  const int x0 = lane * V;
-  const bool lane_ok = x0 < a.nx;
+  const int r = wv / wpr;                 // tile row: 0 = halo row j0-1
+  const int xs = wv - r * wpr;            // x segment of the row
   const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
-  const size_t plane = (size_t)ny * px;
+  const int j0 = ytile * a.ty;
+  const int j = j0 - 1 + r;
+  const bool halo = (r == 0);
+  const bool row_ok = (j >= 0) && (j < ny);
+  const int jc = min(max(j, 0), ny - 1);
+  const int k0 = chunk * a.kz;
+  const int k1 = min(nz, k0 + a.kz);
+  const int kstart = k0 > 0 ? k0 - 1 : 0;
+  const int xl = (xs * kWave + lane) * V;  // first sample of the lane within the row
+  const bool lane_ok = xl < nx;
+  const bool ld_ok = row_ok && lane_ok;
+  const uint32_t plane = (uint32_t)ny * (uint32_t)px;
+  const uint32_t rowoff = (uint32_t)jc * (uint32_t)px + (uint32_t)xl;
   const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
+  const uint64_t cs = a.cstride;
+  const T* __restrict__ fEx = a.fin;
+  const T* __restrict__ fEy = a.fin + cs;
+  const T* __restrict__ fEz = a.fin + 2 * cs;
+  const T* __restrict__ fHx = a.fin + 3 * cs;
+  const T* __restrict__ fHy = a.fin + 4 * cs;
+  const T* __restrict__ fHz = a.fin + 5 * cs;
 
   bool xin[V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) xin[e] = (x0 + e) < nx;
+  for (int e = 0; e < V; ++e) xin[e] = (xl + e) < nx;
 
-  // x-slab membership per element
   const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
-  bool inx[V];
-  int sx[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) {
-    const int i = x0 + e;
-    inx[e] = xin[e] && (i < Lx || i >= nx - Lx);
-    sx[e] = i < Lx ? i : i - nx + 2 * Lx;
-  }
   const bool iny = row_ok && (j < Ly || j >= ny - Ly);
   const int sy = j < Ly ? j : j - ny + 2 * Ly;
-
+  // x-layer membership and the lane's constant x profiles (E and H side)
+  bool inx[V];
+  int sxv[V];
+  C bxe[V], axe[V], kxe[V], bxh[V], axh[V], kxh[V];
+  bool lane_inx = false;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const int i = xl + e;
+    inx[e] = row_ok && xin[e] && (i < Lx || i >= nx - Lx);
+    sxv[e] = i < Lx ? i : i - nx + 2 * Lx;
+    bxe[e] = C(1); axe[e] = C(0); kxe[e] = C(1); bxh[e] = C(1); axh[e] = C(0); kxh[e] = C(1);
+    if (inx[e]) {
+      bxe[e] = a.prof[(0 * 3 + 0) * a.plen + i];
+      axe[e] = a.prof[(0 * 3 + 1) * a.plen + i];
+      kxe[e] = a.prof[(0 * 3 + 2) * a.plen + i];
+      bxh[e] = a.prof[(9 + 0) * a.plen + i];
+      axh[e] = a.prof[(9 + 1) * a.plen + i];
+      kxh[e] = a.prof[(9 + 2) * a.plen + i];
+    }
+    lane_inx = lane_inx || inx[e];
+  }
+  // y profiles (uniform over the row)
+  C bye = 1, aye = 0, kye = 1, byh = 1, ayh = 0, kyh = 1;
+  if (iny) {
+    bye = a.prof[(3 + 0) * a.plen + j]; aye = a.prof[(3 + 1) * a.plen + j]; kye = a.prof[(3 + 2) * a.plen + j];
+    byh = a.prof[(12 + 0) * a.plen + j]; ayh = a.prof[(12 + 1) * a.plen + j]; kyh = a.prof[(12 + 2) * a.plen + j];
+  }
   int segx[V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) segx[e] = xin[e] ? a.segx[x0 + e] : 0;
-  const int segy = row_ok ? a.segy[j] * a.nsx : 0;
+  for (int e = 0; e < V; ++e) segx[e] = xin[e] ? a.seg[xl + e] : 0;
+  const int segy = a.seg[px + jc] * a.nsx;
 
-  const bool ld_ok = row_ok && lane_ok;
-  C ec[3][V];  // E^n(k)
+  // Software pipeline over the z-march: at plane k the registers hold E^n(k),
+  // E^n(k+1), H^{n-1/2}(k) (and, in the halo waves, Ez/Ex of the row above the
+  // tile at plane k).
+  C ec[3][V], en[3][V], hc[3][V], tz[V], tx[V];
+  const int jt = j0 + a.ty;  // row above the tile
+  const bool top_ok = halo && lane_ok && jt < ny;
+  const uint32_t rowoff_t = (uint32_t)min(jt, ny - 1) * (uint32_t)px + (uint32_t)xl;
   {
-    const size_t off = (size_t)kstart * plane + (size_t)max(j, 0) * px + x0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) load_row<T, C, V>(a.e_in[c] + off, ld_ok, ec[c], a.dec[c]);
+    const uint32_t off = (uint32_t)kstart * plane + rowoff;
+    const bool ok1 = ld_ok && (kstart + 1 < nz);
+    load_row<T, C, V>(fEx, off, ld_ok, ec[0], a.dec[0]);
+    load_row<T, C, V>(fEy, off, ld_ok, ec[1], a.dec[1]);
+    load_row<T, C, V>(fEz, off, ld_ok, ec[2], a.dec[2]);
+    load_row<T, C, V>(fEx, off + plane, ok1, en[0], a.dec[0]);
+    load_row<T, C, V>(fEy, off + plane, ok1, en[1], a.dec[1]);
+    load_row<T, C, V>(fEz, off + plane, ok1, en[2], a.dec[2]);
+    load_row<T, C, V>(fHx, off, ld_ok, hc[0], a.dec[3]);
+    load_row<T, C, V>(fHy, off, ld_ok && !halo, hc[1], a.dec[4]);
+    load_row<T, C, V>(fHz, off, ld_ok, hc[2], a.dec[5]);
+    const uint32_t offt = (uint32_t)kstart * plane + rowoff_t;
+    load_row<T, C, V>(fEz, offt, top_ok, tz, a.dec[2]);
+    load_row<T, C, V>(fEx, offt, top_ok, tx, a.dec[0]);
   }
   C hxp[V], hyp[V];  // H^{n+1/2}(k-1), own row
 #pragma unroll
   for (int e = 0; e < V; ++e) { hxp[e] = C(0); hyp[e] = C(0); }
+  int segz_cur = -1;
+  Coef2<C> cf[V];    // (Ca, Cb) of the row's cells in the current z block
+#pragma unroll
+  for (int e = 0; e < V; ++e) { cf[e].ca = C(0); cf[e].cb = C(0); }
+
+  C* rowE = ldsE + r * 3 * RL;        // own row in the E buffer
+  C* rowH = ldsH + r * 3 * RL;        // own row in the H buffer
+  const bool own = !halo && ld_ok;
 
   for (int k = kstart; k < k1; ++k) {
     const bool active = k >= k0;
-    const size_t off = (size_t)k * plane + (size_t)max(j, 0) * px + x0;
-    C en[3][V];  // E^n(k+1)
-    const bool nx_ok = ld_ok && (k + 1 < nz);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) load_row<T, C, V>(a.e_in[c] + off + plane, nx_ok, en[c], a.dec[c]);
-    C ho[3][V];  // H^{n-1/2}(k)
-    load_row<T, C, V>(a.h_in[0] + off, ld_ok, ho[0], a.dec[3]);
-    load_row<T, C, V>(a.h_in[1] + off, ld_ok && !halo, ho[1], a.dec[4]);
-    load_row<T, C, V>(a.h_in[2] + off, ld_ok, ho[2], a.dec[5]);
-
-    if (halo) {
-      // the row above the tile: Ez, Ex at plane k
-      const int jt = j0 + a.ty;
-      const bool ok = lane_ok && jt < ny;
-      const size_t offt = (size_t)k * plane + (size_t)min(jt, ny - 1) * px + x0;
-      C tz[V], tx[V];
-      load_row<T, C, V>(a.e_in[2] + offt, ok, tz, a.dec[2]);
-      load_row<T, C, V>(a.e_in[0] + offt, ok, tx, a.dec[0]);
-      C* r = ldsE + (a.ty + 1) * 2 * RW;
-#pragma unroll
-      for (int e = 0; e < V; ++e) { r[x0 + e] = tz[e]; r[RW + x0 + e] = tx[e]; }
-    }
-    {
-      C* r = ldsE + w * 2 * RW;
-#pragma unroll
-      for (int e = 0; e < V; ++e) { r[x0 + e] = ec[2][e]; r[RW + x0 + e] = ec[0][e]; }
-    }
-    __syncthreads();
-    C ezu[V], exu[V];  // Ez, Ex at row j+1
-    {
-      const C* r = ldsE + (w + 1) * 2 * RW;
-#pragma unroll
-      for (int e = 0; e < V; ++e) { ezu[e] = r[x0 + e]; exu[e] = r[RW + x0 + e]; }
-    }
-
-    // ---------------- H half step at plane k ----------------
-    const bool inz = (k < Lz || k >= nz - Lz);
-    const bool inz_r = inz && row_ok;
+    const bool more = k + 1 < k1;  // another plane follows in this chunk
+    const uint32_t off = (uint32_t)k * plane + rowoff;
+    const bool inz = row_ok && (k < Lz || k >= nz - Lz);
     const int sz = k < Lz ? k : k - nz + 2 * Lz;
-    const bool upd_psi = active && !halo && row_ok;
-    const C ez_r = shfl_down1(ec[2][0], lane);
-    const C ey_r = shfl_down1(ec[1][0], lane);
-    C hx[V], hy[V], hz[V];
-    {
-      // scalar CPML coefficients for the row (y) and plane (z), H side
-      C byh = 1, ayh = 0, kyh = 1, bzh = 1, azh = 0, kzh = 1;
-      if (iny) { byh = a.pb[1][1][j]; ayh = a.pa[1][1][j]; kyh = a.pk[1][1][j]; }
-      if (inz) { bzh = a.pb[1][2][k]; azh = a.pa[1][2][k]; kzh = a.pk[1][2][k]; }
+    const bool upd = active && own;
+
+    // ---- 1. small loads of this plane (issued before the prefetches) ----
+    C pHxy[V], pHzy[V], pHxz[V], pHyz[V], pHyx[V], pHzx[V];
+    C pExy[V], pEzy[V], pExz[V], pEyz[V], pEyx[V], pEzx[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      pHxy[e] = pHzy[e] = pHxz[e] = pHyz[e] = pHyx[e] = pHzx[e] = C(0);
+      pExy[e] = pEzy[e] = pExz[e] = pEyz[e] = pEyx[e] = pEzx[e] = C(0);
+    }
+    const uint32_t qy = ((uint32_t)k * (2 * Ly) + sy) * px + xl;
+    const uint32_t qz = ((uint32_t)sz * ny + jc) * px + xl;
+    const uint32_t qx = ((uint32_t)k * ny + jc) * (2 * Lx);
+    if (iny) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const int i = x0 + e;
-        const C ezn = (e < V - 1) ? ec[2][e + 1] : ez_r;
-        const C eyn = (e < V - 1) ? ec[1][e + 1] : ey_r;
+        if (!xin[e]) continue;
+        pHxy[e] = a.psh_in[a.psoff[PHXY] + qy + e];
+        pHzy[e] = a.psh_in[a.psoff[PHZY] + qy + e];
+        if (upd) { pExy[e] = a.pse[a.psoff[PEXY] + qy + e]; pEzy[e] = a.pse[a.psoff[PEZY] + qy + e]; }
+      }
+    }
+    if (inz) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!xin[e]) continue;
+        pHxz[e] = a.psh_in[a.psoff[PHXZ] + qz + e];
+        pHyz[e] = a.psh_in[a.psoff[PHYZ] + qz + e];
+        if (upd) { pExz[e] = a.pse[a.psoff[PEXZ] + qz + e]; pEyz[e] = a.pse[a.psoff[PEYZ] + qz + e]; }
+      }
+    }
+    if (lane_inx) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!inx[e]) continue;
+        pHyx[e] = a.psh_in[a.psoff[PHYX] + qx + sxv[e]];
+        pHzx[e] = a.psh_in[a.psoff[PHZX] + qx + sxv[e]];
+        if (upd) { pEyx[e] = a.pse[a.psoff[PEYX] + qx + sxv[e]]; pEzx[e] = a.pse[a.psoff[PEZX] + qx + sxv[e]]; }
+      }
+    }
+    C bze = 1, aze = 0, kze = 1, bzh = 1, azh = 0, kzh = 1;
+    if (inz) {
+      bze = a.prof[(6 + 0) * a.plen + k]; aze = a.prof[(6 + 1) * a.plen + k]; kze = a.prof[(6 + 2) * a.plen + k];
+      bzh = a.prof[(15 + 0) * a.plen + k]; azh = a.prof[(15 + 1) * a.plen + k]; kzh = a.prof[(15 + 2) * a.plen + k];
+    }
+    const int sz_blk = a.seg[px + ny + k];
+    if (sz_blk != segz_cur) {
+      segz_cur = sz_blk;
+      const int segyz = segy + sz_blk * a.nsxy;
+#pragma unroll
+      for (int e = 0; e < V; ++e) cf[e] = a.coef[segx[e] + segyz];
+    }
+    const int pl = a.pec_plane[k];
+    uint8_t pmask[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) pmask[e] = 0;
+    if (pl >= 0 && own) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) pmask[e] = a.pec_mask[((uint32_t)pl * ny + jc) * px + xl + e];
+    }
+    const uint8_t flags = a.rowflag[(uint32_t)k * ny + jc];
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the next row above ----
+    C en2[3][V], hn[3][V], tzn[V], txn[V];
+    {
+      const bool ok2 = ld_ok && more && (k + 2 < nz);
+      const bool okh = ld_ok && more;
+      load_row<T, C, V>(fEx, off + 2 * plane, ok2, en2[0], a.dec[0]);
+      load_row<T, C, V>(fEy, off + 2 * plane, ok2, en2[1], a.dec[1]);
+      load_row<T, C, V>(fEz, off + 2 * plane, ok2, en2[2], a.dec[2]);
+      load_row<T, C, V>(fHx, off + plane, okh, hn[0], a.dec[3]);
+      load_row<T, C, V>(fHy, off + plane, okh && !halo, hn[1], a.dec[4]);
+      load_row<T, C, V>(fHz, off + plane, okh, hn[2], a.dec[5]);
+      const uint32_t offt = (uint32_t)(k + 1) * plane + rowoff_t;
+      load_row<T, C, V>(fEz, offt, top_ok && more, tzn, a.dec[2]);
+      load_row<T, C, V>(fEx, offt, top_ok && more, txn, a.dec[0]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 3. publish E^n(k) ----
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      rowE[xl + e] = ec[0][e];
+      rowE[RL + xl + e] = ec[1][e];
+      rowE[2 * RL + xl + e] = ec[2][e];
+    }
+    if (halo) {
+      C* rt = ldsE + (a.ty + 1) * 3 * RL;
+#pragma unroll
+      for (int e = 0; e < V; ++e) { rt[xl + e] = tx[e]; rt[2 * RL + xl + e] = tz[e]; }
+    }
+    __syncthreads();
+
+    // ---- 4. H half step at plane k ----
+    C hx[V], hy[V], hz[V];
+    {
+      const C* up = rowE + 3 * RL;   // row j+1
+      C ezu[V], exu[V], ezr[V], eyr[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        exu[e] = up[xl + e];
+        ezu[e] = up[2 * RL + xl + e];
+      }
+#pragma unroll
+      for (int e = 0; e < V - 1; ++e) { eyr[e] = ec[1][e + 1]; ezr[e] = ec[2][e + 1]; }
+      {
+        const int ir = xl + V;  // x+1 neighbour of the last sample (0 beyond the grid)
+        const bool okr = ir < nx;
+        eyr[V - 1] = okr ? rowE[RL + min(ir, RL - 1)] : C(0);
+        ezr[V - 1] = okr ? rowE[2 * RL + min(ir, RL - 1)] : C(0);
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
         C dEz_dy = (ezu[e] - ec[2][e]) * idy;
         C dEy_dz = (en[1][e] - ec[1][e]) * idz;
         C dEx_dz = (en[0][e] - ec[0][e]) * idz;
-        C dEz_dx = (ezn - ec[2][e]) * idx_;
-        C dEy_dx = (eyn - ec[1][e]) * idx_;
+        C dEz_dx = (ezr[e] - ec[2][e]) * idx_;
+        C dEy_dx = (eyr[e] - ec[1][e]) * idx_;
         C dEx_dy = (exu[e] - ec[0][e]) * idy;
-        if (iny && xin[e]) {
-          const size_t q = ((size_t)k * (2 * Ly) + sy) * px + i;
-          C p1 = byh * a.psi_h_in[PHXY][q] + ayh * dEz_dy;
-          C p2 = byh * a.psi_h_in[PHZY][q] + ayh * dEx_dy;
-          if (upd_psi) { a.psi_h_out[PHXY][q] = p1; a.psi_h_out[PHZY][q] = p2; }
-          dEz_dy = kyh * dEz_dy + p1;
-          dEx_dy = kyh * dEx_dy + p2;
+        if (iny) {
+          pHxy[e] = byh * pHxy[e] + ayh * dEz_dy;
+          pHzy[e] = byh * pHzy[e] + ayh * dEx_dy;
+          dEz_dy = kyh * dEz_dy + pHxy[e];
+          dEx_dy = kyh * dEx_dy + pHzy[e];
         }
-        if (inz_r && xin[e]) {
-          const size_t q = ((size_t)sz * ny + j) * px + i;
-          C p1 = bzh * a.psi_h_in[PHXZ][q] + azh * dEy_dz;
-          C p2 = bzh * a.psi_h_in[PHYZ][q] + azh * dEx_dz;
-          if (upd_psi) { a.psi_h_out[PHXZ][q] = p1; a.psi_h_out[PHYZ][q] = p2; }
-          dEy_dz = kzh * dEy_dz + p1;
-          dEx_dz = kzh * dEx_dz + p2;
+        if (inz) {
+          pHxz[e] = bzh * pHxz[e] + azh * dEy_dz;
+          pHyz[e] = bzh * pHyz[e] + azh * dEx_dz;
+          dEy_dz = kzh * dEy_dz + pHxz[e];
+          dEx_dz = kzh * dEx_dz + pHyz[e];
         }
-        if (inx[e] && row_ok) {
-          const size_t q = ((size_t)k * ny + j) * (2 * Lx) + sx[e];
-          const C bxh = a.pb[1][0][i], axh = a.pa[1][0][i], kxh = a.pk[1][0][i];
-          C p1 = bxh * a.psi_h_in[PHYX][q] + axh * dEz_dx;
-          C p2 = bxh * a.psi_h_in[PHZX][q] + axh * dEy_dx;
-          if (upd_psi) { a.psi_h_out[PHYX][q] = p1; a.psi_h_out[PHZX][q] = p2; }
-          dEz_dx = kxh * dEz_dx + p1;
-          dEy_dx = kxh * dEy_dx + p2;
+        if (inx[e]) {
+          pHyx[e] = bxh[e] * pHyx[e] + axh[e] * dEz_dx;
+          pHzx[e] = bxh[e] * pHzx[e] + axh[e] * dEy_dx;
+          dEz_dx = kxh[e] * dEz_dx + pHyx[e];
+          dEy_dx = kxh[e] * dEy_dx + pHzx[e];
         }
         const bool ok = row_ok && xin[e];
-        hx[e] = ok ? to_storage<T, C>(ho[0][e] - a.dt_mu * (dEz_dy - dEy_dz), a.enc[3], a.dec[3]) : C(0);
-        hy[e] = ok ? to_storage<T, C>(ho[1][e] - a.dt_mu * (dEx_dz - dEz_dx), a.enc[4], a.dec[4]) : C(0);
-        hz[e] = ok ? to_storage<T, C>(ho[2][e] - a.dt_mu * (dEy_dx - dEx_dy), a.enc[5], a.dec[5]) : C(0);
+        hx[e] = ok ? to_storage<T, C>(hc[0][e] - a.dt_mu * (dEz_dy - dEy_dz), a.enc[3], a.dec[3]) : C(0);
+        hy[e] = ok ? to_storage<T, C>(hc[1][e] - a.dt_mu * (dEx_dz - dEz_dx), a.enc[4], a.dec[4]) : C(0);
+        hz[e] = ok ? to_storage<T, C>(hc[2][e] - a.dt_mu * (dEy_dx - dEx_dy), a.enc[5], a.dec[5]) : C(0);
       }
     }
-    {
-      C* r = ldsH + w * 2 * RW;
+
+    // ---- 5. publish H^{n+1/2}(k) ----
 #pragma unroll
-      for (int e = 0; e < V; ++e) { r[x0 + e] = hz[e]; r[RW + x0 + e] = hx[e]; }
+    for (int e = 0; e < V; ++e) {
+      rowH[xl + e] = hx[e];
+      rowH[RL + xl + e] = hy[e];
+      rowH[2 * RL + xl + e] = hz[e];
     }
     __syncthreads();
 
-    // ---------------- E half step at plane k (own rows) ----------------
-    if (!halo && active && row_ok && lane_ok) {
-      C hzd[V], hxd[V];  // Hz, Hx at row j-1
-      {
-        const C* r = ldsH + (w - 1) * 2 * RW;
+    // ---- 6. E half step at plane k (own rows) and stores ----
+    if (upd) {
+      // H-side psi of the own row
+      if (iny) {
 #pragma unroll
-        for (int e = 0; e < V; ++e) { hzd[e] = r[x0 + e]; hxd[e] = r[RW + x0 + e]; }
+        for (int e = 0; e < V; ++e)
+          if (xin[e]) { a.psh_out[a.psoff[PHXY] + qy + e] = pHxy[e]; a.psh_out[a.psoff[PHZY] + qy + e] = pHzy[e]; }
       }
-      const C hy_l = shfl_up1(hy[V - 1], lane);
-      const C hz_l = shfl_up1(hz[V - 1], lane);
-      C bye = 1, aye = 0, kye = 1, bze = 1, aze = 0, kze = 1;
-      if (iny) { bye = a.pb[0][1][j]; aye = a.pa[0][1][j]; kye = a.pk[0][1][j]; }
-      if (inz) { bze = a.pb[0][2][k]; aze = a.pa[0][2][k]; kze = a.pk[0][2][k]; }
-      const int segyz = segy + a.segz[k] * a.nsxy;
-      const int pl = a.pec_plane[k];
+      if (inz) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (xin[e]) { a.psh_out[a.psoff[PHXZ] + qz + e] = pHxz[e]; a.psh_out[a.psoff[PHYZ] + qz + e] = pHyz[e]; }
+      }
+      if (lane_inx) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (inx[e]) {
+            a.psh_out[a.psoff[PHYX] + qx + sxv[e]] = pHyx[e];
+            a.psh_out[a.psoff[PHZX] + qx + sxv[e]] = pHzx[e];
+          }
+      }
+      const C* dn = rowH - 3 * RL;   // row j-1
+      C hxd[V], hzd[V], hyl[V], hzl[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        hxd[e] = dn[xl + e];
+        hzd[e] = dn[2 * RL + xl + e];
+      }
+#pragma unroll
+      for (int e = 1; e < V; ++e) { hyl[e] = hy[e - 1]; hzl[e] = hz[e - 1]; }
+      {
+        const int il = max(xl - 1, 0);   // x-1 neighbour of the first sample (unused at i = 0)
+        hyl[0] = rowH[RL + il];
+        hzl[0] = rowH[2 * RL + il];
+      }
       C exo[V], eyo[V], ezo[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const int i = x0 + e;
-        const C hyl = (e > 0) ? hy[e - 1] : hy_l;
-        const C hzl = (e > 0) ? hz[e - 1] : hz_l;
+        const int i = xl + e;
         C dHz_dy = (hz[e] - hzd[e]) * idy;
         C dHy_dz = (hy[e] - hyp[e]) * idz;
         C dHx_dz = (hx[e] - hxp[e]) * idz;
-        C dHz_dx = (hz[e] - hzl) * idx_;
-        C dHy_dx = (hy[e] - hyl) * idx_;
+        C dHz_dx = (hz[e] - hzl[e]) * idx_;
+        C dHy_dx = (hy[e] - hyl[e]) * idx_;
         C dHx_dy = (hx[e] - hxd[e]) * idy;
-        // wall samples (tangential E on the outer faces) are never updated
+        // tangential E on the outer faces is never updated
         const bool ux = (j > 0) && (k > 0) && xin[e];
         const bool uy = (i > 0) && (k > 0) && xin[e];
         const bool uz = (i > 0) && (j > 0) && xin[e];
-        if (iny && xin[e]) {
-          const size_t q = ((size_t)k * (2 * Ly) + sy) * px + i;
-          if (ux) { C p = bye * a.psi_e[PEXY][q] + aye * dHz_dy; a.psi_e[PEXY][q] = p; dHz_dy = kye * dHz_dy + p; }
-          if (uz) { C p = bye * a.psi_e[PEZY][q] + aye * dHx_dy; a.psi_e[PEZY][q] = p; dHx_dy = kye * dHx_dy + p; }
+        if (iny) {
+          pExy[e] = bye * pExy[e] + aye * dHz_dy;
+          pEzy[e] = bye * pEzy[e] + aye * dHx_dy;
+          dHz_dy = kye * dHz_dy + pExy[e];
+          dHx_dy = kye * dHx_dy + pEzy[e];
         }
-        if (inz && xin[e]) {
-          const size_t q = ((size_t)sz * ny + j) * px + i;
-          if (ux) { C p = bze * a.psi_e[PEXZ][q] + aze * dHy_dz; a.psi_e[PEXZ][q] = p; dHy_dz = kze * dHy_dz + p; }
-          if (uy) { C p = bze * a.psi_e[PEYZ][q] + aze * dHx_dz; a.psi_e[PEYZ][q] = p; dHx_dz = kze * dHx_dz + p; }
+        if (inz) {
+          pExz[e] = bze * pExz[e] + aze * dHy_dz;
+          pEyz[e] = bze * pEyz[e] + aze * dHx_dz;
+          dHy_dz = kze * dHy_dz + pExz[e];
+          dHx_dz = kze * dHx_dz + pEyz[e];
         }
         if (inx[e]) {
-          const size_t q = ((size_t)k * ny + j) * (2 * Lx) + sx[e];
-          const C bxe = a.pb[0][0][i], axe = a.pa[0][0][i], kxe = a.pk[0][0][i];
-          if (uy) { C p = bxe * a.psi_e[PEYX][q] + axe * dHz_dx; a.psi_e[PEYX][q] = p; dHz_dx = kxe * dHz_dx + p; }
-          if (uz) { C p = bxe * a.psi_e[PEZX][q] + axe * dHy_dx; a.psi_e[PEZX][q] = p; dHy_dx = kxe * dHy_dx + p; }
+          pEyx[e] = bxe[e] * pEyx[e] + axe[e] * dHz_dx;
+          pEzx[e] = bxe[e] * pEzx[e] + axe[e] * dHy_dx;
+          dHz_dx = kxe[e] * dHz_dx + pEyx[e];
+          dHy_dx = kxe[e] * dHy_dx + pEzx[e];
         }
-        const Coef2<C> cc = a.coef[segx[e] + segyz];
-        C ca = cc.ca, cb = cc.cb;
-        C cax = ca, cbx = cb, cay = ca, cby = cb, caz = ca, cbz = cb;
-        if (pl >= 0) {
-          const uint8_t m = a.pec_mask[((size_t)pl * ny + j) * px + min(i, px - 1)];
-          if (m & 1) { cax = C(0); cbx = C(0); }
-          if (m & 2) { cay = C(0); cby = C(0); }
-          if (m & 4) { caz = C(0); cbz = C(0); }
-        }
+        const C ca = cf[e].ca, cb = cf[e].cb;
+        const C cax = (pmask[e] & 1) ? C(0) : ca, cbx = (pmask[e] & 1) ? C(0) : cb;
+        const C cay = (pmask[e] & 2) ? C(0) : ca, cby = (pmask[e] & 2) ? C(0) : cb;
+        const C caz = (pmask[e] & 4) ? C(0) : ca, cbz = (pmask[e] & 4) ? C(0) : cb;
         exo[e] = ux ? cax * ec[0][e] + cbx * (dHz_dy - dHy_dz) : ec[0][e];
         eyo[e] = uy ? cay * ec[1][e] + cby * (dHx_dz - dHz_dx) : ec[1][e];
         ezo[e] = uz ? caz * ec[2][e] + cbz * (dHy_dx - dHx_dy) : ec[2][e];
+        // E-side psi of the updated samples (wall samples keep 0)
+        if (!ux) { pExy[e] = C(0); pExz[e] = C(0); }
+        if (!uy) { pEyz[e] = C(0); pEyx[e] = C(0); }
+        if (!uz) { pEzx[e] = C(0); pEzy[e] = C(0); }
       }
-      if (a.rowflag[(size_t)k * ny + j] & 1) {
-        const double tn = (double)(a.n + 1) * a.dt;
+      if (iny) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (xin[e]) { a.pse[a.psoff[PEXY] + qy + e] = pExy[e]; a.pse[a.psoff[PEZY] + qy + e] = pEzy[e]; }
+      }
+      if (inz) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (xin[e]) { a.pse[a.psoff[PEXZ] + qz + e] = pExz[e]; a.pse[a.psoff[PEYZ] + qz + e] = pEyz[e]; }
+      }
+      if (lane_inx) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (inx[e]) { a.pse[a.psoff[PEYX] + qx + sxv[e]] = pEyx[e]; a.pse[a.psoff[PEZX] + qx + sxv[e]] = pEzx[e]; }
+      }
+      if (flags & 1) {
         for (int s = 0; s < a.nsrc; ++s) {
-          const SrcDev sd = a.src[s];
-          if (sd.j == j && sd.k == k && sd.i >= x0 && sd.i < x0 + V) {
-            const C add = static_cast<C>(sd.amp * waveform(sd, tn));
+          const SrcDev sp = a.src[s];
+          if (sp.j == j && sp.k == k) {
+            const C v = ldsS[s];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              if (x0 + e == sd.i) {
-                if (sd.comp == 0) exo[e] += add;
-                else if (sd.comp == 1) eyo[e] += add;
-                else ezo[e] += add;
+              if (xl + e == sp.i) {
+                if (sp.comp == 0) exo[e] += v;
+                else if (sp.comp == 1) eyo[e] += v;
+                else ezo[e] += v;
               }
             }
           }
@@ -397,23 +557,22 @@ step_kernel(const StepArgs<T, C> a) {
         eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1]);
         ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
       }
-      store_row<T, C, V>(a.e_out[0] + off, exo, a.enc[0]);
-      store_row<T, C, V>(a.e_out[1] + off, eyo, a.enc[1]);
-      store_row<T, C, V>(a.e_out[2] + off, ezo, a.enc[2]);
-      store_row<T, C, V>(a.h_out[0] + off, hx, a.enc[3]);
-      store_row<T, C, V>(a.h_out[1] + off, hy, a.enc[4]);
-      store_row<T, C, V>(a.h_out[2] + off, hz, a.enc[5]);
-      if (a.rowflag[(size_t)k * ny + j] & 2) {
-        const int slot = (int)(a.n % a.series_len);
+      store_row<T, C, V>(a.fout, off, exo, a.enc[0]);
+      store_row<T, C, V>(a.fout + cs, off, eyo, a.enc[1]);
+      store_row<T, C, V>(a.fout + 2 * cs, off, ezo, a.enc[2]);
+      store_row<T, C, V>(a.fout + 3 * cs, off, hx, a.enc[3]);
+      store_row<T, C, V>(a.fout + 4 * cs, off, hy, a.enc[4]);
+      store_row<T, C, V>(a.fout + 5 * cs, off, hz, a.enc[5]);
+      if (flags & 2) {
         for (int p = 0; p < a.nprobe; ++p) {
           const int4 pr = a.probe[p];
-          if (pr.z == j && pr.w == k && pr.y >= x0 && pr.y < x0 + V) {
+          if (pr.z == j && pr.w == k) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              if (x0 + e == pr.y) {
-                C v = pr.x == 0 ? exo[e] : pr.x == 1 ? eyo[e] : pr.x == 2 ? ezo[e]
-                    : pr.x == 3 ? hx[e] : pr.x == 4 ? hy[e] : hz[e];
-                a.series[(size_t)slot * a.nprobe + p] = static_cast<double>(v);
+              if (xl + e == pr.y) {
+                const C v = pr.x == 0 ? exo[e] : pr.x == 1 ? eyo[e] : pr.x == 2 ? ezo[e]
+                          : pr.x == 3 ? hx[e] : pr.x == 4 ? hy[e] : hz[e];
+                a.series[(size_t)a.series_slot * a.nprobe + p] = static_cast<double>(v);
               }
             }
           }
@@ -424,8 +583,10 @@ step_kernel(const StepArgs<T, C> a) {
     for (int e = 0; e < V; ++e) {
       hxp[e] = hx[e];
       hyp[e] = hy[e];
+      tz[e] = tzn[e];
+      tx[e] = txn[e];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ec[c][e] = en[c][e];
+      for (int c = 0; c < 3; ++c) { ec[c][e] = en[c][e]; en[c][e] = en2[c][e]; hc[c][e] = hn[c][e]; }
     }
   }
 }

@@ -50,6 +50,10 @@ yee_status fail(yee_status st, const char* fmt, ...) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+#ifndef YEE_COMP_SKEW_BYTES
+#define YEE_COMP_SKEW_BYTES 0
+#endif
+
 struct Region {
   size_t off = 0, bytes = 0;
 };
@@ -63,7 +67,7 @@ struct yee_ctx {
   int px = 0;       // x pitch in elements
   size_t tsize = 0; // storage element size
   size_t csize = 0; // compute element size
-  int ty = 0, kz = 0;
+  int ty = 0, kz = 0, vpl = 0;  // launch shape (0 = automatic)
   size_t lds_limit = 65536;  // per-workgroup LDS, queried at bind time
 
   // host-side configuration
@@ -80,10 +84,11 @@ struct yee_ctx {
   bool bound = false;
   unsigned char* ws = nullptr;
   int64_t ws_bytes = 0;
-  Region fields[2], psi_e, psi_h[2], series, dft, segxr, segyr, segzr, coef, prof, pecplane,
-      pecmask, rowflag, srcr, prober, freqr;
+  Region fields[2], psi_e, psi_h[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
+      srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
+  uint32_t psi_off[6] = {};  // element offsets of the psi arrays inside a region
   size_t prof_len = 0;     // elements of one profile array (max axis length)
   int64_t n = 0;           // steps taken
   int64_t folded = 0;      // steps folded into the DFT
@@ -91,12 +96,10 @@ struct yee_ctx {
 
 namespace {
 
-int choose_v(const yee_grid_desc& d) {
-  const int vmax = d.precision == YEE_F64 ? 4 : 8;
-  for (int v = 1; v <= vmax; v *= 2)
-    if (d.nx <= yee::kWave * v) return v;
-  return 0;
-}
+constexpr int kMaxRow = 512;  // x samples per row a workgroup can cover
+
+// Waves covering one row of nx samples at V samples per lane.
+int waves_per_row(int nx, int V) { return (nx + yee::kWave * V - 1) / (yee::kWave * V); }
 
 size_t storage_size(int prec) { return prec == YEE_F64 ? 8 : prec == YEE_F32 ? 4 : 2; }
 size_t compute_size(int prec) { return prec == YEE_F64 ? 8 : 4; }
@@ -118,20 +121,24 @@ void layout(yee_ctx* c) {
     r.bytes = bytes;
     off += align256(std::max<size_t>(bytes, 1));
   };
-  c->comp_bytes = align256((size_t)d.nz * d.ny * c->px * c->tsize);
+  // component arrays are skewed by an odd number of 256-byte units so that the
+  // same (i, j, k) of the twelve streams does not land on one HBM channel
+  c->comp_bytes = align256((size_t)d.nz * d.ny * c->px * c->tsize) + YEE_COMP_SKEW_BYTES;
   for (int s = 0; s < 2; ++s) take(c->fields[s], 6 * c->comp_bytes);
   psi_lengths(c, c->psi_len);
-  size_t psib = 0;
-  for (int q = 0; q < 6; ++q) psib += align256(c->psi_len[q] * c->csize);
+  size_t psin = 0;
+  for (int q = 0; q < 6; ++q) {
+    c->psi_off[q] = (uint32_t)psin;
+    psin += c->psi_len[q];
+  }
+  const size_t psib = psin * c->csize;
   take(c->psi_e, psib);
   take(c->psi_h[0], psib);
   take(c->psi_h[1], psib);
   const size_t np = c->probes.size(), nf = c->freqs.size();
   take(c->series, (size_t)d.series_len * np * sizeof(double));
   take(c->dft, np * nf * 2 * sizeof(double));
-  take(c->segxr, (size_t)c->px * 4);
-  take(c->segyr, (size_t)d.ny * 4);
-  take(c->segzr, (size_t)d.nz * 4);
+  take(c->segr, ((size_t)c->px + d.ny + d.nz) * 4);
   take(c->coef, (size_t)c->nsx * c->nsy * c->nsz * 2 * c->csize);
   c->prof_len = std::max({d.nx, d.ny, d.nz}) + 1;
   take(c->prof, 2 * 3 * 3 * c->prof_len * c->csize);
@@ -194,18 +201,18 @@ yee_status upload_materials_impl(yee_ctx* c, hipStream_t s) {
   if (c->csize == 8) put<double>(buf, 0, cab); else put<float>(buf, 0, cab);
   yee_status st = upload(c, c->coef, buf.data(), buf.size(), s);
   if (st) return st;
-  std::vector<int32_t> sx(c->px, 0);
-  std::copy(c->segx.begin(), c->segx.end(), sx.begin());
-  if ((st = upload(c, c->segxr, sx.data(), sx.size() * 4, s))) return st;
-  if ((st = upload(c, c->segyr, c->segy.data(), c->segy.size() * 4, s))) return st;
-  if ((st = upload(c, c->segzr, c->segz.data(), c->segz.size() * 4, s))) return st;
+  std::vector<int32_t> seg((size_t)c->px + c->d.ny + c->d.nz, 0);
+  std::copy(c->segx.begin(), c->segx.end(), seg.begin());
+  std::copy(c->segy.begin(), c->segy.end(), seg.begin() + c->px);
+  std::copy(c->segz.begin(), c->segz.end(), seg.begin() + c->px + c->d.ny);
+  if ((st = upload(c, c->segr, seg.data(), seg.size() * 4, s))) return st;
   // pageable source buffers: make sure the copies are done before they go away
   HIP_TRY(hipStreamSynchronize(s));
   return YEE_OK;
 }
 
-size_t step_lds_bytes(const yee_ctx* c, int ty) {
-  return (size_t)((ty + 2) + (ty + 1)) * 2 * yee::kWave * c->V * c->csize;
+size_t step_lds_bytes(const yee_ctx* c, int ty, int V) {
+  return yee::step_lds_elems(ty, waves_per_row(c->d.nx, V), V) * c->csize;
 }
 
 template <class T, class C, int V>
@@ -214,50 +221,36 @@ yee_status launch_step(yee_ctx* c, hipStream_t s) {
   const auto& d = c->d;
   StepArgs<T, C> a{};
   const int cur = (int)(c->n & 1), nxt = cur ^ 1;
-  for (int q = 0; q < 3; ++q) {
-    a.e_in[q] = reinterpret_cast<const T*>(c->ws + c->fields[cur].off + q * c->comp_bytes);
-    a.h_in[q] = reinterpret_cast<const T*>(c->ws + c->fields[cur].off + (3 + q) * c->comp_bytes);
-    a.e_out[q] = reinterpret_cast<T*>(c->ws + c->fields[nxt].off + q * c->comp_bytes);
-    a.h_out[q] = reinterpret_cast<T*>(c->ws + c->fields[nxt].off + (3 + q) * c->comp_bytes);
-  }
-  size_t po = 0;
-  for (int q = 0; q < 6; ++q) {
-    a.psi_e[q] = reinterpret_cast<C*>(c->ws + c->psi_e.off + po);
-    a.psi_h_in[q] = reinterpret_cast<const C*>(c->ws + c->psi_h[cur].off + po);
-    a.psi_h_out[q] = reinterpret_cast<C*>(c->ws + c->psi_h[nxt].off + po);
-    po += align256(c->psi_len[q] * sizeof(C));
-  }
-  const C* prof = reinterpret_cast<const C*>(c->ws + c->prof.off);
-  for (int side = 0; side < 2; ++side)
-    for (int ax = 0; ax < 3; ++ax) {
-      const size_t base = ((size_t)(side * 3 + ax) * 3) * c->prof_len;
-      a.pb[side][ax] = prof + base;
-      a.pa[side][ax] = prof + base + c->prof_len;
-      a.pk[side][ax] = prof + base + 2 * c->prof_len;
-    }
-  a.segx = reinterpret_cast<const int32_t*>(c->ws + c->segxr.off);
-  a.segy = reinterpret_cast<const int32_t*>(c->ws + c->segyr.off);
-  a.segz = reinterpret_cast<const int32_t*>(c->ws + c->segzr.off);
+  a.fin = reinterpret_cast<const T*>(c->ws + c->fields[cur].off);
+  a.fout = reinterpret_cast<T*>(c->ws + c->fields[nxt].off);
+  a.cstride = c->comp_bytes / sizeof(T);
+  a.pse = reinterpret_cast<C*>(c->ws + c->psi_e.off);
+  a.psh_in = reinterpret_cast<const C*>(c->ws + c->psi_h[cur].off);
+  a.psh_out = reinterpret_cast<C*>(c->ws + c->psi_h[nxt].off);
+  for (int q = 0; q < 6; ++q) a.psoff[q] = c->psi_off[q];
+  a.prof = reinterpret_cast<const C*>(c->ws + c->prof.off);
+  a.plen = (int32_t)c->prof_len;
+  a.seg = reinterpret_cast<const int32_t*>(c->ws + c->segr.off);
   a.coef = reinterpret_cast<const Coef2<C>*>(c->ws + c->coef.off);
   a.nsx = c->nsx;
   a.nsxy = c->nsx * c->nsy;
   a.pec_plane = reinterpret_cast<const int32_t*>(c->ws + c->pecplane.off);
   a.pec_mask = reinterpret_cast<const uint8_t*>(c->ws + c->pecmask.off);
   a.rowflag = reinterpret_cast<const uint8_t*>(c->ws + c->rowflag.off);
+  a.probe = reinterpret_cast<const int4*>(c->ws + c->prober.off);
+  a.series = reinterpret_cast<double*>(c->ws + c->series.off);
+  a.nprobe = (int32_t)c->probes.size();
+  a.series_slot = (int32_t)(c->n % d.series_len);
   a.src = reinterpret_cast<const SrcDev*>(c->ws + c->srcr.off);
   a.nsrc = (int32_t)c->src.size();
-  a.probe = reinterpret_cast<const int4*>(c->ws + c->prober.off);
-  a.nprobe = (int32_t)c->probes.size();
-  a.series = reinterpret_cast<double*>(c->ws + c->series.off);
-  a.series_len = d.series_len;
+  a.n = c->n;
+  a.dt = c->dt;
   a.nx = d.nx; a.ny = d.ny; a.nz = d.nz; a.px = c->px;
   for (int q = 0; q < 3; ++q) a.L[q] = d.cpml_cells[q];
   a.inv_d[0] = static_cast<C>(1.0 / d.dx);
   a.inv_d[1] = static_cast<C>(1.0 / d.dy);
   a.inv_d[2] = static_cast<C>(1.0 / d.dz);
   a.dt_mu = static_cast<C>(c->dt / kMu0);
-  a.dt = c->dt;
-  a.n = c->n;
   for (int q = 0; q < 6; ++q) {
     const int e = d.precision == YEE_F16S ? d.fp16_exp[q] : 0;
     a.enc[q] = std::ldexp(1.0f, e);
@@ -269,9 +262,13 @@ yee_status launch_step(yee_ctx* c, hipStream_t s) {
   const int nchunks = (d.nz + c->kz - 1) / c->kz;
   a.ntiles = a.ny_tiles * nchunks;
   const int grid = ((a.ntiles + 7) / 8) * 8;
-  const size_t lds = step_lds_bytes(c, c->ty);
+  a.wpr = waves_per_row(d.nx, V);
+  const int waves = (c->ty + 1) * a.wpr;
+  if (waves > max_block_waves(V))
+    return fail(YEE_EINVAL, "tile of %d rows x %d waves per row exceeds %d waves", c->ty, a.wpr, max_block_waves(V));
+  const size_t lds = step_lds_bytes(c, c->ty, V);
   if (lds > c->lds_limit) return fail(YEE_EINVAL, "tile of %d rows needs %zu bytes of LDS (limit %zu)", c->ty, lds, c->lds_limit);
-  hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * (c->ty + 1)), lds, s, a);
+  hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
   HIP_TRY(hipGetLastError());
   return YEE_OK;
 }
@@ -281,20 +278,13 @@ yee_status launch_step_v(yee_ctx* c, hipStream_t s) {
   switch (c->V) {
     case 1: return launch_step<T, C, 1>(c, s);
     case 2: return launch_step<T, C, 2>(c, s);
-    case 4: return launch_step<T, C, 4>(c, s);
-    default: return launch_step<T, C, 8>(c, s);
+    default: return launch_step<T, C, 4>(c, s);
   }
 }
 
 yee_status launch_one_step(yee_ctx* c, hipStream_t s) {
   switch (c->d.precision) {
-    case YEE_F64: {
-      switch (c->V) {  // FP64 is limited to V <= 4
-        case 1: return launch_step<double, double, 1>(c, s);
-        case 2: return launch_step<double, double, 2>(c, s);
-        default: return launch_step<double, double, 4>(c, s);
-      }
-    }
+    case YEE_F64: return launch_step_v<double, double>(c, s);
     case YEE_F32: return launch_step_v<float, float>(c, s);
     default: return launch_step_v<_Float16, float>(c, s);
   }
@@ -319,9 +309,12 @@ yee_status fold_dft(yee_ctx* c, hipStream_t s) {
 
 void default_launch(yee_ctx* c) {
   const auto& d = c->d;
-  if (c->ty == 0) c->ty = std::min(7, d.ny);
+  // samples per lane: one while a row fits in four waves, else two
+  c->V = c->vpl ? c->vpl : (d.nx <= 4 * yee::kWave ? 1 : 2);
+  const int wpr = waves_per_row(d.nx, c->V);
+  if (c->ty == 0) c->ty = std::max(1, std::min({7, d.ny, yee::max_block_waves(c->V) / wpr - 1}));
   // keep the LDS rows within the device's per-workgroup limit
-  while (c->ty > 1 && step_lds_bytes(c, c->ty) > c->lds_limit) --c->ty;
+  while (c->ty > 1 && step_lds_bytes(c, c->ty, c->V) > c->lds_limit) --c->ty;
   if (c->kz == 0) {
     // enough workgroups to fill 256 CUs several times over, but keep the
     // per-chunk warm-up plane a small fraction of the march
@@ -373,16 +366,19 @@ yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out) {
   auto* c = new (std::nothrow) yee_ctx();
   if (!c) return fail(YEE_ENOMEM, "host allocation failed");
   c->d = d;
-  c->V = choose_v(d);
-  if (c->V == 0) {
+  if (d.nx > kMaxRow) {
     delete c;
-    return fail(YEE_EINVAL, "nx = %d exceeds the row limit (%d)", d.nx, d.precision == YEE_F64 ? 256 : 512);
+    return fail(YEE_EINVAL, "nx = %d exceeds the row limit (%d)", d.nx, kMaxRow);
   }
   c->tsize = storage_size(d.precision);
   c->csize = compute_size(d.precision);
-  const int line = 128 / (int)c->tsize;
-  const int q = std::max(c->V, line);
-  c->px = ((d.nx + q - 1) / q) * q;
+  // x pitch: a whole number of 128-byte lines (and of the widest lane vector)
+  const int line = std::max(128 / (int)c->tsize, 4);
+  c->px = ((d.nx + line - 1) / line) * line;
+  if ((uint64_t)d.nz * d.ny * c->px >= (1ull << 31)) {
+    delete c;
+    return fail(YEE_EINVAL, "grid too large for 32-bit element offsets");
+  }
   c->dt = d.courant / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz)));
   c->segx.assign(d.nx, 0);
   c->segy.assign(d.ny, 0);
@@ -454,6 +450,7 @@ yee_status yee_add_source(yee_ctx* c, const yee_source* s) {
     return fail(YEE_EINVAL, "source (%d,%d,%d) outside the grid", s->i, s->j, s->k);
   if (s->waveform != YEE_GAUSS_DERIV && s->waveform != YEE_MOD_GAUSS) return fail(YEE_EINVAL, "bad waveform");
   if (!(s->tau > 0)) return fail(YEE_EINVAL, "tau must be > 0");
+  if ((int)c->src.size() >= yee::kMaxSources) return fail(YEE_EINVAL, "at most %d sources", yee::kMaxSources);
   yee::SrcDev sd{};
   sd.comp = s->component; sd.i = s->i; sd.j = s->j; sd.k = s->k; sd.kind = s->waveform;
   sd.amp = s->amp; sd.t0 = s->t0; sd.tau = s->tau; sd.f0 = s->f0;
@@ -503,12 +500,20 @@ yee_status yee_bind_workspace(yee_ctx* c, void* dev, int64_t bytes) {
   return YEE_OK;
 }
 
-yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes) {
+yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane) {
   if (!c) return fail(YEE_EINVAL, "NULL context");
-  if (tile_rows < 0 || tile_rows > yee::kMaxTileRows || chunk_planes < 0)
-    return fail(YEE_EINVAL, "tile_rows must be in 0..%d, chunk_planes >= 0", yee::kMaxTileRows);
+  if (samples_per_lane != 0 && samples_per_lane != 1 && samples_per_lane != 2 && samples_per_lane != 4)
+    return fail(YEE_EINVAL, "samples_per_lane must be 0, 1, 2 or 4");
+  const int V = samples_per_lane ? samples_per_lane : (c->d.nx <= 4 * yee::kWave ? 1 : 2);
+  const int wpr = waves_per_row(c->d.nx, V);
+  if (wpr + 1 > 2 * yee::max_block_waves(V) || (wpr * 2 > yee::max_block_waves(V)))
+    return fail(YEE_EINVAL, "rows of %d samples need %d waves at %d samples per lane: too many", c->d.nx, wpr, V);
+  if (tile_rows < 0 || chunk_planes < 0 || (tile_rows > 0 && (tile_rows + 1) * wpr > yee::max_block_waves(V)))
+    return fail(YEE_EINVAL, "tile_rows %d with %d waves per row exceeds %d waves per workgroup", tile_rows, wpr,
+                yee::max_block_waves(V));
   c->ty = tile_rows;
   c->kz = chunk_planes;
+  c->vpl = samples_per_lane;
   if (c->bound) default_launch(c);
   return YEE_OK;
 }

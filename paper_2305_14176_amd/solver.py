@@ -27,7 +27,7 @@ class YeeSolver:
     """A configured, bound and reset context for one workload on one device."""
 
     def __init__(self, wl: Workload, device: str = "cuda:0", series_len: Optional[int] = None,
-                 tile_rows: int = 0, chunk_planes: int = 0, stream=None):
+                 tile_rows: int = 0, chunk_planes: int = 0, samples_per_lane: int = 0, stream=None):
         import torch
         self.torch = torch
         self.lib = _lib.load()
@@ -65,8 +65,8 @@ class YeeSolver:
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
         _lib.check(self.lib.yee_bind_workspace(ctx, C.c_void_p(aligned), self.footprint), "yee_bind_workspace")
-        if tile_rows or chunk_planes:
-            _lib.check(self.lib.yee_set_launch(ctx, tile_rows, chunk_planes), "yee_set_launch")
+        if tile_rows or chunk_planes or samples_per_lane:
+            _lib.check(self.lib.yee_set_launch(ctx, tile_rows, chunk_planes, samples_per_lane), "yee_set_launch")
         self.stream = stream
         self.reset()
 
@@ -121,6 +121,11 @@ class YeeSolver:
         ci = COMP_INDEX[comp] if isinstance(comp, str) else int(comp)
         a = np.ascontiguousarray(np.transpose(np.asarray(arr, np.float64), (2, 1, 0)))
         _lib.check(self.lib.yee_set_field(self.ctx, ci, _ptr(a, C.c_double), self._s()), "yee_set_field")
+
+    def set_launch(self, tile_rows: int = 0, chunk_planes: int = 0, samples_per_lane: int = 0):
+        """Launch shape of the fused step kernel (0 = automatic)."""
+        _lib.check(self.lib.yee_set_launch(self.ctx, int(tile_rows), int(chunk_planes), int(samples_per_lane)),
+                   "yee_set_launch")
 
     def step(self, n: int):
         _lib.check(self.lib.yee_step(self.ctx, int(n), self._s()), "yee_step")

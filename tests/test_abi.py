@@ -53,7 +53,7 @@ def _desc(**kw):
     ({"courant": 0.0}, False),
     ({"n": (1, 16, 16)}, False),
     ({"n": (513, 16, 16)}, False),
-    ({"n": (300, 16, 16), "precision": 0}, False),      # FP64 rows limited to 256
+    ({"n": (300, 16, 16), "precision": 0}, True),
     ({"n": (512, 16, 16)}, True),
     ({"cpml": (9, 0, 0)}, False),                      # 2 L > n
     ({"cpml": (8, 8, 8)}, True),

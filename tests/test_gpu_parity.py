@@ -100,18 +100,20 @@ def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
     _check_fields(s, sim, TOL["f64"])
 
 
-@pytest.mark.parametrize("shape,ty,kz", [
-    ((256, 40, 33), 0, 0),
-    ((256, 40, 33), 3, 5),
-    ((300, 17, 26), 7, 4),     # V = 8
-    ((160, 48, 48), 5, 16),
-    ((512, 9, 12), 1, 1),      # widest rows, one row per tile, one plane per chunk
+@pytest.mark.parametrize("shape,ty,kz,vpl", [
+    ((256, 40, 33), 0, 0, 0),
+    ((256, 40, 33), 3, 5, 0),
+    ((256, 21, 19), 7, 3, 4),   # four samples per lane, one wave per row
+    ((300, 17, 26), 4, 4, 0),   # two samples per lane, ragged row
+    ((160, 48, 48), 4, 16, 0),
+    ((512, 9, 12), 1, 1, 0),    # widest rows, one row per tile, one plane per chunk
+    ((512, 9, 12), 1, 2, 1),    # eight waves per row
 ])
-def test_random_init_fp32_launch_shapes(solver_cls, shape, ty, kz):
+def test_random_init_fp32_launch_shapes(solver_cls, shape, ty, kz, vpl):
     nx, ny, nz = shape
     wl = W.cpml_block_lattice(n=nx, ny=ny, nz=nz, steps=10, precision="f32", cpml=1, nprobes=6, nfreq=8)
     wl.cpml_cells = (min(6, nx // 2), min(4, ny // 2), min(5, nz // 2))
-    s, sim = _run_both(solver_cls, wl, 10, init_seed=12, tile_rows=ty, chunk_planes=kz)
+    s, sim = _run_both(solver_cls, wl, 10, init_seed=12, tile_rows=ty, chunk_planes=kz, samples_per_lane=vpl)
     _check_fields(s, sim, TOL["f32"])
 
 
@@ -131,18 +133,35 @@ def test_cpml_lattice_full_size_fp32_few_steps(solver_cls):
     _check_probes(s, sim, TOL["f32"], 3)
 
 
-def test_fp16_storage_substrate(solver_cls):
-    """FP16 storage with a PEC strip mask, against the FP16-emulating oracle."""
-    # long enough for the pulse (peak at t0 = 4 tau, about 210 steps) to reach the probes
+@pytest.mark.parametrize("steps", [1, 10])
+def test_fp16_storage_few_steps(solver_cls, steps):
+    """FP16 storage, few steps from a common random state: the GPU and the
+    oracle emulating FP16 storage take the same rounding decisions except where
+    FP32 and FP64 arithmetic straddle an fp16 rounding boundary."""
+    wl = W.fp16_substrate(64, 64, 40, steps=steps, cpml=6)
+    s, sim = _run_both(solver_cls, wl, steps, init_seed=31)
+    _check_fields(s, sim, TOL["f16"])
+
+
+def test_fp16_storage_substrate_long_run(solver_cls):
+    """FP16 storage with a PEC strip mask over 500 steps.
+
+    Over many steps the storage rounding noise of two runs decorrelates as soon
+    as one rounding decision differs, so the error against either oracle grows
+    like a random walk of fp16 roundings: about sqrt(N) u with u = 2^-11.  The
+    run is gated at 4 sqrt(N) u and both errors are reported."""
     wl = W.fp16_substrate(64, 64, 40, steps=500, cpml=6)
     s, sim = _run_both(solver_cls, wl, wl.steps)
-    _check_probes(s, sim, TOL["f16"], wl.steps)
-    _check_fields(s, sim, TOL["f16"])
-    # the FP64 (no storage rounding) error is reported, not gated
+    bound = 4.0 * np.sqrt(wl.steps) * 2.0 ** -11
+    got = s.series()
+    e16 = [rel_l2(got[:, p], sim.series_array()[:, p]) for p in range(len(wl.probes))]
     sim64 = oracle_from_workload(wl, storage="f64")
     sim64.run(wl.steps)
-    errs = [rel_l2(s.series()[:, p], sim64.series_array()[:, p]) for p in range(len(wl.probes))]
-    _say(f"[gpu] fp16 storage vs pure FP64 oracle: max series rel L2 = {max(errs):.3e}")
+    e64 = [rel_l2(got[:, p], sim64.series_array()[:, p]) for p in range(len(wl.probes))]
+    _say(f"[gpu] fp16 storage, {wl.steps} steps: max probe rel L2 vs fp16-emulating oracle {max(e16):.3e}, "
+         f"vs pure FP64 oracle {max(e64):.3e} (bound {bound:.3e})")
+    assert max(e16) <= bound and max(e64) <= bound
+    assert min(np.abs(got[:, p]).max() for p in range(len(wl.probes))) > 1e-4   # the pulse arrived
 
 
 def test_series_ring_and_dft_chunking(solver_cls):
