@@ -144,13 +144,29 @@ __device__ __noinline__ double waveform(const SrcDev s, double t) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// LDS footprint of one workgroup (elements of C): E rows j0-1..j0+ty, H rows
-// j0-1..j0+ty-1, each with three components of RL = wpr * 64 * V samples,
-// plus the source values.
-__host__ __device__ inline size_t step_lds_elems(int ty, int wpr, int V) {
+// LDS footprint of one workgroup in bytes: E rows j0-1..j0+ty and H rows
+// j0-1..j0+ty-1, three components of RL = wpr * 64 * V samples each; the
+// source values; and per-plane tables of the z-chunk (kz + 1 planes): six z
+// profiles, the z block offset, the PEC plane index and the row flags.
+__host__ __device__ inline size_t step_lds_bytes_for(int ty, int wpr, int V, int kz, size_t csize) {
   const size_t rl = (size_t)wpr * kWave * V;
-  return (size_t)(ty + 2) * 3 * rl + (size_t)(ty + 1) * 3 * rl + kMaxSources;
+  const size_t nk = (size_t)kz + 1;
+  size_t b = ((size_t)(ty + 2) * 3 * rl + (size_t)(ty + 1) * 3 * rl + kMaxSources + 6 * nk) * csize;
+  b += 2 * nk * sizeof(int32_t);
+  b += (size_t)(ty + 1) * nk;
+  return (b + 15) & ~size_t(15);
 }
+
+// Per-lane data of one plane that is small but still comes from memory: CPML
+// auxiliaries (H side old, E side in place), the material coefficients and
+// the PEC mask.  It is loaded one plane ahead of its use.
+template <class C, int V>
+struct PlaneAux {
+  C ph[6][V];   // H-side psi, PH* order
+  C pe[6][V];   // E-side psi, PE* order
+  Coef2<C> cf[V];
+  uint32_t pm[V];
+};
 
 // ---------------------------------------------------------------------------
 // The fused step kernel
@@ -161,9 +177,14 @@ step_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
   const int wpr = a.wpr;
   const int RL = wpr * kWave * V;                 // LDS row length
+  const int nk1 = a.kz + 1;                       // stride of the per-plane tables
   C* ldsE = reinterpret_cast<C*>(smem_raw);      // [(ty+2)][3][RL]: E^n(k) rows j0-1..j0+ty
   C* ldsH = ldsE + (a.ty + 2) * 3 * RL;           // [(ty+1)][3][RL]: H^{n+1/2}(k) rows j0-1..j0+ty-1
   C* ldsS = ldsH + (a.ty + 1) * 3 * RL;           // [kMaxSources]: amp * w((n+1) dt)
+  C* tzp = ldsS + kMaxSources;                    // [6][nk1]: z profiles bE aE kE bH aH kH
+  int32_t* tzs = reinterpret_cast<int32_t*>(tzp + 6 * nk1);  // [nk1]: z block index * nsx * nsy
+  int32_t* tzl = tzs + nk1;                       // [nk1]: PEC plane index
+  uint8_t* tfl = reinterpret_cast<uint8_t*>(tzl + nk1);      // [ty+1][nk1]: row flags
 
   // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
   // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
@@ -174,28 +195,49 @@ step_kernel(const StepArgs<T, C> a) {
   const int ytile = t % a.ny_tiles;
   const int chunk = t / a.ny_tiles;
 
+  const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
+  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
+  const int j0 = ytile * a.ty;
+  const int k0 = chunk * a.kz;
+  const int k1 = min(nz, k0 + a.kz);
+  const int kstart = k0 > 0 ? k0 - 1 : 0;
+  const int nk = k1 - kstart;
+
+  // ---- per-workgroup tables (sources and the chunk's planes) ----
   if ((int)threadIdx.x < a.nsrc) {
     const SrcDev sd = a.src[threadIdx.x];
     ldsS[threadIdx.x] = static_cast<C>(sd.amp * waveform(sd, (double)(a.n + 1) * a.dt));
   }
-  // (the first barrier of the march orders these writes before any use)
+  for (int q = threadIdx.x; q < nk; q += blockDim.x) {
+    const int k = kstart + q;
+    const bool inz = (k < Lz || k >= nz - Lz);
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int side = u / 3, qq = u % 3;   // b, a, 1/kappa of the E and H side
+      tzp[u * nk1 + q] = inz ? a.prof[((side * 3 + 2) * 3 + qq) * a.plen + k] : (qq == 1 ? C(0) : C(1));
+    }
+    tzs[q] = a.seg[px + ny + k] * a.nsxy;
+    tzl[q] = a.pec_plane[k];
+  }
+  for (int q = threadIdx.x; q < (a.ty + 1) * nk; q += blockDim.x) {
+    const int rr = q / nk, kk = q - rr * nk;
+    const int jj = j0 - 1 + rr;
+    tfl[rr * nk1 + kk] = (jj >= 0 && jj < ny) ? a.rowflag[(uint32_t)(kstart + kk) * ny + jj] : 0;
+  }
+  __syncthreads();
 
   const int wv = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int r = wv / wpr;                 // tile row: 0 = halo row j0-1
   const int xs = wv - r * wpr;            // x segment of the row
-  const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
-  const int j0 = ytile * a.ty;
   const int j = j0 - 1 + r;
   const bool halo = (r == 0);
   const bool row_ok = (j >= 0) && (j < ny);
   const int jc = min(max(j, 0), ny - 1);
-  const int k0 = chunk * a.kz;
-  const int k1 = min(nz, k0 + a.kz);
-  const int kstart = k0 > 0 ? k0 - 1 : 0;
   const int xl = (xs * kWave + lane) * V;  // first sample of the lane within the row
   const bool lane_ok = xl < nx;
   const bool ld_ok = row_ok && lane_ok;
+  const bool own = !halo && ld_ok;
   const uint32_t plane = (uint32_t)ny * (uint32_t)px;
   const uint32_t rowoff = (uint32_t)jc * (uint32_t)px + (uint32_t)xl;
   const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
@@ -211,7 +253,6 @@ step_kernel(const StepArgs<T, C> a) {
 #pragma unroll
   for (int e = 0; e < V; ++e) xin[e] = (xl + e) < nx;
 
-  const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
   const bool iny = row_ok && (j < Ly || j >= ny - Ly);
   const int sy = j < Ly ? j : j - ny + 2 * Ly;
   // x-layer membership and the lane's constant x profiles (E and H side)
@@ -241,19 +282,71 @@ step_kernel(const StepArgs<T, C> a) {
     bye = a.prof[(3 + 0) * a.plen + j]; aye = a.prof[(3 + 1) * a.plen + j]; kye = a.prof[(3 + 2) * a.plen + j];
     byh = a.prof[(12 + 0) * a.plen + j]; ayh = a.prof[(12 + 1) * a.plen + j]; kyh = a.prof[(12 + 2) * a.plen + j];
   }
-  int segx[V];
+  int segxy[V];
 #pragma unroll
-  for (int e = 0; e < V; ++e) segx[e] = xin[e] ? a.seg[xl + e] : 0;
-  const int segy = a.seg[px + jc] * a.nsx;
+  for (int e = 0; e < V; ++e) segxy[e] = (xin[e] ? a.seg[xl + e] : 0) + a.seg[px + jc] * a.nsx;
+
+  // Small per-lane data of plane k (into aux): issued ahead of the plane prefetch.
+  auto load_aux = [&](int k, PlaneAux<C, V>& x) {
+    const bool upd = (k >= k0) && own;
+    const bool inz = row_ok && (k < Lz || k >= nz - Lz);
+    const int sz = k < Lz ? k : k - nz + 2 * Lz;
+    const uint32_t qy = ((uint32_t)k * (2 * Ly) + sy) * px + xl;
+    const uint32_t qz = ((uint32_t)sz * ny + jc) * px + xl;
+    const uint32_t qx = ((uint32_t)k * ny + jc) * (2 * Lx);
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+#pragma unroll
+      for (int u = 0; u < 6; ++u) { x.ph[u][e] = C(0); x.pe[u][e] = C(0); }
+      x.pm[e] = 0;
+    }
+    if (iny) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!xin[e]) continue;
+        x.ph[PHXY][e] = a.psh_in[a.psoff[PHXY] + qy + e];
+        x.ph[PHZY][e] = a.psh_in[a.psoff[PHZY] + qy + e];
+        if (upd) { x.pe[PEXY][e] = a.pse[a.psoff[PEXY] + qy + e]; x.pe[PEZY][e] = a.pse[a.psoff[PEZY] + qy + e]; }
+      }
+    }
+    if (inz) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!xin[e]) continue;
+        x.ph[PHXZ][e] = a.psh_in[a.psoff[PHXZ] + qz + e];
+        x.ph[PHYZ][e] = a.psh_in[a.psoff[PHYZ] + qz + e];
+        if (upd) { x.pe[PEXZ][e] = a.pse[a.psoff[PEXZ] + qz + e]; x.pe[PEYZ][e] = a.pse[a.psoff[PEYZ] + qz + e]; }
+      }
+    }
+    if (lane_inx) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        if (!inx[e]) continue;
+        x.ph[PHYX][e] = a.psh_in[a.psoff[PHYX] + qx + sxv[e]];
+        x.ph[PHZX][e] = a.psh_in[a.psoff[PHZX] + qx + sxv[e]];
+        if (upd) { x.pe[PEYX][e] = a.pse[a.psoff[PEYX] + qx + sxv[e]]; x.pe[PEZX][e] = a.pse[a.psoff[PEZX] + qx + sxv[e]]; }
+      }
+    }
+    const int zs = tzs[k - kstart];
+#pragma unroll
+    for (int e = 0; e < V; ++e) x.cf[e] = a.coef[segxy[e] + zs];
+    const int pl = tzl[k - kstart];
+    if (pl >= 0 && own) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) x.pm[e] = a.pec_mask[((uint32_t)pl * ny + jc) * px + xl + e];
+    }
+  };
 
   // Software pipeline over the z-march: at plane k the registers hold E^n(k),
-  // E^n(k+1), H^{n-1/2}(k) (and, in the halo waves, Ez/Ex of the row above the
-  // tile at plane k).
+  // E^n(k+1), H^{n-1/2}(k), the plane's small data (cur) and, in the halo
+  // waves, Ez/Ex of the row above the tile at plane k.
   C ec[3][V], en[3][V], hc[3][V], tz[V], tx[V];
+  PlaneAux<C, V> cur;
   const int jt = j0 + a.ty;  // row above the tile
   const bool top_ok = halo && lane_ok && jt < ny;
   const uint32_t rowoff_t = (uint32_t)min(jt, ny - 1) * (uint32_t)px + (uint32_t)xl;
   {
+    load_aux(kstart, cur);
     const uint32_t off = (uint32_t)kstart * plane + rowoff;
     const bool ok1 = ld_ok && (kstart + 1 < nz);
     load_row<T, C, V>(fEx, off, ld_ok, ec[0], a.dec[0]);
@@ -272,86 +365,32 @@ step_kernel(const StepArgs<T, C> a) {
   C hxp[V], hyp[V];  // H^{n+1/2}(k-1), own row
 #pragma unroll
   for (int e = 0; e < V; ++e) { hxp[e] = C(0); hyp[e] = C(0); }
-  int segz_cur = -1;
-  Coef2<C> cf[V];    // (Ca, Cb) of the row's cells in the current z block
-#pragma unroll
-  for (int e = 0; e < V; ++e) { cf[e].ca = C(0); cf[e].cb = C(0); }
 
   C* rowE = ldsE + r * 3 * RL;        // own row in the E buffer
   C* rowH = ldsH + r * 3 * RL;        // own row in the H buffer
-  const bool own = !halo && ld_ok;
 
-  for (int k = kstart; k < k1; ++k) {
+  // One plane of the march.  The registers of the plane prefetch come in two
+  // sets used alternately (en/hc/aux/tz of this plane, the other set filled
+  // for the next one), so no register whose load is still in flight is ever
+  // copied; the march is unrolled by two to alternate them.
+  auto plane_step = [&](const int k, C (&en)[3][V], C (&en2)[3][V], C (&hc)[3][V], C (&hn)[3][V],
+                        PlaneAux<C, V>& cur, PlaneAux<C, V>& nxt, C (&tz)[V], C (&tx)[V], C (&tzn)[V],
+                        C (&txn)[V]) {
     const bool active = k >= k0;
     const bool more = k + 1 < k1;  // another plane follows in this chunk
     const uint32_t off = (uint32_t)k * plane + rowoff;
+    const int kq = k - kstart;
     const bool inz = row_ok && (k < Lz || k >= nz - Lz);
     const int sz = k < Lz ? k : k - nz + 2 * Lz;
     const bool upd = active && own;
-
-    // ---- 1. small loads of this plane (issued before the prefetches) ----
-    C pHxy[V], pHzy[V], pHxz[V], pHyz[V], pHyx[V], pHzx[V];
-    C pExy[V], pEzy[V], pExz[V], pEyz[V], pEyx[V], pEzx[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-      pHxy[e] = pHzy[e] = pHxz[e] = pHyz[e] = pHyx[e] = pHzx[e] = C(0);
-      pExy[e] = pEzy[e] = pExz[e] = pEyz[e] = pEyx[e] = pEzx[e] = C(0);
-    }
     const uint32_t qy = ((uint32_t)k * (2 * Ly) + sy) * px + xl;
     const uint32_t qz = ((uint32_t)sz * ny + jc) * px + xl;
     const uint32_t qx = ((uint32_t)k * ny + jc) * (2 * Lx);
-    if (iny) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        if (!xin[e]) continue;
-        pHxy[e] = a.psh_in[a.psoff[PHXY] + qy + e];
-        pHzy[e] = a.psh_in[a.psoff[PHZY] + qy + e];
-        if (upd) { pExy[e] = a.pse[a.psoff[PEXY] + qy + e]; pEzy[e] = a.pse[a.psoff[PEZY] + qy + e]; }
-      }
-    }
-    if (inz) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        if (!xin[e]) continue;
-        pHxz[e] = a.psh_in[a.psoff[PHXZ] + qz + e];
-        pHyz[e] = a.psh_in[a.psoff[PHYZ] + qz + e];
-        if (upd) { pExz[e] = a.pse[a.psoff[PEXZ] + qz + e]; pEyz[e] = a.pse[a.psoff[PEYZ] + qz + e]; }
-      }
-    }
-    if (lane_inx) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        if (!inx[e]) continue;
-        pHyx[e] = a.psh_in[a.psoff[PHYX] + qx + sxv[e]];
-        pHzx[e] = a.psh_in[a.psoff[PHZX] + qx + sxv[e]];
-        if (upd) { pEyx[e] = a.pse[a.psoff[PEYX] + qx + sxv[e]]; pEzx[e] = a.pse[a.psoff[PEZX] + qx + sxv[e]]; }
-      }
-    }
-    C bze = 1, aze = 0, kze = 1, bzh = 1, azh = 0, kzh = 1;
-    if (inz) {
-      bze = a.prof[(6 + 0) * a.plen + k]; aze = a.prof[(6 + 1) * a.plen + k]; kze = a.prof[(6 + 2) * a.plen + k];
-      bzh = a.prof[(15 + 0) * a.plen + k]; azh = a.prof[(15 + 1) * a.plen + k]; kzh = a.prof[(15 + 2) * a.plen + k];
-    }
-    const int sz_blk = a.seg[px + ny + k];
-    if (sz_blk != segz_cur) {
-      segz_cur = sz_blk;
-      const int segyz = segy + sz_blk * a.nsxy;
-#pragma unroll
-      for (int e = 0; e < V; ++e) cf[e] = a.coef[segx[e] + segyz];
-    }
-    const int pl = a.pec_plane[k];
-    uint8_t pmask[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) pmask[e] = 0;
-    if (pl >= 0 && own) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) pmask[e] = a.pec_mask[((uint32_t)pl * ny + jc) * px + xl + e];
-    }
-    const uint8_t flags = a.rowflag[(uint32_t)k * ny + jc];
-    __builtin_amdgcn_sched_barrier(0);
 
-    // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the next row above ----
-    C en2[3][V], hn[3][V], tzn[V], txn[V];
+    // ---- 1. loads for the next iterations: small data of plane k+1 first,
+    //         then E^n(k+2), H^{n-1/2}(k+1) and the next row above ----
+    if (more) load_aux(k + 1, nxt);
+    __builtin_amdgcn_sched_barrier(0);
     {
       const bool ok2 = ld_ok && more && (k + 2 < nz);
       const bool okh = ld_ok && more;
@@ -367,7 +406,7 @@ step_kernel(const StepArgs<T, C> a) {
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // ---- 3. publish E^n(k) ----
+    // ---- 2. publish E^n(k) ----
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       rowE[xl + e] = ec[0][e];
@@ -381,7 +420,9 @@ step_kernel(const StepArgs<T, C> a) {
     }
     __syncthreads();
 
-    // ---- 4. H half step at plane k ----
+    // ---- 3. H half step at plane k ----
+    const C bze = tzp[0 * nk1 + kq], aze = tzp[1 * nk1 + kq], kze = tzp[2 * nk1 + kq];
+    const C bzh = tzp[3 * nk1 + kq], azh = tzp[4 * nk1 + kq], kzh = tzp[5 * nk1 + kq];
     C hx[V], hy[V], hz[V];
     {
       const C* up = rowE + 3 * RL;   // row j+1
@@ -408,22 +449,22 @@ step_kernel(const StepArgs<T, C> a) {
         C dEy_dx = (eyr[e] - ec[1][e]) * idx_;
         C dEx_dy = (exu[e] - ec[0][e]) * idy;
         if (iny) {
-          pHxy[e] = byh * pHxy[e] + ayh * dEz_dy;
-          pHzy[e] = byh * pHzy[e] + ayh * dEx_dy;
-          dEz_dy = kyh * dEz_dy + pHxy[e];
-          dEx_dy = kyh * dEx_dy + pHzy[e];
+          cur.ph[PHXY][e] = byh * cur.ph[PHXY][e] + ayh * dEz_dy;
+          cur.ph[PHZY][e] = byh * cur.ph[PHZY][e] + ayh * dEx_dy;
+          dEz_dy = kyh * dEz_dy + cur.ph[PHXY][e];
+          dEx_dy = kyh * dEx_dy + cur.ph[PHZY][e];
         }
         if (inz) {
-          pHxz[e] = bzh * pHxz[e] + azh * dEy_dz;
-          pHyz[e] = bzh * pHyz[e] + azh * dEx_dz;
-          dEy_dz = kzh * dEy_dz + pHxz[e];
-          dEx_dz = kzh * dEx_dz + pHyz[e];
+          cur.ph[PHXZ][e] = bzh * cur.ph[PHXZ][e] + azh * dEy_dz;
+          cur.ph[PHYZ][e] = bzh * cur.ph[PHYZ][e] + azh * dEx_dz;
+          dEy_dz = kzh * dEy_dz + cur.ph[PHXZ][e];
+          dEx_dz = kzh * dEx_dz + cur.ph[PHYZ][e];
         }
         if (inx[e]) {
-          pHyx[e] = bxh[e] * pHyx[e] + axh[e] * dEz_dx;
-          pHzx[e] = bxh[e] * pHzx[e] + axh[e] * dEy_dx;
-          dEz_dx = kxh[e] * dEz_dx + pHyx[e];
-          dEy_dx = kxh[e] * dEy_dx + pHzx[e];
+          cur.ph[PHYX][e] = bxh[e] * cur.ph[PHYX][e] + axh[e] * dEz_dx;
+          cur.ph[PHZX][e] = bxh[e] * cur.ph[PHZX][e] + axh[e] * dEy_dx;
+          dEz_dx = kxh[e] * dEz_dx + cur.ph[PHYX][e];
+          dEy_dx = kxh[e] * dEy_dx + cur.ph[PHZX][e];
         }
         const bool ok = row_ok && xin[e];
         hx[e] = ok ? to_storage<T, C>(hc[0][e] - a.dt_mu * (dEz_dy - dEy_dz), a.enc[3], a.dec[3]) : C(0);
@@ -432,7 +473,7 @@ step_kernel(const StepArgs<T, C> a) {
       }
     }
 
-    // ---- 5. publish H^{n+1/2}(k) ----
+    // ---- 4. publish H^{n+1/2}(k) ----
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       rowH[xl + e] = hx[e];
@@ -441,25 +482,31 @@ step_kernel(const StepArgs<T, C> a) {
     }
     __syncthreads();
 
-    // ---- 6. E half step at plane k (own rows) and stores ----
+    // ---- 5. E half step at plane k (own rows) and stores ----
     if (upd) {
       // H-side psi of the own row
       if (iny) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          if (xin[e]) { a.psh_out[a.psoff[PHXY] + qy + e] = pHxy[e]; a.psh_out[a.psoff[PHZY] + qy + e] = pHzy[e]; }
+          if (xin[e]) {
+            a.psh_out[a.psoff[PHXY] + qy + e] = cur.ph[PHXY][e];
+            a.psh_out[a.psoff[PHZY] + qy + e] = cur.ph[PHZY][e];
+          }
       }
       if (inz) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          if (xin[e]) { a.psh_out[a.psoff[PHXZ] + qz + e] = pHxz[e]; a.psh_out[a.psoff[PHYZ] + qz + e] = pHyz[e]; }
+          if (xin[e]) {
+            a.psh_out[a.psoff[PHXZ] + qz + e] = cur.ph[PHXZ][e];
+            a.psh_out[a.psoff[PHYZ] + qz + e] = cur.ph[PHYZ][e];
+          }
       }
       if (lane_inx) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
           if (inx[e]) {
-            a.psh_out[a.psoff[PHYX] + qx + sxv[e]] = pHyx[e];
-            a.psh_out[a.psoff[PHZX] + qx + sxv[e]] = pHzx[e];
+            a.psh_out[a.psoff[PHYX] + qx + sxv[e]] = cur.ph[PHYX][e];
+            a.psh_out[a.psoff[PHZX] + qx + sxv[e]] = cur.ph[PHZX][e];
           }
       }
       const C* dn = rowH - 3 * RL;   // row j-1
@@ -491,50 +538,61 @@ step_kernel(const StepArgs<T, C> a) {
         const bool uy = (i > 0) && (k > 0) && xin[e];
         const bool uz = (i > 0) && (j > 0) && xin[e];
         if (iny) {
-          pExy[e] = bye * pExy[e] + aye * dHz_dy;
-          pEzy[e] = bye * pEzy[e] + aye * dHx_dy;
-          dHz_dy = kye * dHz_dy + pExy[e];
-          dHx_dy = kye * dHx_dy + pEzy[e];
+          cur.pe[PEXY][e] = bye * cur.pe[PEXY][e] + aye * dHz_dy;
+          cur.pe[PEZY][e] = bye * cur.pe[PEZY][e] + aye * dHx_dy;
+          dHz_dy = kye * dHz_dy + cur.pe[PEXY][e];
+          dHx_dy = kye * dHx_dy + cur.pe[PEZY][e];
         }
         if (inz) {
-          pExz[e] = bze * pExz[e] + aze * dHy_dz;
-          pEyz[e] = bze * pEyz[e] + aze * dHx_dz;
-          dHy_dz = kze * dHy_dz + pExz[e];
-          dHx_dz = kze * dHx_dz + pEyz[e];
+          cur.pe[PEXZ][e] = bze * cur.pe[PEXZ][e] + aze * dHy_dz;
+          cur.pe[PEYZ][e] = bze * cur.pe[PEYZ][e] + aze * dHx_dz;
+          dHy_dz = kze * dHy_dz + cur.pe[PEXZ][e];
+          dHx_dz = kze * dHx_dz + cur.pe[PEYZ][e];
         }
         if (inx[e]) {
-          pEyx[e] = bxe[e] * pEyx[e] + axe[e] * dHz_dx;
-          pEzx[e] = bxe[e] * pEzx[e] + axe[e] * dHy_dx;
-          dHz_dx = kxe[e] * dHz_dx + pEyx[e];
-          dHy_dx = kxe[e] * dHy_dx + pEzx[e];
+          cur.pe[PEYX][e] = bxe[e] * cur.pe[PEYX][e] + axe[e] * dHz_dx;
+          cur.pe[PEZX][e] = bxe[e] * cur.pe[PEZX][e] + axe[e] * dHy_dx;
+          dHz_dx = kxe[e] * dHz_dx + cur.pe[PEYX][e];
+          dHy_dx = kxe[e] * dHy_dx + cur.pe[PEZX][e];
         }
-        const C ca = cf[e].ca, cb = cf[e].cb;
-        const C cax = (pmask[e] & 1) ? C(0) : ca, cbx = (pmask[e] & 1) ? C(0) : cb;
-        const C cay = (pmask[e] & 2) ? C(0) : ca, cby = (pmask[e] & 2) ? C(0) : cb;
-        const C caz = (pmask[e] & 4) ? C(0) : ca, cbz = (pmask[e] & 4) ? C(0) : cb;
+        const C ca = cur.cf[e].ca, cb = cur.cf[e].cb;
+        const uint32_t m = cur.pm[e];
+        const C cax = (m & 1) ? C(0) : ca, cbx = (m & 1) ? C(0) : cb;
+        const C cay = (m & 2) ? C(0) : ca, cby = (m & 2) ? C(0) : cb;
+        const C caz = (m & 4) ? C(0) : ca, cbz = (m & 4) ? C(0) : cb;
         exo[e] = ux ? cax * ec[0][e] + cbx * (dHz_dy - dHy_dz) : ec[0][e];
         eyo[e] = uy ? cay * ec[1][e] + cby * (dHx_dz - dHz_dx) : ec[1][e];
         ezo[e] = uz ? caz * ec[2][e] + cbz * (dHy_dx - dHx_dy) : ec[2][e];
         // E-side psi of the updated samples (wall samples keep 0)
-        if (!ux) { pExy[e] = C(0); pExz[e] = C(0); }
-        if (!uy) { pEyz[e] = C(0); pEyx[e] = C(0); }
-        if (!uz) { pEzx[e] = C(0); pEzy[e] = C(0); }
+        if (!ux) { cur.pe[PEXY][e] = C(0); cur.pe[PEXZ][e] = C(0); }
+        if (!uy) { cur.pe[PEYZ][e] = C(0); cur.pe[PEYX][e] = C(0); }
+        if (!uz) { cur.pe[PEZX][e] = C(0); cur.pe[PEZY][e] = C(0); }
       }
       if (iny) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          if (xin[e]) { a.pse[a.psoff[PEXY] + qy + e] = pExy[e]; a.pse[a.psoff[PEZY] + qy + e] = pEzy[e]; }
+          if (xin[e]) {
+            a.pse[a.psoff[PEXY] + qy + e] = cur.pe[PEXY][e];
+            a.pse[a.psoff[PEZY] + qy + e] = cur.pe[PEZY][e];
+          }
       }
       if (inz) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          if (xin[e]) { a.pse[a.psoff[PEXZ] + qz + e] = pExz[e]; a.pse[a.psoff[PEYZ] + qz + e] = pEyz[e]; }
+          if (xin[e]) {
+            a.pse[a.psoff[PEXZ] + qz + e] = cur.pe[PEXZ][e];
+            a.pse[a.psoff[PEYZ] + qz + e] = cur.pe[PEYZ][e];
+          }
       }
       if (lane_inx) {
 #pragma unroll
         for (int e = 0; e < V; ++e)
-          if (inx[e]) { a.pse[a.psoff[PEYX] + qx + sxv[e]] = pEyx[e]; a.pse[a.psoff[PEZX] + qx + sxv[e]] = pEzx[e]; }
+          if (inx[e]) {
+            a.pse[a.psoff[PEYX] + qx + sxv[e]] = cur.pe[PEYX][e];
+            a.pse[a.psoff[PEZX] + qx + sxv[e]] = cur.pe[PEZX][e];
+          }
       }
+      const uint8_t flags = tfl[r * nk1 + kq];
       if (flags & 1) {
         for (int s = 0; s < a.nsrc; ++s) {
           const SrcDev sp = a.src[s];
@@ -583,11 +641,16 @@ step_kernel(const StepArgs<T, C> a) {
     for (int e = 0; e < V; ++e) {
       hxp[e] = hx[e];
       hyp[e] = hy[e];
-      tz[e] = tzn[e];
-      tx[e] = txn[e];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) { ec[c][e] = en[c][e]; en[c][e] = en2[c][e]; hc[c][e] = hn[c][e]; }
+      for (int c = 0; c < 3; ++c) ec[c][e] = en[c][e];   // E^n(k+1) has arrived: it was used above
     }
+  };
+
+  C en_b[3][V], hc_b[3][V], tz_b[V], tx_b[V];
+  PlaneAux<C, V> aux_b;
+  for (int k = kstart; k < k1; k += 2) {
+    plane_step(k, en, en_b, hc, hc_b, cur, aux_b, tz, tx, tz_b, tx_b);
+    if (k + 1 < k1) plane_step(k + 1, en_b, en, hc_b, hc, aux_b, cur, tz_b, tx_b, tz, tx);
   }
 }
 

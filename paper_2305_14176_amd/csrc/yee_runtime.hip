@@ -211,8 +211,8 @@ yee_status upload_materials_impl(yee_ctx* c, hipStream_t s) {
   return YEE_OK;
 }
 
-size_t step_lds_bytes(const yee_ctx* c, int ty, int V) {
-  return yee::step_lds_elems(ty, waves_per_row(c->d.nx, V), V) * c->csize;
+size_t step_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
+  return yee::step_lds_bytes_for(ty, waves_per_row(c->d.nx, V), V, kz, c->csize);
 }
 
 template <class T, class C, int V>
@@ -266,7 +266,7 @@ yee_status launch_step(yee_ctx* c, hipStream_t s) {
   const int waves = (c->ty + 1) * a.wpr;
   if (waves > max_block_waves(V))
     return fail(YEE_EINVAL, "tile of %d rows x %d waves per row exceeds %d waves", c->ty, a.wpr, max_block_waves(V));
-  const size_t lds = step_lds_bytes(c, c->ty, V);
+  const size_t lds = step_lds_bytes(c, c->ty, V, c->kz);
   if (lds > c->lds_limit) return fail(YEE_EINVAL, "tile of %d rows needs %zu bytes of LDS (limit %zu)", c->ty, lds, c->lds_limit);
   hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
   HIP_TRY(hipGetLastError());
@@ -312,9 +312,9 @@ void default_launch(yee_ctx* c) {
   // samples per lane: one while a row fits in four waves, else two
   c->V = c->vpl ? c->vpl : (d.nx <= 4 * yee::kWave ? 1 : 2);
   const int wpr = waves_per_row(d.nx, c->V);
+  // as many rows as the workgroup holds, up to seven (measured best for the
+  // 256^3 grid: three rows of four waves plus the halo row)
   if (c->ty == 0) c->ty = std::max(1, std::min({7, d.ny, yee::max_block_waves(c->V) / wpr - 1}));
-  // keep the LDS rows within the device's per-workgroup limit
-  while (c->ty > 1 && step_lds_bytes(c, c->ty, c->V) > c->lds_limit) --c->ty;
   if (c->kz == 0) {
     // enough workgroups to fill 256 CUs several times over, but keep the
     // per-chunk warm-up plane a small fraction of the march
@@ -323,6 +323,8 @@ void default_launch(yee_ctx* c) {
     while (kz > 8 && (long)ny_tiles * ((d.nz + kz - 1) / kz) < 1024) kz = (kz + 1) / 2;
     c->kz = std::max(1, kz);
   }
+  // keep the LDS rows within the device's per-workgroup limit
+  while (c->ty > 1 && step_lds_bytes(c, c->ty, c->V, c->kz) > c->lds_limit) --c->ty;
 }
 
 template <class T>
