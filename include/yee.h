@@ -191,6 +191,40 @@ yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
  * waves, at most 16.  Results do not depend on the launch shape. */
 yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane);
 
+/* ------------------------------------------------------------------------
+ * Batched stepper for serving many grids (continuous batching).
+ *
+ * One launch advances every admitted context ("slot") by one leapfrog step;
+ * a replay is steps_per_replay such launches captured once in a HIP graph.
+ * Requests are admitted and retired between replays, so requests that arrive
+ * while others run join the next replay as slots and memory free up.  The
+ * update of each grid is the same operation as yee_step() (results do not
+ * depend on batching).  Admitted contexts must be FP32 with nx <= 256 and, if
+ * they have probes, series_len >= steps_per_replay.
+ *
+ * The caller owns the batch's device descriptor table (yee_batch_footprint()
+ * bytes, handed over with yee_batch_bind_workspace()) as well as every
+ * context's workspace; the admission budget counts context footprints.
+ * ------------------------------------------------------------------------ */
+typedef struct yee_batch yee_batch;
+
+yee_status yee_batch_footprint(int32_t max_slots, int64_t* bytes);
+/* hbm_budget: sum of admitted context footprints allowed at one time (bytes). */
+yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps_per_replay, yee_batch** out);
+void yee_batch_destroy(yee_batch* batch);
+yee_status yee_batch_bind_workspace(yee_batch* batch, void* device_ptr, int64_t bytes);
+/* Admit a bound context for n_steps more steps.  YEE_EAGAIN: no free slot or
+ * the footprint would exceed the budget (nothing changes; retry later). */
+yee_status yee_batch_admit(yee_batch* batch, yee_ctx* ctx, int64_t n_steps, int32_t* slot);
+/* One replay (steps_per_replay steps of every admitted, unfinished slot) on
+ * `stream`; synchronizes the stream first.  Probe DFTs are folded after it. */
+yee_status yee_batch_run(yee_batch* batch, void* stream);
+/* Slots whose requested steps are all taken (up to cap written to done). */
+yee_status yee_batch_poll(yee_batch* batch, int32_t* done, int32_t cap, int32_t* n_done);
+/* Retire a slot (its context stays valid; read results before or after). */
+yee_status yee_batch_release(yee_batch* batch, int32_t slot);
+yee_status yee_batch_info(const yee_batch* batch, int32_t* active_slots, int64_t* bytes_in_use);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,9 @@ EXPORTED = (
     "yee_set_materials", "yee_upload_materials", "yee_add_pec_plane", "yee_add_source",
     "yee_add_probe", "yee_set_dft_freqs", "yee_footprint", "yee_bind_workspace", "yee_reset",
     "yee_set_field", "yee_step", "yee_steps_done", "yee_read_field", "yee_read_series",
-    "yee_read_dft", "yee_set_launch",
+    "yee_read_dft", "yee_set_launch", "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
+    "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
+    "yee_batch_info",
 )
 
 
@@ -93,6 +95,15 @@ def load():
         "yee_read_series": (I32, [VP, I64, I64, P(D), VP]),
         "yee_read_dft": (I32, [VP, P(D), P(D), VP]),
         "yee_set_launch": (I32, [VP, I32, I32, I32]),
+        "yee_batch_footprint": (I32, [I32, P(I64)]),
+        "yee_batch_create": (I32, [I32, I64, I32, P(VP)]),
+        "yee_batch_destroy": (None, [VP]),
+        "yee_batch_bind_workspace": (I32, [VP, VP, I64]),
+        "yee_batch_admit": (I32, [VP, VP, I64, P(I32)]),
+        "yee_batch_run": (I32, [VP, VP]),
+        "yee_batch_poll": (I32, [VP, P(I32), I32, P(I32)]),
+        "yee_batch_release": (I32, [VP, I32]),
+        "yee_batch_info": (I32, [VP, P(I32), P(I64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -171,10 +171,11 @@ struct PlaneAux {
 // ---------------------------------------------------------------------------
 // The fused step kernel
 // ---------------------------------------------------------------------------
+// One tile (ytile, chunk) of one grid.  Waves beyond (ty + 1) * wpr (spare
+// waves of a fixed-size workgroup) take part in the barriers only.
 template <class T, class C, int V>
-__global__ void __launch_bounds__(kWave * max_block_waves(V))
-step_kernel(const StepArgs<T, C> a) {
-  extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int chunk,
+                                          unsigned char* smem_raw) {
   const int wpr = a.wpr;
   const int RL = wpr * kWave * V;                 // LDS row length
   const int nk1 = a.kz + 1;                       // stride of the per-plane tables
@@ -185,15 +186,6 @@ step_kernel(const StepArgs<T, C> a) {
   int32_t* tzs = reinterpret_cast<int32_t*>(tzp + 6 * nk1);  // [nk1]: z block index * nsx * nsy
   int32_t* tzl = tzs + nk1;                       // [nk1]: PEC plane index
   uint8_t* tfl = reinterpret_cast<uint8_t*>(tzl + nk1);      // [ty+1][nk1]: row flags
-
-  // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
-  // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
-  // y-tiles of one z-chunk share halo rows in that XCD's L2).
-  const int per_xcd = gridDim.x >> 3;
-  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (t >= a.ntiles) return;
-  const int ytile = t % a.ny_tiles;
-  const int chunk = t / a.ny_tiles;
 
   const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
   const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
@@ -228,11 +220,12 @@ step_kernel(const StepArgs<T, C> a) {
 
   const int wv = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int r = wv / wpr;                 // tile row: 0 = halo row j0-1
-  const int xs = wv - r * wpr;            // x segment of the row
+  const bool dummy = wv >= (a.ty + 1) * wpr;  // spare wave: barriers only
+  const int r = dummy ? 0 : wv / wpr;     // tile row: 0 = halo row j0-1
+  const int xs = dummy ? 0 : wv - r * wpr;  // x segment of the row
   const int j = j0 - 1 + r;
-  const bool halo = (r == 0);
-  const bool row_ok = (j >= 0) && (j < ny);
+  const bool halo = !dummy && (r == 0);
+  const bool row_ok = !dummy && (j >= 0) && (j < ny);
   const int jc = min(max(j, 0), ny - 1);
   const int xl = (xs * kWave + lane) * V;  // first sample of the lane within the row
   const bool lane_ok = xl < nx;
@@ -407,11 +400,13 @@ step_kernel(const StepArgs<T, C> a) {
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- 2. publish E^n(k) ----
+    if (!dummy) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      rowE[xl + e] = ec[0][e];
-      rowE[RL + xl + e] = ec[1][e];
-      rowE[2 * RL + xl + e] = ec[2][e];
+      for (int e = 0; e < V; ++e) {
+        rowE[xl + e] = ec[0][e];
+        rowE[RL + xl + e] = ec[1][e];
+        rowE[2 * RL + xl + e] = ec[2][e];
+      }
     }
     if (halo) {
       C* rt = ldsE + (a.ty + 1) * 3 * RL;
@@ -474,11 +469,13 @@ step_kernel(const StepArgs<T, C> a) {
     }
 
     // ---- 4. publish H^{n+1/2}(k) ----
+    if (!dummy) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      rowH[xl + e] = hx[e];
-      rowH[RL + xl + e] = hy[e];
-      rowH[2 * RL + xl + e] = hz[e];
+      for (int e = 0; e < V; ++e) {
+        rowH[xl + e] = hx[e];
+        rowH[RL + xl + e] = hy[e];
+        rowH[2 * RL + xl + e] = hz[e];
+      }
     }
     __syncthreads();
 
@@ -651,6 +648,68 @@ step_kernel(const StepArgs<T, C> a) {
   for (int k = kstart; k < k1; k += 2) {
     plane_step(k, en, en_b, hc, hc_b, cur, aux_b, tz, tx, tz_b, tx_b);
     if (k + 1 < k1) plane_step(k + 1, en_b, en, hc_b, hc, aux_b, cur, tz_b, tx_b, tz, tx);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel: one grid, one tile per workgroup.
+// ---------------------------------------------------------------------------
+template <class T, class C, int V>
+__global__ void __launch_bounds__(kWave * max_block_waves(V))
+step_kernel(const StepArgs<T, C> a) {
+  extern __shared__ unsigned char smem_raw[];
+  // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
+  // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
+  // y-tiles of one z-chunk share halo rows in that XCD's L2).
+  const int per_xcd = gridDim.x >> 3;
+  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (t >= a.ntiles) return;
+  step_tile<T, C, V>(a, t % a.ny_tiles, t / a.ny_tiles, smem_raw);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stepper: many grids ("slots") per launch.  The host writes one
+// descriptor per slot (its static arguments, both field / psi sets, the steps
+// already taken and the steps requested) before a replay; a replay is a
+// sequence of launches with step offsets q = 0, 1, ... (captured once in a
+// HIP graph).  Workgroups stride over the global tile list of all slots, so
+// the grid size is fixed while slots come and go between replays; a slot whose
+// request is complete skips its tiles.
+// ---------------------------------------------------------------------------
+template <class T, class C>
+struct SlotDesc {
+  StepArgs<T, C> a;         // static arguments; fin/fout/psh/n/series_slot are set per step
+  const T* set[2];          // field sets (E, H ping-pong)
+  C* psh[2];                // H-side psi sets
+  int64_t base_n;           // steps taken before this replay
+  int64_t n_end;            // steps requested
+  int32_t series_len;
+  int32_t tile0;            // first global tile of the slot
+  int32_t pad[2];
+};
+
+template <class T, class C, int V>
+__global__ void __launch_bounds__(kWave * max_block_waves(V))
+batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __restrict__ hdr, const int q) {
+  extern __shared__ unsigned char smem_raw[];
+  const int nslots = hdr[0], total = hdr[1];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    int s = 0;
+    while (s + 1 < nslots && slots[s + 1].tile0 <= t) ++s;
+    const int64_t n = slots[s].base_n + q;
+    if (n < slots[s].n_end) {
+      StepArgs<T, C> a = slots[s].a;
+      const int par = (int)(n & 1);
+      a.fin = slots[s].set[par];
+      a.fout = const_cast<T*>(slots[s].set[par ^ 1]);
+      a.psh_in = slots[s].psh[par];
+      a.psh_out = slots[s].psh[par ^ 1];
+      a.n = n;
+      a.series_slot = (int32_t)(n % slots[s].series_len);
+      const int tl = t - slots[s].tile0;
+      step_tile<T, C, V>(a, tl % a.ny_tiles, tl / a.ny_tiles, smem_raw);
+    }
+    __syncthreads();  // the next tile reuses the LDS
   }
 }
 

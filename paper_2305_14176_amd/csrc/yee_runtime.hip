@@ -94,6 +94,30 @@ struct yee_ctx {
   int64_t folded = 0;      // steps folded into the DFT
 };
 
+struct yee_batch {
+  int32_t max_slots = 0;
+  int64_t budget = 0;      // bytes of admitted context workspaces
+  int32_t K = 0;           // steps per replay
+  int32_t grid = 0;        // workgroups of the batched launch
+  size_t lds = 0;
+  unsigned char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  bool bound = false;
+  struct Slot {
+    yee_ctx* ctx = nullptr;
+    int64_t n_end = 0;     // step count at which the request is complete
+    int64_t bytes = 0;
+    int32_t ty = 0, kz = 0;
+    bool used = false;
+  };
+  std::vector<Slot> slots;
+  int64_t in_use = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t capture = nullptr;       // private stream the replay graph is captured on
+  std::vector<unsigned char> staging;  // host image of the descriptor table
+};
+
 namespace {
 
 constexpr int kMaxRow = 512;  // x samples per row a workgroup can cover
@@ -215,8 +239,10 @@ size_t step_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
   return yee::step_lds_bytes_for(ty, waves_per_row(c->d.nx, V), V, kz, c->csize);
 }
 
-template <class T, class C, int V>
-yee_status launch_step(yee_ctx* c, hipStream_t s) {
+// Kernel arguments of one step of context c at its current step count, for a
+// launch shape (V samples per lane, ty rows per tile, kz planes per chunk).
+template <class T, class C>
+yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz) {
   using namespace yee;
   const auto& d = c->d;
   StepArgs<T, C> a{};
@@ -256,13 +282,19 @@ yee_status launch_step(yee_ctx* c, hipStream_t s) {
     a.enc[q] = std::ldexp(1.0f, e);
     a.dec[q] = std::ldexp(1.0f, -e);
   }
-  a.ty = c->ty;
-  a.kz = c->kz;
-  a.ny_tiles = (d.ny + c->ty - 1) / c->ty;
-  const int nchunks = (d.nz + c->kz - 1) / c->kz;
-  a.ntiles = a.ny_tiles * nchunks;
-  const int grid = ((a.ntiles + 7) / 8) * 8;
+  a.ty = ty;
+  a.kz = kz;
   a.wpr = waves_per_row(d.nx, V);
+  a.ny_tiles = (d.ny + ty - 1) / ty;
+  a.ntiles = a.ny_tiles * ((d.nz + kz - 1) / kz);
+  return a;
+}
+
+template <class T, class C, int V>
+yee_status launch_step(yee_ctx* c, hipStream_t s) {
+  using namespace yee;
+  const StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz);
+  const int grid = ((a.ntiles + 7) / 8) * 8;
   const int waves = (c->ty + 1) * a.wpr;
   if (waves > max_block_waves(V))
     return fail(YEE_EINVAL, "tile of %d rows x %d waves per row exceeds %d waves", c->ty, a.wpr, max_block_waves(V));
@@ -335,6 +367,28 @@ void host_to_storage(const double* in, std::vector<unsigned char>& out, const ye
     for (size_t j = 0; j < (size_t)d.ny; ++j)
       for (size_t i = 0; i < (size_t)d.nx; ++i)
         o[(k * d.ny + j) * px + i] = static_cast<T>(static_cast<float>(in[(k * d.ny + j) * d.nx + i]) * enc);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stepper (serving): FP32 contexts with rows of at most 256 samples
+// (one sample per lane) share one fixed-size launch.
+// ---------------------------------------------------------------------------
+constexpr int kBatchBlockWaves = 8;   // waves per workgroup of the batched launch
+constexpr int kBatchMaxChunk = 32;    // planes per z-chunk of a batched grid
+using BatchDesc = yee::SlotDesc<float, float>;
+
+int batch_tile_rows(const yee_ctx* c) {
+  const int wpr = waves_per_row(c->d.nx, 1);
+  return std::max(1, std::min(c->d.ny, kBatchBlockWaves / wpr - 1));
+}
+
+size_t batch_lds_bytes() {
+  size_t m = 0;
+  for (int wpr = 1; wpr <= 4; ++wpr) {
+    const int ty = std::max(1, kBatchBlockWaves / wpr - 1);
+    m = std::max(m, yee::step_lds_bytes_for(ty, wpr, 1, kBatchMaxChunk, sizeof(float)));
+  }
+  return m;
 }
 
 }  // namespace
@@ -681,6 +735,177 @@ yee_status yee_read_dft(yee_ctx* c, double* re, double* im, void* stream) {
     re[q] = buf[2 * q];
     im[q] = buf[2 * q + 1];
   }
+  return YEE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched stepper (continuous batching of many grids)
+// ---------------------------------------------------------------------------
+yee_status yee_batch_footprint(int32_t max_slots, int64_t* bytes) {
+  if (max_slots < 1 || !bytes) return fail(YEE_EINVAL, "max_slots must be >= 1");
+  *bytes = (int64_t)(256 + align256((size_t)max_slots * sizeof(BatchDesc)));
+  return YEE_OK;
+}
+
+yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps_per_replay, yee_batch** out) {
+  if (!out) return fail(YEE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 4096 || hbm_budget <= 0 || steps_per_replay < 1 || steps_per_replay > 4096)
+    return fail(YEE_EINVAL, "bad batch parameters (slots %d, budget %lld, steps per replay %d)", max_slots,
+                (long long)hbm_budget, steps_per_replay);
+  auto* b = new (std::nothrow) yee_batch();
+  if (!b) return fail(YEE_ENOMEM, "host allocation failed");
+  b->max_slots = max_slots;
+  b->budget = hbm_budget;
+  b->K = steps_per_replay;
+  b->slots.resize(max_slots);
+  b->lds = batch_lds_bytes();
+  *out = b;
+  return YEE_OK;
+}
+
+void yee_batch_destroy(yee_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  delete b;
+}
+
+yee_status yee_batch_bind_workspace(yee_batch* b, void* dev, int64_t bytes) {
+  if (!b || !dev) return fail(YEE_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(YEE_EINVAL, "workspace must be 256-byte aligned");
+  int64_t need = 0;
+  yee_batch_footprint(b->max_slots, &need);
+  if (bytes < need) return fail(YEE_ENOMEM, "batch workspace has %lld bytes, needs %lld", (long long)bytes, (long long)need);
+  int dev_id = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev_id));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+  b->grid = std::max(8, 2 * cus);
+  b->ws = static_cast<unsigned char*>(dev);
+  b->ws_bytes = bytes;
+  b->bound = true;
+  return YEE_OK;
+}
+
+yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* slot) {
+  if (!b || !c || !slot) return fail(YEE_EINVAL, "NULL argument");
+  if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
+  if (!c->bound) return fail(YEE_ESTATE, "context workspace not bound");
+  if (n_steps < 1) return fail(YEE_EINVAL, "n_steps must be >= 1");
+  if (c->d.precision != YEE_F32) return fail(YEE_EINVAL, "the batched stepper runs FP32 contexts");
+  if (c->d.nx > 4 * yee::kWave) return fail(YEE_EINVAL, "the batched stepper takes rows of at most %d samples", 4 * yee::kWave);
+  if (!c->probes.empty() && c->d.series_len < b->K)
+    return fail(YEE_EINVAL, "probe ring (%d) shorter than the steps per replay (%d)", c->d.series_len, b->K);
+  for (auto& sl : b->slots)
+    if (sl.used && sl.ctx == c) return fail(YEE_EINVAL, "context already admitted");
+  if (b->in_use + c->ws_bytes > b->budget) return fail(YEE_EAGAIN, "HBM budget exhausted");
+  for (int32_t q = 0; q < b->max_slots; ++q) {
+    auto& sl = b->slots[q];
+    if (sl.used) continue;
+    sl.used = true;
+    sl.ctx = c;
+    sl.n_end = c->n + n_steps;
+    sl.bytes = c->ws_bytes;
+    sl.ty = batch_tile_rows(c);
+    sl.kz = std::min(c->d.nz, kBatchMaxChunk);
+    b->in_use += sl.bytes;
+    *slot = q;
+    return YEE_OK;
+  }
+  return fail(YEE_EAGAIN, "no free slot");
+}
+
+yee_status yee_batch_run(yee_batch* b, void* stream) {
+  if (!b) return fail(YEE_EINVAL, "NULL batch");
+  if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
+  hipStream_t s = (hipStream_t)stream;
+  // the staging image of the previous replay may still be in flight
+  HIP_TRY(hipStreamSynchronize(s));
+  const size_t hdr_bytes = 256;
+  b->staging.assign(hdr_bytes + (size_t)b->max_slots * sizeof(BatchDesc), 0);
+  BatchDesc* desc = reinterpret_cast<BatchDesc*>(b->staging.data() + hdr_bytes);
+  int32_t nact = 0, tiles = 0;
+  std::vector<int32_t> order;
+  for (int32_t q = 0; q < b->max_slots; ++q) {
+    auto& sl = b->slots[q];
+    if (!sl.used || sl.ctx->n >= sl.n_end) continue;
+    yee_ctx* c = sl.ctx;
+    BatchDesc& d = desc[nact++];
+    d.a = fill_args<float, float>(c, 1, sl.ty, sl.kz);
+    d.set[0] = reinterpret_cast<const float*>(c->ws + c->fields[0].off);
+    d.set[1] = reinterpret_cast<const float*>(c->ws + c->fields[1].off);
+    d.psh[0] = reinterpret_cast<float*>(c->ws + c->psi_h[0].off);
+    d.psh[1] = reinterpret_cast<float*>(c->ws + c->psi_h[1].off);
+    d.base_n = c->n;
+    d.n_end = sl.n_end;
+    d.series_len = c->d.series_len;
+    d.tile0 = tiles;
+    tiles += d.a.ntiles;
+    order.push_back(q);
+  }
+  if (nact == 0) return YEE_OK;
+  reinterpret_cast<int32_t*>(b->staging.data())[0] = nact;
+  reinterpret_cast<int32_t*>(b->staging.data())[1] = tiles;
+  HIP_TRY(hipMemcpyAsync(b->ws, b->staging.data(), hdr_bytes + (size_t)nact * sizeof(BatchDesc),
+                         hipMemcpyHostToDevice, s));
+  if (!b->exec) {
+    // capture K launches once; they read the descriptor table from device memory
+    const BatchDesc* dslots = reinterpret_cast<const BatchDesc*>(b->ws + hdr_bytes);
+    const int32_t* dhdr = reinterpret_cast<const int32_t*>(b->ws);
+    // (captured on a private stream: the caller's may be the legacy null stream)
+    if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    for (int q = 0; q < b->K; ++q)
+      hipLaunchKernelGGL((yee::batch_step_kernel<float, float, 1>), dim3(b->grid), dim3(yee::kWave * kBatchBlockWaves),
+                         b->lds, b->capture, dslots, dhdr, q);
+    hipGraph_t g = nullptr;
+    hipError_t e1 = hipStreamEndCapture(b->capture, &g);
+    if (e1 != hipSuccess) return fail(YEE_EHIP, "graph capture failed: %s", hipGetErrorString(e1));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, s));
+  // host bookkeeping: every included slot advanced min(K, remaining) steps
+  for (int32_t q : order) {
+    auto& sl = b->slots[q];
+    yee_ctx* c = sl.ctx;
+    c->n = std::min(sl.n_end, c->n + b->K);
+    yee_status st = fold_dft(c, s);
+    if (st) return st;
+  }
+  return YEE_OK;
+}
+
+yee_status yee_batch_poll(yee_batch* b, int32_t* done, int32_t cap, int32_t* n_done) {
+  if (!b || !n_done || (cap > 0 && !done)) return fail(YEE_EINVAL, "NULL argument");
+  int32_t m = 0;
+  for (int32_t q = 0; q < b->max_slots; ++q) {
+    const auto& sl = b->slots[q];
+    if (sl.used && sl.ctx->n >= sl.n_end) {
+      if (m < cap) done[m] = q;
+      ++m;
+    }
+  }
+  *n_done = m;
+  return YEE_OK;
+}
+
+yee_status yee_batch_release(yee_batch* b, int32_t slot) {
+  if (!b || slot < 0 || slot >= b->max_slots) return fail(YEE_EINVAL, "bad slot");
+  auto& sl = b->slots[slot];
+  if (!sl.used) return fail(YEE_ESTATE, "slot %d is free", slot);
+  b->in_use -= sl.bytes;
+  sl = yee_batch::Slot{};
+  return YEE_OK;
+}
+
+yee_status yee_batch_info(const yee_batch* b, int32_t* active, int64_t* bytes_in_use) {
+  if (!b || !active || !bytes_in_use) return fail(YEE_EINVAL, "NULL argument");
+  int32_t a = 0;
+  for (const auto& sl : b->slots) a += sl.used ? 1 : 0;
+  *active = a;
+  *bytes_in_use = b->in_use;
   return YEE_OK;
 }
 

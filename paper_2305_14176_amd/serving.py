@@ -1,0 +1,155 @@
+"""Continuous-batching request loop over the batched Yee stepper.
+
+Requests (one workload each) arrive over time.  Between replays of the
+batched stepper (``steps_per_replay`` leapfrog steps of every admitted grid,
+replayed from a HIP graph) the server
+  * retires finished requests (results copied to the host),
+  * admits waiting requests that have arrived, as long as a slot is free and
+    the sum of admitted workspace footprints stays within the HBM budget.
+Field state stays resident on the device for the life of a request.  The
+plain alternative, :func:`serve_one_at_a_time`, solves requests first come
+first served with one ``yee_step`` call each.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import _lib
+from .solver import YeeSolver
+from .workloads import Workload
+
+
+@dataclass
+class Request:
+    wl: Workload
+    arrival: float = 0.0                      # seconds after the start of the run
+    rid: int = 0
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    series: Optional[np.ndarray] = None
+    dft: Optional[np.ndarray] = None
+    fields: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class BatchServer:
+    def __init__(self, max_slots: int = 32, hbm_budget: int = 4 << 30, steps_per_replay: int = 64,
+                 device: str = "cuda:0", keep_fields=()):
+        import torch
+        self.torch = torch
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.K = int(steps_per_replay)
+        self.keep_fields = tuple(keep_fields)
+        b = C.c_void_p()
+        _lib.check(self.lib.yee_batch_create(int(max_slots), int(hbm_budget), self.K, C.byref(b)), "yee_batch_create")
+        self.batch = b
+        nb = C.c_int64()
+        _lib.check(self.lib.yee_batch_footprint(int(max_slots), C.byref(nb)), "yee_batch_footprint")
+        self.table = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = (self.table.data_ptr() + 255) & ~255
+        _lib.check(self.lib.yee_batch_bind_workspace(b, C.c_void_p(base), nb.value), "yee_batch_bind_workspace")
+        self.max_slots = int(max_slots)
+        self.replays = 0
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _collect(self, req: Request, solver: YeeSolver, t0: float):
+        if req.wl.probes:
+            req.series = solver.series(solver.steps_done - req.wl.steps + 1, req.wl.steps) \
+                if req.wl.steps <= solver.desc.series_len else None
+            req.dft = solver.dft()
+        for c in self.keep_fields:
+            req.fields[c] = solver.field(c)
+        req.finished = time.perf_counter() - t0
+
+    def serve(self, requests: List[Request], t0: Optional[float] = None) -> List[Request]:
+        """Serve requests with the given arrival offsets (seconds from t0)."""
+        lib = self.lib
+        t0 = time.perf_counter() if t0 is None else t0
+        waiting = sorted(requests, key=lambda r: r.arrival)
+        running = {}                      # slot -> (request, solver)
+        done: List[Request] = []
+        while waiting or running:
+            now = time.perf_counter() - t0
+            # admit arrived requests while slots and budget allow
+            while waiting and waiting[0].arrival <= now:
+                req = waiting[0]
+                solver = YeeSolver(req.wl, device=str(self.device),
+                                   series_len=max(self.K, req.wl.steps if req.wl.probes else 1))
+                slot = C.c_int32()
+                st = lib.yee_batch_admit(self.batch, solver.ctx, int(req.wl.steps), C.byref(slot))
+                if st == -6:              # YEE_EAGAIN: wait for a slot or for memory
+                    solver.close()
+                    if not running:
+                        raise RuntimeError(f"request {req.rid} ({req.wl.name}) does not fit the batch's "
+                                           f"HBM budget even with nothing else admitted")
+                    break
+                _lib.check(st, "yee_batch_admit")
+                req.admitted = time.perf_counter() - t0
+                running[slot.value] = (req, solver)
+                waiting.pop(0)
+            if not running:
+                # nothing to run: wait for the next arrival
+                time.sleep(max(0.0, min(0.001, waiting[0].arrival - now)))
+                continue
+            _lib.check(lib.yee_batch_run(self.batch, self._stream()), "yee_batch_run")
+            self.replays += 1
+            ndone = C.c_int32()
+            buf = (C.c_int32 * self.max_slots)()
+            _lib.check(lib.yee_batch_poll(self.batch, buf, self.max_slots, C.byref(ndone)), "yee_batch_poll")
+            if ndone.value:
+                self.torch.cuda.current_stream(self.device).synchronize()
+            for q in range(ndone.value):
+                slot = buf[q]
+                req, solver = running.pop(slot)
+                self._collect(req, solver, t0)
+                _lib.check(lib.yee_batch_release(self.batch, slot), "yee_batch_release")
+                solver.close()
+                done.append(req)
+        return done
+
+    def close(self):
+        if getattr(self, "batch", None):
+            self.lib.yee_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_one_at_a_time(requests: List[Request], device: str = "cuda:0", keep_fields=(),
+                        t0: Optional[float] = None) -> List[Request]:
+    """First come, first served: one plain ``yee_step`` solve per request."""
+    import torch
+    t0 = time.perf_counter() if t0 is None else t0
+    out = []
+    for req in sorted(requests, key=lambda r: r.arrival):
+        now = time.perf_counter() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        req.admitted = time.perf_counter() - t0
+        solver = YeeSolver(req.wl, device=device, series_len=max(1, req.wl.steps))
+        solver.step(req.wl.steps)
+        torch.cuda.current_stream().synchronize()
+        if req.wl.probes:
+            req.series = solver.series(1, req.wl.steps)
+            req.dft = solver.dft()
+        for c in keep_fields:
+            req.fields[c] = solver.field(c)
+        req.finished = time.perf_counter() - t0
+        solver.close()
+        out.append(req)
+    return out

@@ -1,0 +1,117 @@
+"""GPU tests of the batched stepper and the continuous-batching loop.
+
+A request's results must be the same whether it runs alone (plain
+``yee_step``) or in a batch next to other requests of other sizes, admitted
+and retired while it runs: the batched launch computes the same per-cell
+operation, so fields and probe series are compared bitwise.  The FP64
+running DFT is folded once per replay in the batch and once per call alone,
+so its summation order differs: it is compared to 1e-13 relative.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_14176_amd import workloads as W
+from _helpers import oracle_from_workload, rel_l2, stored
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _requests(specs):
+    from paper_2305_14176_amd.serving import Request
+    out = []
+    for rid, (side, steps, seed, arrival) in enumerate(specs):
+        out.append(Request(W.serving_request(seed, side=side, steps=steps), arrival=arrival, rid=rid))
+    return out
+
+
+SPECS = [(32, 70, 101, 0.0), (48, 45, 102, 0.0), (96, 90, 103, 0.0), (64, 33, 104, 0.0),
+         (160, 40, 105, 0.0), (128, 52, 106, 0.0), (32, 17, 107, 0.0)]
+
+
+def test_batched_results_equal_alone():
+    import torch
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    assert torch.cuda.is_available()
+    keep = ("Ez", "Hx", "Ey")
+    _say("[gpu] serving: alone")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(SPECS), keep_fields=keep)}
+    # three slots and a budget of about two large grids (160^3 needs 216 MiB, 128^3
+    # 114 MiB) force queueing and admissions mid-run
+    _say("[gpu] serving: batched")
+    srv = BatchServer(max_slots=3, hbm_budget=360 << 20, steps_per_replay=16, keep_fields=keep)
+    mixed = {r.rid: r for r in srv.serve(_requests(SPECS))}
+    assert srv.replays > 3
+    assert sorted(mixed) == sorted(alone)
+    for rid in alone:
+        a, b = alone[rid], mixed[rid]
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13, (rid, rel_l2(b.dft, a.dft))
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+    srv.close()
+
+
+def test_batched_request_matches_oracle():
+    from paper_2305_14176_amd.serving import BatchServer
+    reqs = _requests([(48, 60, 201, 0.0), (32, 25, 202, 0.0)])
+    srv = BatchServer(max_slots=4, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=("Ez",))
+    done = {r.rid: r for r in srv.serve(reqs)}
+    for rid, req in done.items():
+        sim = oracle_from_workload(req.wl)
+        sim.run(req.wl.steps)
+        ref = sim.series_array()
+        for p in range(len(req.wl.probes)):
+            assert rel_l2(req.series[:, p], ref[:, p]) <= 1e-5
+            assert rel_l2(req.dft[p], sim.dft[p]) <= 1e-5
+        assert rel_l2(req.fields["Ez"], stored(sim, "Ez")) <= 1e-5
+    srv.close()
+
+
+def test_admission_by_budget_and_slots():
+    import torch
+    from paper_2305_14176_amd import _lib
+    from paper_2305_14176_amd.solver import YeeSolver
+    lib = _lib.load()
+    small = YeeSolver(W.serving_request(1, side=32, steps=10), series_len=16)
+    big = YeeSolver(W.serving_request(2, side=96, steps=10), series_len=16)
+    other = YeeSolver(W.serving_request(3, side=32, steps=10), series_len=16)
+    b = C.c_void_p()
+    assert lib.yee_batch_create(2, small.footprint + other.footprint + 4096, 8, C.byref(b)) == 0
+    nb = C.c_int64()
+    lib.yee_batch_footprint(2, C.byref(nb))
+    t = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    assert lib.yee_batch_bind_workspace(b, C.c_void_p((t.data_ptr() + 255) & ~255), nb.value) == 0
+    slot = C.c_int32()
+    assert lib.yee_batch_admit(b, big.ctx, 10, C.byref(slot)) == -6        # over budget: EAGAIN
+    assert lib.yee_batch_admit(b, small.ctx, 10, C.byref(slot)) == 0
+    s0 = slot.value
+    assert lib.yee_batch_admit(b, small.ctx, 10, C.byref(slot)) == -1      # already admitted
+    assert lib.yee_batch_admit(b, other.ctx, 10, C.byref(slot)) == 0
+    third = YeeSolver(W.serving_request(4, side=32, steps=10), series_len=16)
+    assert lib.yee_batch_admit(b, third.ctx, 10, C.byref(slot)) == -6      # no free slot
+    act, used = C.c_int32(), C.c_int64()
+    lib.yee_batch_info(b, C.byref(act), C.byref(used))
+    assert act.value == 2 and used.value == small.footprint + other.footprint
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.yee_batch_run(b, stream) == 0          # 8 of 10 steps
+    n = C.c_int32()
+    buf = (C.c_int32 * 2)()
+    lib.yee_batch_poll(b, buf, 2, C.byref(n))
+    assert n.value == 0 and small.steps_done == 8
+    assert lib.yee_batch_run(b, stream) == 0          # the remaining 2 steps
+    lib.yee_batch_poll(b, buf, 2, C.byref(n))
+    assert n.value == 2 and small.steps_done == 10 and other.steps_done == 10
+    assert lib.yee_batch_release(b, s0) == 0
+    assert lib.yee_batch_release(b, s0) == -4
+    assert lib.yee_batch_admit(b, third.ctx, 10, C.byref(slot)) == 0
+    lib.yee_batch_destroy(b)
+    for s in (small, big, other, third):
+        s.close()
