@@ -76,6 +76,64 @@ def cpu_baseline(wl, budget_s=15.0, max_steps=5):
                       f"(numpy FP64, single-threaded elementwise), {dt:.1f} s"}
 
 
+def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=32, max_slots=32,
+                      hbm_budget=4 << 30, sample=16):
+    """Serving sweep: Poisson arrivals at `load` x the plain one-at-a-time capacity.
+
+    Requests follow the serving workload (cubic sides from {32, 48, 64, 96, 128,
+    160}, 500-3000 steps, CPML 8, FP32, seeded).  The plain capacity C (requests/s)
+    is measured on the first `sample` requests served back to back; arrivals then
+    come at rate load * C.  Both the plain first-come-first-served loop and the
+    batched server see the same arrival times.
+    """
+    import numpy as np
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.serving import BatchServer, Request, serve_one_at_a_time
+
+    gaps, wls = W.serving_sweep(n_requests, seed=seed)
+    cells = [w.cells * w.steps for w in wls]
+
+    def make(arrivals):
+        return [Request(w, arrival=float(t), rid=i) for i, (w, t) in enumerate(zip(wls, arrivals))]
+
+    # closed-loop capacities on the first `sample` requests (all present at t = 0)
+    t0 = time.perf_counter()
+    serve_one_at_a_time(make(np.zeros(n_requests))[:sample])
+    cap = sample / (time.perf_counter() - t0)
+    srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay)
+    t0 = time.perf_counter()
+    srv.serve(make(np.zeros(n_requests))[:sample])
+    cap_b = sample / (time.perf_counter() - t0)
+    srv.close()
+    # open loop: the same Poisson arrivals for both, at each load
+    runs = {}
+    for load in loads:
+        arrivals = np.asarray(gaps) / (load * cap)
+        plain = serve_one_at_a_time(make(arrivals))
+        srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay)
+        batched = srv.serve(make(arrivals))
+        srv.close()
+        runs[load] = (plain, batched, srv.replays)
+
+    def stats(done):
+        lat = np.array([r.latency for r in done])
+        makespan = max(r.finished for r in done)
+        return {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                "mean_latency_s": round(float(lat.mean()), 4),
+                "makespan_s": round(float(makespan), 3),
+                "mcell_updates_per_s": round(sum(cells) / makespan / 1e6, 1)}
+
+    out = {"requests": n_requests, "plain_capacity_req_per_s": round(cap, 3),
+           "batched_capacity_req_per_s": round(cap_b, 3),
+           "steps_per_replay": steps_per_replay, "max_slots": max_slots, "hbm_budget_bytes": hbm_budget,
+           "workload": "serving_request: side in {32,48,64,96,128,160}, 500-3000 steps, CPML 8, FP32"}
+    for load, (plain, batched, replays) in runs.items():
+        out[f"load_{load}"] = {"arrival_rate_req_per_s": round(load * cap, 3), "batched": stats(batched),
+                               "plain_fifo": stats(plain), "replays": replays}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +143,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk-planes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
+    ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: a few untimed steps, then a plain device copy of "
                          "COPY_MIB MiB (the known-size kernel the HBM counters are scaled by)")
@@ -137,7 +197,7 @@ def main():
     traffic = load_traffic()
 
     out = {
-        "metric": "Mcell-updates/s (FP32 Yee step, 256^3, CPML 10)",
+        "metric": "Mcell-updates/s (FP32 Yee step, 256^3, CPML 10); serving p50/p99 in 'serving'",
         "value": round(value, 1),
         "unit": "Mcell-updates/s",
         "n_gpus": 1,
@@ -163,6 +223,11 @@ def main():
                      "kernel_ms_avg": round(ms_per_step, 5)},
         "wall_s_timed": round(t_wall, 4),
     }
+    if not args.no_serving:
+        del solver
+        torch.cuda.empty_cache()
+        out["serving"] = serving_benchmark(n_requests=args.serving_requests)
+        solver = None
     if not args.no_cpu_baseline:
         del solver
         torch.cuda.empty_cache()
