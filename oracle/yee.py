@@ -356,6 +356,9 @@ class Simulation:
         Ez_new[s] = self.Ca["Ez"][s] * Ez[s] + self.Cb["Ez"][s] * rz
 
         # ---- soft sources at t = (n+1) dt ----
+        # the bracketed curl terms of this E update (interior samples), kept for
+        # the adjoint's gradient: E^{n+1} = Ca E^n + Cb R^n
+        self.last_r = {"Ex": rx, "Ey": ry, "Ez": rz}
         new = {"Ex": Ex_new, "Ey": Ey_new, "Ez": Ez_new}
         t = (self.n + 1) * dt
         for src in self.sources:
