@@ -2,7 +2,9 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-Objective: J = sum over steps n = 1..N and probe samples p of (Ez^n[p])^2.
+Objective: J = sum over steps n = 1..N and probe samples p of (F_p^n)^2, where
+F_p^n is the probed component (any of Ex..Hz; a bare (i, j, k) means Ez) in
+the state after step n (E^n and H^{n-1/2}).
 Gradient: dJ/d eps_r for every cell, with eps_r entering through the lossy
 update coefficients Ca, Cb of the cell's three E samples (index-aligned
 staircase).  The paper defines no solver and no adjoint; this is reverse-mode
@@ -12,8 +14,8 @@ transpose of each sub-map of one step, applied in reverse order:
   forward step n:  (1) psi_H <- b psi_H + a D E        (2) H <- H - (dt/mu0)(K C_e E + S psi_H)
                    (3) psi_E <- b psi_E + a D H        (4) E <- Ca E + Cb (K C_h H + S psi_E)
                    (5) E <- E + source (state independent)
-                   (6) J <- J + sum_p Ez[p]^2
-  reverse step n:  (6^T) Ez_bar[p] += 2 Ez^{n+1}[p]
+                   (6) J <- J + sum_p F[p]^2
+  reverse step n:  (6^T) F_bar[p] += 2 F[p] (E^{n+1} or H^{n+1/2})
                    (4^T) R_bar = Cb E_bar; psi_E_bar += S^T R_bar; H_bar += C_h^T (K R_bar) + D^T (a psi_E_bar);
                          grad += E_bar (dCa/deps E^n + dCb/deps R^n); E_bar <- Ca E_bar; psi_E_bar <- b psi_E_bar
                    (2^T, 1^T) psi_H_bar += -(dt/mu0) S^T H_bar; E_bar += C_e^T(-(dt/mu0) K H_bar) + D^T (a psi_H_bar);
@@ -29,6 +31,21 @@ from typing import Callable, List, Sequence, Tuple
 import numpy as np
 
 from .yee import EPS0, MU0, Simulation
+
+COMPONENTS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+
+def _probe_list(probes):
+    """(comp, i, j, k) tuples with comp in 0..5; a 3-tuple (i, j, k) is an Ez probe."""
+    out = []
+    for p in probes:
+        out.append((2,) + tuple(p) if len(p) == 3 else tuple(p))
+    return out
+
+
+def _probe_value(E, H, p):
+    c, i, j, k = p
+    return float((E if c < 3 else H)[COMPONENTS[c]][i, j, k])
 
 
 def coefficient_derivatives(eps_r, sigma, dt):
@@ -60,7 +77,7 @@ class Adjoint:
 
     def __init__(self, sim: Simulation, probes: Sequence[Tuple[int, int, int]]):
         self.sim = sim
-        self.probes = list(probes)
+        self.probes = _probe_list(probes)
         self.aE = {c: np.zeros_like(v) for c, v in sim.E.items()}
         self.aH = {c: np.zeros_like(v) for c, v in sim.H.items()}
         self.ap = {c: np.zeros_like(v) for c, v in sim.psi.items()}
@@ -77,8 +94,11 @@ class Adjoint:
             self.dCa[c] = np.where(live, dca[np.ix_(ii, jj, kk)], 0.0)
             self.dCb[c] = np.where(live, dcb[np.ix_(ii, jj, kk)], 0.0)
 
-    def reverse_step(self, E_n, R_n, E_np1, objective=True, gradient=True):
-        """Map the adjoint of the state after a step to the adjoint before it."""
+    def reverse_step(self, E_n, R_n, E_np1, H_np1=None, objective=True, gradient=True):
+        """Map the adjoint of the state after a step to the adjoint before it.
+
+        E_n: E before the step; R_n: its bracketed curl terms; E_np1, H_np1: the
+        state after the step (H_np1 is needed only for H probes)."""
         sim = self.sim
         aE, aH, ap = self.aE, self.aH, self.ap
         nx, ny, nz = sim.nx, sim.ny, sim.nz
@@ -91,10 +111,12 @@ class Adjoint:
         bhy, ahy, khy = sim.ph["y"]
         bhz, ahz, khz = sim.ph["z"]
 
-        # (6^T) objective: d/dEz^{n+1} of sum_p Ez^{n+1}[p]^2
+        # (6^T) objective: d/dF of sum_p F[p]^2 on the state after the step
         if objective:
-            for (i, j, k) in self.probes:
-                aE["Ez"][i, j, k] += 2.0 * E_np1["Ez"][i, j, k]
+            for p in self.probes:
+                c, i, j, k = p
+                tgt = aE if c < 3 else aH
+                tgt[COMPONENTS[c]][i, j, k] += 2.0 * _probe_value(E_np1, H_np1, p)
 
         # (4^T, 3^T) E update, per component, on its interior samples
         def e_transpose(c, s, cells, terms):
@@ -154,18 +176,20 @@ class Adjoint:
 
 
 def objective(make_sim: Callable[[], Simulation], nsteps: int, probes) -> float:
-    """J = sum_{n=1}^{N} sum_p (Ez^n[p])^2 of a fresh simulation."""
+    """J = sum_{n=1}^{N} sum_p (F_p^n)^2 of a fresh simulation."""
+    probes = _probe_list(probes)
     sim = make_sim()
     j = 0.0
     for _ in range(nsteps):
         sim.step()
-        for (i, jj, k) in probes:
-            j += float(sim.E["Ez"][i, jj, k]) ** 2
+        for p in probes:
+            j += _probe_value(sim.E, sim.H, p) ** 2
     return j
 
 
 def gradient(make_sim: Callable[[], Simulation], nsteps: int, probes, checkpoint_every: int = 64):
     """(J, dJ/d eps_r per cell) by the discrete adjoint with checkpoint-recompute."""
+    probes = _probe_list(probes)
     sim = make_sim()
     ckpts: List = []
     j = 0.0
@@ -173,18 +197,19 @@ def gradient(make_sim: Callable[[], Simulation], nsteps: int, probes, checkpoint
         if n % checkpoint_every == 0:
             ckpts.append(_state(sim))
         sim.step()
-        for (i, jj, k) in probes:
-            j += float(sim.E["Ez"][i, jj, k]) ** 2
+        for p in probes:
+            j += _probe_value(sim.E, sim.H, p) ** 2
     adj = Adjoint(sim, probes)
     for seg in reversed(range(len(ckpts))):
         n0 = seg * checkpoint_every
         n1 = min(nsteps, n0 + checkpoint_every)
         _restore(sim, ckpts[seg])
-        hist_e, hist_r = [copy.deepcopy(sim.E)], []
+        hist_e, hist_h, hist_r = [copy.deepcopy(sim.E)], [None], []
         for _ in range(n0, n1):
             sim.step()
             hist_e.append(copy.deepcopy(sim.E))
+            hist_h.append(copy.deepcopy(sim.H))
             hist_r.append(copy.deepcopy(sim.last_r))
         for m in reversed(range(n1 - n0)):
-            adj.reverse_step(hist_e[m], hist_r[m], hist_e[m + 1])
+            adj.reverse_step(hist_e[m], hist_r[m], hist_e[m + 1], hist_h[m + 1])
     return j, adj.grad

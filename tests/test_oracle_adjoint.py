@@ -4,7 +4,8 @@
   states x and adjoints l, <l, L x> = <L^T l, x> (L = one source-free step,
   CPML with kappa and alpha, lossy materials and a PEC plane included).
 * The gradient equals central finite differences of the objective (FP64,
-  h = 1e-3 on eps_r), on cells inside, at the edge of and outside the CPML.
+  h = 1e-3 on eps_r), on cells inside, at the edge of and outside the CPML,
+  for Ez probes and for probes of every E and H component.
 * The coefficient derivatives match finite differences of Ca, Cb.
 """
 import numpy as np
@@ -86,10 +87,16 @@ def test_reverse_step_is_transpose_of_forward_step():
     assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs)
 
 
-@pytest.mark.parametrize("ckpt", [64, 7])
-def test_gradient_matches_central_differences(ckpt):
+@pytest.mark.parametrize("ckpt,probes", [
+    (64, [(6, 5, 4), (2, 6, 2)]),
+    (7, [(6, 5, 4), (2, 6, 2)]),
+    # Ex and Ey probes, one sample probed twice
+    (16, [(0, 5, 4, 3), (1, 4, 4, 4), (1, 4, 4, 4)]),
+    # H probes only (H is ~1/377 of E: mixed with E probes its terms would vanish in J)
+    (16, [(4, 3, 5, 2), (5, 6, 2, 4), (3, 2, 3, 5), (3, 2, 3, 5)]),
+])
+def test_gradient_matches_central_differences(ckpt, probes):
     eps, sig = _materials(3)
-    probes = [(6, 5, 4), (2, 6, 2)]
     nsteps = 45
 
     def make(e):
