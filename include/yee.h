@@ -225,6 +225,55 @@ yee_status yee_batch_poll(yee_batch* batch, int32_t* done, int32_t cap, int32_t*
 yee_status yee_batch_release(yee_batch* batch, int32_t slot);
 yee_status yee_batch_info(const yee_batch* batch, int32_t* active_slots, int64_t* bytes_in_use);
 
+/* ------------------------------------------------------------------------
+ * Discrete adjoint: gradient of a probe objective with respect to eps_r.
+ *
+ * Objective  J = sum_{n=1}^{N} sum_p y_p[n]^2  over every probe of the
+ * context (y_p[n] as recorded by yee_add_probe; a sample probed twice counts
+ * twice).  Gradient  g(i, j, k) = dJ / d eps_r(i, j, k)  for each cell of a box
+ * [i0, i1) x [j0, j1) x [k0, k1), where eps_r of a cell enters only through
+ * Ca and Cb of the cell's three E samples (the materials formula of
+ * yee_set_materials; E samples on the outer faces or under a PEC mask do not
+ * depend on it).  The gradient is the exact derivative of the discrete update
+ * (reverse-mode: the transposed step applied backward in time, Giles & Pierce
+ * 2000 on discrete adjoints; CPML recursions included), not of the continuous
+ * equations.  The paper defines no solver and no adjoint.
+ *
+ * Schedule: yee_adjoint_forward() runs the N steps from step 0, storing
+ * (E, H, psi) every checkpoint_every steps and the probe samples of every step;
+ * yee_adjoint_backward() walks the segments newest first, restores each
+ * checkpoint, recomputes its steps (storing E of the box cells) and runs the
+ * reverse steps.  Adjoint fields use the context's compute precision; the
+ * gradient is accumulated in FP64.  Contexts must be YEE_F64 or YEE_F32.
+ *
+ * The caller owns the adjoint's device workspace (yee_adjoint_footprint()
+ * bytes, 256-byte aligned): (N/K + 1) checkpoints of the context state,
+ * K + 1 copies of E over the box, 12 adjoint arrays of the grid's size and
+ * N x n_probes doubles.
+ * ------------------------------------------------------------------------ */
+typedef struct yee_adjoint yee_adjoint;
+
+/* box = {i0, i1, j0, j1, k0, k1} with 0 <= lo < hi <= n per axis.  The context
+ * must be bound; its probes and grid fix the workspace size. */
+yee_status yee_adjoint_create(yee_ctx* ctx, int64_t n_steps, int32_t checkpoint_every,
+                              const int32_t* box, yee_adjoint** out);
+void yee_adjoint_destroy(yee_adjoint* adj);
+yee_status yee_adjoint_footprint(const yee_adjoint* adj, int64_t* bytes);
+yee_status yee_adjoint_bind_workspace(yee_adjoint* adj, void* device_ptr, int64_t bytes);
+
+/* Forward run of n_steps from the context's state at step 0 (after
+ * yee_reset() and optional yee_set_field(); materials uploaded and unchanged
+ * until the backward run ends).  Leaves the context exactly as yee_step()
+ * would (fields, probe ring, DFT) and writes J to *objective (host).
+ * Synchronizes the stream.  YEE_ESTATE if the context is not at step 0. */
+yee_status yee_adjoint_forward(yee_adjoint* adj, double* objective, void* stream);
+
+/* Gradient of the last forward run into grad (device pointer, FP64,
+ * [k1-k0][j1-j0][i1-i0], i fastest; overwritten).  Asynchronous on `stream`;
+ * the context returns to its state after the forward run.  YEE_ESTATE if no
+ * forward run was recorded or the context was stepped since. */
+yee_status yee_adjoint_backward(yee_adjoint* adj, double* grad, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyee.so")
 
 SOURCES = ["yee_runtime.hip"]
-HEADERS = ["yee_kernels.hpp", os.path.join("..", "..", "include", "yee.h")]
+HEADERS = ["yee_kernels.hpp", "yee_adjoint.hpp", os.path.join("..", "..", "include", "yee.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

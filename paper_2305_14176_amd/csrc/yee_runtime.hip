@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/yee.h"
+#include "yee_adjoint.hpp"
 #include "yee_kernels.hpp"
 
 namespace {
@@ -241,8 +242,10 @@ size_t step_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
 
 // Kernel arguments of one step of context c at its current step count, for a
 // launch shape (V samples per lane, ty rows per tile, kz planes per chunk).
+// record = false: the step writes no probe samples (recomputation of steps
+// already recorded).
 template <class T, class C>
-yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz) {
+yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool record = true) {
   using namespace yee;
   const auto& d = c->d;
   StepArgs<T, C> a{};
@@ -265,7 +268,7 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz) {
   a.rowflag = reinterpret_cast<const uint8_t*>(c->ws + c->rowflag.off);
   a.probe = reinterpret_cast<const int4*>(c->ws + c->prober.off);
   a.series = reinterpret_cast<double*>(c->ws + c->series.off);
-  a.nprobe = (int32_t)c->probes.size();
+  a.nprobe = record ? (int32_t)c->probes.size() : 0;
   a.series_slot = (int32_t)(c->n % d.series_len);
   a.src = reinterpret_cast<const SrcDev*>(c->ws + c->srcr.off);
   a.nsrc = (int32_t)c->src.size();
@@ -291,9 +294,9 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz) {
 }
 
 template <class T, class C, int V>
-yee_status launch_step(yee_ctx* c, hipStream_t s) {
+yee_status launch_step(yee_ctx* c, hipStream_t s, bool record) {
   using namespace yee;
-  const StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz);
+  const StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz, record);
   const int grid = ((a.ntiles + 7) / 8) * 8;
   const int waves = (c->ty + 1) * a.wpr;
   if (waves > max_block_waves(V))
@@ -306,19 +309,19 @@ yee_status launch_step(yee_ctx* c, hipStream_t s) {
 }
 
 template <class T, class C>
-yee_status launch_step_v(yee_ctx* c, hipStream_t s) {
+yee_status launch_step_v(yee_ctx* c, hipStream_t s, bool record) {
   switch (c->V) {
-    case 1: return launch_step<T, C, 1>(c, s);
-    case 2: return launch_step<T, C, 2>(c, s);
-    default: return launch_step<T, C, 4>(c, s);
+    case 1: return launch_step<T, C, 1>(c, s, record);
+    case 2: return launch_step<T, C, 2>(c, s, record);
+    default: return launch_step<T, C, 4>(c, s, record);
   }
 }
 
-yee_status launch_one_step(yee_ctx* c, hipStream_t s) {
+yee_status launch_one_step(yee_ctx* c, hipStream_t s, bool record = true) {
   switch (c->d.precision) {
-    case YEE_F64: return launch_step_v<double, double>(c, s);
-    case YEE_F32: return launch_step_v<float, float>(c, s);
-    default: return launch_step_v<_Float16, float>(c, s);
+    case YEE_F64: return launch_step_v<double, double>(c, s, record);
+    case YEE_F32: return launch_step_v<float, float>(c, s, record);
+    default: return launch_step_v<_Float16, float>(c, s, record);
   }
 }
 
@@ -907,6 +910,362 @@ yee_status yee_batch_info(const yee_batch* b, int32_t* active, int64_t* bytes_in
   *active = a;
   *bytes_in_use = b->in_use;
   return YEE_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Discrete adjoint (reverse-mode derivative of J = sum_n sum_p y_p[n]^2 with
+// respect to eps_r of the cells of a box), with checkpoint-recompute.
+// ===========================================================================
+struct yee_adjoint {
+  yee_ctx* c = nullptr;
+  int64_t N = 0;          // steps of the forward run
+  int32_t K = 0;          // steps between checkpoints
+  int32_t S = 0;          // segments: ceil(N / K)
+  int32_t box[6] = {};    // i0, i1, j0, j1, k0, k1
+  int32_t bx = 0, by = 0, bz = 0;
+  size_t nbox = 0;
+  bool bound = false;
+  unsigned char* ws = nullptr;
+  int64_t ws_bytes = 0;
+  Region ckpt, hist, u, hb, pe[2], ph[2], phist, jout, dcoef, inj;
+  size_t ckpt_bytes = 0;  // one checkpoint: fields | psi_E | psi_H
+  size_t ucomp = 0;       // bytes of one adjoint component array
+  int32_t hist_seg = -1;  // segment whose E history the workspace holds
+  bool have_forward = false;
+  std::vector<yee::InjDev> inj_host;
+  std::vector<double> dcoef_host;
+};
+
+namespace {
+
+void adj_layout(yee_adjoint* A) {
+  const yee_ctx* c = A->c;
+  const auto& d = c->d;
+  size_t off = 0;
+  auto take = [&](Region& r, size_t bytes) {
+    r.off = off;
+    r.bytes = bytes;
+    off += align256(std::max<size_t>(bytes, 1));
+  };
+  A->ckpt_bytes = align256(6 * c->comp_bytes) + 2 * align256(c->psi_e.bytes);
+  take(A->ckpt, (size_t)(A->S + 1) * A->ckpt_bytes);
+  take(A->hist, (size_t)(A->K + 1) * 3 * A->nbox * c->tsize);
+  A->ucomp = align256((size_t)d.nz * d.ny * c->px * c->csize);
+  take(A->u, 3 * A->ucomp);
+  take(A->hb, 3 * A->ucomp);
+  for (int q = 0; q < 2; ++q) take(A->pe[q], c->psi_e.bytes);
+  for (int q = 0; q < 2; ++q) take(A->ph[q], c->psi_e.bytes);
+  take(A->phist, (size_t)A->N * c->probes.size() * sizeof(double));
+  take(A->jout, sizeof(double));
+  take(A->dcoef, (size_t)c->nsx * c->nsy * c->nsz * 2 * sizeof(double));
+  take(A->inj, c->probes.size() * sizeof(yee::InjDev));
+  A->ws_bytes = (int64_t)off;
+}
+
+yee_status adj_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+  return YEE_OK;
+}
+
+// Checkpoint slot q <-> the context's current state (fields, psi_E, psi_H).
+yee_status adj_checkpoint(yee_adjoint* A, int q, bool save, hipStream_t s) {
+  yee_ctx* c = A->c;
+  const int cur = (int)(c->n & 1);
+  unsigned char* slot = A->ws + A->ckpt.off + (size_t)q * A->ckpt_bytes;
+  unsigned char* parts[3] = {slot, slot + align256(6 * c->comp_bytes),
+                             slot + align256(6 * c->comp_bytes) + align256(c->psi_e.bytes)};
+  unsigned char* live[3] = {c->ws + c->fields[cur].off, c->ws + c->psi_e.off, c->ws + c->psi_h[cur].off};
+  const size_t bytes[3] = {6 * c->comp_bytes, c->psi_e.bytes, c->psi_e.bytes};
+  for (int p = 0; p < 3; ++p) {
+    yee_status st = save ? adj_copy(parts[p], live[p], bytes[p], s) : adj_copy(live[p], parts[p], bytes[p], s);
+    if (st) return st;
+  }
+  return YEE_OK;
+}
+
+// E of the box cells at the current step into history slot m.
+yee_status adj_store(yee_adjoint* A, int m, hipStream_t s) {
+  yee_ctx* c = A->c;
+  const int cur = (int)(c->n & 1);
+  const int4 lo = {A->box[0], A->box[2], A->box[4], 0};
+  const dim3 grid((A->bx + yee::kAdjBX - 1) / yee::kAdjBX, (A->by + yee::kAdjBY - 1) / yee::kAdjBY, A->bz);
+  const dim3 block(yee::kAdjBX, yee::kAdjBY);
+  const uint64_t hs = A->nbox;
+  if (c->d.precision == YEE_F64) {
+    const double* f = reinterpret_cast<const double*>(c->ws + c->fields[cur].off);
+    double* slot = reinterpret_cast<double*>(A->ws + A->hist.off) + (size_t)m * 3 * hs;
+    hipLaunchKernelGGL(yee::adj_store_kernel<double>, grid, block, 0, s, f, (uint64_t)(c->comp_bytes / 8),
+                       c->d.ny, c->px, lo, A->bx, A->by, slot, hs);
+  } else {
+    const float* f = reinterpret_cast<const float*>(c->ws + c->fields[cur].off);
+    float* slot = reinterpret_cast<float*>(A->ws + A->hist.off) + (size_t)m * 3 * hs;
+    hipLaunchKernelGGL(yee::adj_store_kernel<float>, grid, block, 0, s, f, (uint64_t)(c->comp_bytes / 4),
+                       c->d.ny, c->px, lo, A->bx, A->by, slot, hs);
+  }
+  HIP_TRY(hipGetLastError());
+  return YEE_OK;
+}
+
+// Probe samples of steps s0+1 .. s0+count from the ring into the full history.
+yee_status adj_gather(yee_adjoint* A, int64_t s0, int64_t count, hipStream_t s) {
+  yee_ctx* c = A->c;
+  const int np = (int)c->probes.size();
+  if (np == 0 || count <= 0) return YEE_OK;
+  const int total = (int)(count * np);
+  hipLaunchKernelGGL(yee::adj_gather_kernel, dim3((total + 255) / 256), dim3(256), 0, s,
+                     reinterpret_cast<const double*>(c->ws + c->series.off), np, c->d.series_len, s0, (int)count,
+                     reinterpret_cast<double*>(A->ws + A->phist.off));
+  HIP_TRY(hipGetLastError());
+  return YEE_OK;
+}
+
+template <class T, class C>
+yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int m, int pin, int pout, bool e_side) {
+  using namespace yee;
+  yee_ctx* c = A->c;
+  const auto& d = c->d;
+  AdjArgs<T, C> a{};
+  a.u = reinterpret_cast<C*>(A->ws + A->u.off);
+  a.hb = reinterpret_cast<C*>(A->ws + A->hb.off);
+  a.ustride = A->ucomp / sizeof(C);
+  const Region* pr = e_side ? A->ph : A->pe;
+  a.pin = reinterpret_cast<const C*>(A->ws + pr[pin].off);
+  a.pout = reinterpret_cast<C*>(A->ws + pr[pout].off);
+  for (int q = 0; q < 6; ++q) a.psoff[q] = c->psi_off[q];
+  a.prof = reinterpret_cast<const C*>(c->ws + c->prof.off);
+  a.plen = (int32_t)c->prof_len;
+  a.seg = reinterpret_cast<const int32_t*>(c->ws + c->segr.off);
+  a.coef = reinterpret_cast<const Coef2<C>*>(c->ws + c->coef.off);
+  a.dcoef = reinterpret_cast<const double2*>(A->ws + A->dcoef.off);
+  a.nsx = c->nsx;
+  a.nsxy = c->nsx * c->nsy;
+  a.pec_plane = reinterpret_cast<const int32_t*>(c->ws + c->pecplane.off);
+  a.pec_mask = reinterpret_cast<const uint8_t*>(c->ws + c->pecmask.off);
+  const T* h0 = reinterpret_cast<const T*>(A->ws + A->hist.off);
+  a.hstride = A->nbox;
+  a.hist_n = h0 + (size_t)m * 3 * A->nbox;
+  a.hist_np1 = h0 + (size_t)(m + 1) * 3 * A->nbox;
+  for (int q = 0; q < 6; ++q) a.box[q] = A->box[q];
+  a.src = reinterpret_cast<const SrcDev*>(c->ws + c->srcr.off);
+  a.nsrc = (int32_t)c->src.size();
+  a.n = n;
+  a.dt = c->dt;
+  a.nx = d.nx; a.ny = d.ny; a.nz = d.nz; a.px = c->px;
+  for (int q = 0; q < 3; ++q) a.L[q] = d.cpml_cells[q];
+  a.inv_d[0] = static_cast<C>(1.0 / d.dx);
+  a.inv_d[1] = static_cast<C>(1.0 / d.dy);
+  a.inv_d[2] = static_cast<C>(1.0 / d.dz);
+  a.dt_mu = static_cast<C>(c->dt / kMu0);
+  return a;
+}
+
+// One reverse step of forward step n (n0 <= n < n0 + K, history slot m = n - n0).
+template <class C>
+yee_status adj_reverse_step(yee_adjoint* A, int64_t n, int m, int& pe, int& ph, double* grad, hipStream_t s) {
+  using namespace yee;
+  yee_ctx* c = A->c;
+  const auto& d = c->d;
+  const int np = (int)c->probes.size();
+  const int ninj = (int)A->inj_host.size();
+  if (ninj > 0) {
+    hipLaunchKernelGGL(adj_inject_kernel<C>, dim3((ninj + 63) / 64), dim3(64), 0, s,
+                       reinterpret_cast<const InjDev*>(A->ws + A->inj.off), ninj,
+                       reinterpret_cast<const int4*>(c->ws + c->prober.off), np,
+                       reinterpret_cast<const double*>(A->ws + A->phist.off) + (size_t)n * np,
+                       reinterpret_cast<C*>(A->ws + A->u.off), reinterpret_cast<C*>(A->ws + A->hb.off),
+                       (uint64_t)(A->ucomp / sizeof(C)));
+    HIP_TRY(hipGetLastError());
+  }
+  const dim3 grid((d.nx + kAdjBX - 1) / kAdjBX, (d.ny + kAdjBY - 1) / kAdjBY, d.nz);
+  const dim3 block(kAdjBX, kAdjBY);
+  AdjArgs<C, C> ah = adj_args<C, C>(A, n, m, pe, pe ^ 1, false);
+  hipLaunchKernelGGL(adj_h_kernel<C>, grid, block, 0, s, ah);
+  HIP_TRY(hipGetLastError());
+  pe ^= 1;
+  AdjArgs<C, C> ae = adj_args<C, C>(A, n, m, ph, ph ^ 1, true);
+  ae.grad = grad;
+  hipLaunchKernelGGL((adj_e_kernel<C, C>), grid, block, 0, s, ae);
+  HIP_TRY(hipGetLastError());
+  ph ^= 1;
+  return YEE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+yee_status yee_adjoint_create(yee_ctx* c, int64_t n_steps, int32_t checkpoint_every, const int32_t* box,
+                              yee_adjoint** out) {
+  if (!out) return fail(YEE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!c || !box) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "context workspace not bound");
+  if (c->d.precision == YEE_F16S) return fail(YEE_EINVAL, "the adjoint runs FP64 or FP32 contexts");
+  if (n_steps < 1 || checkpoint_every < 1) return fail(YEE_EINVAL, "n_steps and checkpoint_every must be >= 1");
+  const int n3[3] = {c->d.nx, c->d.ny, c->d.nz};
+  for (int q = 0; q < 3; ++q)
+    if (box[2 * q] < 0 || box[2 * q] >= box[2 * q + 1] || box[2 * q + 1] > n3[q])
+      return fail(YEE_EINVAL, "box [%d, %d) invalid on an axis of %d cells", box[2 * q], box[2 * q + 1], n3[q]);
+  if (c->d.nz > 65535) return fail(YEE_EINVAL, "the adjoint kernels take nz <= 65535");
+  const int64_t S = (n_steps + checkpoint_every - 1) / checkpoint_every;
+  if (S > (1 << 20)) return fail(YEE_EINVAL, "too many checkpoints (%lld)", (long long)S);
+  if ((uint64_t)n_steps * c->probes.size() >= (1ull << 31))
+    return fail(YEE_EINVAL, "probe history of %lld steps too long", (long long)n_steps);
+  auto* A = new (std::nothrow) yee_adjoint();
+  if (!A) return fail(YEE_ENOMEM, "host allocation failed");
+  A->c = c;
+  A->N = n_steps;
+  A->K = (int32_t)std::min<int64_t>(checkpoint_every, n_steps);
+  A->S = (int32_t)S;
+  for (int q = 0; q < 6; ++q) A->box[q] = box[q];
+  A->bx = box[1] - box[0];
+  A->by = box[3] - box[2];
+  A->bz = box[5] - box[4];
+  A->nbox = (size_t)A->bx * A->by * A->bz;
+  adj_layout(A);
+  *out = A;
+  return YEE_OK;
+}
+
+void yee_adjoint_destroy(yee_adjoint* A) { delete A; }
+
+yee_status yee_adjoint_footprint(const yee_adjoint* A, int64_t* bytes) {
+  if (!A || !bytes) return fail(YEE_EINVAL, "NULL argument");
+  *bytes = A->ws_bytes;
+  return YEE_OK;
+}
+
+yee_status yee_adjoint_bind_workspace(yee_adjoint* A, void* dev, int64_t bytes) {
+  if (!A || !dev) return fail(YEE_EINVAL, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(YEE_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < A->ws_bytes)
+    return fail(YEE_ENOMEM, "adjoint workspace has %lld bytes, needs %lld", (long long)bytes, (long long)A->ws_bytes);
+  A->ws = static_cast<unsigned char*>(dev);
+  A->bound = true;
+  A->have_forward = false;
+  A->hist_seg = -1;
+  return YEE_OK;
+}
+
+yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) {
+  if (!A || !objective) return fail(YEE_EINVAL, "NULL argument");
+  if (!A->bound) return fail(YEE_ESTATE, "adjoint workspace not bound");
+  yee_ctx* c = A->c;
+  if (c->n != 0) return fail(YEE_ESTATE, "the forward run starts at step 0 (context is at step %lld)", (long long)c->n);
+  hipStream_t s = (hipStream_t)stream;
+  const auto& d = c->d;
+  A->have_forward = false;
+  // derivative table per block: (dCa/deps_r / Cb, dCb/deps_r / Cb^2) in FP64
+  const size_t nb = (size_t)c->nsx * c->nsy * c->nsz;
+  A->dcoef_host.assign(2 * nb, 0.0);
+  for (size_t b = 0; b < nb; ++b) {
+    const double er = c->eps[b];
+    const double sg = c->sig[b] * c->dt / (2.0 * kEps0 * er);
+    const double cb = (c->dt / (kEps0 * er)) / (1.0 + sg);
+    const double dca = 2.0 * sg / (er * (1.0 + sg) * (1.0 + sg));
+    const double dcb = -cb / (er * (1.0 + sg));
+    A->dcoef_host[2 * b] = dca / cb;
+    A->dcoef_host[2 * b + 1] = dcb / (cb * cb);
+  }
+  // unique probed samples and their injection weights (2 Cb as the step uses it)
+  A->inj_host.clear();
+  const int np = (int)c->probes.size();
+  for (int p = 0; p < np; ++p) {
+    const int4 pr = c->probes[p];
+    bool seen = false;
+    for (int q = 0; q < p && !seen; ++q) {
+      const int4 o = c->probes[q];
+      seen = o.x == pr.x && o.y == pr.y && o.z == pr.z && o.w == pr.w;
+    }
+    if (seen) continue;
+    yee::InjDev e{};
+    e.comp = pr.x; e.i = pr.y; e.j = pr.z; e.k = pr.w; e.first = p;
+    e.off = (uint32_t)(((size_t)pr.w * d.ny + pr.z) * c->px + pr.y);
+    e.w = 2.0;
+    if (pr.x < 3) {
+      const int i = pr.y, j = pr.z, k = pr.w;
+      bool upd = pr.x == 0 ? (j > 0 && k > 0) : pr.x == 1 ? (i > 0 && k > 0) : (i > 0 && j > 0);
+      for (size_t q = 0; q < c->pec_k.size(); ++q)
+        if (c->pec_k[q] == k && (c->pec_masks[q][(size_t)j * c->px + i] >> pr.x & 1)) upd = false;
+      const size_t b = (size_t)c->segx[i] + (size_t)c->segy[j] * c->nsx + (size_t)c->segz[k] * c->nsx * c->nsy;
+      const double eps = kEps0 * c->eps[b];
+      const double sg = c->sig[b] * c->dt / (2.0 * eps);
+      const double cb = (c->dt / eps) / (1.0 + sg);
+      const double cbc = c->csize == 8 ? cb : (double)(float)cb;
+      e.w = upd ? 2.0 * cbc : 0.0;
+    }
+    A->inj_host.push_back(e);
+  }
+  yee_status st = YEE_OK;
+  HIP_TRY(hipMemcpyAsync(A->ws + A->dcoef.off, A->dcoef_host.data(), A->dcoef_host.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s));
+  if (!A->inj_host.empty())
+    HIP_TRY(hipMemcpyAsync(A->ws + A->inj.off, A->inj_host.data(), A->inj_host.size() * sizeof(yee::InjDev),
+                           hipMemcpyHostToDevice, s));
+  int64_t gathered = 0;
+  for (int32_t seg = 0; seg < A->S; ++seg) {
+    const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
+    const bool last = seg == A->S - 1;
+    if ((st = adj_checkpoint(A, seg, true, s))) return st;
+    if (last && (st = adj_store(A, 0, s))) return st;
+    for (int64_t n = n0; n < n1; ++n) {
+      if ((st = launch_one_step(c, s))) return st;
+      c->n += 1;
+      if (last && (st = adj_store(A, (int)(c->n - n0), s))) return st;
+      if (c->n - gathered >= d.series_len) {
+        if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
+        gathered = c->n;
+      }
+      if (c->n - c->folded >= d.series_len && (st = fold_dft(c, s))) return st;
+    }
+  }
+  if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
+  if ((st = fold_dft(c, s))) return st;
+  if ((st = adj_checkpoint(A, A->S, true, s))) return st;
+  hipLaunchKernelGGL(yee::adj_objective_kernel, dim3(1), dim3(256), 0, s,
+                     reinterpret_cast<const double*>(A->ws + A->phist.off), (int64_t)A->N * np,
+                     reinterpret_cast<double*>(A->ws + A->jout.off));
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(objective, A->ws + A->jout.off, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  A->hist_seg = A->S - 1;
+  A->have_forward = true;
+  return YEE_OK;
+}
+
+yee_status yee_adjoint_backward(yee_adjoint* A, double* grad, void* stream) {
+  if (!A || !grad) return fail(YEE_EINVAL, "NULL argument");
+  if (!A->bound || !A->have_forward) return fail(YEE_ESTATE, "no forward run recorded");
+  yee_ctx* c = A->c;
+  if (c->n != A->N) return fail(YEE_ESTATE, "context was stepped after the forward run");
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemsetAsync(A->ws + A->u.off, 0, A->ph[1].off + A->ph[1].bytes - A->u.off, s));
+  HIP_TRY(hipMemsetAsync(grad, 0, A->nbox * sizeof(double), s));
+  int pe = 0, ph = 0;
+  yee_status st = YEE_OK;
+  for (int32_t seg = A->S - 1; seg >= 0; --seg) {
+    const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
+    if (A->hist_seg != seg) {
+      c->n = n0;
+      if ((st = adj_checkpoint(A, seg, false, s))) return st;
+      if ((st = adj_store(A, 0, s))) return st;
+      for (int64_t n = n0; n < n1; ++n) {
+        if ((st = launch_one_step(c, s, false))) return st;
+        c->n += 1;
+        if ((st = adj_store(A, (int)(c->n - n0), s))) return st;
+      }
+      A->hist_seg = seg;
+    }
+    for (int64_t n = n1 - 1; n >= n0; --n) {
+      st = c->csize == 8 ? adj_reverse_step<double>(A, n, (int)(n - n0), pe, ph, grad, s)
+                         : adj_reverse_step<float>(A, n, (int)(n - n0), pe, ph, grad, s);
+      if (st) return st;
+    }
+  }
+  c->n = A->N;
+  return adj_checkpoint(A, A->S, false, s);
 }
 
 }  // extern "C"

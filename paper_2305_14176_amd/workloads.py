@@ -93,6 +93,7 @@ class Workload:
     probes: List[Tuple[int, int, int, int]] = field(default_factory=list)   # (comp, i, j, k)
     freqs: np.ndarray = field(default_factory=lambda: np.zeros(0))
     steps: int = 100
+    design: Optional[Tuple[int, int]] = None  # [d0, d1) per axis of a gradient workload
 
     def __post_init__(self):
         if self.seg_x is None:
@@ -317,6 +318,43 @@ def adjoint_design(n: int = 128, design: Tuple[int, int] = (32, 96), steps: int 
     wl.probes = _interior_probes(rng, wl, nprobes, exclude=[src],
                                  region=((d0, d1), (d0, d1), (d0, d1)))
     wl.design = (d0, d1)
+    return wl
+
+
+def adjoint_case(seed: int, nx: int = 26, ny: int = 22, nz: int = 20, steps: int = 150,
+                 precision: str = "f64", probes: str = "e", cpml: int = 3) -> Workload:
+    """Small gradient case with every feature the adjoint transposes: graded
+    CPML with kappa and alpha, non-cubic cells, a lossy 4-cell block lattice
+    (eps_r ~ U[1, 6), sigma ~ U[0, 0.3) S/m), a PEC mask plane, two sources and
+    probes of E components ("e": Ez, Ex, Ey, one sample probed twice) or of H
+    components only ("h")."""
+    rng = rng_for(seed)
+    block = 4
+    bx, by, bz = (nx + block - 1) // block, (ny + block - 1) // block, (nz + block - 1) // block
+    nb = bx * by * bz
+    seg = [np.arange(n, dtype=np.int32) // block for n in (nx, ny, nz)]
+    wl = Workload(f"adjoint_case_{nx}x{ny}x{nz}_{probes}", nx, ny, nz, 1.0e-3, 1.1e-3, 0.9e-3, precision=precision,
+                  cpml_cells=(cpml, cpml, cpml), cpml_kappa_max=1.6, cpml_alpha_max=0.03,
+                  seg_x=seg[0], seg_y=seg[1], seg_z=seg[2], eps_blk=rng.uniform(1.0, 6.0, nb),
+                  sig_blk=rng.uniform(0.0, 0.3, nb), nsx=bx, nsy=by, nsz=bz, steps=steps)
+    kp = nz // 2 + 2
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[ny // 3: ny // 3 + 3, nx // 4: nx // 4 + 6] = 3
+    mask[2 * ny // 3, nx // 2: nx // 2 + 4] = 7
+    wl.pec_planes = [(kp, mask)]
+    f0 = 30e9
+    tau = 1.0 / (2.0 * f0)
+    wl.sources = [SourceSpec(2, nx // 2, ny // 2, nz // 2, "mod_gauss", 1.0, 3 * tau, tau, f0, unit="s"),
+                  SourceSpec(0, cpml + 2, ny // 2 + 1, nz // 3, "gauss_deriv", 0.5, 10.0, 4.0, unit="dt")]
+    if probes == "e":
+        pts = _interior_probes(rng, wl, 3, comp=2, exclude=[(nx // 2, ny // 2, nz // 2)])
+        pts += _interior_probes(rng, wl, 2, comp=0) + _interior_probes(rng, wl, 1, comp=1)
+        pts.append(pts[0])
+    else:
+        pts = (_interior_probes(rng, wl, 2, comp=3) + _interior_probes(rng, wl, 2, comp=4)
+               + _interior_probes(rng, wl, 1, comp=5))
+        pts.append(pts[-1])
+    wl.probes = pts
     return wl
 
 

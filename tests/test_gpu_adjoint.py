@@ -1,0 +1,263 @@
+"""GPU parity of the discrete adjoint (through the C ABI).
+
+* Gradient and objective against the FP64 oracle's discrete adjoint on the
+  same seeded inputs: FP64 mode to 1e-12 relative L2 (rounding order only; the
+  GPU rebuilds Cb R^n from the stored E history), FP32 mode to 1e-4 (FP32
+  fields against an FP64 reference), objective to 1e-12 / 1e-5.
+* Gradient against central finite differences of the objective computed by
+  plain GPU solves in FP64 (h = 1e-3 on eps_r): small grid, and the full
+  128^3 design workload on 64 seeded design cells.
+* The autograd function returns the library's gradient; an adjoint run
+  leaves the context exactly as plain steps do; error states.
+"""
+import ctypes as C
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_14176_amd import workloads as W
+from _helpers import oracle_from_workload, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+JTOL = {"f64": 1e-12, "f32": 1e-5}
+GTOL = {"f64": 1e-12, "f32": 1e-4}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _case(prec, probes, seed, steps=150):
+    wl = W.adjoint_case(seed, precision=prec, probes=probes, steps=steps)
+    return wl
+
+
+def _gpu_gradient(wl, box, ckpt, init=None):
+    from paper_2305_14176_amd.adjoint import AdjointRun
+    from paper_2305_14176_amd.solver import YeeSolver
+    s = YeeSolver(wl, series_len=wl.steps)
+    if init is not None:
+        for c, a in init.items():
+            s.set_field(c, a)
+    run = AdjointRun(s, wl.steps, box, checkpoint_every=ckpt)
+    j = run.forward()
+    g = run.backward().cpu().numpy()
+    run.close()
+    s.close()
+    return j, g
+
+
+def _oracle_gradient(wl, ckpt, init=None):
+    from oracle.adjoint import gradient
+    return gradient(lambda: oracle_from_workload(wl, initial=init), wl.steps, wl.probes, checkpoint_every=ckpt)
+
+
+BOX_IN = (4, 22, 3, 19, 2, 17)     # crosses the CPML on five faces and the PEC plane
+BOX_ALL = (0, 26, 0, 22, 0, 20)    # every cell, outer faces included
+
+
+@pytest.mark.parametrize("prec,probes,box,ckpt,init", [
+    ("f64", "e", BOX_IN, 16, None),
+    ("f32", "e", BOX_IN, 16, None),
+    ("f64", "h", BOX_ALL, 64, 7),
+    ("f32", "h", BOX_ALL, 64, 7),
+    ("f64", "e", (13, 14, 11, 12, 10, 11), 1, None),
+])
+def test_gradient_matches_oracle(prec, probes, box, ckpt, init):
+    steps = 40 if ckpt == 1 else 150
+    wl = _case(prec, probes, seed=11, steps=steps)
+    fields = W.random_initial_fields(wl, init) if init is not None else None
+    _say(f"[gpu] adjoint {wl.name} prec={prec} box={box} K={ckpt} init={init}")
+    j, g = _gpu_gradient(wl, box, ckpt, fields)
+    jr, gr = _oracle_gradient(wl, ckpt, fields)
+    ref = gr[box[0]:box[1], box[2]:box[3], box[4]:box[5]]
+    assert np.abs(ref).max() > 0
+    assert abs(j - jr) <= JTOL[prec] * jr, (j, jr)
+    err = rel_l2(g, ref)
+    _say(f"[gpu]   J rel {abs(j - jr) / jr:.2e}  grad rel L2 {err:.2e}")
+    assert err <= GTOL[prec], err
+
+
+def _plain_objective(solver, steps):
+    solver.reset()
+    solver.step(steps)
+    y = solver.series(1, steps)
+    return float(np.sum(y * y))
+
+
+def test_gradient_matches_finite_differences_small():
+    from paper_2305_14176_amd.adjoint import DesignProblem
+    wl = _case("f64", "e", seed=12, steps=120)
+    box = BOX_IN
+    _say(f"[gpu] adjoint FD {wl.name}")
+    prob = DesignProblem(wl, box, checkpoint_every=32)
+    eps0 = prob.initial_design
+    prob.forward(eps0)
+    g = prob.gradient().cpu().numpy()
+    rng = np.random.default_rng(3)
+    h = 1e-3
+    gmax = np.abs(g).max()
+    cells = [tuple(int(rng.integers(0, n)) for n in g.shape) for _ in range(8)]
+    for c in cells:
+        vals = []
+        for sgn in (1, -1):
+            e = eps0.copy()
+            e[c] += sgn * h
+            prob.set_design(e)
+            vals.append(_plain_objective(prob.solver, wl.steps))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[c]) <= 1e-6 * gmax + 1e-5 * abs(g[c]), (c, fd, g[c])
+    prob.close()
+
+
+def test_full_size_gradient():
+    """The 128^3 design workload: FP64 gradient against central differences on
+    64 seeded design cells; the FP32 gradient against the FP64 one."""
+    from paper_2305_14176_amd.adjoint import DesignProblem
+    out = {}
+    for prec in ("f64", "f32"):
+        wl = dataclasses.replace(W.adjoint_design(), precision=prec)
+        d0, d1 = wl.design
+        box = (d0, d1, d0, d1, d0, d1)
+        _say(f"[gpu] adjoint {wl.name} prec={prec} steps={wl.steps}")
+        prob = DesignProblem(wl, box, checkpoint_every=64)
+        eps0 = prob.initial_design
+        j = prob.forward(eps0)
+        g = prob.gradient().cpu().numpy()
+        out[prec] = (j, g, prob)
+        if prec == "f32":
+            prob.close()
+    j64, g64, prob = out["f64"]
+    j32, g32, _ = out["f32"]
+    assert abs(j32 - j64) <= 1e-5 * j64, (j32, j64)
+    err = rel_l2(g32, g64)
+    _say(f"[gpu]   FP32 vs FP64: J rel {abs(j32 - j64) / j64:.2e} grad rel L2 {err:.2e}")
+    assert err <= 1e-4, err
+    rng = np.random.default_rng(64)
+    eps0 = prob.initial_design
+    gmax = np.abs(g64).max()
+    h = 1e-3
+    worst = 0.0
+    for q in range(64):
+        c = tuple(int(rng.integers(0, n)) for n in g64.shape)
+        vals = []
+        for sgn in (1, -1):
+            e = eps0.copy()
+            e[c] += sgn * h
+            prob.set_design(e)
+            vals.append(_plain_objective(prob.solver, prob.n_steps))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        dev = abs(fd - g64[c]) / (1e-6 * gmax + 1e-5 * abs(g64[c]))
+        worst = max(worst, dev)
+        assert dev <= 1.0, (c, fd, g64[c])
+        if q % 16 == 15:
+            _say(f"[gpu]   FD cells checked: {q + 1}")
+    _say(f"[gpu]   worst FD deviation / tolerance {worst:.3f}")
+    prob.close()
+
+
+def test_autograd_function_returns_the_library_gradient():
+    import torch
+    from paper_2305_14176_amd.adjoint import DesignProblem, YeeObjective
+    wl = _case("f32", "e", seed=13, steps=100)
+    box = BOX_IN
+    _say(f"[gpu] adjoint autograd {wl.name}")
+    prob = DesignProblem(wl, box, checkpoint_every=32)
+    rng = np.random.default_rng(5)
+    design = prob.initial_design + rng.uniform(0, 0.5, prob.block.shape)
+    eps = torch.tensor(design, dtype=torch.float64, device="cuda", requires_grad=True)
+    j = YeeObjective.apply(eps, prob)
+    (3.0 * j).backward()
+    j2 = prob.forward(design)
+    g2 = prob.gradient().cpu().numpy()
+    assert float(j.detach()) == j2
+    np.testing.assert_array_equal(eps.grad.cpu().numpy(), 3.0 * g2)
+    # and the definition: the oracle's gradient on the same materials
+    from oracle.adjoint import gradient
+    e = np.array(prob.wl.eps_blk)
+    e[prob.block] = design
+    wd = dataclasses.replace(prob.wl, eps_blk=e)
+    jr, gr = gradient(lambda: oracle_from_workload(wd), wl.steps, wl.probes, checkpoint_every=32)
+    assert rel_l2(g2, gr[box[0]:box[1], box[2]:box[3], box[4]:box[5]]) <= 1e-4
+    # a newer forward invalidates the older graph
+    e1 = torch.tensor(design, dtype=torch.float64, device="cuda", requires_grad=True)
+    ja = YeeObjective.apply(e1, prob)
+    prob.forward(design)
+    with pytest.raises(RuntimeError):
+        ja.backward()
+    prob.close()
+
+
+def test_adjoint_leaves_context_as_plain_steps():
+    from paper_2305_14176_amd.adjoint import AdjointRun
+    from paper_2305_14176_amd.solver import YeeSolver
+    wl = _case("f32", "e", seed=14, steps=90)
+    wl.freqs = W.dft_frequencies(30e9, 8)
+    _say(f"[gpu] adjoint state {wl.name}")
+    # a probe ring shorter than the run and the checkpoint interval
+    a = YeeSolver(wl, series_len=20)
+    b = YeeSolver(wl, series_len=20)
+    run = AdjointRun(a, wl.steps, BOX_IN, checkpoint_every=32)
+    run.forward()
+    g1 = run.backward().cpu().numpy()
+    g2 = run.backward().cpu().numpy()
+    np.testing.assert_array_equal(g1, g2)
+    b.step(wl.steps)
+    assert a.steps_done == b.steps_done == wl.steps
+    for c in ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz"):
+        np.testing.assert_array_equal(a.field(c), b.field(c), err_msg=c)
+    np.testing.assert_array_equal(a.series(wl.steps - 19, 20), b.series(wl.steps - 19, 20))
+    np.testing.assert_array_equal(a.dft(), b.dft())
+    # the objective of the forward run equals the plain run's probe samples
+    c = YeeSolver(wl, series_len=wl.steps)
+    c.step(wl.steps)
+    y = c.series(1, wl.steps)
+    a.reset()
+    j = run.forward()
+    assert abs(j - float(np.sum(y * y))) <= 1e-12 * j
+    run.close()
+    for s in (a, b, c):
+        s.close()
+
+
+def test_adjoint_error_states():
+    from paper_2305_14176_amd import _lib
+    from paper_2305_14176_amd.solver import YeeSolver
+    lib = _lib.load()
+    wl = _case("f32", "e", seed=15, steps=10)
+    s = YeeSolver(wl, series_len=10)
+    h = C.c_void_p()
+    bad = (C.c_int32 * 6)(0, 27, 0, 22, 0, 20)
+    assert lib.yee_adjoint_create(s.ctx, 10, 4, bad, C.byref(h)) == -1
+    empty = (C.c_int32 * 6)(3, 3, 0, 22, 0, 20)
+    assert lib.yee_adjoint_create(s.ctx, 10, 4, empty, C.byref(h)) == -1
+    box = (C.c_int32 * 6)(*BOX_IN)
+    assert lib.yee_adjoint_create(s.ctx, 0, 4, box, C.byref(h)) == -1
+    assert lib.yee_adjoint_create(s.ctx, 10, 4, box, C.byref(h)) == 0
+    jv = C.c_double()
+    assert lib.yee_adjoint_forward(h, C.byref(jv), None) == -4          # workspace not bound
+    nb = C.c_int64()
+    lib.yee_adjoint_footprint(h, C.byref(nb))
+    import torch
+    ws = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    assert lib.yee_adjoint_bind_workspace(h, C.c_void_p(ptr), nb.value - 1) == -2
+    assert lib.yee_adjoint_bind_workspace(h, C.c_void_p(ptr), nb.value) == 0
+    g = torch.empty(18 * 16 * 15, dtype=torch.float64, device="cuda")
+    assert lib.yee_adjoint_backward(h, C.c_void_p(g.data_ptr()), None) == -4   # no forward run
+    s.step(1)
+    assert lib.yee_adjoint_forward(h, C.byref(jv), None) == -4          # not at step 0
+    s.reset()
+    assert lib.yee_adjoint_forward(h, C.byref(jv), None) == 0
+    s.step(1)
+    assert lib.yee_adjoint_backward(h, C.c_void_p(g.data_ptr()), None) == -4   # stepped since
+    lib.yee_adjoint_destroy(h)
+    f16 = YeeSolver(dataclasses.replace(wl, precision="f16"), series_len=10)
+    assert lib.yee_adjoint_create(f16.ctx, 10, 4, box, C.byref(h)) == -1
+    torch.cuda.synchronize()
+    s.close()
+    f16.close()
