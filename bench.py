@@ -134,6 +134,46 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     return out
 
 
+def adjoint_benchmark(checkpoint_every=64):
+    """Gradient of the 128^3 design workload (FP32 fields, FP64 gradient):
+    forward run with checkpoints, backward run (recompute + reverse steps),
+    against the same N plain steps."""
+    import torch
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.adjoint import DesignProblem
+    wl = W.adjoint_design()
+    d0, d1 = wl.design
+    box = (d0, d1, d0, d1, d0, d1)
+    prob = DesignProblem(wl, box, checkpoint_every=checkpoint_every)
+    eps0 = prob.initial_design
+    prob.forward(eps0)
+    prob.gradient()              # warm-up of both passes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob.forward(eps0)           # synchronizes (returns J to the host)
+    t1 = time.perf_counter()
+    g = prob.gradient()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prob.solver.reset()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    prob.solver.step(prob.n_steps)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    nbox = g.numel()
+    fwd, bwd, plain = t1 - t0, t2 - t1, t4 - t3
+    out = {"workload": f"{wl.name}: design [{d0},{d1})^3, {prob.n_steps} steps, {len(wl.probes)} Ez probes, "
+                       f"checkpoint every {checkpoint_every}",
+           "dtype": "f32 fields, f64 gradient",
+           "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
+           "gradient_ms": round((fwd + bwd) * 1e3, 2), "plain_forward_ms": round(plain * 1e3, 2),
+           "gradient_over_plain": round((fwd + bwd) / plain, 3),
+           "design_cells": nbox, "workspace_bytes": prob.run.footprint}
+    prob.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +185,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient measurement")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: a few untimed steps, then a plain device copy of "
                          "COPY_MIB MiB (the known-size kernel the HBM counters are scaled by)")
@@ -223,6 +264,8 @@ def main():
                      "kernel_ms_avg": round(ms_per_step, 5)},
         "wall_s_timed": round(t_wall, 4),
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_benchmark()
     if not args.no_serving:
         del solver
         torch.cuda.empty_cache()
