@@ -48,7 +48,7 @@ struct AdjArgs {
   const C* pin;             // psi adjoint (E side in adj_h, H side in adj_e), old
   C* pout;                  // new
   uint32_t psoff[6];
-  const C* prof;            // CPML profiles [side E,H][axis][b | a | 1/kappa][plen]
+  const C* prof;            // CPML profiles [side E,H][axis][1 - b | a | 1/kappa][plen]
   int32_t plen;
   const int32_t* seg;       // block index per cell: x [px] | y [ny] | z [nz]
   const Coef2<C>* coef;     // (Ca, Cb) per block
@@ -175,21 +175,21 @@ adj_h_kernel(const AdjArgs<C, C> a) {
   // psi_E adjoint of the own samples: P <- b (P + s u)
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
-    const C bv = pr[3 * pl + j];
-    a.pout[a.psoff[PEXY] + q] = bv * (P[a.psoff[PEXY] + q] + ux);
-    a.pout[a.psoff[PEZY] + q] = bv * (P[a.psoff[PEZY] + q] - uz);
+    const C ob = pr[3 * pl + j];
+    { const C t = P[a.psoff[PEXY] + q] + ux; a.pout[a.psoff[PEXY] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEZY] + q] - uz; a.pout[a.psoff[PEZY] + q] = t - ob * t; }
   }
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
-    const C bv = pr[6 * pl + k];
-    a.pout[a.psoff[PEYZ] + q] = bv * (P[a.psoff[PEYZ] + q] + uy);
-    a.pout[a.psoff[PEXZ] + q] = bv * (P[a.psoff[PEXZ] + q] - ux);
+    const C ob = pr[6 * pl + k];
+    { const C t = P[a.psoff[PEYZ] + q] + uy; a.pout[a.psoff[PEYZ] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEXZ] + q] - ux; a.pout[a.psoff[PEXZ] + q] = t - ob * t; }
   }
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
-    const C bv = pr[0 * pl + i];
-    a.pout[a.psoff[PEZX] + q] = bv * (P[a.psoff[PEZX] + q] + uz);
-    a.pout[a.psoff[PEYX] + q] = bv * (P[a.psoff[PEYX] + q] - uy);
+    const C ob = pr[0 * pl + i];
+    { const C t = P[a.psoff[PEZX] + q] + uz; a.pout[a.psoff[PEZX] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEYX] + q] - uy; a.pout[a.psoff[PEYX] + q] = t - ob * t; }
   }
 }
 
@@ -315,21 +315,21 @@ adj_e_kernel(const AdjArgs<T, C> a) {
   // psi_H adjoint of the own samples: Q <- b (Q - mu s H_bar)
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
-    const C bv = pr[12 * pl + j];
-    a.pout[a.psoff[PHXY] + q] = bv * (Q[a.psoff[PHXY] + q] - mu * hx);
-    a.pout[a.psoff[PHZY] + q] = bv * (Q[a.psoff[PHZY] + q] + mu * hz);
+    const C ob = pr[12 * pl + j];
+    { const C t = Q[a.psoff[PHXY] + q] - mu * hx; a.pout[a.psoff[PHXY] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHZY] + q] + mu * hz; a.pout[a.psoff[PHZY] + q] = t - ob * t; }
   }
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
-    const C bv = pr[15 * pl + k];
-    a.pout[a.psoff[PHYZ] + q] = bv * (Q[a.psoff[PHYZ] + q] - mu * hy);
-    a.pout[a.psoff[PHXZ] + q] = bv * (Q[a.psoff[PHXZ] + q] + mu * hx);
+    const C ob = pr[15 * pl + k];
+    { const C t = Q[a.psoff[PHYZ] + q] - mu * hy; a.pout[a.psoff[PHYZ] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHXZ] + q] + mu * hx; a.pout[a.psoff[PHXZ] + q] = t - ob * t; }
   }
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
-    const C bv = pr[9 * pl + i];
-    a.pout[a.psoff[PHZX] + q] = bv * (Q[a.psoff[PHZX] + q] - mu * hz);
-    a.pout[a.psoff[PHYX] + q] = bv * (Q[a.psoff[PHYX] + q] + mu * hy);
+    const C ob = pr[9 * pl + i];
+    { const C t = Q[a.psoff[PHZX] + q] - mu * hz; a.pout[a.psoff[PHZX] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHYX] + q] + mu * hy; a.pout[a.psoff[PHYX] + q] = t - ob * t; }
   }
 }
 

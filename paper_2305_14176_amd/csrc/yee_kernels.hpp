@@ -65,7 +65,7 @@ struct StepArgs {
   const C* psh_in;          // H-side psi, old
   C* psh_out;               // H-side psi, new
   uint32_t psoff[6];        // element offset of each psi array inside its region
-  const C* prof;            // CPML profiles [side E,H][axis][b | a | 1/kappa][plen]
+  const C* prof;            // CPML profiles [side E,H][axis][1 - b | a | 1/kappa][plen]
   int32_t plen;
   const int32_t* seg;       // block index per cell: x [px] | y [ny] | z [nz]
   const Coef2<C>* coef;     // (Ca, Cb) per block [nsz][nsy][nsx]
@@ -86,6 +86,8 @@ struct StepArgs {
   C dt_mu;
   float enc[6], dec[6];     // FP16 storage scales (2^s, 2^-s)
   int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, planes per chunk, waves per row
+  uint32_t psi_bytes;       // bytes of one psi region (E side; each H-side set is as large)
+  uint32_t coef_bytes;      // bytes of the (Ca, Cb) table
 };
 
 // ---------------------------------------------------------------------------
@@ -107,27 +109,6 @@ struct alignas(sizeof(T) * V) VecT {
   T v[V];
 };
 
-template <class T, class C, int V>
-__device__ __forceinline__ void load_row(const T* __restrict__ base, uint32_t off, bool ok, C (&out)[V],
-                                         float dec) {
-  if (ok) {
-    const VecT<T, V> r = *reinterpret_cast<const VecT<T, V>*>(base + off);
-#pragma unroll
-    for (int e = 0; e < V; ++e) out[e] = Conv<T, C>::ld(r.v[e], dec);
-  } else {
-#pragma unroll
-    for (int e = 0; e < V; ++e) out[e] = C(0);
-  }
-}
-
-template <class T, class C, int V>
-__device__ __forceinline__ void store_row(T* __restrict__ base, uint32_t off, const C (&in)[V], float enc) {
-  VecT<T, V> r;
-#pragma unroll
-  for (int e = 0; e < V; ++e) r.v[e] = Conv<T, C>::st(in[e], enc);
-  *reinterpret_cast<VecT<T, V>*>(base + off) = r;
-}
-
 // Round a computed value to what storage would hold (identity unless FP16).
 template <class T, class C>
 __device__ __forceinline__ C to_storage(C v, float enc, float dec) {
@@ -144,450 +125,636 @@ __device__ __noinline__ double waveform(const SrcDev s, double t) {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// LDS footprint of one workgroup in bytes: E rows j0-1..j0+ty and H rows
-// j0-1..j0+ty-1, three components of RL = wpr * 64 * V samples each; the
-// source values; and per-plane tables of the z-chunk (kz + 1 planes): six z
-// profiles, the z block offset, the PEC plane index and the row flags.
+// LDS layout of one workgroup, in compute-type elements unless noted:
+//   E rows j0-1 .. j0+ty        [ty+2][3][RS]  (RS = wpr*64*V + 2V: one zero
+//   H rows j0-1 .. j0+ty-1      [ty+1][3][RS]   pad vector on each side of a row)
+//   source values               [kMaxSources]
+//   z profiles of the chunk     [6][kz+1]      (1 - b, a, 1/kappa of the E side, then H side)
+//   x profiles                  [6][wpr*64*V]
+//   y profiles of the tile rows [6][ty+1]
+//   int32: z block offset [kz+1], PEC plane index [kz+1]; uint8: row flags [ty+1][kz+1]
 __host__ __device__ inline size_t step_lds_bytes_for(int ty, int wpr, int V, int kz, size_t csize) {
   const size_t rl = (size_t)wpr * kWave * V;
+  const size_t rs = rl + 2 * (size_t)V;
   const size_t nk = (size_t)kz + 1;
-  size_t b = ((size_t)(ty + 2) * 3 * rl + (size_t)(ty + 1) * 3 * rl + kMaxSources + 6 * nk) * csize;
+  size_t b = ((size_t)(2 * ty + 3) * 3 * rs + kMaxSources + 6 * nk + 6 * rl + 6 * (size_t)(ty + 1)) * csize;
   b += 2 * nk * sizeof(int32_t);
   b += (size_t)(ty + 1) * nk;
   return (b + 15) & ~size_t(15);
 }
 
-// Per-lane data of one plane that is small but still comes from memory: CPML
-// auxiliaries (H side old, E side in place), the material coefficients and
-// the PEC mask.  It is loaded one plane ahead of its use.
 template <class C, int V>
-struct PlaneAux {
-  C ph[6][V];   // H-side psi, PH* order
-  C pe[6][V];   // E-side psi, PE* order
-  Coef2<C> cf[V];
-  uint32_t pm[V];
+__device__ __forceinline__ void lds_put(C* p, const C (&v)[V]) {
+  VecT<C, V> t;
+#pragma unroll
+  for (int e = 0; e < V; ++e) t.v[e] = v[e];
+  *reinterpret_cast<VecT<C, V>*>(p) = t;
+}
+
+template <class C, int V>
+__device__ __forceinline__ void lds_get(const C* p, C (&v)[V]) {
+  const VecT<C, V> t = *reinterpret_cast<const VecT<C, V>*>(p);
+#pragma unroll
+  for (int e = 0; e < V; ++e) v[e] = t.v[e];
+}
+
+// Buffer resources (V#): a base address, a byte range and the gfx9 data
+// format word.  Every load and store of the step goes through one of them
+// with a per-lane byte offset that stays fixed over the march (VGPR) and a
+// uniform byte offset (SGPR), so no lane does 64-bit address arithmetic.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <int N>
+struct Raw;
+template <>
+struct Raw<2> {
+  struct U { unsigned short x; };
+  static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return U{__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)};
+  }
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b16(v.x, r, vo, so, 0);
+  }
+};
+template <>
+struct Raw<4> {
+  struct U { unsigned int x; };
+  static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return U{__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)};
+  }
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b32(v.x, r, vo, so, 0);
+  }
+};
+template <>
+struct Raw<8> {
+  struct U { u32x2 x; };
+  static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return U{__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0)};
+  }
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b64(v.x, r, vo, so, 0);
+  }
+};
+template <>
+struct Raw<16> {
+  struct U { u32x4 x; };
+  static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return U{__builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0)};
+  }
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 0);
+  }
+};
+template <>
+struct Raw<32> {
+  struct U { u32x4 x, y; };
+  static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
+    return U{__builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0), __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0)};
+  }
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
+    __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v.y, r, vo + 16, so, 0);
+  }
 };
 
+template <class X>
+__device__ __forceinline__ X buf_ld(rsrc_t r, uint32_t vo, uint32_t so) {
+  using R = Raw<sizeof(X)>;
+  return __builtin_bit_cast(X, R::ld(r, vo, so));
+}
+template <class X>
+__device__ __forceinline__ void buf_st(const X& v, rsrc_t r, uint32_t vo, uint32_t so) {
+  using R = Raw<sizeof(X)>;
+  R::st(__builtin_bit_cast(typename R::U, v), r, vo, so);
+}
+
+template <class T, class C, int V>
+__device__ __forceinline__ void ld_row(rsrc_t r, uint32_t vo, uint32_t so, C (&out)[V], float dec) {
+  const VecT<T, V> v = buf_ld<VecT<T, V>>(r, vo, so);
+#pragma unroll
+  for (int e = 0; e < V; ++e) out[e] = Conv<T, C>::ld(v.v[e], dec);
+}
+
+template <class T, class C, int V>
+__device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const C (&in)[V], float enc) {
+  VecT<T, V> v;
+#pragma unroll
+  for (int e = 0; e < V; ++e) v.v[e] = Conv<T, C>::st(in[e], enc);
+  buf_st<VecT<T, V>>(v, r, vo, so);
+}
+
 // ---------------------------------------------------------------------------
-// The fused step kernel
+// The fused step: one tile (ytile, chunk) of one grid.  Waves beyond
+// (ty + 1) * wpr (spare waves of a fixed-size workgroup) take part in the
+// barriers only.
+//
+// Lanes with nothing to load or store (beyond nx, rows outside the grid,
+// samples outside an x layer for the x-layer auxiliaries) carry the byte offset
+// kOut, outside every buffer range: their loads return 0 and their stores are
+// dropped, so the march has no per-lane branches.  Uniform conditions (rows,
+// planes, layers) are scalar branches.
+//
+// Per plane k the registers hold E^n(k), E^n(k+1), H^{n-1/2}(k), H^{n+1/2}(k-1)
+// and the H-side psi of plane k.  E^n(k+2), H^{n-1/2}(k+1) are prefetched at
+// the top of the iteration, after the small loads the E half waits for (E-side
+// psi and coefficients of plane k): gfx9 counts vector memory operations in
+// one in-order counter, so a wait never covers the prefetch.  The H-side psi of
+// plane k+1 is loaded once plane k's has been consumed.
 // ---------------------------------------------------------------------------
-// One tile (ytile, chunk) of one grid.  Waves beyond (ty + 1) * wpr (spare
-// waves of a fixed-size workgroup) take part in the barriers only.
+constexpr uint32_t kOut = 0x80000000u;
+
 template <class T, class C, int V>
 __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int chunk,
                                           unsigned char* smem_raw) {
   const int wpr = a.wpr;
-  const int RL = wpr * kWave * V;                 // LDS row length
-  const int nk1 = a.kz + 1;                       // stride of the per-plane tables
-  C* ldsE = reinterpret_cast<C*>(smem_raw);      // [(ty+2)][3][RL]: E^n(k) rows j0-1..j0+ty
-  C* ldsH = ldsE + (a.ty + 2) * 3 * RL;           // [(ty+1)][3][RL]: H^{n+1/2}(k) rows j0-1..j0+ty-1
-  C* ldsS = ldsH + (a.ty + 1) * 3 * RL;           // [kMaxSources]: amp * w((n+1) dt)
-  C* tzp = ldsS + kMaxSources;                    // [6][nk1]: z profiles bE aE kE bH aH kH
-  int32_t* tzs = reinterpret_cast<int32_t*>(tzp + 6 * nk1);  // [nk1]: z block index * nsx * nsy
-  int32_t* tzl = tzs + nk1;                       // [nk1]: PEC plane index
-  uint8_t* tfl = reinterpret_cast<uint8_t*>(tzl + nk1);      // [ty+1][nk1]: row flags
+  const int ty = a.ty;
+  const int RL = wpr * kWave * V;
+  const int RS = RL + 2 * V;
+  const int nk1 = a.kz + 1;
+  C* ldsE = reinterpret_cast<C*>(smem_raw);
+  C* ldsH = ldsE + (ty + 2) * 3 * RS;
+  C* ldsS = ldsH + (ty + 1) * 3 * RS;
+  C* tzp = ldsS + kMaxSources;
+  C* txp = tzp + 6 * nk1;
+  C* typ = txp + 6 * RL;
+  int32_t* tzs = reinterpret_cast<int32_t*>(typ + 6 * (ty + 1));
+  int32_t* tzl = tzs + nk1;
+  uint8_t* tfl = reinterpret_cast<uint8_t*>(tzl + nk1);
 
   const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
   const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
-  const int j0 = ytile * a.ty;
+  const int j0 = ytile * ty;
   const int k0 = chunk * a.kz;
   const int k1 = min(nz, k0 + a.kz);
   const int kstart = k0 > 0 ? k0 - 1 : 0;
   const int nk = k1 - kstart;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
 
-  // ---- per-workgroup tables (sources and the chunk's planes) ----
-  if ((int)threadIdx.x < a.nsrc) {
-    const SrcDev sd = a.src[threadIdx.x];
-    ldsS[threadIdx.x] = static_cast<C>(sd.amp * waveform(sd, (double)(a.n + 1) * a.dt));
+  // ---- per-workgroup tables ----
+  if (tid < a.nsrc) {
+    const SrcDev sd = a.src[tid];
+    ldsS[tid] = static_cast<C>(sd.amp * waveform(sd, (double)(a.n + 1) * a.dt));
   }
-  for (int q = threadIdx.x; q < nk; q += blockDim.x) {
+  for (int q = tid; q < nk; q += nthr) {
     const int k = kstart + q;
     const bool inz = (k < Lz || k >= nz - Lz);
 #pragma unroll
     for (int u = 0; u < 6; ++u) {
-      const int side = u / 3, qq = u % 3;   // b, a, 1/kappa of the E and H side
-      tzp[u * nk1 + q] = inz ? a.prof[((side * 3 + 2) * 3 + qq) * a.plen + k] : (qq == 1 ? C(0) : C(1));
+      const int side = u / 3, qq = u % 3;
+      tzp[u * nk1 + q] = inz ? a.prof[((side * 3 + 2) * 3 + qq) * a.plen + k] : (qq == 2 ? C(1) : C(0));
     }
     tzs[q] = a.seg[px + ny + k] * a.nsxy;
     tzl[q] = a.pec_plane[k];
   }
-  for (int q = threadIdx.x; q < (a.ty + 1) * nk; q += blockDim.x) {
+  for (int q = tid; q < 6 * RL; q += nthr) {
+    const int u = q / RL, i = q - u * RL;
+    const int side = u / 3, qq = u % 3;
+    const bool inx = i < nx && (i < Lx || i >= nx - Lx);
+    txp[q] = inx ? a.prof[((side * 3 + 0) * 3 + qq) * a.plen + i] : (qq == 2 ? C(1) : C(0));
+  }
+  for (int q = tid; q < 6 * (ty + 1); q += nthr) {
+    const int u = q / (ty + 1), rr = q - u * (ty + 1);
+    const int side = u / 3, qq = u % 3;
+    const int jj = j0 - 1 + rr;
+    const bool iny = jj >= 0 && jj < ny && (jj < Ly || jj >= ny - Ly);
+    typ[q] = iny ? a.prof[((side * 3 + 1) * 3 + qq) * a.plen + jj] : (qq == 2 ? C(1) : C(0));
+  }
+  for (int q = tid; q < (ty + 1) * nk; q += nthr) {
     const int rr = q / nk, kk = q - rr * nk;
     const int jj = j0 - 1 + rr;
     tfl[rr * nk1 + kk] = (jj >= 0 && jj < ny) ? a.rowflag[(uint32_t)(kstart + kk) * ny + jj] : 0;
   }
+  for (int q = tid; q < (2 * ty + 3) * 3 * 2 * V; q += nthr) {
+    const int row = q / (2 * V), p = q - row * 2 * V;
+    ldsE[row * RS + (p < V ? p : RL + p)] = C(0);
+  }
   __syncthreads();
 
-  const int wv = uniform(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const bool dummy = wv >= (a.ty + 1) * wpr;  // spare wave: barriers only
-  const int r = dummy ? 0 : wv / wpr;     // tile row: 0 = halo row j0-1
-  const int xs = dummy ? 0 : wv - r * wpr;  // x segment of the row
+  // ---- wave roles (uniform) ----
+  const int wv = uniform(tid >> 6);
+  const int lane = tid & 63;
+  const bool dummy = wv >= (ty + 1) * wpr;
+  const int r = dummy ? 0 : wv / wpr;        // tile row: 0 = halo row j0-1
+  const int xs = dummy ? 0 : wv - r * wpr;   // x segment of the row
   const int j = j0 - 1 + r;
-  const bool halo = !dummy && (r == 0);
-  const bool row_ok = !dummy && (j >= 0) && (j < ny);
+  const bool halo = !dummy && r == 0;
+  const bool row_ok = !dummy && j >= 0 && j < ny;
+  const bool own = row_ok && !halo;
   const int jc = min(max(j, 0), ny - 1);
-  const int xl = (xs * kWave + lane) * V;  // first sample of the lane within the row
-  const bool lane_ok = xl < nx;
-  const bool ld_ok = row_ok && lane_ok;
-  const bool own = !halo && ld_ok;
-  const uint32_t plane = (uint32_t)ny * (uint32_t)px;
-  const uint32_t rowoff = (uint32_t)jc * (uint32_t)px + (uint32_t)xl;
-  const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
-  const uint64_t cs = a.cstride;
-  const T* __restrict__ fEx = a.fin;
-  const T* __restrict__ fEy = a.fin + cs;
-  const T* __restrict__ fEz = a.fin + 2 * cs;
-  const T* __restrict__ fHx = a.fin + 3 * cs;
-  const T* __restrict__ fHy = a.fin + 4 * cs;
-  const T* __restrict__ fHz = a.fin + 5 * cs;
-
-  bool xin[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) xin[e] = (xl + e) < nx;
-
   const bool iny = row_ok && (j < Ly || j >= ny - Ly);
   const int sy = j < Ly ? j : j - ny + 2 * Ly;
-  // x-layer membership and the lane's constant x profiles (E and H side)
-  bool inx[V];
-  int sxv[V];
-  C bxe[V], axe[V], kxe[V], bxh[V], axh[V], kxh[V];
-  bool lane_inx = false;
+  const int jt = j0 + ty;                    // row above the tile
+  const bool top_ok = halo && jt < ny;
+  const int wx0 = xs * kWave * V;            // first sample of the wave
+  const bool wave_inx = row_ok && Lx > 0 && (wx0 < Lx || wx0 + kWave * V > nx - Lx);
+
+  // ---- per-lane offsets (loop invariant; kOut: nothing there) ----
+  const int xl = wx0 + lane * V;             // first sample of the lane
+  const bool lane_ok = xl < nx;
+  constexpr uint32_t TB = sizeof(T), CB = sizeof(C);
+  const uint32_t plane = (uint32_t)ny * (uint32_t)px;
+  const uint32_t vrow = (row_ok && lane_ok) ? ((uint32_t)jc * (uint32_t)px + (uint32_t)xl) * TB : kOut;
+  const uint32_t vtop = (top_ok && lane_ok) ? ((uint32_t)jt * (uint32_t)px + (uint32_t)xl) * TB : kOut;
+  const uint32_t vxc = (row_ok && lane_ok) ? (uint32_t)xl * CB : kOut;
+  uint32_t vxs[V], vcf[V];
+  const int sx0 = xl < Lx ? xl : xl - nx + 2 * Lx;
+  bool lane_inx = false;   // the lane holds x-layer samples: x-slab accesses are exec-masked to
+                           // these lanes (out-of-range lanes would still occupy the address unit)
 #pragma unroll
   for (int e = 0; e < V; ++e) {
     const int i = xl + e;
-    inx[e] = row_ok && xin[e] && (i < Lx || i >= nx - Lx);
-    sxv[e] = i < Lx ? i : i - nx + 2 * Lx;
-    bxe[e] = C(1); axe[e] = C(0); kxe[e] = C(1); bxh[e] = C(1); axh[e] = C(0); kxh[e] = C(1);
-    if (inx[e]) {
-      bxe[e] = a.prof[(0 * 3 + 0) * a.plen + i];
-      axe[e] = a.prof[(0 * 3 + 1) * a.plen + i];
-      kxe[e] = a.prof[(0 * 3 + 2) * a.plen + i];
-      bxh[e] = a.prof[(9 + 0) * a.plen + i];
-      axh[e] = a.prof[(9 + 1) * a.plen + i];
-      kxh[e] = a.prof[(9 + 2) * a.plen + i];
-    }
-    lane_inx = lane_inx || inx[e];
+    const bool inx = row_ok && i < nx && (i < Lx || i >= nx - Lx);
+    lane_inx = lane_inx || inx;
+    vxs[e] = inx ? (uint32_t)(sx0 + e) * CB : kOut;
+    vcf[e] = (row_ok && i < nx) ? (uint32_t)(a.seg[i] + a.seg[px + jc] * a.nsx) * (uint32_t)sizeof(Coef2<C>) : kOut;
   }
-  // y profiles (uniform over the row)
-  C bye = 1, aye = 0, kye = 1, byh = 1, ayh = 0, kyh = 1;
-  if (iny) {
-    bye = a.prof[(3 + 0) * a.plen + j]; aye = a.prof[(3 + 1) * a.plen + j]; kye = a.prof[(3 + 2) * a.plen + j];
-    byh = a.prof[(12 + 0) * a.plen + j]; ayh = a.prof[(12 + 1) * a.plen + j]; kyh = a.prof[(12 + 2) * a.plen + j];
-  }
-  int segxy[V];
-#pragma unroll
-  for (int e = 0; e < V; ++e) segxy[e] = (xin[e] ? a.seg[xl + e] : 0) + a.seg[px + jc] * a.nsx;
-
-  // Small per-lane data of plane k (into aux): issued ahead of the plane prefetch.
-  auto load_aux = [&](int k, PlaneAux<C, V>& x) {
-    const bool upd = (k >= k0) && own;
-    const bool inz = row_ok && (k < Lz || k >= nz - Lz);
+  const uint32_t plane_b = plane * TB;
+  const uint32_t cs_b = (uint32_t)(a.cstride * TB);   // field sets are < 2 GiB (checked on the host)
+  const rsrc_t rin = make_rsrc(a.fin, 6 * cs_b);
+  const rsrc_t rout = make_rsrc(a.fout, 6 * cs_b);
+  const char* psb = reinterpret_cast<const char*>(a.pse);
+  const uint32_t phin = (uint32_t)(reinterpret_cast<const char*>(a.psh_in) - psb);
+  const uint32_t phout = (uint32_t)(reinterpret_cast<const char*>(a.psh_out) - psb);
+  const rsrc_t rpsi = make_rsrc(a.pse, max(phin, phout) + a.psi_bytes);
+  const rsrc_t rcoef = make_rsrc(a.coef, a.coef_bytes);
+  const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
+  const C dtm = a.dt_mu;
+  // byte offsets (inside a psi region) of plane k of array q in the y, z, x slabs
+  auto yso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * (2 * Ly) + sy) * (uint32_t)px) * CB; };
+  auto zso = [&](int k, int q) {
     const int sz = k < Lz ? k : k - nz + 2 * Lz;
-    const uint32_t qy = ((uint32_t)k * (2 * Ly) + sy) * px + xl;
-    const uint32_t qz = ((uint32_t)sz * ny + jc) * px + xl;
-    const uint32_t qx = ((uint32_t)k * ny + jc) * (2 * Lx);
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-#pragma unroll
-      for (int u = 0; u < 6; ++u) { x.ph[u][e] = C(0); x.pe[u][e] = C(0); }
-      x.pm[e] = 0;
+    return (a.psoff[q] + ((uint32_t)sz * ny + jc) * (uint32_t)px) * CB;
+  };
+  auto xso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * ny + jc) * (uint32_t)(2 * Lx)) * CB; };
+  auto in_z = [&](int k) { return k < Lz || k >= nz - Lz; };
+
+  C* myE = ldsE + r * 3 * RS + V + xl;       // lane's samples in its LDS rows (+ c * RS)
+  C* myH = ldsH + r * 3 * RS + V + xl;
+
+  auto load_E = [&](int k, C (&out)[3][V]) {
+    const uint32_t so = (uint32_t)k * plane_b;   // k <= nz: plane nz is the zero plane
+    ld_row<T, C, V>(rin, vrow, so, out[0], a.dec[0]);
+    ld_row<T, C, V>(rin, vrow, so + cs_b, out[1], a.dec[1]);
+    ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[2]);
+  };
+  auto load_H = [&](int k, C (&out)[3][V]) {
+    const uint32_t so = 3 * cs_b + (uint32_t)k * plane_b;
+    ld_row<T, C, V>(rin, vrow, so, out[0], a.dec[3]);
+    if (!halo) ld_row<T, C, V>(rin, vrow, so + cs_b, out[1], a.dec[4]);
+    ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[5]);
+  };
+  auto load_top = [&](int k, C (&tz)[V], C (&tx)[V]) {
+    if (top_ok) {
+      const uint32_t so = (uint32_t)k * plane_b;
+      ld_row<T, C, V>(rin, vtop, so + 2 * cs_b, tz, a.dec[2]);
+      ld_row<T, C, V>(rin, vtop, so, tx, a.dec[0]);
     }
+  };
+  C ph[6][V];   // H-side psi of the current plane
+  auto load_ph = [&](int k) {
     if (iny) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        if (!xin[e]) continue;
-        x.ph[PHXY][e] = a.psh_in[a.psoff[PHXY] + qy + e];
-        x.ph[PHZY][e] = a.psh_in[a.psoff[PHZY] + qy + e];
-        if (upd) { x.pe[PEXY][e] = a.pse[a.psoff[PEXY] + qy + e]; x.pe[PEZY][e] = a.pse[a.psoff[PEZY] + qy + e]; }
+        ph[PHXY][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + yso(k, PHXY));
+        ph[PHZY][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + yso(k, PHZY));
       }
     }
-    if (inz) {
+    if (row_ok && in_z(k)) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        if (!xin[e]) continue;
-        x.ph[PHXZ][e] = a.psh_in[a.psoff[PHXZ] + qz + e];
-        x.ph[PHYZ][e] = a.psh_in[a.psoff[PHYZ] + qz + e];
-        if (upd) { x.pe[PEXZ][e] = a.pse[a.psoff[PEXZ] + qz + e]; x.pe[PEYZ][e] = a.pse[a.psoff[PEYZ] + qz + e]; }
+        ph[PHXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + zso(k, PHXZ));
+        ph[PHYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + zso(k, PHYZ));
       }
     }
-    if (lane_inx) {
+    if (wave_inx && lane_inx) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        if (!inx[e]) continue;
-        x.ph[PHYX][e] = a.psh_in[a.psoff[PHYX] + qx + sxv[e]];
-        x.ph[PHZX][e] = a.psh_in[a.psoff[PHZX] + qx + sxv[e]];
-        if (upd) { x.pe[PEYX][e] = a.pse[a.psoff[PEYX] + qx + sxv[e]]; x.pe[PEZX][e] = a.pse[a.psoff[PEZX] + qx + sxv[e]]; }
+        ph[PHYX][e] = buf_ld<C>(rpsi, vxs[e], phin + xso(k, PHYX));
+        ph[PHZX][e] = buf_ld<C>(rpsi, vxs[e], phin + xso(k, PHZX));
       }
-    }
-    const int zs = tzs[k - kstart];
-#pragma unroll
-    for (int e = 0; e < V; ++e) x.cf[e] = a.coef[segxy[e] + zs];
-    const int pl = tzl[k - kstart];
-    if (pl >= 0 && own) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) x.pm[e] = a.pec_mask[((uint32_t)pl * ny + jc) * px + xl + e];
     }
   };
 
-  // Software pipeline over the z-march: at plane k the registers hold E^n(k),
-  // E^n(k+1), H^{n-1/2}(k), the plane's small data (cur) and, in the halo
-  // waves, Ez/Ex of the row above the tile at plane k.
-  C ec[3][V], en[3][V], hc[3][V], tz[V], tx[V];
-  PlaneAux<C, V> cur;
-  const int jt = j0 + a.ty;  // row above the tile
-  const bool top_ok = halo && lane_ok && jt < ny;
-  const uint32_t rowoff_t = (uint32_t)min(jt, ny - 1) * (uint32_t)px + (uint32_t)xl;
-  {
-    load_aux(kstart, cur);
-    const uint32_t off = (uint32_t)kstart * plane + rowoff;
-    const bool ok1 = ld_ok && (kstart + 1 < nz);
-    load_row<T, C, V>(fEx, off, ld_ok, ec[0], a.dec[0]);
-    load_row<T, C, V>(fEy, off, ld_ok, ec[1], a.dec[1]);
-    load_row<T, C, V>(fEz, off, ld_ok, ec[2], a.dec[2]);
-    load_row<T, C, V>(fEx, off + plane, ok1, en[0], a.dec[0]);
-    load_row<T, C, V>(fEy, off + plane, ok1, en[1], a.dec[1]);
-    load_row<T, C, V>(fEz, off + plane, ok1, en[2], a.dec[2]);
-    load_row<T, C, V>(fHx, off, ld_ok, hc[0], a.dec[3]);
-    load_row<T, C, V>(fHy, off, ld_ok && !halo, hc[1], a.dec[4]);
-    load_row<T, C, V>(fHz, off, ld_ok, hc[2], a.dec[5]);
-    const uint32_t offt = (uint32_t)kstart * plane + rowoff_t;
-    load_row<T, C, V>(fEz, offt, top_ok, tz, a.dec[2]);
-    load_row<T, C, V>(fEx, offt, top_ok, tx, a.dec[0]);
+  // ---- prologue: plane kstart ----
+  C e0[3][V], e1[3][V], e2[3][V], h0[3][V], h1[3][V];
+  C hxp[V], hyp[V], tz0[V], tx0[V], tz1[V], tx1[V];
+  C pe[6][V];
+  Coef2<C> cf[V];
+  int cf_blk = -1;   // z block offset the coefficients in cf belong to
+  uint32_t pm[V];
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { e0[c][e] = C(0); e1[c][e] = C(0); e2[c][e] = C(0); h0[c][e] = C(0); h1[c][e] = C(0); }
+#pragma unroll
+    for (int u = 0; u < 6; ++u) { ph[u][e] = C(0); pe[u][e] = C(0); }
+    hxp[e] = C(0); hyp[e] = C(0); tz0[e] = C(0); tx0[e] = C(0); tz1[e] = C(0); tx1[e] = C(0);
+    pm[e] = 0u;
+    cf[e].ca = C(0); cf[e].cb = C(0);
   }
-  C hxp[V], hyp[V];  // H^{n+1/2}(k-1), own row
-#pragma unroll
-  for (int e = 0; e < V; ++e) { hxp[e] = C(0); hyp[e] = C(0); }
+  if (!dummy) {
+    load_ph(kstart);
+    load_E(kstart, e0);
+    load_E(kstart + 1, e1);
+    load_H(kstart, h0);
+    load_top(kstart, tz0, tx0);
+  }
 
-  C* rowE = ldsE + r * 3 * RL;        // own row in the E buffer
-  C* rowH = ldsH + r * 3 * RL;        // own row in the H buffer
-
-  // One plane of the march.  The registers of the plane prefetch come in two
-  // sets used alternately (en/hc/aux/tz of this plane, the other set filled
-  // for the next one), so no register whose load is still in flight is ever
-  // copied; the march is unrolled by two to alternate them.
-  auto plane_step = [&](const int k, C (&en)[3][V], C (&en2)[3][V], C (&hc)[3][V], C (&hn)[3][V],
-                        PlaneAux<C, V>& cur, PlaneAux<C, V>& nxt, C (&tz)[V], C (&tx)[V], C (&tzn)[V],
-                        C (&txn)[V]) {
-    const bool active = k >= k0;
-    const bool more = k + 1 < k1;  // another plane follows in this chunk
-    const uint32_t off = (uint32_t)k * plane + rowoff;
+  for (int k = kstart; k < k1; ++k) {
     const int kq = k - kstart;
-    const bool inz = row_ok && (k < Lz || k >= nz - Lz);
-    const int sz = k < Lz ? k : k - nz + 2 * Lz;
-    const bool upd = active && own;
-    const uint32_t qy = ((uint32_t)k * (2 * Ly) + sy) * px + xl;
-    const uint32_t qz = ((uint32_t)sz * ny + jc) * px + xl;
-    const uint32_t qx = ((uint32_t)k * ny + jc) * (2 * Lx);
+    const bool upd = own && k >= k0;      // uniform: this wave updates E and stores at plane k
+    const bool more = k + 1 < k1;
+    const bool inz = row_ok && in_z(k);
+    const int pln = uniform(tzl[kq]);
 
-    // ---- 1. loads for the next iterations: small data of plane k+1 first,
-    //         then E^n(k+2), H^{n-1/2}(k+1) and the next row above ----
-    if (more) load_aux(k + 1, nxt);
-    __builtin_amdgcn_sched_barrier(0);
-    {
-      const bool ok2 = ld_ok && more && (k + 2 < nz);
-      const bool okh = ld_ok && more;
-      load_row<T, C, V>(fEx, off + 2 * plane, ok2, en2[0], a.dec[0]);
-      load_row<T, C, V>(fEy, off + 2 * plane, ok2, en2[1], a.dec[1]);
-      load_row<T, C, V>(fEz, off + 2 * plane, ok2, en2[2], a.dec[2]);
-      load_row<T, C, V>(fHx, off + plane, okh, hn[0], a.dec[3]);
-      load_row<T, C, V>(fHy, off + plane, okh && !halo, hn[1], a.dec[4]);
-      load_row<T, C, V>(fHz, off + plane, okh, hn[2], a.dec[5]);
-      const uint32_t offt = (uint32_t)(k + 1) * plane + rowoff_t;
-      load_row<T, C, V>(fEz, offt, top_ok && more, tzn, a.dec[2]);
-      load_row<T, C, V>(fEx, offt, top_ok && more, txn, a.dec[0]);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-
-    // ---- 2. publish E^n(k) ----
-    if (!dummy) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        rowE[xl + e] = ec[0][e];
-        rowE[RL + xl + e] = ec[1][e];
-        rowE[2 * RL + xl + e] = ec[2][e];
-      }
-    }
-    if (halo) {
-      C* rt = ldsE + (a.ty + 1) * 3 * RL;
-#pragma unroll
-      for (int e = 0; e < V; ++e) { rt[xl + e] = tx[e]; rt[2 * RL + xl + e] = tz[e]; }
-    }
-    __syncthreads();
-
-    // ---- 3. H half step at plane k ----
-    const C bze = tzp[0 * nk1 + kq], aze = tzp[1 * nk1 + kq], kze = tzp[2 * nk1 + kq];
-    const C bzh = tzp[3 * nk1 + kq], azh = tzp[4 * nk1 + kq], kzh = tzp[5 * nk1 + kq];
-    C hx[V], hy[V], hz[V];
-    {
-      const C* up = rowE + 3 * RL;   // row j+1
-      C ezu[V], exu[V], ezr[V], eyr[V];
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        exu[e] = up[xl + e];
-        ezu[e] = up[2 * RL + xl + e];
-      }
-#pragma unroll
-      for (int e = 0; e < V - 1; ++e) { eyr[e] = ec[1][e + 1]; ezr[e] = ec[2][e + 1]; }
-      {
-        const int ir = xl + V;  // x+1 neighbour of the last sample (0 beyond the grid)
-        const bool okr = ir < nx;
-        eyr[V - 1] = okr ? rowE[RL + min(ir, RL - 1)] : C(0);
-        ezr[V - 1] = okr ? rowE[2 * RL + min(ir, RL - 1)] : C(0);
-      }
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        C dEz_dy = (ezu[e] - ec[2][e]) * idy;
-        C dEy_dz = (en[1][e] - ec[1][e]) * idz;
-        C dEx_dz = (en[0][e] - ec[0][e]) * idz;
-        C dEz_dx = (ezr[e] - ec[2][e]) * idx_;
-        C dEy_dx = (eyr[e] - ec[1][e]) * idx_;
-        C dEx_dy = (exu[e] - ec[0][e]) * idy;
-        if (iny) {
-          cur.ph[PHXY][e] = byh * cur.ph[PHXY][e] + ayh * dEz_dy;
-          cur.ph[PHZY][e] = byh * cur.ph[PHZY][e] + ayh * dEx_dy;
-          dEz_dy = kyh * dEz_dy + cur.ph[PHXY][e];
-          dEx_dy = kyh * dEx_dy + cur.ph[PHZY][e];
-        }
-        if (inz) {
-          cur.ph[PHXZ][e] = bzh * cur.ph[PHXZ][e] + azh * dEy_dz;
-          cur.ph[PHYZ][e] = bzh * cur.ph[PHYZ][e] + azh * dEx_dz;
-          dEy_dz = kzh * dEy_dz + cur.ph[PHXZ][e];
-          dEx_dz = kzh * dEx_dz + cur.ph[PHYZ][e];
-        }
-        if (inx[e]) {
-          cur.ph[PHYX][e] = bxh[e] * cur.ph[PHYX][e] + axh[e] * dEz_dx;
-          cur.ph[PHZX][e] = bxh[e] * cur.ph[PHZX][e] + axh[e] * dEy_dx;
-          dEz_dx = kxh[e] * dEz_dx + cur.ph[PHYX][e];
-          dEy_dx = kxh[e] * dEy_dx + cur.ph[PHZX][e];
-        }
-        const bool ok = row_ok && xin[e];
-        hx[e] = ok ? to_storage<T, C>(hc[0][e] - a.dt_mu * (dEz_dy - dEy_dz), a.enc[3], a.dec[3]) : C(0);
-        hy[e] = ok ? to_storage<T, C>(hc[1][e] - a.dt_mu * (dEx_dz - dEz_dx), a.enc[4], a.dec[4]) : C(0);
-        hz[e] = ok ? to_storage<T, C>(hc[2][e] - a.dt_mu * (dEy_dx - dEx_dy), a.enc[5], a.dec[5]) : C(0);
-      }
-    }
-
-    // ---- 4. publish H^{n+1/2}(k) ----
-    if (!dummy) {
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        rowH[xl + e] = hx[e];
-        rowH[RL + xl + e] = hy[e];
-        rowH[2 * RL + xl + e] = hz[e];
-      }
-    }
-    __syncthreads();
-
-    // ---- 5. E half step at plane k (own rows) and stores ----
+    // ---- 1. small loads of plane k for the E half ----
     if (upd) {
-      // H-side psi of the own row
       if (iny) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (xin[e]) {
-            a.psh_out[a.psoff[PHXY] + qy + e] = cur.ph[PHXY][e];
-            a.psh_out[a.psoff[PHZY] + qy + e] = cur.ph[PHZY][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          pe[PEXY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEXY));
+          pe[PEZY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEZY));
+        }
       }
       if (inz) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (xin[e]) {
-            a.psh_out[a.psoff[PHXZ] + qz + e] = cur.ph[PHXZ][e];
-            a.psh_out[a.psoff[PHYZ] + qz + e] = cur.ph[PHYZ][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          pe[PEXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEXZ));
+          pe[PEYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEYZ));
+        }
       }
-      if (lane_inx) {
+      if (wave_inx && lane_inx) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (inx[e]) {
-            a.psh_out[a.psoff[PHYX] + qx + sxv[e]] = cur.ph[PHYX][e];
-            a.psh_out[a.psoff[PHZX] + qx + sxv[e]] = cur.ph[PHZX][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          pe[PEYX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEYX));
+          pe[PEZX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEZX));
+        }
       }
-      const C* dn = rowH - 3 * RL;   // row j-1
-      C hxd[V], hzd[V], hyl[V], hzl[V];
+      const int zblk = uniform(tzs[kq]);
+      if (zblk != cf_blk) {   // (Ca, Cb) change along z only where the z block does
+        cf_blk = zblk;
+        const uint32_t cso = (uint32_t)zblk * (uint32_t)sizeof(Coef2<C>);
+#pragma unroll
+        for (int e = 0; e < V; ++e) cf[e] = buf_ld<Coef2<C>>(rcoef, vcf[e], cso);
+      }
+      if (pln >= 0) {
+        if (lane_ok) {
+          const uint8_t* mb = a.pec_mask + ((size_t)pln * ny + jc) * px + xl;
+#pragma unroll
+          for (int e = 0; e < V; ++e) pm[e] = mb[e];
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
+    if (more && !dummy) {
+      load_E(k + 2, e2);
+      load_H(k + 1, h1);
+      load_top(k + 1, tz1, tx1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 3. publish E^n(k) ----
+    if (!dummy) {
+      lds_put<C, V>(myE, e0[0]);
+      lds_put<C, V>(myE + RS, e0[1]);
+      lds_put<C, V>(myE + 2 * RS, e0[2]);
+      if (halo) {
+        C* rt = ldsE + (ty + 1) * 3 * RS + V + xl;
+        lds_put<C, V>(rt, tx0);
+        lds_put<C, V>(rt + 2 * RS, tz0);
+      }
+    }
+    __syncthreads();
+
+    // ---- 4. H half step at plane k ----
+    C hx[V], hy[V], hz[V];
+#pragma unroll
+    for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
+    if (row_ok) {
+      C exu[V], ezu[V], eyr[V], ezr[V];
+      lds_get<C, V>(myE + 3 * RS, exu);           // row j+1
+      lds_get<C, V>(myE + 5 * RS, ezu);
+#pragma unroll
+      for (int e = 0; e < V - 1; ++e) { eyr[e] = e0[1][e + 1]; ezr[e] = e0[2][e + 1]; }
+      eyr[V - 1] = myE[RS + V];                   // x+1 of the last sample (right pad: 0)
+      ezr[V - 1] = myE[2 * RS + V];
+      C dEz_dy[V], dEy_dz[V], dEx_dz[V], dEz_dx[V], dEy_dx[V], dEx_dy[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        hxd[e] = dn[xl + e];
-        hzd[e] = dn[2 * RL + xl + e];
+        dEz_dy[e] = (ezu[e] - e0[2][e]) * idy;
+        dEy_dz[e] = (e1[1][e] - e0[1][e]) * idz;
+        dEx_dz[e] = (e1[0][e] - e0[0][e]) * idz;
+        dEz_dx[e] = (ezr[e] - e0[2][e]) * idx_;
+        dEy_dx[e] = (eyr[e] - e0[1][e]) * idx_;
+        dEx_dy[e] = (exu[e] - e0[0][e]) * idy;
       }
+      if (iny) {
+        const C ob = typ[3 * (ty + 1) + r], av = typ[4 * (ty + 1) + r], kv = typ[5 * (ty + 1) + r];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          ph[PHXY][e] = ph[PHXY][e] - ob * ph[PHXY][e] + av * dEz_dy[e];
+          ph[PHZY][e] = ph[PHZY][e] - ob * ph[PHZY][e] + av * dEx_dy[e];
+          dEz_dy[e] = kv * dEz_dy[e] + ph[PHXY][e];
+          dEx_dy[e] = kv * dEx_dy[e] + ph[PHZY][e];
+        }
+      }
+      if (inz) {
+        const C ob = tzp[3 * nk1 + kq], av = tzp[4 * nk1 + kq], kv = tzp[5 * nk1 + kq];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          ph[PHXZ][e] = ph[PHXZ][e] - ob * ph[PHXZ][e] + av * dEy_dz[e];
+          ph[PHYZ][e] = ph[PHYZ][e] - ob * ph[PHYZ][e] + av * dEx_dz[e];
+          dEy_dz[e] = kv * dEy_dz[e] + ph[PHXZ][e];
+          dEx_dz[e] = kv * dEx_dz[e] + ph[PHYZ][e];
+        }
+      }
+      if (wave_inx) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          // lanes outside the layer read (1 - b, a, 1/kappa) = (0, 0, 1) and psi 0
+          const int i = xl + e;
+          const C ob = txp[3 * RL + i], av = txp[4 * RL + i], kv = txp[5 * RL + i];
+          ph[PHYX][e] = ph[PHYX][e] - ob * ph[PHYX][e] + av * dEz_dx[e];
+          ph[PHZX][e] = ph[PHZX][e] - ob * ph[PHZX][e] + av * dEy_dx[e];
+          dEz_dx[e] = kv * dEz_dx[e] + ph[PHYX][e];
+          dEy_dx[e] = kv * dEy_dx[e] + ph[PHZX][e];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        hx[e] = to_storage<T, C>(h0[0][e] - dtm * (dEz_dy[e] - dEy_dz[e]), a.enc[3], a.dec[3]);
+        hy[e] = halo ? C(0) : to_storage<T, C>(h0[1][e] - dtm * (dEx_dz[e] - dEz_dx[e]), a.enc[4], a.dec[4]);
+        hz[e] = to_storage<T, C>(h0[2][e] - dtm * (dEy_dx[e] - dEx_dy[e]), a.enc[5], a.dec[5]);
+      }
+      // new H-side psi of the own rows
+      if (upd) {
+        if (iny) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            buf_st<C>(ph[PHXY][e], rpsi, vxc + e * CB, phout + yso(k, PHXY));
+            buf_st<C>(ph[PHZY][e], rpsi, vxc + e * CB, phout + yso(k, PHZY));
+          }
+        }
+        if (inz) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            buf_st<C>(ph[PHXZ][e], rpsi, vxc + e * CB, phout + zso(k, PHXZ));
+            buf_st<C>(ph[PHYZ][e], rpsi, vxc + e * CB, phout + zso(k, PHYZ));
+          }
+        }
+        if (wave_inx && lane_inx) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            buf_st<C>(ph[PHYX][e], rpsi, vxs[e], phout + xso(k, PHYX));
+            buf_st<C>(ph[PHZX][e], rpsi, vxs[e], phout + xso(k, PHZX));
+          }
+        }
+      }
+    }
+    // lanes beyond nx publish zeros (the x+1 neighbour of the last sample)
+    if (!lane_ok) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
+    }
+
+    // ---- 5. publish H^{n+1/2}(k) ----
+    if (!dummy) {
+      lds_put<C, V>(myH, hx);
+      lds_put<C, V>(myH + RS, hy);
+      lds_put<C, V>(myH + 2 * RS, hz);
+    }
+    __syncthreads();
+
+    // ---- 6. H-side psi of plane k+1 (its registers are free now) ----
+    if (more && !dummy) load_ph(k + 1);
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- 7. E half step at plane k (own rows) and stores ----
+    if (upd) {
+      C hxd[V], hzd[V], hyl[V], hzl[V];
+      lds_get<C, V>(myH - 3 * RS, hxd);             // row j-1
+      lds_get<C, V>(myH - RS, hzd);
 #pragma unroll
       for (int e = 1; e < V; ++e) { hyl[e] = hy[e - 1]; hzl[e] = hz[e - 1]; }
-      {
-        const int il = max(xl - 1, 0);   // x-1 neighbour of the first sample (unused at i = 0)
-        hyl[0] = rowH[RL + il];
-        hzl[0] = rowH[2 * RL + il];
-      }
-      C exo[V], eyo[V], ezo[V];
+      hyl[0] = myH[RS - 1];                         // x-1 of the first sample (left pad at i = 0)
+      hzl[0] = myH[2 * RS - 1];
+      C dHz_dy[V], dHy_dz[V], dHx_dz[V], dHz_dx[V], dHy_dx[V], dHx_dy[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        const int i = xl + e;
-        C dHz_dy = (hz[e] - hzd[e]) * idy;
-        C dHy_dz = (hy[e] - hyp[e]) * idz;
-        C dHx_dz = (hx[e] - hxp[e]) * idz;
-        C dHz_dx = (hz[e] - hzl[e]) * idx_;
-        C dHy_dx = (hy[e] - hyl[e]) * idx_;
-        C dHx_dy = (hx[e] - hxd[e]) * idy;
-        // tangential E on the outer faces is never updated
-        const bool ux = (j > 0) && (k > 0) && xin[e];
-        const bool uy = (i > 0) && (k > 0) && xin[e];
-        const bool uz = (i > 0) && (j > 0) && xin[e];
-        if (iny) {
-          cur.pe[PEXY][e] = bye * cur.pe[PEXY][e] + aye * dHz_dy;
-          cur.pe[PEZY][e] = bye * cur.pe[PEZY][e] + aye * dHx_dy;
-          dHz_dy = kye * dHz_dy + cur.pe[PEXY][e];
-          dHx_dy = kye * dHx_dy + cur.pe[PEZY][e];
+        dHz_dy[e] = (hz[e] - hzd[e]) * idy;
+        dHy_dz[e] = (hy[e] - hyp[e]) * idz;
+        dHx_dz[e] = (hx[e] - hxp[e]) * idz;
+        dHz_dx[e] = (hz[e] - hzl[e]) * idx_;
+        dHy_dx[e] = (hy[e] - hyl[e]) * idx_;
+        dHx_dy[e] = (hx[e] - hxd[e]) * idy;
+      }
+      if (iny) {
+        const C ob = typ[0 * (ty + 1) + r], av = typ[1 * (ty + 1) + r], kv = typ[2 * (ty + 1) + r];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          pe[PEXY][e] = pe[PEXY][e] - ob * pe[PEXY][e] + av * dHz_dy[e];
+          pe[PEZY][e] = pe[PEZY][e] - ob * pe[PEZY][e] + av * dHx_dy[e];
+          dHz_dy[e] = kv * dHz_dy[e] + pe[PEXY][e];
+          dHx_dy[e] = kv * dHx_dy[e] + pe[PEZY][e];
         }
-        if (inz) {
-          cur.pe[PEXZ][e] = bze * cur.pe[PEXZ][e] + aze * dHy_dz;
-          cur.pe[PEYZ][e] = bze * cur.pe[PEYZ][e] + aze * dHx_dz;
-          dHy_dz = kze * dHy_dz + cur.pe[PEXZ][e];
-          dHx_dz = kze * dHx_dz + cur.pe[PEYZ][e];
+      }
+      if (inz) {
+        const C ob = tzp[0 * nk1 + kq], av = tzp[1 * nk1 + kq], kv = tzp[2 * nk1 + kq];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          pe[PEXZ][e] = pe[PEXZ][e] - ob * pe[PEXZ][e] + av * dHy_dz[e];
+          pe[PEYZ][e] = pe[PEYZ][e] - ob * pe[PEYZ][e] + av * dHx_dz[e];
+          dHy_dz[e] = kv * dHy_dz[e] + pe[PEXZ][e];
+          dHx_dz[e] = kv * dHx_dz[e] + pe[PEYZ][e];
         }
-        if (inx[e]) {
-          cur.pe[PEYX][e] = bxe[e] * cur.pe[PEYX][e] + axe[e] * dHz_dx;
-          cur.pe[PEZX][e] = bxe[e] * cur.pe[PEZX][e] + axe[e] * dHy_dx;
-          dHz_dx = kxe[e] * dHz_dx + cur.pe[PEYX][e];
-          dHy_dx = kxe[e] * dHy_dx + cur.pe[PEZX][e];
+      }
+      if (wave_inx) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int i = xl + e;
+          const C ob = txp[0 * RL + i], av = txp[1 * RL + i], kv = txp[2 * RL + i];
+          pe[PEYX][e] = pe[PEYX][e] - ob * pe[PEYX][e] + av * dHz_dx[e];
+          pe[PEZX][e] = pe[PEZX][e] - ob * pe[PEZX][e] + av * dHy_dx[e];
+          dHz_dx[e] = kv * dHz_dx[e] + pe[PEYX][e];
+          dHy_dx[e] = kv * dHy_dx[e] + pe[PEZX][e];
         }
-        const C ca = cur.cf[e].ca, cb = cur.cf[e].cb;
-        const uint32_t m = cur.pm[e];
-        const C cax = (m & 1) ? C(0) : ca, cbx = (m & 1) ? C(0) : cb;
-        const C cay = (m & 2) ? C(0) : ca, cby = (m & 2) ? C(0) : cb;
-        const C caz = (m & 4) ? C(0) : ca, cbz = (m & 4) ? C(0) : cb;
-        exo[e] = ux ? cax * ec[0][e] + cbx * (dHz_dy - dHy_dz) : ec[0][e];
-        eyo[e] = uy ? cay * ec[1][e] + cby * (dHx_dz - dHz_dx) : ec[1][e];
-        ezo[e] = uz ? caz * ec[2][e] + cbz * (dHy_dx - dHx_dy) : ec[2][e];
-        // E-side psi of the updated samples (wall samples keep 0)
-        if (!ux) { cur.pe[PEXY][e] = C(0); cur.pe[PEXZ][e] = C(0); }
-        if (!uy) { cur.pe[PEYZ][e] = C(0); cur.pe[PEYX][e] = C(0); }
-        if (!uz) { cur.pe[PEZX][e] = C(0); cur.pe[PEZY][e] = C(0); }
+      }
+      C exo[V], eyo[V], ezo[V];
+      const bool ux = j > 0 && k > 0;     // uniform: Ex off the outer faces
+      const bool uy = k > 0;              // uniform part (Ey, Ez also need i > 0)
+      const bool uz = j > 0;
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        C cax = cf[e].ca, cbx = cf[e].cb, cay = cax, cby = cbx, caz = cax, cbz = cbx;
+        if (pln >= 0) {
+          const uint32_t m = pm[e];
+          if (m & 1) { cax = C(0); cbx = C(0); }
+          if (m & 2) { cay = C(0); cby = C(0); }
+          if (m & 4) { caz = C(0); cbz = C(0); }
+        }
+        exo[e] = cax * e0[0][e] + cbx * (dHz_dy[e] - dHy_dz[e]);
+        eyo[e] = cay * e0[1][e] + cby * (dHx_dz[e] - dHz_dx[e]);
+        ezo[e] = caz * e0[2][e] + cbz * (dHy_dx[e] - dHx_dy[e]);
+      }
+      if (!ux) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) { exo[e] = e0[0][e]; pe[PEXY][e] = C(0); pe[PEXZ][e] = C(0); }
+      }
+      if (!uy) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) { eyo[e] = e0[1][e]; pe[PEYZ][e] = C(0); pe[PEYX][e] = C(0); }
+      }
+      if (!uz) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) { ezo[e] = e0[2][e]; pe[PEZX][e] = C(0); pe[PEZY][e] = C(0); }
+      }
+      // samples beyond nx in a lane's vector (rows not a multiple of V): never updated
+      if (V > 1 && (nx % V) != 0 && wx0 + kWave * V > nx) {
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+          if (xl + e >= nx) {
+            exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e];
+#pragma unroll
+            for (int u = 0; u < 6; ++u) pe[u][e] = C(0);
+          }
+      }
+      // E samples at i = 0 are on the outer face: never updated
+      if (xs == 0) {
+        if (lane == 0) {
+          eyo[0] = e0[1][0];
+          ezo[0] = e0[2][0];
+          pe[PEYZ][0] = C(0); pe[PEYX][0] = C(0); pe[PEZX][0] = C(0); pe[PEZY][0] = C(0);
+        }
       }
       if (iny) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (xin[e]) {
-            a.pse[a.psoff[PEXY] + qy + e] = cur.pe[PEXY][e];
-            a.pse[a.psoff[PEZY] + qy + e] = cur.pe[PEZY][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          buf_st<C>(pe[PEXY][e], rpsi, vxc + e * CB, yso(k, PEXY));
+          buf_st<C>(pe[PEZY][e], rpsi, vxc + e * CB, yso(k, PEZY));
+        }
       }
       if (inz) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (xin[e]) {
-            a.pse[a.psoff[PEXZ] + qz + e] = cur.pe[PEXZ][e];
-            a.pse[a.psoff[PEYZ] + qz + e] = cur.pe[PEYZ][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          buf_st<C>(pe[PEXZ][e], rpsi, vxc + e * CB, zso(k, PEXZ));
+          buf_st<C>(pe[PEYZ][e], rpsi, vxc + e * CB, zso(k, PEYZ));
+        }
       }
-      if (lane_inx) {
+      if (wave_inx && lane_inx) {
 #pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (inx[e]) {
-            a.pse[a.psoff[PEYX] + qx + sxv[e]] = cur.pe[PEYX][e];
-            a.pse[a.psoff[PEZX] + qx + sxv[e]] = cur.pe[PEZX][e];
-          }
+        for (int e = 0; e < V; ++e) {
+          buf_st<C>(pe[PEYX][e], rpsi, vxs[e], xso(k, PEYX));
+          buf_st<C>(pe[PEZX][e], rpsi, vxs[e], xso(k, PEZX));
+        }
       }
       const uint8_t flags = tfl[r * nk1 + kq];
       if (flags & 1) {
@@ -612,12 +779,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1]);
         ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
       }
-      store_row<T, C, V>(a.fout, off, exo, a.enc[0]);
-      store_row<T, C, V>(a.fout + cs, off, eyo, a.enc[1]);
-      store_row<T, C, V>(a.fout + 2 * cs, off, ezo, a.enc[2]);
-      store_row<T, C, V>(a.fout + 3 * cs, off, hx, a.enc[3]);
-      store_row<T, C, V>(a.fout + 4 * cs, off, hy, a.enc[4]);
-      store_row<T, C, V>(a.fout + 5 * cs, off, hz, a.enc[5]);
+      const uint32_t so = (uint32_t)k * plane_b;
+      st_row<T, C, V>(rout, vrow, so, exo, a.enc[0]);
+      st_row<T, C, V>(rout, vrow, so + cs_b, eyo, a.enc[1]);
+      st_row<T, C, V>(rout, vrow, so + 2 * cs_b, ezo, a.enc[2]);
+      st_row<T, C, V>(rout, vrow, so + 3 * cs_b, hx, a.enc[3]);
+      st_row<T, C, V>(rout, vrow, so + 4 * cs_b, hy, a.enc[4]);
+      st_row<T, C, V>(rout, vrow, so + 5 * cs_b, hz, a.enc[5]);
       if (flags & 2) {
         for (int p = 0; p < a.nprobe; ++p) {
           const int4 pr = a.probe[p];
@@ -634,28 +802,35 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         }
       }
     }
+
+    // ---- 8. advance the register window ----
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       hxp[e] = hx[e];
       hyp[e] = hy[e];
+      tz0[e] = tz1[e];
+      tx0[e] = tx1[e];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ec[c][e] = en[c][e];   // E^n(k+1) has arrived: it was used above
+      for (int c = 0; c < 3; ++c) {
+        e0[c][e] = e1[c][e];
+        e1[c][e] = e2[c][e];
+        h0[c][e] = h1[c][e];
+      }
     }
-  };
-
-  C en_b[3][V], hc_b[3][V], tz_b[V], tx_b[V];
-  PlaneAux<C, V> aux_b;
-  for (int k = kstart; k < k1; k += 2) {
-    plane_step(k, en, en_b, hc, hc_b, cur, aux_b, tz, tx, tz_b, tx_b);
-    if (k + 1 < k1) plane_step(k + 1, en_b, en, hc_b, hc, aux_b, cur, tz_b, tx_b, tz, tx);
   }
 }
 
 // ---------------------------------------------------------------------------
 // The fused step kernel: one grid, one tile per workgroup.
 // ---------------------------------------------------------------------------
+// Waves per SIMD the step kernel is compiled for: two 16-wave workgroups per
+// CU in FP32 / FP16 storage with one sample per lane (at most 64 VGPRs).
+template <class C, int V>
+constexpr int step_waves_per_eu() { return 1; }
+
 template <class T, class C, int V>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
+__attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 step_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
   // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to

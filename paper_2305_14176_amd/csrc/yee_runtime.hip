@@ -7,7 +7,9 @@
 //                                                  (Taflove & Hagness ch. 3)
 //   CPML: x = depth/L, sigma = sigma_max x^m, kappa = 1 + (kappa_max - 1) x^m,
 //         alpha = alpha_max (1 - x), b = exp(-(sigma/kappa + alpha) dt/eps0),
-//         a = sigma (b - 1)/(kappa (sigma + kappa alpha))     (Roden & Gedney 2000)
+//         a = sigma (b - 1)/(kappa (sigma + kappa alpha))     (Roden & Gedney 2000);
+//         the tables hold 1 - b, and psi <- b psi + a dF is evaluated as
+//         psi - (1 - b) psi + a dF
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -148,7 +150,9 @@ void layout(yee_ctx* c) {
   };
   // component arrays are skewed by an odd number of 256-byte units so that the
   // same (i, j, k) of the twelve streams does not land on one HBM channel
-  c->comp_bytes = align256((size_t)d.nz * d.ny * c->px * c->tsize) + YEE_COMP_SKEW_BYTES;
+  // one zero plane after the last one: the march prefetches plane nz (the
+  // tangential E above the top face, identically zero) without a branch
+  c->comp_bytes = align256((size_t)(d.nz + 1) * d.ny * c->px * c->tsize) + YEE_COMP_SKEW_BYTES;
   for (int s = 0; s < 2; ++s) take(c->fields[s], 6 * c->comp_bytes);
   psi_lengths(c, c->psi_len);
   size_t psin = 0;
@@ -178,9 +182,12 @@ void layout(yee_ctx* c) {
 
 // Roden-Gedney profile along one axis of n cells with a layer of L cells.
 // side 0: E (positions 0..n-1 integer), side 1: H (positions i + 1/2).
+// The decay factor is kept as omb = 1 - b (computed with expm1): near the
+// inner edge of the layer b is within 1e-4 of 1, and in FP32 the difference
+// would otherwise carry a relative error of order 1e-3.
 void cpml_profile(const yee_grid_desc& d, double dw, double dt, int n, int L, int side,
-                  std::vector<double>& b, std::vector<double>& a, std::vector<double>& kinv) {
-  b.assign(n, 1.0);
+                  std::vector<double>& omb, std::vector<double>& a, std::vector<double>& kinv) {
+  omb.assign(n, 0.0);
   a.assign(n, 0.0);
   kinv.assign(n, 1.0);
   if (L <= 0) return;
@@ -193,10 +200,10 @@ void cpml_profile(const yee_grid_desc& d, double dw, double dt, int n, int L, in
     const double sg = smax * xm;
     const double kp = 1.0 + (d.cpml_kappa_max - 1.0) * xm;
     const double al = d.cpml_alpha_max * (1.0 - x);
-    const double bb = std::exp(-(sg / kp + al) * dt / kEps0);
+    const double om = -std::expm1(-(sg / kp + al) * dt / kEps0);
     const double den = kp * (sg + kp * al);
-    b[i] = bb;
-    a[i] = (sg > 0.0 && den > 0.0) ? sg * (bb - 1.0) / den : 0.0;
+    omb[i] = om;
+    a[i] = (sg > 0.0 && den > 0.0) ? -sg * om / den : 0.0;
     kinv[i] = 1.0 / kp;
   }
 }
@@ -290,6 +297,8 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   a.wpr = waves_per_row(d.nx, V);
   a.ny_tiles = (d.ny + ty - 1) / ty;
   a.ntiles = a.ny_tiles * ((d.nz + kz - 1) / kz);
+  a.psi_bytes = (uint32_t)c->psi_e.bytes;
+  a.coef_bytes = (uint32_t)c->coef.bytes;
   return a;
 }
 
@@ -347,9 +356,10 @@ void default_launch(yee_ctx* c) {
   // samples per lane: one while a row fits in four waves, else two
   c->V = c->vpl ? c->vpl : (d.nx <= 4 * yee::kWave ? 1 : 2);
   const int wpr = waves_per_row(d.nx, c->V);
-  // as many rows as the workgroup holds, up to seven (measured best for the
-  // 256^3 grid: three rows of four waves plus the halo row)
-  if (c->ty == 0) c->ty = std::max(1, std::min({7, d.ny, yee::max_block_waves(c->V) / wpr - 1}));
+  // rows per tile: workgroups of at most 12 waves, so that two fit a CU (the
+  // step kernel uses 64 VGPRs); measured best for the 256^3 grid: two rows of
+  // four waves plus the halo row
+  if (c->ty == 0) c->ty = std::max(1, std::min({7, d.ny, 12 / wpr - 1}));
   if (c->kz == 0) {
     // enough workgroups to fill 256 CUs several times over, but keep the
     // per-chunk warm-up plane a small fraction of the march
@@ -437,6 +447,12 @@ yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out) {
   if ((uint64_t)d.nz * d.ny * c->px >= (1ull << 31)) {
     delete c;
     return fail(YEE_EINVAL, "grid too large for 32-bit element offsets");
+  }
+  // the step addresses a field set (six components) and the psi regions with
+  // 32-bit byte offsets
+  if (6 * ((uint64_t)(d.nz + 1) * d.ny * c->px * c->tsize + 256) >= (1ull << 31)) {
+    delete c;
+    return fail(YEE_EINVAL, "grid too large: a set of six components must stay below 2 GiB");
   }
   c->dt = d.courant / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz)));
   c->segx.assign(d.nx, 0);
@@ -595,7 +611,7 @@ yee_status yee_reset(yee_ctx* c, void* stream) {
     for (int ax = 0; ax < 3; ++ax) {
       std::vector<double> b, a, k;
       cpml_profile(d, dw[ax], c->dt, n3[ax], d.cpml_cells[ax], side, b, a, k);
-      b.resize(c->prof_len, 1.0); a.resize(c->prof_len, 0.0); k.resize(c->prof_len, 1.0);
+      b.resize(c->prof_len, 0.0); a.resize(c->prof_len, 0.0); k.resize(c->prof_len, 1.0);
       const size_t base = ((size_t)(side * 3 + ax) * 3) * c->prof_len * c->csize;
       if (c->csize == 8) {
         put<double>(pbuf, base, b); put<double>(pbuf, base + c->prof_len * 8, a); put<double>(pbuf, base + 2 * c->prof_len * 8, k);
