@@ -26,9 +26,10 @@ What is computed (the paper is silent on all of it; textbook definitions):
 * Soft sources add amp * w((n+1) dt) to one E sample after the E update.
 * Probes record a component after the step; the running DFT accumulates
   X(f) += y^{n+1} exp(-i 2 pi f (n+1) dt) dt in FP64.
-* Optional FP16-storage emulation: each stored component is rounded as
-  x <- fp16_RNE(x 2^s) 2^-s once per step (H after the H update, E after the
-  E update and the source injection); the arithmetic stays FP64.
+* Optional storage emulation: each stored component is rounded once per step
+  (H after the H update, E after the E update and the source injection), as
+  x <- fp16_RNE(x 2^s) 2^-s (FP16 storage) or x <- fp32_RNE(x) (FP32
+  storage); the arithmetic stays FP64.
 """
 from __future__ import annotations
 
@@ -73,6 +74,11 @@ def material_coefficients(eps_r, sigma, dt):
     ca = (1.0 - s) / (1.0 + s)
     cb = (dt / eps) / (1.0 + s)
     return ca, cb
+
+
+def round_fp32(x):
+    """fp32 storage emulation: round to binary32 (nearest even) and back."""
+    return np.asarray(np.asarray(x, dtype=np.float64).astype(np.float32), dtype=np.float64)
 
 
 def round_fp16_scaled(x, s: int):
@@ -195,8 +201,8 @@ class Simulation:
     pec : optional dict "Ex"/"Ey"/"Ez" -> bool array of that component's shape;
         True samples get Ca = Cb = 0.
     cpml : CpmlParams (cells = 0 for a plain PEC box).
-    storage : "f64" or "f16" (FP16-storage emulation with exponents fp16_exp
-        for Ex, Ey, Ez, Hx, Hy, Hz).
+    storage : "f64", "f16" (FP16-storage emulation with exponents fp16_exp
+        for Ex, Ey, Ez, Hx, Hy, Hz) or "f32" (FP32-storage emulation).
     """
 
     def __init__(self, nx, ny, nz, dx, dy=None, dz=None, courant=0.99,
@@ -273,11 +279,13 @@ class Simulation:
     def _store(self, comp_index, x):
         if self.storage == "f16":
             return round_fp16_scaled(x, self.fp16_exp[comp_index])
+        if self.storage == "f32":
+            return round_fp32(x)
         return x
 
     def set_fields(self, **arrays):
         """Set initial components (E^0 or H^{-1/2}); stored values are rounded
-        like every other stored value in FP16-storage mode."""
+        like every other stored value in a storage-emulation mode."""
         for name, arr in arrays.items():
             idx = COMPONENTS.index(name)
             tgt = self.E if name in self.E else self.H

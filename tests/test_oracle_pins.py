@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from oracle.yee import (C0, EPS0, MU0, COMPONENTS, CpmlParams, Probe, Simulation,
-                        Source, dft_accumulate, material_coefficients, round_fp16_scaled,
+                        Source, dft_accumulate, material_coefficients, round_fp16_scaled, round_fp32,
                         time_step, yee_shape)
 
 
@@ -612,6 +612,15 @@ def test_waveform_closed_forms():
     m = Source(2, 0, 0, 0, "mod_gauss", 1.0, 200e-12, 50e-12, 10e9)
     assert m.waveform(200e-12) == 0.0
     assert abs(m.waveform(200e-12 + 25e-12) - np.exp(-0.25)) < 1e-15
+
+
+def test_fp32_rounding_rules():
+    assert round_fp32(1 + 2.0 ** -24) == 1.0                         # tie -> even
+    assert round_fp32(1 + 3 * 2.0 ** -24) == 1 + 2.0 ** -22           # tie -> even (up)
+    assert round_fp32(2.0 ** -149) == 2.0 ** -149                     # smallest subnormal kept
+    assert round_fp32(2.0 ** -151) == 0.0
+    x = np.random.default_rng(1).standard_normal(1000)
+    assert np.all(np.abs(round_fp32(x) - x) <= 2.0 ** -24 * np.abs(x))
 
 
 def test_fp16_rounding_rules():
