@@ -386,7 +386,13 @@ void host_to_storage(const double* in, std::vector<unsigned char>& out, const ye
 // Batched stepper (serving): FP32 contexts with rows of at most 256 samples
 // (one sample per lane) share one fixed-size launch.
 // ---------------------------------------------------------------------------
-constexpr int kBatchBlockWaves = 16;  // waves per workgroup of the batched launch
+#ifndef YEE_BATCH_WAVES
+#define YEE_BATCH_WAVES 12
+#endif
+#ifndef YEE_BATCH_GRID
+#define YEE_BATCH_GRID 3
+#endif
+constexpr int kBatchBlockWaves = YEE_BATCH_WAVES;  // waves per workgroup of the batched launch
 constexpr int kBatchMaxChunk = 32;    // planes per z-chunk of a batched grid
 using BatchDesc = yee::SlotDesc<float, float>;
 
@@ -800,7 +806,7 @@ yee_status yee_batch_bind_workspace(yee_batch* b, void* dev, int64_t bytes) {
   int dev_id = 0, cus = 0;
   HIP_TRY(hipGetDevice(&dev_id));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
-  b->grid = std::max(8, 2 * cus);  // two waves of workgroups over the CUs
+  b->grid = std::max(8, YEE_BATCH_GRID * cus);  // workgroups per CU of the persistent launch
   b->ws = static_cast<unsigned char*>(dev);
   b->ws_bytes = bytes;
   b->bound = true;
