@@ -85,7 +85,9 @@ struct StepArgs {
   C inv_d[3];
   C dt_mu;
   float enc[6], dec[6];     // FP16 storage scales (2^s, 2^-s)
-  int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, planes per chunk, waves per row
+  int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, most planes per segment, waves per row
+  const int32_t* wseg;      // segments of workgroup w: segs[wseg[w] .. wseg[w + 1])
+  const int4* segs;         // (y tile, first plane, end plane, 0)
   uint32_t psi_bytes;       // bytes of one psi region (E side; each H-side set is as large)
   uint32_t coef_bytes;      // bytes of the (Ca, Cb) table
 };
@@ -251,7 +253,7 @@ __device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const
 }
 
 // ---------------------------------------------------------------------------
-// The fused step: one tile (ytile, chunk) of one grid.  Waves beyond
+// The fused step: planes [k0, k1) of y-tile ytile of one grid (k1 - k0 <= kz).  Waves beyond
 // (ty + 1) * wpr (spare waves of a fixed-size workgroup) take part in the
 // barriers only.
 //
@@ -271,8 +273,8 @@ __device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const
 constexpr uint32_t kOut = 0x80000000u;
 
 template <class T, class C, int V>
-__device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int chunk,
-                                          unsigned char* smem_raw) {
+__device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int k0,
+                                          const int k1, unsigned char* smem_raw) {
   const int wpr = a.wpr;
   const int ty = a.ty;
   const int RL = wpr * kWave * V;
@@ -291,8 +293,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
   const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
   const int j0 = ytile * ty;
-  const int k0 = chunk * a.kz;
-  const int k1 = min(nz, k0 + a.kz);
   const int kstart = k0 > 0 ? k0 - 1 : 0;
   const int nk = k1 - kstart;
   const int tid = threadIdx.x;
@@ -405,10 +405,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     ld_row<T, C, V>(rin, vrow, so + cs_b, out[1], a.dec[1]);
     ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[2]);
   };
+  // Hy of the halo row is not needed; its load is still issued (with every
+  // lane out of range), so that every wave issues the same prefetch
+  const uint32_t vrow_hy = halo ? kOut : vrow;
   auto load_H = [&](int k, C (&out)[3][V]) {
     const uint32_t so = 3 * cs_b + (uint32_t)k * plane_b;
     ld_row<T, C, V>(rin, vrow, so, out[0], a.dec[3]);
-    if (!halo) ld_row<T, C, V>(rin, vrow, so + cs_b, out[1], a.dec[4]);
+    ld_row<T, C, V>(rin, vrow_hy, so + cs_b, out[1], a.dec[4]);
     ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[5]);
   };
   auto load_top = [&](int k, C (&tz)[V], C (&tx)[V]) {
@@ -460,13 +463,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     pm[e] = 0u;
     cf[e].ca = C(0); cf[e].cb = C(0);
   }
-  if (!dummy) {
-    load_ph(kstart);
-    load_E(kstart, e0);
-    load_E(kstart + 1, e1);
-    load_H(kstart, h0);
-    load_top(kstart, tz0, tx0);
-  }
+  load_ph(kstart);
+  load_E(kstart, e0);
+  load_E(kstart + 1, e1);
+  load_H(kstart, h0);
+  load_top(kstart, tz0, tx0);
+  // Let the prologue's loads land before the march: otherwise the wait
+  // analysis carries them into the loop as pending on the window registers and
+  // waits for every outstanding load in the middle of each plane.
+  __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 
   for (int k = kstart; k < k1; ++k) {
     const int kq = k - kstart;
@@ -515,10 +520,14 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     }
     __builtin_amdgcn_sched_barrier(0);
     // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
-    if (more && !dummy) {
-      load_E(k + 2, e2);
-      load_H(k + 1, h1);
-      load_top(k + 1, tz1, tx1);
+    // The rows of a wave that updates E always issue the same loads here, so
+    // that waits for the small loads above count past them (after the last
+    // plane: the zero plane, read once per segment).
+    {
+      const int kn = more ? k + 1 : nz;
+      load_E(more ? k + 2 : nz, e2);
+      load_H(kn, h1);
+      load_top(kn, tz1, tx1);
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -821,25 +830,35 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
 }
 
 // ---------------------------------------------------------------------------
-// The fused step kernel: one grid, one tile per workgroup.
+// The fused step kernel: one grid.  Workgroup w runs the z-segments
+// segs[wseg[w] .. wseg[w + 1]) one after another.  The host builds the list:
+// either one fixed chunk of kz planes per workgroup, or a partition of the
+// grid into as many pieces of equal modelled cost as workgroups fit the
+// device at once (a single round, so no workgroup waits for a slot and none
+// ends a long way behind the others).
 // ---------------------------------------------------------------------------
-// Waves per SIMD the step kernel is compiled for: two 16-wave workgroups per
-// CU in FP32 / FP16 storage with one sample per lane (at most 64 VGPRs).
+// Waves per SIMD the step kernel is compiled for.  FP32 arithmetic with one
+// sample per lane: six, so that two 12-wave workgroups share a CU (at most 80
+// VGPRs); otherwise no bound.
 template <class C, int V>
-constexpr int step_waves_per_eu() { return 1; }
+constexpr int step_waves_per_eu() { return (sizeof(C) == 4 && V == 1) ? 6 : 1; }
 
 template <class T, class C, int V>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 step_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
-  // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
-  // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
-  // y-tiles of one z-chunk share halo rows in that XCD's L2).
+  // XCD-aware order: consecutive workgroup ids are dealt round-robin to the
+  // 8 XCDs, so each XCD gets a contiguous run of the piece list (neighbouring
+  // y-tiles over one z-range, which share halo rows in that XCD's L2).
   const int per_xcd = gridDim.x >> 3;
-  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (t >= a.ntiles) return;
-  step_tile<T, C, V>(a, t % a.ny_tiles, t / a.ny_tiles, smem_raw);
+  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int s0 = a.wseg[w], s1 = a.wseg[w + 1];
+  for (int s = s0; s < s1; ++s) {
+    const int4 g = a.segs[s];
+    if (s > s0) __syncthreads();   // the next segment rebuilds the LDS tables
+    step_tile<T, C, V>(a, g.x, g.y, g.z, smem_raw);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -882,7 +901,8 @@ batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __res
       a.n = n;
       a.series_slot = (int32_t)(n % slots[s].series_len);
       const int tl = t - slots[s].tile0;
-      step_tile<T, C, V>(a, tl % a.ny_tiles, tl / a.ny_tiles, smem_raw);
+      const int kb = (tl / a.ny_tiles) * a.kz;
+      step_tile<T, C, V>(a, tl % a.ny_tiles, kb, min(a.nz, kb + a.kz), smem_raw);
     }
     __syncthreads();  // the next tile reuses the LDS
   }
