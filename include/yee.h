@@ -191,26 +191,6 @@ yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
  * waves, at most 16.  Results do not depend on the launch shape. */
 yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane);
 
-/* Work partition of the fused step kernel (host only: needs no device; a
- * context uses the same partition).  The (y-tile, plane) units of a grid of
- * ny rows and nz planes, cut into tiles of tile_rows rows, are split among
- * workgroups:
- *   chunk_planes > 0: one workgroup per (y tile, chunk of chunk_planes planes);
- *   chunk_planes = 0: `workgroups` (rounded down to a multiple of 8, at least
- *     8) pieces of equal modelled cost, so a launch of as many workgroups as
- *     fit the device at once runs in a single round.  Planes inside the y and
- *     z CPML layers (cpml_y, cpml_z cells thick) cost more per plane.
- * Workgroup w runs segments wseg[w] .. wseg[w + 1] - 1 in order; segment s
- * is segs[4 s .. 4 s + 3] = (y tile, first plane, end plane, 0).  Every unit
- * belongs to exactly one segment.  Outputs *n_workgroups (the launch grid),
- * *n_segments and *max_planes (longest segment); wseg (n_workgroups + 1
- * entries) and segs (room for max_segs segments) are filled when non-NULL.
- * YEE_EINVAL for sizes out of range or max_segs too small. */
-yee_status yee_plan_segments(int32_t ny, int32_t nz, int32_t tile_rows, int32_t cpml_y, int32_t cpml_z,
-                             int32_t chunk_planes, int32_t workgroups, int32_t* n_workgroups,
-                             int32_t* n_segments, int32_t* max_planes, int32_t* wseg, int32_t* segs,
-                             int32_t max_segs);
-
 /* ------------------------------------------------------------------------
  * Batched stepper for serving many grids (continuous batching).
  *

@@ -27,7 +27,7 @@ EXPORTED = (
     "yee_read_dft", "yee_set_launch", "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
     "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
     "yee_batch_info", "yee_adjoint_create", "yee_adjoint_destroy", "yee_adjoint_footprint",
-    "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward", "yee_plan_segments",
+    "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward",
 )
 
 
@@ -96,7 +96,6 @@ def load():
         "yee_read_series": (I32, [VP, I64, I64, P(D), VP]),
         "yee_read_dft": (I32, [VP, P(D), P(D), VP]),
         "yee_set_launch": (I32, [VP, I32, I32, I32]),
-        "yee_plan_segments": (I32, [I32, I32, I32, I32, I32, I32, I32, P(I32), P(I32), P(I32), P(I32), P(I32), I32]),
         "yee_batch_footprint": (I32, [I32, P(I64)]),
         "yee_batch_create": (I32, [I32, I64, I32, P(VP)]),
         "yee_batch_destroy": (None, [VP]),
@@ -126,21 +125,3 @@ def check(status, fn):
         msg = load().yee_last_error().decode(errors="replace")
         raise YeeError(status, fn, msg)
 
-
-def plan_segments(ny, nz, tile_rows, cpml_y=0, cpml_z=0, chunk_planes=0, workgroups=512):
-    """Work partition of the fused step kernel (host only, see yee_plan_segments).
-
-    Returns (wseg, segs, max_planes): wseg[w] .. wseg[w + 1] index the segments
-    of workgroup w; segs[s] = (y tile, first plane, end plane)."""
-    lib = load()
-    nwg, nseg, kzm = C.c_int32(), C.c_int32(), C.c_int32()
-    null = C.POINTER(C.c_int32)()
-    check(lib.yee_plan_segments(ny, nz, tile_rows, cpml_y, cpml_z, chunk_planes, workgroups,
-                                C.byref(nwg), C.byref(nseg), C.byref(kzm), null, null, 0), "yee_plan_segments")
-    wseg = (C.c_int32 * (nwg.value + 1))()
-    segs = (C.c_int32 * (4 * max(1, nseg.value)))()
-    check(lib.yee_plan_segments(ny, nz, tile_rows, cpml_y, cpml_z, chunk_planes, workgroups,
-                                C.byref(nwg), C.byref(nseg), C.byref(kzm), wseg, segs, nseg.value),
-          "yee_plan_segments")
-    s = [tuple(segs[4 * i:4 * i + 3]) for i in range(nseg.value)]
-    return list(wseg), s, kzm.value

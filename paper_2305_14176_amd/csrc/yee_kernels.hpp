@@ -85,9 +85,7 @@ struct StepArgs {
   C inv_d[3];
   C dt_mu;
   float enc[6], dec[6];     // FP16 storage scales (2^s, 2^-s)
-  int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, most planes per segment, waves per row
-  const int32_t* wseg;      // segments of workgroup w: segs[wseg[w] .. wseg[w + 1])
-  const int4* segs;         // (y tile, first plane, end plane, 0)
+  int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, planes per chunk, waves per row
   uint32_t psi_bytes;       // bytes of one psi region (E side; each H-side set is as large)
   uint32_t coef_bytes;      // bytes of the (Ca, Cb) table
 };
@@ -126,6 +124,12 @@ __device__ __noinline__ double waveform(const SrcDev s, double t) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Wave role of the march (0 own rows, 1 halo row, 2 spare), as a type.
+template <int N>
+struct Role {
+  static constexpr int value = N;
+};
 
 // LDS layout of one workgroup, in compute-type elements unless noted:
 //   E rows j0-1 .. j0+ty        [ty+2][3][RS]  (RS = wpr*64*V + 2V: one zero
@@ -347,7 +351,6 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   const int j = j0 - 1 + r;
   const bool halo = !dummy && r == 0;
   const bool row_ok = !dummy && j >= 0 && j < ny;
-  const bool own = row_ok && !halo;
   const int jc = min(max(j, 0), ny - 1);
   const bool iny = row_ok && (j < Ly || j >= ny - Ly);
   const int sy = j < Ly ? j : j - ny + 2 * Ly;
@@ -463,379 +466,405 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     pm[e] = 0u;
     cf[e].ca = C(0); cf[e].cb = C(0);
   }
-  load_ph(kstart);
-  load_E(kstart, e0);
-  load_E(kstart + 1, e1);
-  load_H(kstart, h0);
-  load_top(kstart, tz0, tx0);
-  // Let the prologue's loads land before the march: otherwise the wait
-  // analysis carries them into the loop as pending on the window registers and
-  // waits for every outstanding load in the middle of each plane.
+  // Wave roles.  own: a row j0 .. j0+ty-1 inside the grid; halo: row j0-1
+  // (its H is recomputed; it also loads the row above the tile); spare: a row
+  // beyond the grid (its LDS rows hold zeros, the neighbours of the last row)
+  // or a wave beyond the tile.  Each role marches in a loop of its own, whose
+  // memory operations are the same at every plane, so that the compiler's
+  // count-based waits for a load never cover loads or stores issued after it.
+  const bool spare = dummy || (!halo && !row_ok);
+  if (!spare) {
+    load_ph(kstart);
+    load_E(kstart, e0);
+    load_E(kstart + 1, e1);
+    load_H(kstart, h0);
+    load_top(kstart, tz0, tx0);
+  } else if (!dummy) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lds_put<C, V>(myE + c * RS, e0[c]);
+      lds_put<C, V>(myH + c * RS, h0[c]);
+    }
+  }
+  // the prologue's loads land before the march (the wait analysis would
+  // otherwise carry them into the loop as pending on the window registers)
   __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 
-  for (int k = kstart; k < k1; ++k) {
-    const int kq = k - kstart;
-    const bool upd = own && k >= k0;      // uniform: this wave updates E and stores at plane k
-    const bool more = k + 1 < k1;
-    const bool inz = row_ok && in_z(k);
-    const int pln = uniform(tzl[kq]);
+  auto march = [&](auto role) {
+    constexpr int R = decltype(role)::value;
+    constexpr bool OWN = R == 0, HALO = R == 1;
+    for (int k = kstart; k < k1; ++k) {
+      if constexpr (R == 2) {
+        __syncthreads();
+        __syncthreads();
+        continue;
+      } else {
+      const int kq = k - kstart;
+      const bool upd = OWN && k >= k0;      // uniform: this wave updates E and stores at plane k
+      const bool more = k + 1 < k1;
+      const bool inz = row_ok && in_z(k);
+      const int pln = uniform(tzl[kq]);
 
-    // ---- 1. small loads of plane k for the E half ----
-    if (upd) {
-      if (iny) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pe[PEXY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEXY));
-          pe[PEZY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEZY));
-        }
-      }
-      if (inz) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pe[PEXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEXZ));
-          pe[PEYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEYZ));
-        }
-      }
-      if (wave_inx && lane_inx) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pe[PEYX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEYX));
-          pe[PEZX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEZX));
-        }
-      }
-      const int zblk = uniform(tzs[kq]);
-      if (zblk != cf_blk) {   // (Ca, Cb) change along z only where the z block does
-        cf_blk = zblk;
-        const uint32_t cso = (uint32_t)zblk * (uint32_t)sizeof(Coef2<C>);
-#pragma unroll
-        for (int e = 0; e < V; ++e) cf[e] = buf_ld<Coef2<C>>(rcoef, vcf[e], cso);
-      }
-      if (pln >= 0) {
-        if (lane_ok) {
-          const uint8_t* mb = a.pec_mask + ((size_t)pln * ny + jc) * px + xl;
-#pragma unroll
-          for (int e = 0; e < V; ++e) pm[e] = mb[e];
-        }
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
-    // The rows of a wave that updates E always issue the same loads here, so
-    // that waits for the small loads above count past them (after the last
-    // plane: the zero plane, read once per segment).
-    {
-      const int kn = more ? k + 1 : nz;
-      load_E(more ? k + 2 : nz, e2);
-      load_H(kn, h1);
-      load_top(kn, tz1, tx1);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-
-    // ---- 3. publish E^n(k) ----
-    if (!dummy) {
-      lds_put<C, V>(myE, e0[0]);
-      lds_put<C, V>(myE + RS, e0[1]);
-      lds_put<C, V>(myE + 2 * RS, e0[2]);
-      if (halo) {
-        C* rt = ldsE + (ty + 1) * 3 * RS + V + xl;
-        lds_put<C, V>(rt, tx0);
-        lds_put<C, V>(rt + 2 * RS, tz0);
-      }
-    }
-    __syncthreads();
-
-    // ---- 4. H half step at plane k ----
-    C hx[V], hy[V], hz[V];
-#pragma unroll
-    for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
-    if (row_ok) {
-      C exu[V], ezu[V], eyr[V], ezr[V];
-      lds_get<C, V>(myE + 3 * RS, exu);           // row j+1
-      lds_get<C, V>(myE + 5 * RS, ezu);
-#pragma unroll
-      for (int e = 0; e < V - 1; ++e) { eyr[e] = e0[1][e + 1]; ezr[e] = e0[2][e + 1]; }
-      eyr[V - 1] = myE[RS + V];                   // x+1 of the last sample (right pad: 0)
-      ezr[V - 1] = myE[2 * RS + V];
-      C dEz_dy[V], dEy_dz[V], dEx_dz[V], dEz_dx[V], dEy_dx[V], dEx_dy[V];
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        dEz_dy[e] = (ezu[e] - e0[2][e]) * idy;
-        dEy_dz[e] = (e1[1][e] - e0[1][e]) * idz;
-        dEx_dz[e] = (e1[0][e] - e0[0][e]) * idz;
-        dEz_dx[e] = (ezr[e] - e0[2][e]) * idx_;
-        dEy_dx[e] = (eyr[e] - e0[1][e]) * idx_;
-        dEx_dy[e] = (exu[e] - e0[0][e]) * idy;
-      }
-      if (iny) {
-        const C ob = typ[3 * (ty + 1) + r], av = typ[4 * (ty + 1) + r], kv = typ[5 * (ty + 1) + r];
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          ph[PHXY][e] = ph[PHXY][e] - ob * ph[PHXY][e] + av * dEz_dy[e];
-          ph[PHZY][e] = ph[PHZY][e] - ob * ph[PHZY][e] + av * dEx_dy[e];
-          dEz_dy[e] = kv * dEz_dy[e] + ph[PHXY][e];
-          dEx_dy[e] = kv * dEx_dy[e] + ph[PHZY][e];
-        }
-      }
-      if (inz) {
-        const C ob = tzp[3 * nk1 + kq], av = tzp[4 * nk1 + kq], kv = tzp[5 * nk1 + kq];
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          ph[PHXZ][e] = ph[PHXZ][e] - ob * ph[PHXZ][e] + av * dEy_dz[e];
-          ph[PHYZ][e] = ph[PHYZ][e] - ob * ph[PHYZ][e] + av * dEx_dz[e];
-          dEy_dz[e] = kv * dEy_dz[e] + ph[PHXZ][e];
-          dEx_dz[e] = kv * dEx_dz[e] + ph[PHYZ][e];
-        }
-      }
-      if (wave_inx) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          // lanes outside the layer read (1 - b, a, 1/kappa) = (0, 0, 1) and psi 0
-          const int i = xl + e;
-          const C ob = txp[3 * RL + i], av = txp[4 * RL + i], kv = txp[5 * RL + i];
-          ph[PHYX][e] = ph[PHYX][e] - ob * ph[PHYX][e] + av * dEz_dx[e];
-          ph[PHZX][e] = ph[PHZX][e] - ob * ph[PHZX][e] + av * dEy_dx[e];
-          dEz_dx[e] = kv * dEz_dx[e] + ph[PHYX][e];
-          dEy_dx[e] = kv * dEy_dx[e] + ph[PHZX][e];
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        hx[e] = to_storage<T, C>(h0[0][e] - dtm * (dEz_dy[e] - dEy_dz[e]), a.enc[3], a.dec[3]);
-        hy[e] = halo ? C(0) : to_storage<T, C>(h0[1][e] - dtm * (dEx_dz[e] - dEz_dx[e]), a.enc[4], a.dec[4]);
-        hz[e] = to_storage<T, C>(h0[2][e] - dtm * (dEy_dx[e] - dEx_dy[e]), a.enc[5], a.dec[5]);
-      }
-      // new H-side psi of the own rows
+      // ---- 1. small loads of plane k for the E half ----
       if (upd) {
         if (iny) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            buf_st<C>(ph[PHXY][e], rpsi, vxc + e * CB, phout + yso(k, PHXY));
-            buf_st<C>(ph[PHZY][e], rpsi, vxc + e * CB, phout + yso(k, PHZY));
+            pe[PEXY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEXY));
+            pe[PEZY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEZY));
           }
         }
         if (inz) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            buf_st<C>(ph[PHXZ][e], rpsi, vxc + e * CB, phout + zso(k, PHXZ));
-            buf_st<C>(ph[PHYZ][e], rpsi, vxc + e * CB, phout + zso(k, PHYZ));
+            pe[PEXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEXZ));
+            pe[PEYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEYZ));
           }
         }
         if (wave_inx && lane_inx) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            buf_st<C>(ph[PHYX][e], rpsi, vxs[e], phout + xso(k, PHYX));
-            buf_st<C>(ph[PHZX][e], rpsi, vxs[e], phout + xso(k, PHZX));
+            pe[PEYX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEYX));
+            pe[PEZX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEZX));
+          }
+        }
+        const int zblk = uniform(tzs[kq]);
+        if (zblk != cf_blk) {   // (Ca, Cb) change along z only where the z block does
+          cf_blk = zblk;
+          const uint32_t cso = (uint32_t)zblk * (uint32_t)sizeof(Coef2<C>);
+#pragma unroll
+          for (int e = 0; e < V; ++e) cf[e] = buf_ld<Coef2<C>>(rcoef, vcf[e], cso);
+        }
+        if (pln >= 0) {
+          if (lane_ok) {
+            const uint8_t* mb = a.pec_mask + ((size_t)pln * ny + jc) * px + xl;
+#pragma unroll
+            for (int e = 0; e < V; ++e) pm[e] = mb[e];
           }
         }
       }
-    }
-    // lanes beyond nx publish zeros (the x+1 neighbour of the last sample)
-    if (!lane_ok) {
+      __builtin_amdgcn_sched_barrier(0);
+      // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
+      // (after the last plane: the zero plane, read once per segment)
+      {
+        const int kn = more ? k + 1 : nz;
+        load_E(more ? k + 2 : nz, e2);
+        load_H(kn, h1);
+        if constexpr (HALO) load_top(kn, tz1, tx1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+
+      // ---- 3. publish E^n(k) ----
+      lds_put<C, V>(myE, e0[0]);
+      lds_put<C, V>(myE + RS, e0[1]);
+      lds_put<C, V>(myE + 2 * RS, e0[2]);
+      if constexpr (HALO) {
+        C* rt = ldsE + (ty + 1) * 3 * RS + V + xl;
+        lds_put<C, V>(rt, tx0);
+        lds_put<C, V>(rt + 2 * RS, tz0);
+      }
+      __syncthreads();
+
+      // ---- 4. H half step at plane k ----
+      C hx[V], hy[V], hz[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
-    }
+      if (OWN || row_ok) {
+        C exu[V], ezu[V], eyr[V], ezr[V];
+        lds_get<C, V>(myE + 3 * RS, exu);           // row j+1
+        lds_get<C, V>(myE + 5 * RS, ezu);
+#pragma unroll
+        for (int e = 0; e < V - 1; ++e) { eyr[e] = e0[1][e + 1]; ezr[e] = e0[2][e + 1]; }
+        eyr[V - 1] = myE[RS + V];                   // x+1 of the last sample (right pad: 0)
+        ezr[V - 1] = myE[2 * RS + V];
+        C dEz_dy[V], dEy_dz[V], dEx_dz[V], dEz_dx[V], dEy_dx[V], dEx_dy[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          dEz_dy[e] = (ezu[e] - e0[2][e]) * idy;
+          dEy_dz[e] = (e1[1][e] - e0[1][e]) * idz;
+          dEx_dz[e] = (e1[0][e] - e0[0][e]) * idz;
+          dEz_dx[e] = (ezr[e] - e0[2][e]) * idx_;
+          dEy_dx[e] = (eyr[e] - e0[1][e]) * idx_;
+          dEx_dy[e] = (exu[e] - e0[0][e]) * idy;
+        }
+        if (iny) {
+          const C ob = typ[3 * (ty + 1) + r], av = typ[4 * (ty + 1) + r], kv = typ[5 * (ty + 1) + r];
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            ph[PHXY][e] = ph[PHXY][e] - ob * ph[PHXY][e] + av * dEz_dy[e];
+            ph[PHZY][e] = ph[PHZY][e] - ob * ph[PHZY][e] + av * dEx_dy[e];
+            dEz_dy[e] = kv * dEz_dy[e] + ph[PHXY][e];
+            dEx_dy[e] = kv * dEx_dy[e] + ph[PHZY][e];
+          }
+        }
+        if (inz) {
+          const C ob = tzp[3 * nk1 + kq], av = tzp[4 * nk1 + kq], kv = tzp[5 * nk1 + kq];
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            ph[PHXZ][e] = ph[PHXZ][e] - ob * ph[PHXZ][e] + av * dEy_dz[e];
+            ph[PHYZ][e] = ph[PHYZ][e] - ob * ph[PHYZ][e] + av * dEx_dz[e];
+            dEy_dz[e] = kv * dEy_dz[e] + ph[PHXZ][e];
+            dEx_dz[e] = kv * dEx_dz[e] + ph[PHYZ][e];
+          }
+        }
+        if (wave_inx) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            // lanes outside the layer read (1 - b, a, 1/kappa) = (0, 0, 1) and psi 0
+            const int i = xl + e;
+            const C ob = txp[3 * RL + i], av = txp[4 * RL + i], kv = txp[5 * RL + i];
+            ph[PHYX][e] = ph[PHYX][e] - ob * ph[PHYX][e] + av * dEz_dx[e];
+            ph[PHZX][e] = ph[PHZX][e] - ob * ph[PHZX][e] + av * dEy_dx[e];
+            dEz_dx[e] = kv * dEz_dx[e] + ph[PHYX][e];
+            dEy_dx[e] = kv * dEy_dx[e] + ph[PHZX][e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          hx[e] = to_storage<T, C>(h0[0][e] - dtm * (dEz_dy[e] - dEy_dz[e]), a.enc[3], a.dec[3]);
+          hy[e] = HALO ? C(0) : to_storage<T, C>(h0[1][e] - dtm * (dEx_dz[e] - dEz_dx[e]), a.enc[4], a.dec[4]);
+          hz[e] = to_storage<T, C>(h0[2][e] - dtm * (dEy_dx[e] - dEx_dy[e]), a.enc[5], a.dec[5]);
+        }
+        // new H-side psi of the own rows
+        if (upd) {
+          if (iny) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(ph[PHXY][e], rpsi, vxc + e * CB, phout + yso(k, PHXY));
+              buf_st<C>(ph[PHZY][e], rpsi, vxc + e * CB, phout + yso(k, PHZY));
+            }
+          }
+          if (inz) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(ph[PHXZ][e], rpsi, vxc + e * CB, phout + zso(k, PHXZ));
+              buf_st<C>(ph[PHYZ][e], rpsi, vxc + e * CB, phout + zso(k, PHYZ));
+            }
+          }
+          if (wave_inx && lane_inx) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(ph[PHYX][e], rpsi, vxs[e], phout + xso(k, PHYX));
+              buf_st<C>(ph[PHZX][e], rpsi, vxs[e], phout + xso(k, PHZX));
+            }
+          }
+        }
+      }
+      // lanes beyond nx publish zeros (the x+1 neighbour of the last sample)
+      if (!lane_ok) {
+#pragma unroll
+        for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
+      }
 
-    // ---- 5. publish H^{n+1/2}(k) ----
-    if (!dummy) {
+      // ---- 5. publish H^{n+1/2}(k) ----
       lds_put<C, V>(myH, hx);
       lds_put<C, V>(myH + RS, hy);
       lds_put<C, V>(myH + 2 * RS, hz);
-    }
-    __syncthreads();
+      __syncthreads();
 
-    // ---- 6. H-side psi of plane k+1 (its registers are free now) ----
-    if (more && !dummy) load_ph(k + 1);
-    __builtin_amdgcn_sched_barrier(0);
+      // ---- 6. H-side psi of plane k+1 (its registers are free now) ----
+      if (more) load_ph(k + 1);
+      __builtin_amdgcn_sched_barrier(0);
 
-    // ---- 7. E half step at plane k (own rows) and stores ----
-    if (upd) {
-      C hxd[V], hzd[V], hyl[V], hzl[V];
-      lds_get<C, V>(myH - 3 * RS, hxd);             // row j-1
-      lds_get<C, V>(myH - RS, hzd);
+      // ---- 7. E half step at plane k and stores ----
+      if constexpr (OWN) {
+        C exo[V], eyo[V], ezo[V];
 #pragma unroll
-      for (int e = 1; e < V; ++e) { hyl[e] = hy[e - 1]; hzl[e] = hz[e - 1]; }
-      hyl[0] = myH[RS - 1];                         // x-1 of the first sample (left pad at i = 0)
-      hzl[0] = myH[2 * RS - 1];
-      C dHz_dy[V], dHy_dz[V], dHx_dz[V], dHz_dx[V], dHy_dx[V], dHx_dy[V];
+        for (int e = 0; e < V; ++e) { exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e]; }
+        uint8_t flags = 0;
+        if (upd) {
+          C hxd[V], hzd[V], hyl[V], hzl[V];
+          lds_get<C, V>(myH - 3 * RS, hxd);             // row j-1
+          lds_get<C, V>(myH - RS, hzd);
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        dHz_dy[e] = (hz[e] - hzd[e]) * idy;
-        dHy_dz[e] = (hy[e] - hyp[e]) * idz;
-        dHx_dz[e] = (hx[e] - hxp[e]) * idz;
-        dHz_dx[e] = (hz[e] - hzl[e]) * idx_;
-        dHy_dx[e] = (hy[e] - hyl[e]) * idx_;
-        dHx_dy[e] = (hx[e] - hxd[e]) * idy;
-      }
-      if (iny) {
-        const C ob = typ[0 * (ty + 1) + r], av = typ[1 * (ty + 1) + r], kv = typ[2 * (ty + 1) + r];
+          for (int e = 1; e < V; ++e) { hyl[e] = hy[e - 1]; hzl[e] = hz[e - 1]; }
+          hyl[0] = myH[RS - 1];                         // x-1 of the first sample (left pad at i = 0)
+          hzl[0] = myH[2 * RS - 1];
+          C dHz_dy[V], dHy_dz[V], dHx_dz[V], dHz_dx[V], dHy_dx[V], dHx_dy[V];
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pe[PEXY][e] = pe[PEXY][e] - ob * pe[PEXY][e] + av * dHz_dy[e];
-          pe[PEZY][e] = pe[PEZY][e] - ob * pe[PEZY][e] + av * dHx_dy[e];
-          dHz_dy[e] = kv * dHz_dy[e] + pe[PEXY][e];
-          dHx_dy[e] = kv * dHx_dy[e] + pe[PEZY][e];
-        }
-      }
-      if (inz) {
-        const C ob = tzp[0 * nk1 + kq], av = tzp[1 * nk1 + kq], kv = tzp[2 * nk1 + kq];
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          pe[PEXZ][e] = pe[PEXZ][e] - ob * pe[PEXZ][e] + av * dHy_dz[e];
-          pe[PEYZ][e] = pe[PEYZ][e] - ob * pe[PEYZ][e] + av * dHx_dz[e];
-          dHy_dz[e] = kv * dHy_dz[e] + pe[PEXZ][e];
-          dHx_dz[e] = kv * dHx_dz[e] + pe[PEYZ][e];
-        }
-      }
-      if (wave_inx) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          const int i = xl + e;
-          const C ob = txp[0 * RL + i], av = txp[1 * RL + i], kv = txp[2 * RL + i];
-          pe[PEYX][e] = pe[PEYX][e] - ob * pe[PEYX][e] + av * dHz_dx[e];
-          pe[PEZX][e] = pe[PEZX][e] - ob * pe[PEZX][e] + av * dHy_dx[e];
-          dHz_dx[e] = kv * dHz_dx[e] + pe[PEYX][e];
-          dHy_dx[e] = kv * dHy_dx[e] + pe[PEZX][e];
-        }
-      }
-      C exo[V], eyo[V], ezo[V];
-      const bool ux = j > 0 && k > 0;     // uniform: Ex off the outer faces
-      const bool uy = k > 0;              // uniform part (Ey, Ez also need i > 0)
-      const bool uz = j > 0;
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        C cax = cf[e].ca, cbx = cf[e].cb, cay = cax, cby = cbx, caz = cax, cbz = cbx;
-        if (pln >= 0) {
-          const uint32_t m = pm[e];
-          if (m & 1) { cax = C(0); cbx = C(0); }
-          if (m & 2) { cay = C(0); cby = C(0); }
-          if (m & 4) { caz = C(0); cbz = C(0); }
-        }
-        exo[e] = cax * e0[0][e] + cbx * (dHz_dy[e] - dHy_dz[e]);
-        eyo[e] = cay * e0[1][e] + cby * (dHx_dz[e] - dHz_dx[e]);
-        ezo[e] = caz * e0[2][e] + cbz * (dHy_dx[e] - dHx_dy[e]);
-      }
-      if (!ux) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) { exo[e] = e0[0][e]; pe[PEXY][e] = C(0); pe[PEXZ][e] = C(0); }
-      }
-      if (!uy) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) { eyo[e] = e0[1][e]; pe[PEYZ][e] = C(0); pe[PEYX][e] = C(0); }
-      }
-      if (!uz) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) { ezo[e] = e0[2][e]; pe[PEZX][e] = C(0); pe[PEZY][e] = C(0); }
-      }
-      // samples beyond nx in a lane's vector (rows not a multiple of V): never updated
-      if (V > 1 && (nx % V) != 0 && wx0 + kWave * V > nx) {
-#pragma unroll
-        for (int e = 0; e < V; ++e)
-          if (xl + e >= nx) {
-            exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e];
-#pragma unroll
-            for (int u = 0; u < 6; ++u) pe[u][e] = C(0);
+          for (int e = 0; e < V; ++e) {
+            dHz_dy[e] = (hz[e] - hzd[e]) * idy;
+            dHy_dz[e] = (hy[e] - hyp[e]) * idz;
+            dHx_dz[e] = (hx[e] - hxp[e]) * idz;
+            dHz_dx[e] = (hz[e] - hzl[e]) * idx_;
+            dHy_dx[e] = (hy[e] - hyl[e]) * idx_;
+            dHx_dy[e] = (hx[e] - hxd[e]) * idy;
           }
-      }
-      // E samples at i = 0 are on the outer face: never updated
-      if (xs == 0) {
-        if (lane == 0) {
-          eyo[0] = e0[1][0];
-          ezo[0] = e0[2][0];
-          pe[PEYZ][0] = C(0); pe[PEYX][0] = C(0); pe[PEZX][0] = C(0); pe[PEZY][0] = C(0);
-        }
-      }
-      if (iny) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          buf_st<C>(pe[PEXY][e], rpsi, vxc + e * CB, yso(k, PEXY));
-          buf_st<C>(pe[PEZY][e], rpsi, vxc + e * CB, yso(k, PEZY));
-        }
-      }
-      if (inz) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          buf_st<C>(pe[PEXZ][e], rpsi, vxc + e * CB, zso(k, PEXZ));
-          buf_st<C>(pe[PEYZ][e], rpsi, vxc + e * CB, zso(k, PEYZ));
-        }
-      }
-      if (wave_inx && lane_inx) {
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-          buf_st<C>(pe[PEYX][e], rpsi, vxs[e], xso(k, PEYX));
-          buf_st<C>(pe[PEZX][e], rpsi, vxs[e], xso(k, PEZX));
-        }
-      }
-      const uint8_t flags = tfl[r * nk1 + kq];
-      if (flags & 1) {
-        for (int s = 0; s < a.nsrc; ++s) {
-          const SrcDev sp = a.src[s];
-          if (sp.j == j && sp.k == k) {
-            const C v = ldsS[s];
+          if (iny) {
+            const C ob = typ[0 * (ty + 1) + r], av = typ[1 * (ty + 1) + r], kv = typ[2 * (ty + 1) + r];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              if (xl + e == sp.i) {
-                if (sp.comp == 0) exo[e] += v;
-                else if (sp.comp == 1) eyo[e] += v;
-                else ezo[e] += v;
+              pe[PEXY][e] = pe[PEXY][e] - ob * pe[PEXY][e] + av * dHz_dy[e];
+              pe[PEZY][e] = pe[PEZY][e] - ob * pe[PEZY][e] + av * dHx_dy[e];
+              dHz_dy[e] = kv * dHz_dy[e] + pe[PEXY][e];
+              dHx_dy[e] = kv * dHx_dy[e] + pe[PEZY][e];
+            }
+          }
+          if (inz) {
+            const C ob = tzp[0 * nk1 + kq], av = tzp[1 * nk1 + kq], kv = tzp[2 * nk1 + kq];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              pe[PEXZ][e] = pe[PEXZ][e] - ob * pe[PEXZ][e] + av * dHy_dz[e];
+              pe[PEYZ][e] = pe[PEYZ][e] - ob * pe[PEYZ][e] + av * dHx_dz[e];
+              dHy_dz[e] = kv * dHy_dz[e] + pe[PEXZ][e];
+              dHx_dz[e] = kv * dHx_dz[e] + pe[PEYZ][e];
+            }
+          }
+          if (wave_inx) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              const int i = xl + e;
+              const C ob = txp[0 * RL + i], av = txp[1 * RL + i], kv = txp[2 * RL + i];
+              pe[PEYX][e] = pe[PEYX][e] - ob * pe[PEYX][e] + av * dHz_dx[e];
+              pe[PEZX][e] = pe[PEZX][e] - ob * pe[PEZX][e] + av * dHy_dx[e];
+              dHz_dx[e] = kv * dHz_dx[e] + pe[PEYX][e];
+              dHy_dx[e] = kv * dHy_dx[e] + pe[PEZX][e];
+            }
+          }
+          const bool ux = j > 0 && k > 0;     // uniform: Ex off the outer faces
+          const bool uy = k > 0;              // uniform part (Ey, Ez also need i > 0)
+          const bool uz = j > 0;
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            C cax = cf[e].ca, cbx = cf[e].cb, cay = cax, cby = cbx, caz = cax, cbz = cbx;
+            if (pln >= 0) {
+              const uint32_t m = pm[e];
+              if (m & 1) { cax = C(0); cbx = C(0); }
+              if (m & 2) { cay = C(0); cby = C(0); }
+              if (m & 4) { caz = C(0); cbz = C(0); }
+            }
+            exo[e] = cax * e0[0][e] + cbx * (dHz_dy[e] - dHy_dz[e]);
+            eyo[e] = cay * e0[1][e] + cby * (dHx_dz[e] - dHz_dx[e]);
+            ezo[e] = caz * e0[2][e] + cbz * (dHy_dx[e] - dHx_dy[e]);
+          }
+          if (!ux) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) { exo[e] = e0[0][e]; pe[PEXY][e] = C(0); pe[PEXZ][e] = C(0); }
+          }
+          if (!uy) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) { eyo[e] = e0[1][e]; pe[PEYZ][e] = C(0); pe[PEYX][e] = C(0); }
+          }
+          if (!uz) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) { ezo[e] = e0[2][e]; pe[PEZX][e] = C(0); pe[PEZY][e] = C(0); }
+          }
+          // samples beyond nx in a lane's vector (rows not a multiple of V): never updated
+          if (V > 1 && (nx % V) != 0 && wx0 + kWave * V > nx) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+              if (xl + e >= nx) {
+                exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e];
+#pragma unroll
+                for (int u = 0; u < 6; ++u) pe[u][e] = C(0);
+              }
+          }
+          // E samples at i = 0 are on the outer face: never updated
+          if (xs == 0) {
+            if (lane == 0) {
+              eyo[0] = e0[1][0];
+              ezo[0] = e0[2][0];
+              pe[PEYZ][0] = C(0); pe[PEYX][0] = C(0); pe[PEZX][0] = C(0); pe[PEZY][0] = C(0);
+            }
+          }
+          if (iny) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(pe[PEXY][e], rpsi, vxc + e * CB, yso(k, PEXY));
+              buf_st<C>(pe[PEZY][e], rpsi, vxc + e * CB, yso(k, PEZY));
+            }
+          }
+          if (inz) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(pe[PEXZ][e], rpsi, vxc + e * CB, zso(k, PEXZ));
+              buf_st<C>(pe[PEYZ][e], rpsi, vxc + e * CB, zso(k, PEYZ));
+            }
+          }
+          if (wave_inx && lane_inx) {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              buf_st<C>(pe[PEYX][e], rpsi, vxs[e], xso(k, PEYX));
+              buf_st<C>(pe[PEZX][e], rpsi, vxs[e], xso(k, PEZX));
+            }
+          }
+          flags = tfl[r * nk1 + kq];
+          if (flags & 1) {
+            for (int s = 0; s < a.nsrc; ++s) {
+              const SrcDev sp = a.src[s];
+              if (sp.j == j && sp.k == k) {
+                const C v = ldsS[s];
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                  if (xl + e == sp.i) {
+                    if (sp.comp == 0) exo[e] += v;
+                    else if (sp.comp == 1) eyo[e] += v;
+                    else ezo[e] += v;
+                  }
+                }
+              }
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            exo[e] = to_storage<T, C>(exo[e], a.enc[0], a.dec[0]);
+            eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1]);
+            ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
+          }
+        }
+        // The field stores are issued at every plane; below the segment (the
+        // warm-up plane, which updates nothing) every lane is out of range.
+        const uint32_t vst = upd ? vrow : kOut;
+        const uint32_t so = (uint32_t)k * plane_b;
+        st_row<T, C, V>(rout, vst, so, exo, a.enc[0]);
+        st_row<T, C, V>(rout, vst, so + cs_b, eyo, a.enc[1]);
+        st_row<T, C, V>(rout, vst, so + 2 * cs_b, ezo, a.enc[2]);
+        st_row<T, C, V>(rout, vst, so + 3 * cs_b, hx, a.enc[3]);
+        st_row<T, C, V>(rout, vst, so + 4 * cs_b, hy, a.enc[4]);
+        st_row<T, C, V>(rout, vst, so + 5 * cs_b, hz, a.enc[5]);
+        if (flags & 2) {
+          for (int p = 0; p < a.nprobe; ++p) {
+            const int4 pr = a.probe[p];
+            if (pr.z == j && pr.w == k) {
+#pragma unroll
+              for (int e = 0; e < V; ++e) {
+                if (xl + e == pr.y) {
+                  const C v = pr.x == 0 ? exo[e] : pr.x == 1 ? eyo[e] : pr.x == 2 ? ezo[e]
+                            : pr.x == 3 ? hx[e] : pr.x == 4 ? hy[e] : hz[e];
+                  a.series[(size_t)a.series_slot * a.nprobe + p] = static_cast<double>(v);
+                }
               }
             }
           }
         }
       }
+
+      // ---- 8. advance the register window ----
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        exo[e] = to_storage<T, C>(exo[e], a.enc[0], a.dec[0]);
-        eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1]);
-        ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
-      }
-      const uint32_t so = (uint32_t)k * plane_b;
-      st_row<T, C, V>(rout, vrow, so, exo, a.enc[0]);
-      st_row<T, C, V>(rout, vrow, so + cs_b, eyo, a.enc[1]);
-      st_row<T, C, V>(rout, vrow, so + 2 * cs_b, ezo, a.enc[2]);
-      st_row<T, C, V>(rout, vrow, so + 3 * cs_b, hx, a.enc[3]);
-      st_row<T, C, V>(rout, vrow, so + 4 * cs_b, hy, a.enc[4]);
-      st_row<T, C, V>(rout, vrow, so + 5 * cs_b, hz, a.enc[5]);
-      if (flags & 2) {
-        for (int p = 0; p < a.nprobe; ++p) {
-          const int4 pr = a.probe[p];
-          if (pr.z == j && pr.w == k) {
+        hxp[e] = hx[e];
+        hyp[e] = hy[e];
+        tz0[e] = tz1[e];
+        tx0[e] = tx1[e];
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-              if (xl + e == pr.y) {
-                const C v = pr.x == 0 ? exo[e] : pr.x == 1 ? eyo[e] : pr.x == 2 ? ezo[e]
-                          : pr.x == 3 ? hx[e] : pr.x == 4 ? hy[e] : hz[e];
-                a.series[(size_t)a.series_slot * a.nprobe + p] = static_cast<double>(v);
-              }
-            }
-          }
+        for (int c = 0; c < 3; ++c) {
+          e0[c][e] = e1[c][e];
+          e1[c][e] = e2[c][e];
+          h0[c][e] = h1[c][e];
         }
       }
-    }
-
-    // ---- 8. advance the register window ----
-#pragma unroll
-    for (int e = 0; e < V; ++e) {
-      hxp[e] = hx[e];
-      hyp[e] = hy[e];
-      tz0[e] = tz1[e];
-      tx0[e] = tx1[e];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        e0[c][e] = e1[c][e];
-        e1[c][e] = e2[c][e];
-        h0[c][e] = h1[c][e];
       }
     }
-  }
+  };
+  if (spare) march(Role<2>{});
+  else if (halo) march(Role<1>{});
+  else march(Role<0>{});
 }
 
 // ---------------------------------------------------------------------------
-// The fused step kernel: one grid.  Workgroup w runs the z-segments
-// segs[wseg[w] .. wseg[w + 1]) one after another.  The host builds the list:
-// either one fixed chunk of kz planes per workgroup, or a partition of the
-// grid into as many pieces of equal modelled cost as workgroups fit the
-// device at once (a single round, so no workgroup waits for a slot and none
-// ends a long way behind the others).
+// The fused step kernel: one grid, one tile (y-tile, chunk of kz planes) per
+// workgroup.  The host picks kz so that every tile fits the device at once
+// (one round: no workgroup waits for a slot).
 // ---------------------------------------------------------------------------
 // Waves per SIMD the step kernel is compiled for.  FP32 arithmetic with one
 // sample per lane: six, so that two 12-wave workgroups share a CU (at most 80
@@ -848,17 +877,14 @@ __global__ void __launch_bounds__(kWave * max_block_waves(V))
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 step_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
-  // XCD-aware order: consecutive workgroup ids are dealt round-robin to the
-  // 8 XCDs, so each XCD gets a contiguous run of the piece list (neighbouring
-  // y-tiles over one z-range, which share halo rows in that XCD's L2).
+  // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
+  // the 8 XCDs, so give each XCD a contiguous run of tiles (neighbouring
+  // y-tiles of one z-chunk, which share halo rows in that XCD's L2).
   const int per_xcd = gridDim.x >> 3;
-  const int w = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  const int s0 = a.wseg[w], s1 = a.wseg[w + 1];
-  for (int s = s0; s < s1; ++s) {
-    const int4 g = a.segs[s];
-    if (s > s0) __syncthreads();   // the next segment rebuilds the LDS tables
-    step_tile<T, C, V>(a, g.x, g.y, g.z, smem_raw);
-  }
+  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (t >= a.ntiles) return;
+  const int k0 = (t / a.ny_tiles) * a.kz;
+  step_tile<T, C, V>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -884,6 +910,7 @@ struct SlotDesc {
 
 template <class T, class C, int V>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
+__attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __restrict__ hdr, const int q) {
   extern __shared__ unsigned char smem_raw[];
   const int nslots = hdr[0], total = hdr[1];

@@ -72,11 +72,6 @@ struct yee_ctx {
   size_t csize = 0; // compute element size
   int ty = 0, kz = 0, vpl = 0;  // launch shape (0 = automatic)
   int ty_req = 0, kz_req = 0;   // as requested by yee_set_launch
-  // work partition of the step kernel (host image; uploaded to `plan`)
-  std::vector<int32_t> plan_wseg;
-  std::vector<int4> plan_segs;
-  int plan_grid = 0;            // workgroups of a step launch
-  bool plan_dirty = true;       // the device copy is out of date
   size_t lds_limit = 65536;  // per-workgroup LDS, queried at bind time
 
   // host-side configuration
@@ -94,7 +89,7 @@ struct yee_ctx {
   unsigned char* ws = nullptr;
   int64_t ws_bytes = 0;
   Region fields[2], psi_e, psi_h[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
-      srcr, prober, freqr, plan;
+      srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
   uint32_t psi_off[6] = {};  // element offsets of the psi arrays inside a region
@@ -183,10 +178,6 @@ void layout(yee_ctx* c) {
   take(c->srcr, c->src.size() * sizeof(yee::SrcDev));
   take(c->prober, np * sizeof(int4));
   take(c->freqr, nf * sizeof(double));
-  // plan: workgroup offsets [wg + 1] int32, then segments [segs] int4.  Every
-  // partition has at most ny * nz workgroups and twice as many segments.
-  const size_t cells_yz = (size_t)d.ny * d.nz;
-  take(c->plan, align256((cells_yz + 16) * 4) + (2 * cells_yz + 16) * sizeof(int4));
   c->ws_bytes = (int64_t)off;
 }
 
@@ -307,8 +298,7 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   a.wpr = waves_per_row(d.nx, V);
   a.ny_tiles = (d.ny + ty - 1) / ty;
   a.ntiles = a.ny_tiles * ((d.nz + kz - 1) / kz);
-  a.wseg = reinterpret_cast<const int32_t*>(c->ws + c->plan.off);
-  a.segs = reinterpret_cast<const int4*>(c->ws + c->plan.off + align256(((size_t)d.ny * d.nz + 16) * 4));
+
   a.psi_bytes = (uint32_t)c->psi_e.bytes;
   a.coef_bytes = (uint32_t)c->coef.bytes;
   return a;
@@ -318,15 +308,7 @@ template <class T, class C, int V>
 yee_status launch_step(yee_ctx* c, hipStream_t s, bool record) {
   using namespace yee;
   const StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz, record);
-  if (c->plan_dirty) {
-    // the host image lives in the context until the next launch-shape change
-    HIP_TRY(hipMemcpyAsync(const_cast<int32_t*>(a.wseg), c->plan_wseg.data(), c->plan_wseg.size() * 4,
-                           hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(const_cast<int4*>(a.segs), c->plan_segs.data(), c->plan_segs.size() * sizeof(int4),
-                           hipMemcpyHostToDevice, s));
-    c->plan_dirty = false;
-  }
-  const int grid = c->plan_grid;
+  const int grid = ((a.ntiles + 7) / 8) * 8;
   const int waves = (c->ty + 1) * a.wpr;
   if (waves > max_block_waves(V))
     return fail(YEE_EINVAL, "tile of %d rows x %d waves per row exceeds %d waves", c->ty, a.wpr, max_block_waves(V));
@@ -371,106 +353,7 @@ yee_status fold_dft(yee_ctx* c, hipStream_t s) {
   return YEE_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Work partition of the step kernel.
-//
-// Fixed: one workgroup per tile (y-tile, chunk of kz planes).
-// Balanced: as many pieces as workgroups fit the device at once, so the
-// launch is a single round.  The (y-tile, plane) units are put in a line --
-// z-range after z-range, y-tile after y-tile inside a range, planes upward --
-// and the line is cut into pieces of equal modelled cost.  Consecutive pieces
-// go to one XCD; in the interior, where the cost per plane is the same in
-// every tile, neighbouring y-tiles are cut at the same planes and march in
-// step, so the halo rows they share are still read once from HBM.
-// ---------------------------------------------------------------------------
-// Cost model, in units of one plane of an interior tile (per-workgroup
-// real-time stamps of the 256^3 FP32 grid with 10-cell CPML).
-constexpr double kCostYLayer = 0.12;  // extra per plane for a tile whose rows all lie in a y layer
-constexpr double kCostZLayer = 0.20;  // extra per plane inside a z layer
-constexpr double kCostWarm = 0.6;     // the H-only plane below a segment that starts above k = 0
-constexpr double kCostSeg = 0.3;      // tables and prologue of a segment
-constexpr int kMinPiecePlanes = 8;    // smallest piece the balanced partition makes
-
-struct Plan {
-  std::vector<int32_t> wseg;  // [grid + 1]
-  std::vector<int4> segs;     // (y tile, k0, k1, 0)
-  int grid = 0;               // workgroups
-  int kz = 0;                 // planes of the longest segment
-};
-
-void plan_fixed(int ny, int nz, int ty, int kz, Plan& p) {
-  const int nyt = (ny + ty - 1) / ty, nch = (nz + kz - 1) / kz;
-  const int nt = nyt * nch;
-  p.grid = ((nt + 7) / 8) * 8;
-  p.wseg.assign(p.grid + 1, 0);
-  for (int w = 0; w <= p.grid; ++w) p.wseg[w] = std::min(w, nt);
-  p.segs.clear();
-  p.kz = 0;
-  for (int t = 0; t < nt; ++t) {
-    const int k0 = (t / nyt) * kz, k1 = std::min(nz, k0 + kz);
-    p.segs.push_back(int4{t % nyt, k0, k1, 0});
-    p.kz = std::max(p.kz, k1 - k0);
-  }
-}
-
-void plan_balanced(int ny, int nz, int ty, int Ly, int Lz, int workgroups, Plan& p) {
-  const int nyt = (ny + ty - 1) / ty;
-  std::vector<double> ycost(nyt);
-  for (int t = 0; t < nyt; ++t) {
-    int in = 0;
-    for (int j = t * ty; j < std::min(ny, t * ty + ty); ++j) in += (j < Ly || j >= ny - Ly);
-    ycost[t] = 1.0 + kCostYLayer * in / ty;
-  }
-  auto zcost = [&](int k) { return (k < Lz || k >= nz - Lz) ? kCostZLayer : 0.0; };
-  const long units = (long)nyt * nz;
-  const int P = (int)std::max<long>(8, std::min<long>(workgroups, units / kMinPiecePlanes) / 8 * 8);
-  const int nzr = std::max(1, std::min(nz / kMinPiecePlanes, (int)std::lround((double)P / nyt)));
-  std::vector<int> zb(nzr + 1);
-  for (int r = 0; r <= nzr; ++r) zb[r] = (int)((long)r * nz / nzr);
-  auto seg_cost = [](int k) { return kCostSeg + (k > 0 ? kCostWarm : 0.0); };
-  // Greedy cut of the line at piece cost <= T (a piece takes at least one
-  // unit); returns the pieces used and, if asked, the segments.
-  auto cut = [&](double T, Plan* out) {
-    int n = 0;
-    double cur = 0.0;
-    bool open = false;
-    for (int r = 0; r < nzr; ++r)
-      for (int t = 0; t < nyt; ++t)
-        for (int k = zb[r]; k < zb[r + 1]; ++k) {
-          const double c = ycost[t] + zcost(k);
-          const bool first = k == zb[r];   // a new column range starts a segment
-          if (open && cur + c + (first ? seg_cost(k) : 0.0) > T) open = false;
-          if (!open || first) {
-            if (!open) {
-              ++n;
-              cur = 0.0;
-              open = true;
-              if (out) out->wseg.push_back((int32_t)out->segs.size());
-            }
-            cur += seg_cost(k);
-            if (out) out->segs.push_back(int4{t, k, k + 1, 0});
-          } else if (out) {
-            out->segs.back().z = k + 1;
-          }
-          cur += c;
-        }
-    return n;
-  };
-  double lo = 0.0, hi = 0.0;
-  for (int t = 0; t < nyt; ++t)
-    for (int k = 0; k < nz; ++k) hi += ycost[t] + zcost(k) + kCostSeg + kCostWarm;
-  for (int it = 0; it < 60 && hi - lo > 1e-9 * hi; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (cut(mid, nullptr) <= P) hi = mid; else lo = mid;
-  }
-  p.wseg.clear();
-  p.segs.clear();
-  const int n = cut(hi, &p);
-  p.grid = P;
-  for (int w = n; w <= P; ++w) p.wseg.push_back((int32_t)p.segs.size());
-  p.kz = 0;
-  for (const int4& g : p.segs) p.kz = std::max(p.kz, g.z - g.y);
-}
+constexpr int kMinChunk = 8;   // fewest planes per chunk of the automatic launch shape
 
 // Workgroups of the step kernel that fit one CU at once.
 template <class T, class C, int V>
@@ -503,35 +386,31 @@ int step_slots(const yee_ctx* c, int threads, size_t lds) {
   return per_cu * cus;
 }
 
-void make_plan(const yee_grid_desc& d, int ty, int kz_req, int workgroups, Plan& p) {
-  if (kz_req > 0) plan_fixed(d.ny, d.nz, ty, std::min(kz_req, d.nz), p);
-  else plan_balanced(d.ny, d.nz, ty, d.cpml_cells[1], d.cpml_cells[2], workgroups, p);
-}
-
 void default_launch(yee_ctx* c) {
   const auto& d = c->d;
   // samples per lane: one while a row fits in four waves, else two
   c->V = c->vpl ? c->vpl : (d.nx <= 4 * yee::kWave ? 1 : 2);
   const int wpr = waves_per_row(d.nx, c->V);
-  // rows per tile: workgroups of at most 12 waves, so that two fit a CU (the
-  // step kernel uses 64 VGPRs); measured best for the 256^3 grid: two rows of
-  // four waves plus the halo row
+  // rows per tile: workgroups of at most 12 waves, so that two fit a CU;
+  // measured best for the 256^3 grid: two rows of four waves plus the halo row
   c->ty = c->ty_req ? c->ty_req : std::max(1, std::min({7, d.ny, 12 / wpr - 1}));
-  Plan p;
   for (;;) {
-    // occupancy is taken with the LDS of the longest possible segment
-    const int threads = (c->ty + 1) * wpr * yee::kWave;
-    const int slots = c->kz_req > 0 ? 0 : step_slots(c, threads, step_lds_bytes(c, c->ty, c->V, d.nz));
-    make_plan(d, c->ty, c->kz_req, slots, p);
+    if (c->kz_req > 0) {
+      c->kz = std::min(c->kz_req, d.nz);
+    } else {
+      // planes per chunk: the fewest (at least 8) that let every tile be
+      // resident at once, so the launch runs in one round and each chunk
+      // pays its warm-up plane once over as long a march as possible
+      const int threads = (c->ty + 1) * wpr * yee::kWave;
+      const int slots = step_slots(c, threads, step_lds_bytes(c, c->ty, c->V, d.nz));
+      const int ny_tiles = (d.ny + c->ty - 1) / c->ty;
+      const int chunks = std::max(1, slots / ny_tiles);
+      c->kz = std::min(d.nz, std::max(kMinChunk, (d.nz + chunks - 1) / chunks));
+    }
     // keep the LDS rows and z tables within the device's per-workgroup limit
-    if (c->ty == 1 || step_lds_bytes(c, c->ty, c->V, p.kz) <= c->lds_limit) break;
+    if (c->ty == 1 || step_lds_bytes(c, c->ty, c->V, c->kz) <= c->lds_limit) break;
     --c->ty;
   }
-  c->kz = p.kz;
-  c->plan_grid = p.grid;
-  c->plan_wseg.swap(p.wseg);
-  c->plan_segs.swap(p.segs);
-  c->plan_dirty = true;
 }
 
 template <class T>
@@ -761,36 +640,6 @@ yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes, i
     // a step in flight may still read the current partition
     HIP_TRY(hipDeviceSynchronize());
     default_launch(c);
-  }
-  return YEE_OK;
-}
-
-yee_status yee_plan_segments(int32_t ny, int32_t nz, int32_t tile_rows, int32_t cpml_y, int32_t cpml_z,
-                             int32_t chunk_planes, int32_t workgroups, int32_t* n_workgroups,
-                             int32_t* n_segments, int32_t* max_planes, int32_t* wseg, int32_t* segs,
-                             int32_t max_segs) {
-  if (ny < 1 || nz < 1 || tile_rows < 1 || tile_rows > ny || chunk_planes < 0 || workgroups < 0 ||
-      cpml_y < 0 || 2 * cpml_y > ny || cpml_z < 0 || 2 * cpml_z > nz)
-    return fail(YEE_EINVAL, "plan sizes out of range");
-  if ((int64_t)ny * nz > (int64_t)1 << 28) return fail(YEE_EINVAL, "plan of %d x %d units too large", ny, nz);
-  yee_grid_desc d{};
-  d.ny = ny;
-  d.nz = nz;
-  d.cpml_cells[1] = cpml_y;
-  d.cpml_cells[2] = cpml_z;
-  Plan p;
-  make_plan(d, tile_rows, chunk_planes, workgroups, p);
-  if (n_workgroups) *n_workgroups = p.grid;
-  if (n_segments) *n_segments = (int32_t)p.segs.size();
-  if (max_planes) *max_planes = p.kz;
-  if (wseg || segs) {
-    if (!wseg || !segs || max_segs < (int32_t)p.segs.size())
-      return fail(YEE_EINVAL, "wseg and segs must both be given, with room for %zu segments", p.segs.size());
-    std::copy(p.wseg.begin(), p.wseg.end(), wseg);
-    for (size_t i = 0; i < p.segs.size(); ++i) {
-      segs[4 * i] = p.segs[i].x; segs[4 * i + 1] = p.segs[i].y;
-      segs[4 * i + 2] = p.segs[i].z; segs[4 * i + 3] = 0;
-    }
   }
   return YEE_OK;
 }

@@ -146,88 +146,3 @@ def test_workloads_are_seeded_and_consistent():
     for (_, i, j, k) in ad.probes:
         assert not (12 <= i < 28 and 12 <= j < 28 and 12 <= k < 28)
 
-
-def _cover(ny, nz, ty, wseg, segs):
-    """Each (y tile, plane) unit in exactly one segment; segments in range."""
-    nyt = -(-ny // ty)
-    hit = np.zeros((nyt, nz), dtype=np.int32)
-    for (t, k0, k1) in segs:
-        assert 0 <= t < nyt and 0 <= k0 < k1 <= nz
-        hit[t, k0:k1] += 1
-    assert (hit == 1).all()
-    assert wseg[0] == 0 and wseg[-1] == len(segs)
-    assert all(a <= b for a, b in zip(wseg, wseg[1:]))
-
-
-def _piece_cost(segs, ny, nz, ty, Ly, Lz):
-    """The partition's cost model written out: 1 per plane, +0.12 times the
-    fraction of the tile's rows inside a y layer, +0.2 inside a z layer, and
-    0.3 per segment plus 0.6 for a segment starting above plane 0."""
-    c = 0.0
-    for (t, k0, k1) in segs:
-        rows = [j for j in range(t * ty, min(ny, t * ty + ty))]
-        fy = sum(1 for j in rows if j < Ly or j >= ny - Ly) / ty
-        for k in range(k0, k1):
-            c += 1.0 + 0.12 * fy + (0.2 if (k < Lz or k >= nz - Lz) else 0.0)
-        c += 0.3 + (0.6 if k0 > 0 else 0.0)
-    return c
-
-
-@pytest.mark.parametrize("ny,nz,ty,Ly,Lz,wg", [
-    (256, 256, 2, 10, 10, 512),     # the 256^3 benchmark grid on 256 CUs, two workgroups each
-    (64, 64, 2, 8, 8, 512),         # small grid: pieces of at least 8 planes
-    (37, 23, 3, 4, 3, 96),          # ragged tiles
-    (29, 9, 7, 0, 0, 8),
-    (3, 2, 1, 0, 0, 1000),          # fewer units than workgroups
-])
-def test_balanced_partition_covers_the_grid_once(ny, nz, ty, Ly, Lz, wg):
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("libyee.so not built")
-    wseg, segs, kzm = _lib.plan_segments(ny, nz, ty, Ly, Lz, 0, wg)
-    nwg = len(wseg) - 1
-    assert nwg % 8 == 0 and nwg >= 8
-    assert nwg <= max(8, wg)
-    _cover(ny, nz, ty, wseg, segs)
-    assert kzm == max(k1 - k0 for (_, k0, k1) in segs)
-    # segments of one workgroup follow the line: z range, then y tile, then plane
-    costs = []
-    for w in range(nwg):
-        mine = segs[wseg[w]:wseg[w + 1]]
-        if mine:
-            costs.append(_piece_cost(mine, ny, nz, ty, Ly, Lz))
-    # no piece costs more than an even share of the whole plus two units with
-    # their segment starts (the greedy cut overshoots by less than a unit)
-    unit = 1.0 + 0.12 + 0.2 + 0.3 + 0.6
-    assert max(costs) <= sum(costs) / nwg + 2 * unit + 1e-9
-
-
-def test_balanced_partition_of_the_benchmark_grid():
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("libyee.so not built")
-    wseg, segs, kzm = _lib.plan_segments(256, 256, 2, 10, 10, 0, 512)
-    assert len(wseg) - 1 == 512
-    assert sum(1 for w in range(512) if wseg[w + 1] > wseg[w]) >= 500
-    assert kzm <= 64 + 8
-    # at most one column boundary per piece (pieces of about one column range)
-    assert max(wseg[w + 1] - wseg[w] for w in range(512)) <= 3
-
-
-@pytest.mark.parametrize("ny,nz,ty,kz", [(256, 256, 2, 32), (37, 23, 3, 5), (16, 16, 1, 16)])
-def test_fixed_partition_is_one_tile_per_workgroup(ny, nz, ty, kz):
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("libyee.so not built")
-    wseg, segs, kzm = _lib.plan_segments(ny, nz, ty, 0, 0, kz, 0)
-    nyt, nch = -(-ny // ty), -(-nz // kz)
-    assert len(segs) == nyt * nch and (len(wseg) - 1) % 8 == 0
-    _cover(ny, nz, ty, wseg, segs)
-    for t, (yt, k0, k1) in enumerate(segs):
-        assert wseg[t] == t and yt == t % nyt and k0 == (t // nyt) * kz and k1 == min(nz, k0 + kz)
-
-
-def test_plan_rejects_bad_sizes():
-    if not os.path.exists(_lib.LIB_PATH):
-        pytest.skip("libyee.so not built")
-    with pytest.raises(_lib.YeeError):
-        _lib.plan_segments(16, 16, 0)
-    with pytest.raises(_lib.YeeError):
-        _lib.plan_segments(16, 16, 2, 9, 0)
