@@ -216,8 +216,10 @@ yee_status yee_batch_bind_workspace(yee_batch* batch, void* device_ptr, int64_t 
 /* Admit a bound context for n_steps more steps.  YEE_EAGAIN: no free slot or
  * the footprint would exceed the budget (nothing changes; retry later). */
 yee_status yee_batch_admit(yee_batch* batch, yee_ctx* ctx, int64_t n_steps, int32_t* slot);
-/* One replay (steps_per_replay steps of every admitted, unfinished slot) on
- * `stream`; synchronizes the stream first.  Probe DFTs are folded after it. */
+/* One replay (steps_per_replay steps of every admitted, unfinished slot),
+ * queued on `stream` without waiting for earlier replays (the descriptor
+ * table is rewritten by a copy on the same stream, behind them): successive
+ * runs of one batch must use one stream.  Probe DFTs are folded after it. */
 yee_status yee_batch_run(yee_batch* batch, void* stream);
 /* Slots whose requested steps are all taken (up to cap written to done). */
 yee_status yee_batch_poll(yee_batch* batch, int32_t* done, int32_t cap, int32_t* n_done);

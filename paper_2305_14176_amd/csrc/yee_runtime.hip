@@ -119,7 +119,13 @@ struct yee_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t capture = nullptr;       // private stream the replay graph is captured on
-  std::vector<unsigned char> staging;  // host image of the descriptor table
+  // host images of the descriptor table (pinned, used in turn; the event of
+  // each marks the end of the copy that last read it)
+  unsigned char* staging[2] = {nullptr, nullptr};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  bool staged_used[2] = {false, false};
+  size_t staging_bytes = 0;
+  int64_t runs = 0;
 };
 
 namespace {
@@ -430,11 +436,8 @@ void host_to_storage(const double* in, std::vector<unsigned char>& out, const ye
 #ifndef YEE_BATCH_WAVES
 #define YEE_BATCH_WAVES 12
 #endif
-#ifndef YEE_BATCH_GRID
-#define YEE_BATCH_GRID 3
-#endif
 constexpr int kBatchBlockWaves = YEE_BATCH_WAVES;  // waves per workgroup of the batched launch
-constexpr int kBatchMaxChunk = 32;    // planes per z-chunk of a batched grid
+constexpr int kBatchMaxChunk = 32;    // most planes per z-chunk of a batched grid
 using BatchDesc = yee::SlotDesc<float, float>;
 
 int batch_tile_rows(const yee_ctx* c) {
@@ -836,6 +839,13 @@ yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps
 
 void yee_batch_destroy(yee_batch* b) {
   if (!b) return;
+  for (int i = 0; i < 2; ++i) {
+    if (b->staged[i]) {
+      (void)hipEventSynchronize(b->staged[i]);
+      (void)hipEventDestroy(b->staged[i]);
+    }
+    if (b->staging[i]) (void)hipHostFree(b->staging[i]);
+  }
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -848,15 +858,40 @@ yee_status yee_batch_bind_workspace(yee_batch* b, void* dev, int64_t bytes) {
   int64_t need = 0;
   yee_batch_footprint(b->max_slots, &need);
   if (bytes < need) return fail(YEE_ENOMEM, "batch workspace has %lld bytes, needs %lld", (long long)bytes, (long long)need);
-  int dev_id = 0, cus = 0;
+  int dev_id = 0, cus = 0, per_cu = 0;
   HIP_TRY(hipGetDevice(&dev_id));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
-  b->grid = std::max(8, YEE_BATCH_GRID * cus);  // workgroups per CU of the persistent launch
+  // the persistent launch: as many workgroups as are resident at once
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, yee::batch_step_kernel<float, float, 1>,
+                                                       yee::kWave * kBatchBlockWaves, b->lds));
+  b->grid = std::max(8, std::max(1, per_cu) * cus);
+  b->staging_bytes = 256 + (size_t)b->max_slots * sizeof(BatchDesc);
+  for (int i = 0; i < 2; ++i) {
+    if (!b->staging[i]) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->staging[i]), b->staging_bytes, 0));
+    if (!b->staged[i]) HIP_TRY(hipEventCreateWithFlags(&b->staged[i], hipEventDisableTiming));
+  }
   b->ws = static_cast<unsigned char*>(dev);
   b->ws_bytes = bytes;
   b->bound = true;
   return YEE_OK;
 }
+
+namespace {
+// (y-tile, plane) units of the unfinished slots, and their tiles at kz planes per chunk
+int64_t batch_units(const yee_batch* b) {
+  int64_t u = 0;
+  for (auto& sl : b->slots)
+    if (sl.used && sl.ctx->n < sl.n_end) u += (int64_t)((sl.ctx->d.ny + sl.ty - 1) / sl.ty) * sl.ctx->d.nz;
+  return u;
+}
+int64_t batch_tiles(const yee_batch* b, int kz) {
+  int64_t t = 0;
+  for (auto& sl : b->slots)
+    if (sl.used && sl.ctx->n < sl.n_end)
+      t += (int64_t)((sl.ctx->d.ny + sl.ty - 1) / sl.ty) * ((sl.ctx->d.nz + kz - 1) / kz);
+  return t;
+}
+}  // namespace
 
 yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* slot) {
   if (!b || !c || !slot) return fail(YEE_EINVAL, "NULL argument");
@@ -878,7 +913,6 @@ yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* s
     sl.n_end = c->n + n_steps;
     sl.bytes = c->ws_bytes;
     sl.ty = batch_tile_rows(c);
-    sl.kz = std::min(c->d.nz, kBatchMaxChunk);
     b->in_use += sl.bytes;
     *slot = q;
     return YEE_OK;
@@ -890,18 +924,29 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
   if (!b) return fail(YEE_EINVAL, "NULL batch");
   if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
   hipStream_t s = (hipStream_t)stream;
-  // the staging image of the previous replay may still be in flight
-  HIP_TRY(hipStreamSynchronize(s));
+  // The device table is rewritten by a copy on `stream`, behind the replays
+  // already queued there, so the host runs ahead of the device; only the host
+  // image used two runs ago must have been copied out.
+  const int sb = (int)(b->runs & 1);
+  if (b->staged_used[sb]) HIP_TRY(hipEventSynchronize(b->staged[sb]));
   const size_t hdr_bytes = 256;
-  b->staging.assign(hdr_bytes + (size_t)b->max_slots * sizeof(BatchDesc), 0);
-  BatchDesc* desc = reinterpret_cast<BatchDesc*>(b->staging.data() + hdr_bytes);
+  unsigned char* stg = b->staging[sb];
+  std::memset(stg, 0, b->staging_bytes);
+  BatchDesc* desc = reinterpret_cast<BatchDesc*>(stg + hdr_bytes);
   int32_t nact = 0, tiles = 0;
   std::vector<int32_t> order;
+  // planes per chunk for this replay: the fewest (8 .. kBatchMaxChunk) that
+  // spread the (y-tile, plane) units of every active slot over the resident
+  // workgroups in one round -- short marches when few requests run, long
+  // ones (less warm-up) when many do
+  int kz_all = (int)std::min<int64_t>(kBatchMaxChunk, std::max<int64_t>(kMinChunk, (batch_units(b) + b->grid - 1) / b->grid));
+  while (kz_all < kBatchMaxChunk && batch_tiles(b, kz_all) > b->grid) ++kz_all;
   for (int32_t q = 0; q < b->max_slots; ++q) {
     auto& sl = b->slots[q];
     if (!sl.used || sl.ctx->n >= sl.n_end) continue;
     yee_ctx* c = sl.ctx;
     BatchDesc& d = desc[nact++];
+    sl.kz = std::min(c->d.nz, kz_all);
     d.a = fill_args<float, float>(c, 1, sl.ty, sl.kz);
     d.set[0] = reinterpret_cast<const float*>(c->ws + c->fields[0].off);
     d.set[1] = reinterpret_cast<const float*>(c->ws + c->fields[1].off);
@@ -915,10 +960,12 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
     order.push_back(q);
   }
   if (nact == 0) return YEE_OK;
-  reinterpret_cast<int32_t*>(b->staging.data())[0] = nact;
-  reinterpret_cast<int32_t*>(b->staging.data())[1] = tiles;
-  HIP_TRY(hipMemcpyAsync(b->ws, b->staging.data(), hdr_bytes + (size_t)nact * sizeof(BatchDesc),
-                         hipMemcpyHostToDevice, s));
+  reinterpret_cast<int32_t*>(stg)[0] = nact;
+  reinterpret_cast<int32_t*>(stg)[1] = tiles;
+  HIP_TRY(hipMemcpyAsync(b->ws, stg, hdr_bytes + (size_t)nact * sizeof(BatchDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(b->staged[sb], s));
+  b->staged_used[sb] = true;
+  b->runs += 1;
   if (!b->exec) {
     // capture K launches once; they read the descriptor table from device memory
     const BatchDesc* dslots = reinterpret_cast<const BatchDesc*>(b->ws + hdr_bytes);
