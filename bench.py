@@ -134,6 +134,38 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     return out
 
 
+def precision_benchmark(steps=100, warmup=10):
+    """The other precision modes at their configurations: FP16 storage
+    (FP32 arithmetic, FP64 DFT) on the 512 x 512 x 256 layered substrate with a
+    PEC strip mask, and FP64 on the 32^3 PEC box."""
+    import torch
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.solver import YeeSolver
+    out = {}
+    for wl, eb, n in ((W.fp16_substrate(), 2, steps), (W.plain_pec_box(seed=1), 8, 200)):
+        solver = YeeSolver(wl, device="cuda:0", series_len=max(1000, n))
+        stream = torch.cuda.current_stream()
+        solver.step(warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        solver.step(n)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / n
+        alg, fields_b, psi_b = algorithmic_bytes_per_step(wl, elem_bytes=eb, psi_bytes=8 if eb == 8 else 4)
+        gbs = alg / (ms / 1e3) / 1e9
+        out[wl.name] = {"dtype": {2: "f16 storage, f32 math, f64 dft", 8: "f64"}[eb], "steps": n,
+                        "ms_per_step": round(ms, 5), "mcell_updates_per_s": round(wl.cells / (ms / 1e3) / 1e6, 1),
+                        "algorithmic_bytes_per_step": alg, "hbm_gbs_algorithmic": round(gbs, 1),
+                        "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        solver.close()
+        del solver
+        torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_benchmark(checkpoint_every=64):
     """Gradient of the 128^3 design workload (FP32 fields, FP64 gradient):
     forward run with checkpoints, backward run (recompute + reverse steps),
@@ -186,6 +218,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient measurement")
+    ap.add_argument("--no-precisions", action="store_true", help="skip the FP16-storage and FP64 configurations")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: a few untimed steps, then a plain device copy of "
                          "COPY_MIB MiB (the known-size kernel the HBM counters are scaled by)")
@@ -264,6 +297,8 @@ def main():
                      "kernel_ms_avg": round(ms_per_step, 5)},
         "wall_s_timed": round(t_wall, 4),
     }
+    if not args.no_precisions:
+        out["precision_modes"] = precision_benchmark()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark()
     if not args.no_serving:

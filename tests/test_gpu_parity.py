@@ -105,10 +105,11 @@ def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
     ((256, 40, 33), 0, 0, 0),
     ((256, 40, 33), 3, 5, 0),
     ((256, 21, 19), 7, 3, 4),   # four samples per lane, one wave per row
-    ((300, 17, 26), 4, 4, 0),   # two samples per lane, ragged row
+    ((300, 17, 26), 4, 4, 2),   # two samples per lane, ragged row
+    ((300, 17, 26), 0, 0, 0),   # automatic: one sample per lane, five waves per row
     ((160, 48, 48), 4, 16, 0),
-    ((512, 9, 12), 1, 1, 0),    # widest rows, one row per tile, one plane per chunk
-    ((512, 9, 12), 1, 2, 1),    # eight waves per row
+    ((512, 9, 12), 1, 1, 0),    # widest rows (automatic: eight waves), one plane per chunk
+    ((512, 9, 12), 1, 2, 2),    # widest rows, two samples per lane
 ])
 def test_random_init_fp32_launch_shapes(solver_cls, shape, ty, kz, vpl):
     nx, ny, nz = shape
@@ -203,3 +204,14 @@ def test_series_ring_and_dft_chunking(solver_cls):
         assert rel_l2(gd[p], sim.dft[p]) <= TOL["f32"]
     with pytest.raises(Exception):
         s.series(1, 10)   # no longer in the ring
+
+
+@pytest.mark.timeout(600)
+def test_fp16_substrate_full_size_one_step(solver_cls):
+    """512 x 512 x 256 with FP16 storage (the layered substrate with its PEC
+    strip mask) in the benchmark's launch shape: one step from a random state
+    (every update term, layer and mask is active) against the oracle emulating
+    FP16 storage.  The oracle needs about a minute and 30 GB of host memory."""
+    wl = W.fp16_substrate(steps=1)
+    s, sim = _run_both(solver_cls, wl, 1, init_seed=41)
+    _check_fields(s, sim, TOL["f16"])
