@@ -59,6 +59,9 @@ def _desc(**kw):
     ({"cpml": (8, 8, 8)}, True),
     ({"series_len": 0}, False),
     ({"precision": 7}, False),
+    ({"n": (446, 446, 446)}, True),    # largest FP32 cube whose six components (+ zero plane) stay < 2 GiB
+    ({"n": (448, 448, 448)}, False),   # 6 x 449 x 448 x 448 x 4 B > 2^31: rejected
+    ({"n": (448, 448, 448), "precision": 2}, True),   # the same grid in FP16 storage fits
 ])
 def test_create_validates(kw, ok):
     if not os.path.exists(_lib.LIB_PATH):
