@@ -69,28 +69,58 @@ struct AdjArgs {
   int32_t L[3];
   C inv_d[3];
   C dt_mu;
+  // objective seeds folded into the kernels (see adj_inject_kernel)
+  const InjDev* inj;        // unique probed samples
+  int32_t ninj;
+  const int4* probe;        // (comp, i, j, k)
+  int32_t nprobe;
+  const uint8_t* rowflag;   // [nz][ny], bit 1: a probe in the row
+  const double* yrow_h;     // adj_h: probe samples whose H seeds this step adds (or null)
+  const double* yrow_e;     // adj_e: probe samples whose E seeds the next reverse step needs (or null)
 };
 
 constexpr int kAdjBX = 64, kAdjBY = 4;  // threads per workgroup along x, y
 
-__device__ __forceinline__ bool in_layer(int i, int n, int L) { return i < L || i >= n - L; }
-__device__ __forceinline__ int slab(int i, int n, int L) { return i < L ? i : i - n + 2 * L; }
-
-// ---------------------------------------------------------------------------
-// 1. Objective: each unique probed sample adds 2 w sum_p y_p[n+1].
-// ---------------------------------------------------------------------------
-template <class C>
-__global__ void adj_inject_kernel(const InjDev* __restrict__ inj, int ninj, const int4* __restrict__ probe,
-                                  int nprobe, const double* __restrict__ yrow, C* u, C* hb,
-                                  uint64_t ustride) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= ninj) return;
-  const InjDev d = inj[q];
+// Seed of probed sample d: w * (sum of the samples of the probes on it).
+__device__ __forceinline__ double inj_seed(const InjDev& d, const int4* probe, int nprobe, const double* yrow) {
   double s = 0.0;
   for (int p = d.first; p < nprobe; ++p) {
     const int4 pr = probe[p];
     if (pr.x == d.comp && pr.y == d.i && pr.z == d.j && pr.w == d.k) s += yrow[p];
   }
+  return s;
+}
+
+// Seeds of the samples of components [c0, c0 + 3) at element offset o.
+template <class C>
+__device__ __forceinline__ void inj_seeds(const InjDev* inj, int ninj, const int4* probe, int nprobe,
+                                          const double* yrow, int c0, uint32_t o, C (&out)[3]) {
+  for (int q = 0; q < ninj; ++q) {
+    const InjDev d = inj[q];
+    if (d.comp >= c0 && d.comp < c0 + 3 && d.off == o)
+      out[d.comp - c0] += static_cast<C>(d.w) * static_cast<C>(inj_seed(d, probe, nprobe, yrow));
+  }
+}
+
+__device__ __forceinline__ bool in_layer(int i, int n, int L) { return i < L || i >= n - L; }
+__device__ __forceinline__ int slab(int i, int n, int L) { return i < L ? i : i - n + 2 * L; }
+
+// ---------------------------------------------------------------------------
+// 1. Objective: each unique probed sample adds w sum_p y_p[n+1] (w = 2 Cb for
+//    E samples, 2 for H samples).  The seeds of a reverse step are folded into
+//    the kernels: adj_h adds the H seeds of its own step while it updates
+//    H_bar, and adj_e adds the E seeds of the next reverse step as it writes
+//    u.  This kernel only seeds u before the first reverse step.
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ void adj_inject_kernel(const InjDev* __restrict__ inj, int ninj, const int4* __restrict__ probe,
+                                  int nprobe, const double* __restrict__ yrow, C* u, C* hb,
+                                  uint64_t ustride, int comp_end) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ninj) return;
+  const InjDev d = inj[q];
+  if (d.comp >= comp_end) return;
+  const double s = inj_seed(d, probe, nprobe, yrow);
   C* base = d.comp < 3 ? u + (uint64_t)d.comp * ustride : hb + (uint64_t)(d.comp - 3) * ustride;
   base[d.off] += static_cast<C>(d.w) * static_cast<C>(s);
 }
@@ -168,9 +198,12 @@ adj_h_kernel(const AdjArgs<C, C> a) {
   C* H0 = a.hb;
   C* H1 = a.hb + a.ustride;
   C* H2 = a.hb + 2 * a.ustride;
-  H0[o] += (dzy0 - dzy1) * idy + (dyz0 - dyz1) * idz;
-  H1[o] += (dxz0 - dxz1) * idz + (dzx0 - dzx1) * idx;
-  H2[o] += (dxy0 - dxy1) * idy + (dyx0 - dyx1) * idx;
+  C sd[3] = {C(0), C(0), C(0)};   // objective seeds of this step's H samples here
+  if (a.yrow_h && (a.rowflag[(uint32_t)k * ny + j] & 2))
+    inj_seeds<C>(a.inj, a.ninj, a.probe, a.nprobe, a.yrow_h, 3, o, sd);
+  H0[o] = (H0[o] + sd[0]) + ((dzy0 - dzy1) * idy + (dyz0 - dyz1) * idz);
+  H1[o] = (H1[o] + sd[1]) + ((dxz0 - dxz1) * idz + (dzx0 - dzx1) * idx);
+  H2[o] = (H2[o] + sd[2]) + ((dxy0 - dxy1) * idy + (dyx0 - dyx1) * idx);
 
   // psi_E adjoint of the own samples: P <- b (P + s u)
   if (in_layer(j, ny, Ly)) {
@@ -308,9 +341,12 @@ adj_e_kernel(const AdjArgs<T, C> a) {
     a.grad[h] += acc;
   }
 
-  U0[o] = ux_ok ? cf.ca * ux + cf.cb * gx : C(0);
-  U1[o] = uy_ok ? cf.ca * uy + cf.cb * gy : C(0);
-  U2[o] = uz_ok ? cf.ca * uz + cf.cb * gz : C(0);
+  C sd[3] = {C(0), C(0), C(0)};   // objective seeds of the next reverse step's E samples here
+  if (a.yrow_e && (a.rowflag[(uint32_t)k * ny + j] & 2))
+    inj_seeds<C>(a.inj, a.ninj, a.probe, a.nprobe, a.yrow_e, 0, o, sd);
+  U0[o] = (ux_ok ? cf.ca * ux + cf.cb * gx : C(0)) + sd[0];
+  U1[o] = (uy_ok ? cf.ca * uy + cf.cb * gy : C(0)) + sd[1];
+  U2[o] = (uz_ok ? cf.ca * uz + cf.cb * gz : C(0)) + sd[2];
 
   // psi_H adjoint of the own samples: Q <- b (Q - mu s H_bar)
   if (in_layer(j, ny, Ly)) {

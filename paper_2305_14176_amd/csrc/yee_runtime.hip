@@ -1180,6 +1180,13 @@ yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int m, int pin, int pout,
   a.inv_d[1] = static_cast<C>(1.0 / d.dy);
   a.inv_d[2] = static_cast<C>(1.0 / d.dz);
   a.dt_mu = static_cast<C>(c->dt / kMu0);
+  a.inj = reinterpret_cast<const InjDev*>(A->ws + A->inj.off);
+  a.ninj = (int32_t)A->inj_host.size();
+  a.probe = reinterpret_cast<const int4*>(c->ws + c->prober.off);
+  a.nprobe = (int32_t)c->probes.size();
+  a.rowflag = reinterpret_cast<const uint8_t*>(c->ws + c->rowflag.off);
+  a.yrow_h = nullptr;
+  a.yrow_e = nullptr;
   return a;
 }
 
@@ -1191,22 +1198,27 @@ yee_status adj_reverse_step(yee_adjoint* A, int64_t n, int m, int& pe, int& ph, 
   const auto& d = c->d;
   const int np = (int)c->probes.size();
   const int ninj = (int)A->inj_host.size();
-  if (ninj > 0) {
+  const double* yrow = reinterpret_cast<const double*>(A->ws + A->phist.off);
+  // The objective seeds of step n: the E ones were added by the previous
+  // reverse step's adj_e, except before the first reverse step; the H ones
+  // are added by adj_h below.
+  if (ninj > 0 && n == A->N - 1) {
     hipLaunchKernelGGL(adj_inject_kernel<C>, dim3((ninj + 63) / 64), dim3(64), 0, s,
                        reinterpret_cast<const InjDev*>(A->ws + A->inj.off), ninj,
-                       reinterpret_cast<const int4*>(c->ws + c->prober.off), np,
-                       reinterpret_cast<const double*>(A->ws + A->phist.off) + (size_t)n * np,
+                       reinterpret_cast<const int4*>(c->ws + c->prober.off), np, yrow + (size_t)n * np,
                        reinterpret_cast<C*>(A->ws + A->u.off), reinterpret_cast<C*>(A->ws + A->hb.off),
-                       (uint64_t)(A->ucomp / sizeof(C)));
+                       (uint64_t)(A->ucomp / sizeof(C)), 3);
     HIP_TRY(hipGetLastError());
   }
   const dim3 grid((d.nx + kAdjBX - 1) / kAdjBX, (d.ny + kAdjBY - 1) / kAdjBY, d.nz);
   const dim3 block(kAdjBX, kAdjBY);
   AdjArgs<C, C> ah = adj_args<C, C>(A, n, m, pe, pe ^ 1, false);
+  ah.yrow_h = ninj > 0 ? yrow + (size_t)n * np : nullptr;
   hipLaunchKernelGGL(adj_h_kernel<C>, grid, block, 0, s, ah);
   HIP_TRY(hipGetLastError());
   pe ^= 1;
   AdjArgs<C, C> ae = adj_args<C, C>(A, n, m, ph, ph ^ 1, true);
+  ae.yrow_e = (ninj > 0 && n > 0) ? yrow + (size_t)(n - 1) * np : nullptr;
   ae.grad = grad;
   hipLaunchKernelGGL((adj_e_kernel<C, C>), grid, block, 0, s, ae);
   HIP_TRY(hipGetLastError());
