@@ -47,7 +47,7 @@ struct AdjArgs {
   uint64_t ustride;
   const C* pin;             // psi adjoint (E side in adj_h, H side in adj_e), old
   C* pout;                  // new
-  uint32_t psoff[6];
+  uint32_t psoff[6];        // element offset of the pair array holding each auxiliary (see yee_kernels.hpp)
   const C* prof;            // CPML profiles [side E,H][axis][1 - b | a | 1/kappa][plen]
   int32_t plen;
   const int32_t* seg;       // block index per cell: x [px] | y [ny] | z [nz]
@@ -156,28 +156,28 @@ adj_h_kernel(const AdjArgs<C, C> a) {
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
     const C kv = pr[5 * pl + j], av = pr[4 * pl + j];
-    dxy0 = kv * ux + av * (P[a.psoff[PEXY] + q] + ux);
-    dzy0 = -kv * uz + av * (P[a.psoff[PEZY] + q] - uz);
+    dxy0 = kv * ux + av * (P[a.psoff[PEXY] + 2 * q + psi_member(PEXY)] + ux);
+    dzy0 = -kv * uz + av * (P[a.psoff[PEZY] + 2 * q + psi_member(PEZY)] - uz);
   }
   if (yp && in_layer(j + 1, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j + 1, ny, Ly)) * px + i;
     const C kv = pr[5 * pl + j + 1], av = pr[4 * pl + j + 1];
-    dxy1 = kv * ux_y + av * (P[a.psoff[PEXY] + q] + ux_y);
-    dzy1 = -kv * uz_y + av * (P[a.psoff[PEZY] + q] - uz_y);
+    dxy1 = kv * ux_y + av * (P[a.psoff[PEXY] + 2 * q + psi_member(PEXY)] + ux_y);
+    dzy1 = -kv * uz_y + av * (P[a.psoff[PEZY] + 2 * q + psi_member(PEZY)] - uz_y);
   }
   // z terms (YZ: +Ey, XZ: -Ex) at k and k + 1
   C dyz0 = uy, dyz1 = uy_z, dxz0 = -ux, dxz1 = -ux_z;
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
     const C kv = pr[8 * pl + k], av = pr[7 * pl + k];
-    dyz0 = kv * uy + av * (P[a.psoff[PEYZ] + q] + uy);
-    dxz0 = -kv * ux + av * (P[a.psoff[PEXZ] + q] - ux);
+    dyz0 = kv * uy + av * (P[a.psoff[PEYZ] + 2 * q + psi_member(PEYZ)] + uy);
+    dxz0 = -kv * ux + av * (P[a.psoff[PEXZ] + 2 * q + psi_member(PEXZ)] - ux);
   }
   if (zp && in_layer(k + 1, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k + 1, nz, Lz) * ny + j) * px + i;
     const C kv = pr[8 * pl + k + 1], av = pr[7 * pl + k + 1];
-    dyz1 = kv * uy_z + av * (P[a.psoff[PEYZ] + q] + uy_z);
-    dxz1 = -kv * ux_z + av * (P[a.psoff[PEXZ] + q] - ux_z);
+    dyz1 = kv * uy_z + av * (P[a.psoff[PEYZ] + 2 * q + psi_member(PEYZ)] + uy_z);
+    dxz1 = -kv * ux_z + av * (P[a.psoff[PEXZ] + 2 * q + psi_member(PEXZ)] - ux_z);
   }
   // x terms (ZX: +Ez, YX: -Ey) at i and i + 1
   C dzx0 = uz, dzx1 = uz_x, dyx0 = -uy, dyx1 = -uy_x;
@@ -185,14 +185,14 @@ adj_h_kernel(const AdjArgs<C, C> a) {
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
     const C kv = pr[2 * pl + i], av = pr[1 * pl + i];
-    dzx0 = kv * uz + av * (P[a.psoff[PEZX] + q] + uz);
-    dyx0 = -kv * uy + av * (P[a.psoff[PEYX] + q] - uy);
+    dzx0 = kv * uz + av * (P[a.psoff[PEZX] + 2 * q + psi_member(PEZX)] + uz);
+    dyx0 = -kv * uy + av * (P[a.psoff[PEYX] + 2 * q + psi_member(PEYX)] - uy);
   }
   if (xp && in_layer(i + 1, nx, Lx)) {
     const uint32_t q = qx + slab(i + 1, nx, Lx);
     const C kv = pr[2 * pl + i + 1], av = pr[1 * pl + i + 1];
-    dzx1 = kv * uz_x + av * (P[a.psoff[PEZX] + q] + uz_x);
-    dyx1 = -kv * uy_x + av * (P[a.psoff[PEYX] + q] - uy_x);
+    dzx1 = kv * uz_x + av * (P[a.psoff[PEZX] + 2 * q + psi_member(PEZX)] + uz_x);
+    dyx1 = -kv * uy_x + av * (P[a.psoff[PEYX] + 2 * q + psi_member(PEYX)] - uy_x);
   }
   const C idx = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
   C* H0 = a.hb;
@@ -209,20 +209,20 @@ adj_h_kernel(const AdjArgs<C, C> a) {
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
     const C ob = pr[3 * pl + j];
-    { const C t = P[a.psoff[PEXY] + q] + ux; a.pout[a.psoff[PEXY] + q] = t - ob * t; }
-    { const C t = P[a.psoff[PEZY] + q] - uz; a.pout[a.psoff[PEZY] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEXY] + 2 * q + psi_member(PEXY)] + ux; a.pout[a.psoff[PEXY] + 2 * q + psi_member(PEXY)] = t - ob * t; }
+    { const C t = P[a.psoff[PEZY] + 2 * q + psi_member(PEZY)] - uz; a.pout[a.psoff[PEZY] + 2 * q + psi_member(PEZY)] = t - ob * t; }
   }
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
     const C ob = pr[6 * pl + k];
-    { const C t = P[a.psoff[PEYZ] + q] + uy; a.pout[a.psoff[PEYZ] + q] = t - ob * t; }
-    { const C t = P[a.psoff[PEXZ] + q] - ux; a.pout[a.psoff[PEXZ] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEYZ] + 2 * q + psi_member(PEYZ)] + uy; a.pout[a.psoff[PEYZ] + 2 * q + psi_member(PEYZ)] = t - ob * t; }
+    { const C t = P[a.psoff[PEXZ] + 2 * q + psi_member(PEXZ)] - ux; a.pout[a.psoff[PEXZ] + 2 * q + psi_member(PEXZ)] = t - ob * t; }
   }
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
     const C ob = pr[0 * pl + i];
-    { const C t = P[a.psoff[PEZX] + q] + uz; a.pout[a.psoff[PEZX] + q] = t - ob * t; }
-    { const C t = P[a.psoff[PEYX] + q] - uy; a.pout[a.psoff[PEYX] + q] = t - ob * t; }
+    { const C t = P[a.psoff[PEZX] + 2 * q + psi_member(PEZX)] + uz; a.pout[a.psoff[PEZX] + 2 * q + psi_member(PEZX)] = t - ob * t; }
+    { const C t = P[a.psoff[PEYX] + 2 * q + psi_member(PEYX)] - uy; a.pout[a.psoff[PEYX] + 2 * q + psi_member(PEYX)] = t - ob * t; }
   }
 }
 
@@ -259,28 +259,28 @@ adj_e_kernel(const AdjArgs<T, C> a) {
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
     const C kv = pr[14 * pl + j], av = pr[13 * pl + j];
-    gxy1 = -mu * kv * hx + av * (Q[a.psoff[PHXY] + q] - mu * hx);
-    gzy1 = mu * kv * hz + av * (Q[a.psoff[PHZY] + q] + mu * hz);
+    gxy1 = -mu * kv * hx + av * (Q[a.psoff[PHXY] + 2 * q + psi_member(PHXY)] - mu * hx);
+    gzy1 = mu * kv * hz + av * (Q[a.psoff[PHZY] + 2 * q + psi_member(PHZY)] + mu * hz);
   }
   if (ym && in_layer(j - 1, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j - 1, ny, Ly)) * px + i;
     const C kv = pr[14 * pl + j - 1], av = pr[13 * pl + j - 1];
-    gxy0 = -mu * kv * hx_y + av * (Q[a.psoff[PHXY] + q] - mu * hx_y);
-    gzy0 = mu * kv * hz_y + av * (Q[a.psoff[PHZY] + q] + mu * hz_y);
+    gxy0 = -mu * kv * hx_y + av * (Q[a.psoff[PHXY] + 2 * q + psi_member(PHXY)] - mu * hx_y);
+    gzy0 = mu * kv * hz_y + av * (Q[a.psoff[PHZY] + 2 * q + psi_member(PHZY)] + mu * hz_y);
   }
   // z terms (YZ: +Hy, XZ: -Hx) at k - 1 and k
   C gyz1 = -mu * hy, gyz0 = -mu * hy_z, gxz1 = mu * hx, gxz0 = mu * hx_z;
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
     const C kv = pr[17 * pl + k], av = pr[16 * pl + k];
-    gyz1 = -mu * kv * hy + av * (Q[a.psoff[PHYZ] + q] - mu * hy);
-    gxz1 = mu * kv * hx + av * (Q[a.psoff[PHXZ] + q] + mu * hx);
+    gyz1 = -mu * kv * hy + av * (Q[a.psoff[PHYZ] + 2 * q + psi_member(PHYZ)] - mu * hy);
+    gxz1 = mu * kv * hx + av * (Q[a.psoff[PHXZ] + 2 * q + psi_member(PHXZ)] + mu * hx);
   }
   if (zm && in_layer(k - 1, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k - 1, nz, Lz) * ny + j) * px + i;
     const C kv = pr[17 * pl + k - 1], av = pr[16 * pl + k - 1];
-    gyz0 = -mu * kv * hy_z + av * (Q[a.psoff[PHYZ] + q] - mu * hy_z);
-    gxz0 = mu * kv * hx_z + av * (Q[a.psoff[PHXZ] + q] + mu * hx_z);
+    gyz0 = -mu * kv * hy_z + av * (Q[a.psoff[PHYZ] + 2 * q + psi_member(PHYZ)] - mu * hy_z);
+    gxz0 = mu * kv * hx_z + av * (Q[a.psoff[PHXZ] + 2 * q + psi_member(PHXZ)] + mu * hx_z);
   }
   // x terms (ZX: +Hz, YX: -Hy) at i - 1 and i
   C gzx1 = -mu * hz, gzx0 = -mu * hz_x, gyx1 = mu * hy, gyx0 = mu * hy_x;
@@ -288,14 +288,14 @@ adj_e_kernel(const AdjArgs<T, C> a) {
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
     const C kv = pr[11 * pl + i], av = pr[10 * pl + i];
-    gzx1 = -mu * kv * hz + av * (Q[a.psoff[PHZX] + q] - mu * hz);
-    gyx1 = mu * kv * hy + av * (Q[a.psoff[PHYX] + q] + mu * hy);
+    gzx1 = -mu * kv * hz + av * (Q[a.psoff[PHZX] + 2 * q + psi_member(PHZX)] - mu * hz);
+    gyx1 = mu * kv * hy + av * (Q[a.psoff[PHYX] + 2 * q + psi_member(PHYX)] + mu * hy);
   }
   if (xm && in_layer(i - 1, nx, Lx)) {
     const uint32_t q = qx + slab(i - 1, nx, Lx);
     const C kv = pr[11 * pl + i - 1], av = pr[10 * pl + i - 1];
-    gzx0 = -mu * kv * hz_x + av * (Q[a.psoff[PHZX] + q] - mu * hz_x);
-    gyx0 = mu * kv * hy_x + av * (Q[a.psoff[PHYX] + q] + mu * hy_x);
+    gzx0 = -mu * kv * hz_x + av * (Q[a.psoff[PHZX] + 2 * q + psi_member(PHZX)] - mu * hz_x);
+    gyx0 = mu * kv * hy_x + av * (Q[a.psoff[PHYX] + 2 * q + psi_member(PHYX)] + mu * hy_x);
   }
   const C idx = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
   // D_f^T: the E sample m collects gbar[m - 1] - gbar[m]
@@ -352,20 +352,20 @@ adj_e_kernel(const AdjArgs<T, C> a) {
   if (in_layer(j, ny, Ly)) {
     const uint32_t q = ((uint32_t)k * (2 * Ly) + slab(j, ny, Ly)) * px + i;
     const C ob = pr[12 * pl + j];
-    { const C t = Q[a.psoff[PHXY] + q] - mu * hx; a.pout[a.psoff[PHXY] + q] = t - ob * t; }
-    { const C t = Q[a.psoff[PHZY] + q] + mu * hz; a.pout[a.psoff[PHZY] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHXY] + 2 * q + psi_member(PHXY)] - mu * hx; a.pout[a.psoff[PHXY] + 2 * q + psi_member(PHXY)] = t - ob * t; }
+    { const C t = Q[a.psoff[PHZY] + 2 * q + psi_member(PHZY)] + mu * hz; a.pout[a.psoff[PHZY] + 2 * q + psi_member(PHZY)] = t - ob * t; }
   }
   if (in_layer(k, nz, Lz)) {
     const uint32_t q = ((uint32_t)slab(k, nz, Lz) * ny + j) * px + i;
     const C ob = pr[15 * pl + k];
-    { const C t = Q[a.psoff[PHYZ] + q] - mu * hy; a.pout[a.psoff[PHYZ] + q] = t - ob * t; }
-    { const C t = Q[a.psoff[PHXZ] + q] + mu * hx; a.pout[a.psoff[PHXZ] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHYZ] + 2 * q + psi_member(PHYZ)] - mu * hy; a.pout[a.psoff[PHYZ] + 2 * q + psi_member(PHYZ)] = t - ob * t; }
+    { const C t = Q[a.psoff[PHXZ] + 2 * q + psi_member(PHXZ)] + mu * hx; a.pout[a.psoff[PHXZ] + 2 * q + psi_member(PHXZ)] = t - ob * t; }
   }
   if (in_layer(i, nx, Lx)) {
     const uint32_t q = qx + slab(i, nx, Lx);
     const C ob = pr[9 * pl + i];
-    { const C t = Q[a.psoff[PHZX] + q] - mu * hz; a.pout[a.psoff[PHZX] + q] = t - ob * t; }
-    { const C t = Q[a.psoff[PHYX] + q] + mu * hy; a.pout[a.psoff[PHYX] + q] = t - ob * t; }
+    { const C t = Q[a.psoff[PHZX] + 2 * q + psi_member(PHZX)] - mu * hz; a.pout[a.psoff[PHZX] + 2 * q + psi_member(PHZX)] = t - ob * t; }
+    { const C t = Q[a.psoff[PHYX] + 2 * q + psi_member(PHYX)] + mu * hy; a.pout[a.psoff[PHYX] + 2 * q + psi_member(PHYX)] = t - ob * t; }
   }
 }
 

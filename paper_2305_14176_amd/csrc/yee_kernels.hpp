@@ -40,9 +40,18 @@ constexpr int kMaxBlockWaves = 16;   // 1024 threads
 __host__ __device__ constexpr int max_block_waves(int V) { return V >= 4 ? 8 : 16; }
 constexpr int kMaxSources = 8;
 
-// psi array order (E side in place; H side ping-ponged)
+// psi auxiliaries (E side in place; H side ping-ponged).  The two of one
+// CPML axis are stored interleaved, as pairs: y slab (XY, ZY), z slab
+// (XZ, YZ), x slab (YX, ZX); psoff[q] is the element offset of the pair array
+// holding q, and psi_member(q) its place in the pair.
 enum { PEXY = 0, PEXZ, PEYZ, PEYX, PEZX, PEZY };
 enum { PHXY = 0, PHXZ, PHYZ, PHYX, PHZX, PHZY };
+__host__ __device__ constexpr int psi_member(int q) { return (q == 5 || q == 2 || q == 4) ? 1 : 0; }
+
+template <class C>
+struct alignas(2 * sizeof(C)) Pair {
+  C a, b;
+};
 
 struct SrcDev {
   int32_t comp, i, j, k, kind, pad;
@@ -64,7 +73,7 @@ struct StepArgs {
   C* pse;                   // E-side psi, updated in place
   const C* psh_in;          // H-side psi, old
   C* psh_out;               // H-side psi, new
-  uint32_t psoff[6];        // element offset of each psi array inside its region
+  uint32_t psoff[6];        // element offset of the pair array holding each psi auxiliary
   const C* prof;            // CPML profiles [side E,H][axis][1 - b | a | 1/kappa][plen]
   int32_t plen;
   const int32_t* seg;       // block index per cell: x [px] | y [ny] | z [nz]
@@ -366,7 +375,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   const uint32_t plane = (uint32_t)ny * (uint32_t)px;
   const uint32_t vrow = (row_ok && lane_ok) ? ((uint32_t)jc * (uint32_t)px + (uint32_t)xl) * TB : kOut;
   const uint32_t vtop = (top_ok && lane_ok) ? ((uint32_t)jt * (uint32_t)px + (uint32_t)xl) * TB : kOut;
-  const uint32_t vxc = (row_ok && lane_ok) ? (uint32_t)xl * CB : kOut;
+  const uint32_t vxc = (row_ok && lane_ok) ? (uint32_t)xl * 2 * CB : kOut;   // psi pairs: 2 C per sample
   uint32_t vxs[V], vcf[V];
   const int sx0 = xl < Lx ? xl : xl - nx + 2 * Lx;
   bool lane_inx = false;   // the lane holds x-layer samples: x-slab accesses are exec-masked to
@@ -376,7 +385,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     const int i = xl + e;
     const bool inx = row_ok && i < nx && (i < Lx || i >= nx - Lx);
     lane_inx = lane_inx || inx;
-    vxs[e] = inx ? (uint32_t)(sx0 + e) * CB : kOut;
+    vxs[e] = inx ? (uint32_t)(sx0 + e) * 2 * CB : kOut;
     vcf[e] = (row_ok && i < nx) ? (uint32_t)(a.seg[i] + a.seg[px + jc] * a.nsx) * (uint32_t)sizeof(Coef2<C>) : kOut;
   }
   const uint32_t plane_b = plane * TB;
@@ -391,12 +400,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
   const C dtm = a.dt_mu;
   // byte offsets (inside a psi region) of plane k of array q in the y, z, x slabs
-  auto yso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * (2 * Ly) + sy) * (uint32_t)px) * CB; };
+  auto yso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * (2 * Ly) + sy) * (uint32_t)px * 2) * CB; };
   auto zso = [&](int k, int q) {
     const int sz = k < Lz ? k : k - nz + 2 * Lz;
-    return (a.psoff[q] + ((uint32_t)sz * ny + jc) * (uint32_t)px) * CB;
+    return (a.psoff[q] + ((uint32_t)sz * ny + jc) * (uint32_t)px * 2) * CB;
   };
-  auto xso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * ny + jc) * (uint32_t)(2 * Lx)) * CB; };
+  auto xso = [&](int k, int q) { return (a.psoff[q] + ((uint32_t)k * ny + jc) * (uint32_t)(2 * Lx) * 2) * CB; };
   auto in_z = [&](int k) { return k < Lz || k >= nz - Lz; };
 
   C* myE = ldsE + r * 3 * RS + V + xl;       // lane's samples in its LDS rows (+ c * RS)
@@ -429,22 +438,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     if (iny) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        ph[PHXY][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + yso(k, PHXY));
-        ph[PHZY][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + yso(k, PHZY));
+        { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxc + e * 2 * CB, phin + yso(k, PHXY)); ph[PHXY][e] = v_.a; ph[PHZY][e] = v_.b; }
       }
     }
     if (row_ok && in_z(k)) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        ph[PHXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + zso(k, PHXZ));
-        ph[PHYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, phin + zso(k, PHYZ));
+        { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxc + e * 2 * CB, phin + zso(k, PHXZ)); ph[PHXZ][e] = v_.a; ph[PHYZ][e] = v_.b; }
       }
     }
     if (wave_inx && lane_inx) {
 #pragma unroll
       for (int e = 0; e < V; ++e) {
-        ph[PHYX][e] = buf_ld<C>(rpsi, vxs[e], phin + xso(k, PHYX));
-        ph[PHZX][e] = buf_ld<C>(rpsi, vxs[e], phin + xso(k, PHZX));
+        { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxs[e], phin + xso(k, PHYX)); ph[PHYX][e] = v_.a; ph[PHZX][e] = v_.b; }
       }
     }
   };
@@ -510,22 +516,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         if (iny) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            pe[PEXY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEXY));
-            pe[PEZY][e] = buf_ld<C>(rpsi, vxc + e * CB, yso(k, PEZY));
+            { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxc + e * 2 * CB, yso(k, PEXY)); pe[PEXY][e] = v_.a; pe[PEZY][e] = v_.b; }
           }
         }
         if (inz) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            pe[PEXZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEXZ));
-            pe[PEYZ][e] = buf_ld<C>(rpsi, vxc + e * CB, zso(k, PEYZ));
+            { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxc + e * 2 * CB, zso(k, PEXZ)); pe[PEXZ][e] = v_.a; pe[PEYZ][e] = v_.b; }
           }
         }
         if (wave_inx && lane_inx) {
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            pe[PEYX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEYX));
-            pe[PEZX][e] = buf_ld<C>(rpsi, vxs[e], xso(k, PEZX));
+            { const Pair<C> v_ = buf_ld<Pair<C>>(rpsi, vxs[e], xso(k, PEYX)); pe[PEYX][e] = v_.a; pe[PEZX][e] = v_.b; }
           }
         }
         const int zblk = uniform(tzs[kq]);
@@ -630,22 +633,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           if (iny) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(ph[PHXY][e], rpsi, vxc + e * CB, phout + yso(k, PHXY));
-              buf_st<C>(ph[PHZY][e], rpsi, vxc + e * CB, phout + yso(k, PHZY));
+              buf_st<Pair<C>>(Pair<C>{ph[PHXY][e], ph[PHZY][e]}, rpsi, vxc + e * 2 * CB, phout + yso(k, PHXY));
             }
           }
           if (inz) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(ph[PHXZ][e], rpsi, vxc + e * CB, phout + zso(k, PHXZ));
-              buf_st<C>(ph[PHYZ][e], rpsi, vxc + e * CB, phout + zso(k, PHYZ));
+              buf_st<Pair<C>>(Pair<C>{ph[PHXZ][e], ph[PHYZ][e]}, rpsi, vxc + e * 2 * CB, phout + zso(k, PHXZ));
             }
           }
           if (wave_inx && lane_inx) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(ph[PHYX][e], rpsi, vxs[e], phout + xso(k, PHYX));
-              buf_st<C>(ph[PHZX][e], rpsi, vxs[e], phout + xso(k, PHZX));
+              buf_st<Pair<C>>(Pair<C>{ph[PHYX][e], ph[PHZX][e]}, rpsi, vxs[e], phout + xso(k, PHYX));
             }
           }
         }
@@ -770,22 +770,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           if (iny) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(pe[PEXY][e], rpsi, vxc + e * CB, yso(k, PEXY));
-              buf_st<C>(pe[PEZY][e], rpsi, vxc + e * CB, yso(k, PEZY));
+              buf_st<Pair<C>>(Pair<C>{pe[PEXY][e], pe[PEZY][e]}, rpsi, vxc + e * 2 * CB, yso(k, PEXY));
             }
           }
           if (inz) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(pe[PEXZ][e], rpsi, vxc + e * CB, zso(k, PEXZ));
-              buf_st<C>(pe[PEYZ][e], rpsi, vxc + e * CB, zso(k, PEYZ));
+              buf_st<Pair<C>>(Pair<C>{pe[PEXZ][e], pe[PEYZ][e]}, rpsi, vxc + e * 2 * CB, zso(k, PEXZ));
             }
           }
           if (wave_inx && lane_inx) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<C>(pe[PEYX][e], rpsi, vxs[e], xso(k, PEYX));
-              buf_st<C>(pe[PEZX][e], rpsi, vxs[e], xso(k, PEZX));
+              buf_st<Pair<C>>(Pair<C>{pe[PEYX][e], pe[PEZX][e]}, rpsi, vxs[e], xso(k, PEYX));
             }
           }
           flags = tfl[r * nk1 + kq];

@@ -92,7 +92,7 @@ struct yee_ctx {
       srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
-  uint32_t psi_off[6] = {};  // element offsets of the psi arrays inside a region
+  uint32_t psi_off[6] = {};  // element offset of the pair array holding each psi auxiliary
   size_t prof_len = 0;     // elements of one profile array (max axis length)
   int64_t n = 0;           // steps taken
   int64_t folded = 0;      // steps folded into the DFT
@@ -162,11 +162,13 @@ void layout(yee_ctx* c) {
   c->comp_bytes = align256((size_t)(d.nz + 1) * d.ny * c->px * c->tsize) + YEE_COMP_SKEW_BYTES;
   for (int s = 0; s < 2; ++s) take(c->fields[s], 6 * c->comp_bytes);
   psi_lengths(c, c->psi_len);
-  size_t psin = 0;
-  for (int q = 0; q < 6; ++q) {
-    c->psi_off[q] = (uint32_t)psin;
-    psin += c->psi_len[q];
-  }
+  // the two auxiliaries of one axis are interleaved: pair arrays y (XY, ZY),
+  // z (XZ, YZ), x (YX, ZX); psi_off[q] is the offset of q's pair array
+  const size_t ypair = 2 * c->psi_len[0], zpair = 2 * c->psi_len[1], xpair = 2 * c->psi_len[3];
+  c->psi_off[0] = c->psi_off[5] = 0;
+  c->psi_off[1] = c->psi_off[2] = (uint32_t)ypair;
+  c->psi_off[3] = c->psi_off[4] = (uint32_t)(ypair + zpair);
+  const size_t psin = ypair + zpair + xpair;
   const size_t psib = psin * c->csize;
   take(c->psi_e, psib);
   take(c->psi_h[0], psib);
