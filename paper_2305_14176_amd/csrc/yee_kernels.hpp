@@ -656,15 +656,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
       }
 
-      // ---- 5. publish H^{n+1/2}(k) ----
+      // ---- 5. H-side psi of plane k+1 (its registers are free now; issued
+      // before the barrier, which adds the barrier wait to their lead) ----
+      if (more) load_ph(k + 1);
+      __builtin_amdgcn_sched_barrier(0);
+
+      // ---- 6. publish H^{n+1/2}(k) ----
       lds_put<C, V>(myH, hx);
       lds_put<C, V>(myH + RS, hy);
       lds_put<C, V>(myH + 2 * RS, hz);
       __syncthreads();
-
-      // ---- 6. H-side psi of plane k+1 (its registers are free now) ----
-      if (more) load_ph(k + 1);
-      __builtin_amdgcn_sched_barrier(0);
 
       // ---- 7. E half step at plane k and stores ----
       if constexpr (OWN) {
