@@ -1293,6 +1293,29 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
   hipStream_t s = (hipStream_t)stream;
   const auto& d = c->d;
   A->have_forward = false;
+  yee_status st = YEE_OK;
+  int64_t gathered = 0;
+  for (int32_t seg = 0; seg < A->S; ++seg) {
+    const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
+    const bool last = seg == A->S - 1;
+    if ((st = adj_checkpoint(A, seg, true, s))) return st;
+    if (last && (st = adj_store(A, 0, s))) return st;
+    for (int64_t n = n0; n < n1; ++n) {
+      if ((st = launch_one_step(c, s))) return st;
+      c->n += 1;
+      if (last && (st = adj_store(A, (int)(c->n - n0), s))) return st;
+      if (c->n - gathered >= d.series_len) {
+        if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
+        gathered = c->n;
+      }
+      if (c->n - c->folded >= d.series_len && (st = fold_dft(c, s))) return st;
+    }
+  }
+  if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
+  if ((st = fold_dft(c, s))) return st;
+  if ((st = adj_checkpoint(A, A->S, true, s))) return st;
+  // Tables only the backward run reads, built on the host while the queued
+  // steps run on the device:
   // derivative table per block: (dCa/deps_r / Cb, dCb/deps_r / Cb^2) in FP64
   const size_t nb = (size_t)c->nsx * c->nsy * c->nsz;
   A->dcoef_host.assign(2 * nb, 0.0);
@@ -1334,32 +1357,12 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
     }
     A->inj_host.push_back(e);
   }
-  yee_status st = YEE_OK;
   HIP_TRY(hipMemcpyAsync(A->ws + A->dcoef.off, A->dcoef_host.data(), A->dcoef_host.size() * sizeof(double),
                          hipMemcpyHostToDevice, s));
   if (!A->inj_host.empty())
     HIP_TRY(hipMemcpyAsync(A->ws + A->inj.off, A->inj_host.data(), A->inj_host.size() * sizeof(yee::InjDev),
                            hipMemcpyHostToDevice, s));
-  int64_t gathered = 0;
-  for (int32_t seg = 0; seg < A->S; ++seg) {
-    const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
-    const bool last = seg == A->S - 1;
-    if ((st = adj_checkpoint(A, seg, true, s))) return st;
-    if (last && (st = adj_store(A, 0, s))) return st;
-    for (int64_t n = n0; n < n1; ++n) {
-      if ((st = launch_one_step(c, s))) return st;
-      c->n += 1;
-      if (last && (st = adj_store(A, (int)(c->n - n0), s))) return st;
-      if (c->n - gathered >= d.series_len) {
-        if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
-        gathered = c->n;
-      }
-      if (c->n - c->folded >= d.series_len && (st = fold_dft(c, s))) return st;
-    }
-  }
-  if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
-  if ((st = fold_dft(c, s))) return st;
-  if ((st = adj_checkpoint(A, A->S, true, s))) return st;
+
   hipLaunchKernelGGL(yee::adj_objective_kernel, dim3(1), dim3(256), 0, s,
                      reinterpret_cast<const double*>(A->ws + A->phist.off), (int64_t)A->N * np,
                      reinterpret_cast<double*>(A->ws + A->jout.off));
