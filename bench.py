@@ -134,6 +134,29 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     return out
 
 
+def copy_bandwidth(mib=1024, reps=20):
+    """A practical HBM ceiling on this device: a plain device-to-device copy of
+    `mib` MiB (read + write bytes per second, best of `reps`)."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    return nbytes / (best / 1e3) / 1e9
+
+
 def precision_benchmark(steps=100, warmup=10):
     """The other precision modes at their configurations: FP16 storage
     (FP32 arithmetic, FP64 DFT) on the 512 x 512 x 256 layered substrate with a
@@ -264,6 +287,7 @@ def main():
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
 
+    copy_gbs = copy_bandwidth()
     cells = wl.cells
     value = cells * args.steps / (ms / 1e3) / 1e6
     alg, fields_b, psi_b = algorithmic_bytes_per_step(wl)
@@ -294,7 +318,9 @@ def main():
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg,
                      "kernel": "yee::step_kernel (fused H + E + CPML step)",
-                     "kernel_ms_avg": round(ms_per_step, 5)},
+                     "kernel_ms_avg": round(ms_per_step, 5),
+                     "copy_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "wall_s_timed": round(t_wall, 4),
     }
     if not args.no_precisions:
