@@ -187,8 +187,11 @@ yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
 
 /* Launch shape of the fused step kernel: y-rows per workgroup tile, planes
  * per z-chunk and x samples per lane (1, 2 or 4); 0 keeps the automatic
- * choice.  A workgroup holds (tile_rows + 1) * ceil(nx / (64 * samples))
- * waves, at most 16.  Results do not depend on the launch shape. */
+ * choice (one sample per lane up to 256 samples per row, and in FP32 up to
+ * 512; workgroups of at most 12 waves; the shortest chunk, at least 8 planes,
+ * that lets every tile be resident on the device at once).  A workgroup holds
+ * (tile_rows + 1) * ceil(nx / (64 * samples)) waves, at most 16.  Results do
+ * not depend on the launch shape. */
 yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane);
 
 /* ------------------------------------------------------------------------

@@ -649,11 +649,7 @@ yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes, i
   c->ty_req = tile_rows;
   c->kz_req = chunk_planes;
   c->vpl = samples_per_lane;
-  if (c->bound) {
-    // a step in flight may still read the current partition
-    HIP_TRY(hipDeviceSynchronize());
-    default_launch(c);
-  }
+  if (c->bound) default_launch(c);   // host state only: steps already queued keep their arguments
   return YEE_OK;
 }
 
