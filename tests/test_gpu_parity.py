@@ -84,9 +84,10 @@ def test_plain_pec_box_fp64_full():
 
 
 @pytest.mark.parametrize("shape,cpml,v", [
-    ((37, 29, 23), (4, 3, 5), "ragged V=1"),
-    ((100, 21, 18), (6, 2, 0), "V=2, no z layer"),
-    ((200, 12, 30), (10, 5, 7), "V=4"),
+    ((37, 29, 23), (4, 3, 5), "ragged rows"),
+    ((100, 21, 18), (6, 2, 0), "no z layer"),
+    ((200, 12, 30), (10, 5, 7), "four waves per row"),
+    ((300, 9, 11), (6, 2, 3), "rows past 256: two samples per lane"),
     ((2, 2, 2), (0, 0, 0), "smallest grid"),
 ])
 def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
@@ -215,3 +216,21 @@ def test_fp16_substrate_full_size_one_step(solver_cls):
     wl = W.fp16_substrate(steps=1)
     s, sim = _run_both(solver_cls, wl, 1, init_seed=41)
     _check_fields(s, sim, TOL["f16"])
+
+
+@pytest.mark.parametrize("vpl", [0, 1])
+def test_fp16_storage_wide_rows(solver_cls, vpl):
+    """FP16 storage on rows of 300 samples: the automatic two samples per lane
+    (three waves per row) and one sample per lane (five waves, 2-byte loads)."""
+    wl = W.fp16_substrate(300, 40, 40, steps=4, cpml=4)
+    s, sim = _run_both(solver_cls, wl, 4, init_seed=51, samples_per_lane=vpl)
+    _check_fields(s, sim, TOL["f16"])
+
+
+def test_fp32_fewer_planes_than_a_chunk(solver_cls):
+    """nz below the smallest automatic chunk (one chunk, one warm-up-free march)."""
+    wl = W.cpml_block_lattice(n=96, ny=50, nz=5, steps=6, precision="f32", cpml=1, nprobes=2, nfreq=4)
+    wl.cpml_cells = (5, 4, 1)
+    s, sim = _run_both(solver_cls, wl, 6, init_seed=52)
+    _check_fields(s, sim, TOL["f32"])
+    _check_probes(s, sim, TOL["f32"], 6)
