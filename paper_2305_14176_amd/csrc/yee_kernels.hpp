@@ -19,12 +19,15 @@
 // E, H and the H-side psi are ping-ponged, so a tile that recomputes its
 // neighbour's halo row reads old values only.
 //
-// Memory pipelining.  gfx9 counts outstanding vector loads in one in-order
-// counter, so waiting for any load also waits for every load issued before
-// it.  Each iteration therefore issues its small loads (CPML auxiliaries,
-// material and mask data) first and the plane prefetches (E^n(k+2),
-// H^{n-1/2}(k+1)) last; waits for the small loads then leave the prefetches
-// in flight for a whole iteration.
+// Memory pipelining.  gfx9 counts outstanding vector loads and stores in one
+// in-order counter, so waiting for any load also waits for every operation
+// issued before it, and the compiler's wait for a register counts the
+// operations issued after its load on the path with the fewest.  Each
+// iteration therefore issues its small loads (CPML auxiliaries, material and
+// mask data) first and the plane prefetches (E^n(k+2), H^{n-1/2}(k+1)) after
+// them; own rows, the halo row and spare waves march in separate loops, each
+// issuing the same prefetch and field stores at every plane, so a wait never
+// covers more than the operations it needs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -548,7 +551,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
       }
       __builtin_amdgcn_sched_barrier(0);
       // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
-      // (after the last plane: the zero plane, read once per segment)
+      // (after the last plane: the zero plane, read once per chunk)
       {
         const int kn = more ? k + 1 : nz;
         load_E(more ? k + 2 : nz, e2);
@@ -810,7 +813,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
             ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
           }
         }
-        // The field stores are issued at every plane; below the segment (the
+        // The field stores are issued at every plane; below the chunk (the
         // warm-up plane, which updates nothing) every lane is out of range.
         const uint32_t vst = upd ? vrow : kOut;
         const uint32_t so = (uint32_t)k * plane_b;
