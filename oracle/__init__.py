@@ -14,4 +14,9 @@ time-stepping scheme.  The oracle therefore writes out the textbook scheme
 (Yee 1966 staggering and leapfrog; Taflove & Hagness ch. 3 lossy Ca/Cb form;
 Roden & Gedney 2000 CPML).  Every point those sources leave open is an
 explicit argument of :class:`oracle.yee.Simulation`.
+
+``oracle.raymeta`` is the oracle of the paper's own method (Section II,
+Eqs. 1-7: hit update, path lengths, antenna displacement, delays, IF
+synthesis, range-Doppler transform and span masks), written from the paper's
+equations; its inputs come from ``paper_2305_14176_amd.rayscene``.
 """

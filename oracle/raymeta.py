@@ -1,0 +1,162 @@
+"""FP64 CPU oracle for ray-meta-data IF synthesis (Section II, Eqs. 1-7).
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path imports, calls or
+links this module: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+path; both receive the same inputs from ``paper_2305_14176_amd.rayscene``.
+
+Each function follows one passage of the paper, in its order and notation,
+evaluated plainly in float64 with numpy (library primitives only as whole
+steps: vector norms, ``exp``, ``fft2``).  Readings where the paper is silent
+or ambiguous:
+  * Eq. 2's exponent is 2 pi i (mu t tau + f_c tau): the "j" there is the
+    imaginary unit (j also indexes chirps), and the sum runs over all rays.
+  * Fast time is t_n = n / f_s, n = 0 .. N_s - 1, starting at each chirp's
+    start; chirp j sees the vertex snapshot taken at j T_d (no motion within a
+    chirp).
+  * The path length d_i(j) of Eq. 1 is TX -> first hit -> ... -> last hit ->
+    RX, hits in stored order (Section II.A); Eq. 7's l_i is the same length
+    for a displaced antenna pair.
+  * A(alpha, beta) is a per-ray weight, 1 unless given, the same for every
+    chirp and antenna pair; there is no other per-ray amplitude.
+  * Eq. 4 is the plain forward 2-D DFT, exp(-2 pi i k n / N) on both axes,
+    unnormalised, with no window and no zero padding; the output is indexed
+    [pair][Doppler bin][range bin].
+  * Eq. 5's spans are per-ray 0/1 masks from filter rules on the meta data
+    (mesh IDs and hit counts); s^h uses the rays the rule keeps.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+C0 = 299792458.0       # speed of light [m/s]
+
+
+def hit_positions(verts_j, tris, mesh_tri_off, hit_mesh, hit_tri, hit_u, hit_v):
+    """Eq. 6: p = (1 - u - v) v1 + u v2 + v v3 on triangle b_k of mesh a_k,
+    with the vertex positions of one snapshot ``verts_j`` (n_verts, 3)."""
+    t = mesh_tri_off[hit_mesh].astype(np.int64) + hit_tri
+    u = hit_u.astype(np.float64)[:, None]
+    v = hit_v.astype(np.float64)[:, None]
+    v1 = verts_j[tris[t, 0]]
+    v2 = verts_j[tris[t, 1]]
+    v3 = verts_j[tris[t, 2]]
+    return (1.0 - u - v) * v1 + u * v2 + v * v3
+
+
+def path_lengths(p, ray_off, x_tx, x_rx):
+    """Section II.A: d_i = |p_1 - x_tx| + sum_k |p_{k+1} - p_k| + |p_K - x_rx|
+    over the hits of ray i.  Returns (d, first hit, last hit).  A ray with no
+    hits has no path: its entries are 0 (its weight is 0 in ``ray_weights``)."""
+    first = ray_off[:-1].astype(np.int64)
+    last = ray_off[1:].astype(np.int64) - 1
+    n_rays = first.shape[0]
+    empty = last < first
+    if p.shape[0] == 0:
+        z = np.zeros((n_rays, 3))
+        return np.zeros(n_rays), z, z
+    first = np.where(empty, 0, first)
+    last = np.where(empty, 0, last)
+    seg = np.zeros(p.shape[0])
+    if p.shape[0] > 1:
+        step = np.linalg.norm(p[1:] - p[:-1], axis=1)
+        seg[1:] = step
+    seg[first] = 0.0                      # no segment into a ray's first hit
+    owner = np.repeat(np.arange(n_rays), np.diff(ray_off))
+    inner = np.bincount(owner, weights=seg, minlength=n_rays)
+    pf = p[first]
+    pl = p[last]
+    d = np.linalg.norm(pf - x_tx, axis=1) + inner + np.linalg.norm(pl - x_rx, axis=1)
+    d[empty] = 0.0
+    return d, pf, pl
+
+
+def displaced_lengths(d, pf, pl, x_tx, x_rx, x_tx2, x_rx2):
+    """Eq. 7: l = d - |p^f - x_tx| + |p^f - x'_tx| - |p^l - x_rx| + |p^l - x'_rx|."""
+    return (d - np.linalg.norm(pf - x_tx, axis=1) + np.linalg.norm(pf - x_tx2, axis=1)
+            - np.linalg.norm(pl - x_rx, axis=1) + np.linalg.norm(pl - x_rx2, axis=1))
+
+
+def delays(lengths):
+    """Eq. 1: tau = d / c."""
+    return lengths / C0
+
+
+def slope(radar):
+    """Eq. 3: mu = B / T_c."""
+    return radar.bandwidth / radar.t_chirp
+
+
+def fast_time(radar):
+    return np.arange(radar.n_samples) / radar.f_s
+
+
+def if_signal(tau, weight, radar, ray_block=4096):
+    """Eq. 2 for one chirp and antenna pair:
+    s(t_n) = sum_i A_i exp(2 pi i (mu t_n tau_i + f_c tau_i)), summed over
+    rays in blocks of ``ray_block`` (a memory bound, not a reordering)."""
+    mu = slope(radar)
+    t = fast_time(radar)
+    s = np.zeros(radar.n_samples, dtype=np.complex128)
+    for b in range(0, tau.shape[0], ray_block):
+        tb = tau[b:b + ray_block, None]
+        wb = weight[b:b + ray_block, None].astype(np.float64)
+        s += np.sum(wb * np.exp(2j * np.pi * (mu * t[None, :] * tb + radar.f_c * tb)), axis=0)
+    return s
+
+
+def ray_weights(scene, span=None):
+    """A_i (1 unless the scene carries a pattern weight) times the span mask;
+    0 for a ray with no hits."""
+    w = np.ones(scene.n_rays) if scene.amp is None else scene.amp.astype(np.float64)
+    w = np.where(np.diff(scene.ray_off) > 0, w, 0.0)
+    if span is not None:
+        w = w * span_mask(scene, **span)
+    return w
+
+
+def if_cube(scene, span=None, chirps=None, pairs=None):
+    """The IF cube s[q, j, n] for antenna pairs q and chirps j (Eqs. 1, 2, 6, 7)."""
+    radar = scene.radar
+    chirps = range(radar.n_chirps) if chirps is None else chirps
+    pairs = range(scene.n_pairs) if pairs is None else pairs
+    w = ray_weights(scene, span)
+    out = np.zeros((len(pairs), len(chirps), radar.n_samples), dtype=np.complex128)
+    for jj, j in enumerate(chirps):
+        p = hit_positions(scene.verts[j], scene.tris, scene.mesh_tri_off, scene.hit_mesh, scene.hit_tri,
+                          scene.hit_u, scene.hit_v)
+        d, pf, pl = path_lengths(p, scene.ray_off, scene.x_tx, scene.x_rx)
+        for qq, q in enumerate(pairs):
+            l = displaced_lengths(d, pf, pl, scene.x_tx, scene.x_rx, scene.tx_virt[q], scene.rx_virt[q])
+            out[qq, jj] = if_signal(delays(l), w, radar)
+    return out
+
+
+def range_doppler(s):
+    """Eq. 4: the 2-D DFT over (chirp, fast time) of each pair's block."""
+    return np.fft.fft2(s, axes=(-2, -1))
+
+
+# Eq. 5 span rules.  mode: 0 = the ray hits a mesh of the set at least once,
+# 1 = it hits none of them, 2 = all of its hits are on meshes of the set;
+# and the ray has between min_hits and max_hits hits (inclusive).
+SPAN_ANY, SPAN_NONE, SPAN_ALL = 0, 1, 2
+
+
+def span_mask(scene, meshes=(), mode=SPAN_ANY, min_hits=1, max_hits=1 << 30):
+    """Eq. 5: 0/1 mask of the rays a filter rule keeps (one ray at a time)."""
+    keep = np.zeros(scene.n_rays)
+    chosen = set(int(m) for m in meshes)
+    for i in range(scene.n_rays):
+        ids = [int(a) for a in scene.hit_mesh[scene.ray_off[i]:scene.ray_off[i + 1]]]
+        inside = [a in chosen for a in ids]
+        if mode == SPAN_ANY:
+            ok = any(inside)
+        elif mode == SPAN_NONE:
+            ok = not any(inside)
+        elif mode == SPAN_ALL:
+            ok = all(inside)
+        else:
+            raise ValueError(mode)
+        keep[i] = 1.0 if (ok and min_hits <= len(ids) <= max_hits) else 0.0
+    return keep

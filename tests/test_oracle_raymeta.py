@@ -1,0 +1,272 @@
+"""Pins of the ray-meta-data IF oracle against what the paper and the
+mathematics fix (closed forms, invariants, brute force on tiny inputs).
+
+Each pin is chosen so that a plausible slip in the oracle fails it: a wrong
+barycentric weight (Eq. 6), a missing or extra path leg (Section II.A), a sign
+in Eq. 7, the delay scale (Eq. 1), the slope (Eq. 3), the sign or scale of
+either phase term of Eq. 2, the fast-time grid, and the direction and
+normalisation of the 2-D DFT (Eq. 4).
+"""
+import cmath
+import math
+
+import numpy as np
+import pytest
+
+from oracle import raymeta as R
+from paper_2305_14176_amd import rayscene as S
+
+
+def _tiny_scene(n_rays=5, n_chirps=2, n_samples=8, seed=3, n_tx=2, n_rx=1):
+    sc = S.pedestrian_scene(n_rays=n_rays, n_meshes=2, tris_per_mesh=8,
+                            radar=S.Radar(n_samples=n_samples, n_chirps=n_chirps), n_tx=n_tx, n_rx=n_rx, seed=seed)
+    return sc
+
+
+def _point_scene(dists, radar, amp=None, verts=None):
+    """One mesh, one triangle with its first vertex at (r, 0, 0) per chirp;
+    each ray is a single hit at u = v = 0 (exactly that vertex); TX = RX =
+    origin, one antenna pair with no displacement."""
+    n = len(dists)
+    if verts is None:
+        verts = np.zeros((radar.n_chirps, 3, 3))
+        for j in range(radar.n_chirps):
+            verts[j, 0] = [dists[0], 0.0, 0.0]
+            verts[j, 1] = [dists[0], 1.0, 0.0]
+            verts[j, 2] = [dists[0], 0.0, 1.0]
+    o = np.zeros(3)
+    return S.RayScene("point", radar, np.array([0, 1], np.int32), np.array([[0, 1, 2]], np.int32), verts,
+                      np.arange(n + 1, dtype=np.int32), np.zeros(n, np.int32), np.zeros(n, np.int32),
+                      np.zeros(n, np.float32), np.zeros(n, np.float32), o, o, o[None], o[None],
+                      None if amp is None else np.asarray(amp, np.float32))
+
+
+# ---------------------------------------------------------------- Eq. 6
+
+def test_eq6_vertices_and_barycentre():
+    """(u, v) = (0, 0), (1, 0), (0, 1) give v1, v2, v3; (1/3, 1/3) the centroid."""
+    verts = np.array([[1.0, 2.0, 3.0], [-4.0, 0.5, 2.0], [7.0, -1.0, 0.25], [9.0, 9.0, 9.0]])
+    tris = np.array([[3, 3, 3], [0, 1, 2]], np.int32)
+    off = np.array([0, 1, 2], np.int32)     # mesh 0: triangle 0, mesh 1: triangle 1
+    u = np.array([0.0, 1.0, 0.0, 1 / 3], np.float32)
+    v = np.array([0.0, 0.0, 1.0, 1 / 3], np.float32)
+    p = R.hit_positions(verts, tris, off, np.ones(4, np.int32), np.zeros(4, np.int32), u, v)
+    np.testing.assert_array_equal(p[0], verts[0])
+    np.testing.assert_array_equal(p[1], verts[1])
+    np.testing.assert_array_equal(p[2], verts[2])
+    np.testing.assert_allclose(p[3], verts[:3].mean(axis=0) + (np.float64(np.float32(1 / 3)) - 1 / 3)
+                               * (verts[1] + verts[2] - 2 * verts[0]), rtol=0, atol=1e-14)
+
+
+def test_eq6_rigid_motion_moves_hits_with_the_triangle():
+    """A rotation + translation of the vertices moves every hit point by the
+    same motion (the property Section II.D relies on), and the hit keeps its
+    barycentric coordinates: solving for (u, v) returns them."""
+    sc = S.small_scene(n_rays=300, n_chirps=1, n_samples=8)
+    rng = np.random.default_rng(0)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    shift = rng.normal(size=3) * 5
+    args = (sc.tris, sc.mesh_tri_off, sc.hit_mesh, sc.hit_tri, sc.hit_u, sc.hit_v)
+    p0 = R.hit_positions(sc.verts[0], *args)
+    p1 = R.hit_positions(sc.verts[0] @ q.T + shift, *args)
+    np.testing.assert_allclose(p1, p0 @ q.T + shift, atol=1e-12)
+    t = sc.mesh_tri_off[sc.hit_mesh] + sc.hit_tri
+    a, b, c = (sc.verts[0][sc.tris[t, k]] for k in range(3))
+    for k in range(0, sc.n_hits, 37):
+        m = np.stack([b[k] - a[k], c[k] - a[k]], axis=1)
+        uv, *_ = np.linalg.lstsq(m, p0[k] - a[k], rcond=None)
+        np.testing.assert_allclose(uv, [sc.hit_u[k], sc.hit_v[k]], atol=1e-9)
+
+
+# ------------------------------------------------- path length and Eq. 7
+
+def _brute_lengths(sc, j, tx, rx):
+    out = []
+    for i in range(sc.n_rays):
+        pts = []
+        for k in range(sc.ray_off[i], sc.ray_off[i + 1]):
+            t = sc.mesh_tri_off[sc.hit_mesh[k]] + sc.hit_tri[k]
+            a, b, c = (sc.verts[j][sc.tris[t][m]] for m in range(3))
+            u, v = float(sc.hit_u[k]), float(sc.hit_v[k])
+            pts.append([(1 - u - v) * a[m] + u * b[m] + v * c[m] for m in range(3)])
+        route = [list(tx)] + pts + [list(rx)]
+        out.append(sum(math.dist(route[m], route[m + 1]) for m in range(len(route) - 1)))
+    return np.array(out)
+
+
+def test_path_length_brute_force():
+    """TX -> hits in order -> RX, by explicit loops over each ray's route."""
+    sc = S.small_scene(n_rays=200, n_chirps=2, n_samples=8)
+    for j in range(2):
+        p = R.hit_positions(sc.verts[j], sc.tris, sc.mesh_tri_off, sc.hit_mesh, sc.hit_tri, sc.hit_u, sc.hit_v)
+        d, _, _ = R.path_lengths(p, sc.ray_off, sc.x_tx, sc.x_rx)
+        np.testing.assert_allclose(d, _brute_lengths(sc, j, sc.x_tx, sc.x_rx), rtol=1e-14)
+
+
+def test_path_length_closed_form_monostatic():
+    """TX = RX at the origin, one hit at distance r: d = 2 r; two hits at r1
+    then r2 along one ray line: d = r1 + |r2 - r1| + r2."""
+    radar = S.Radar(n_samples=8, n_chirps=1)
+    sc = _point_scene([7.25], radar)
+    p = R.hit_positions(sc.verts[0], sc.tris, sc.mesh_tri_off, sc.hit_mesh, sc.hit_tri, sc.hit_u, sc.hit_v)
+    d, _, _ = R.path_lengths(p, sc.ray_off, sc.x_tx, sc.x_rx)
+    assert d[0] == 14.5
+    p2 = np.array([[3.0, 4.0, 0.0], [6.0, 8.0, 0.0]])
+    d2, pf, pl = R.path_lengths(p2, np.array([0, 2]), np.zeros(3), np.zeros(3))
+    assert d2[0] == pytest.approx(5.0 + 5.0 + 10.0, rel=1e-15)
+    np.testing.assert_array_equal(pf[0], p2[0])
+    np.testing.assert_array_equal(pl[0], p2[1])
+
+
+def test_eq7_identity_and_direct_path():
+    """Zero displacement leaves l = d; a displaced pair gives exactly the route
+    length from the displaced antennas (brute force over the hits)."""
+    sc = S.small_scene(n_rays=150, n_chirps=1, n_samples=8)
+    p = R.hit_positions(sc.verts[0], sc.tris, sc.mesh_tri_off, sc.hit_mesh, sc.hit_tri, sc.hit_u, sc.hit_v)
+    d, pf, pl = R.path_lengths(p, sc.ray_off, sc.x_tx, sc.x_rx)
+    np.testing.assert_allclose(R.displaced_lengths(d, pf, pl, sc.x_tx, sc.x_rx, sc.x_tx, sc.x_rx), d, rtol=1e-15)
+    tx2 = sc.x_tx + np.array([0.3, -0.7, 0.2])
+    rx2 = sc.x_rx + np.array([-0.1, 0.4, 0.9])
+    l = R.displaced_lengths(d, pf, pl, sc.x_tx, sc.x_rx, tx2, rx2)
+    np.testing.assert_allclose(l, _brute_lengths(sc, 0, tx2, rx2), rtol=1e-13)
+
+
+def test_eq7_far_field_phase_shift():
+    """Far field: moving TX by delta changes the path by -delta . u_hat (u_hat
+    the unit vector from TX to the first hit), to O(|delta|^2 / r)."""
+    delta = np.array([0.0, 0.002, 0.0])
+    for r in (10.0, 100.0, 1000.0):
+        hit = np.array([r * 0.8, r * 0.6, 0.0])
+        d, pf, pl = R.path_lengths(hit[None], np.array([0, 1]), np.zeros(3), np.zeros(3))
+        l = R.displaced_lengths(d, pf, pl, np.zeros(3), np.zeros(3), delta, np.zeros(3))
+        assert abs((l[0] - d[0]) - (-0.6 * 0.002)) < 0.002 ** 2 / r
+
+
+# ------------------------------------------------------------ Eqs. 1-3
+
+def test_eq2_on_bin_tone_closed_form():
+    """One ray whose beat frequency mu tau falls on range bin k0: the DFT over
+    fast time is N_s A exp(2 pi i f_c tau) at bin k0 and zero elsewhere.  This
+    fixes the delay scale (Eq. 1), the slope (Eq. 3), the sign and both phase
+    terms of Eq. 2, t_n = n / f_s and the DFT convention of Eq. 4."""
+    radar = S.Radar(n_samples=64, n_chirps=1, f_s=10e6, bandwidth=1e9, t_chirp=51.2e-6)
+    mu = radar.bandwidth / radar.t_chirp
+    k0 = 13
+    tau = k0 * radar.f_s / (radar.n_samples * mu)          # on-bin beat frequency
+    r = tau * R.C0 / 2
+    sc = _point_scene([r], radar, amp=[0.75])
+    s = R.if_cube(sc)[0, 0]
+    spec = np.fft.fft(s)
+    tau_exact = 2 * np.float64(r) / R.C0
+    expect = 64 * 0.75 * cmath.exp(2j * math.pi * radar.f_c * tau_exact)
+    assert abs(spec[k0] - expect) < 1e-6 * 64
+    spec[k0] = 0
+    assert np.abs(spec).max() < 1e-6 * 64
+    # and the full 2-D transform puts it at Doppler bin 0
+    big = R.range_doppler(R.if_cube(sc))
+    assert np.unravel_index(np.abs(big[0]).argmax(), big[0].shape) == (0, k0)
+
+
+def test_static_scene_identical_chirps_zero_doppler():
+    sc = S.small_scene(n_rays=64, n_chirps=4, n_samples=32)
+    sc.verts[:] = sc.verts[0]
+    s = R.if_cube(sc)
+    for j in range(1, 4):
+        np.testing.assert_array_equal(s[:, j], s[:, 0])
+    spec = R.range_doppler(s)
+    assert np.abs(spec[:, 1:, :]).max() < 1e-9 * np.abs(spec).max()
+
+
+def test_moving_point_doppler_bin():
+    """A point receding at v: the chirp-to-chirp phase step is
+    4 pi f_c v T_d / c (Section II.A).  With v chosen for Doppler bin m the
+    range-Doppler peak sits at (m, range bin), and the chirp-to-chirp phase
+    ratio of the range bin is exactly that step."""
+    radar = S.Radar(n_samples=64, n_chirps=16)
+    m = 3
+    v = m / radar.n_chirps * R.C0 / (2 * radar.f_c * radar.t_frame)
+    r0 = 12.0
+    verts = np.zeros((radar.n_chirps, 3, 3))
+    for j in range(radar.n_chirps):
+        x = r0 + v * j * radar.t_frame
+        verts[j] = [[x, 0, 0], [x, 1, 0], [x, 0, 1]]
+    sc = _point_scene([r0], radar, verts=verts)
+    s = R.if_cube(sc)[0]
+    step = np.angle(s[1:, 0] / s[:-1, 0])
+    expect = math.remainder(4 * math.pi * radar.f_c * v * radar.t_frame / R.C0, 2 * math.pi)
+    np.testing.assert_allclose(step, expect, atol=1e-6)
+    spec = np.abs(R.range_doppler(s))
+    assert np.unravel_index(spec.argmax(), spec.shape)[0] == m
+
+
+# -------------------------------------------------------- brute force
+
+def test_cube_brute_force_tiny():
+    """Everything from scratch with scalar loops and cmath on a tiny scene
+    (five rays, two chirps, two pairs, eight samples) against the oracle."""
+    sc = _tiny_scene()
+    sc.amp = S.random_amplitudes(sc, 9)
+    mu = sc.radar.bandwidth / sc.radar.t_chirp
+    ref = np.zeros((sc.n_pairs, sc.radar.n_chirps, sc.radar.n_samples), complex)
+    for q in range(sc.n_pairs):
+        for j in range(sc.radar.n_chirps):
+            lens = _brute_lengths(sc, j, sc.tx_virt[q], sc.rx_virt[q])
+            for n in range(sc.radar.n_samples):
+                t = n / sc.radar.f_s
+                ref[q, j, n] = sum(float(sc.amp[i]) * cmath.exp(2j * math.pi * (mu * t * lens[i] / R.C0
+                                                                                + sc.radar.f_c * lens[i] / R.C0))
+                                   for i in range(sc.n_rays))
+    got = R.if_cube(sc)
+    assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
+    # Eq. 4 by explicit sums
+    nq, nc, ns = ref.shape
+    spec = np.zeros_like(ref)
+    for q in range(nq):
+        for fd in range(nc):
+            for fr in range(ns):
+                spec[q, fd, fr] = sum(ref[q, j, n] * cmath.exp(-2j * math.pi * (fd * j / nc + fr * n / ns))
+                                      for j in range(nc) for n in range(ns))
+    np.testing.assert_allclose(R.range_doppler(got), spec, atol=1e-9 * np.abs(spec).max())
+
+
+def test_range_doppler_parseval():
+    s = R.if_cube(S.small_scene(n_rays=50, n_chirps=4, n_samples=16))
+    spec = R.range_doppler(s)
+    np.testing.assert_allclose(np.sum(np.abs(spec) ** 2), 4 * 16 * np.sum(np.abs(s) ** 2), rtol=1e-12)
+
+
+# ------------------------------------------------------------- Eq. 5
+
+def test_span_masks_hand_built():
+    """Hand-checked masks on four rays: hits (mesh IDs) [0], [1, 0], [2, 2, 2], [1]."""
+    sc = _tiny_scene(n_rays=4)
+    sc.ray_off = np.array([0, 1, 3, 6, 7], np.int32)
+    sc.hit_mesh = np.array([0, 1, 0, 2, 2, 2, 1], np.int32)
+    m = lambda **kw: R.span_mask(sc, **kw).astype(int).tolist()   # noqa: E731
+    assert m(meshes=[0], mode=R.SPAN_ANY) == [1, 1, 0, 0]
+    assert m(meshes=[0], mode=R.SPAN_NONE) == [0, 0, 1, 1]
+    assert m(meshes=[1, 2], mode=R.SPAN_ALL) == [0, 0, 1, 1]
+    assert m(meshes=[0, 1, 2], mode=R.SPAN_ANY, min_hits=2) == [0, 1, 1, 0]     # ghost rays
+    assert m(meshes=[1], mode=R.SPAN_ANY, max_hits=1) == [0, 0, 0, 1]           # direct, mesh 1
+
+
+def test_span_partition_sums_to_whole():
+    """Eq. 5: spans that partition the rays sum to the full signal."""
+    sc = S.small_scene(n_rays=120, n_chirps=2, n_samples=16)
+    whole = R.if_cube(sc)
+    parts = [R.if_cube(sc, span=dict(meshes=[0], mode=R.SPAN_ANY)),
+             R.if_cube(sc, span=dict(meshes=[0], mode=R.SPAN_NONE))]
+    np.testing.assert_allclose(parts[0] + parts[1], whole, atol=1e-10 * np.abs(whole).max())
+    by_hits = sum(R.if_cube(sc, span=dict(meshes=[0, 1, 2], mode=R.SPAN_ALL, min_hits=k, max_hits=k))
+                  for k in range(1, 5))
+    np.testing.assert_allclose(by_hits, whole, atol=1e-10 * np.abs(whole).max())
+
+
+def test_empty_ray_contributes_nothing():
+    sc = _tiny_scene(n_rays=3)
+    base = R.if_cube(sc)
+    # insert an empty ray between rays 0 and 1
+    sc2 = _tiny_scene(n_rays=3)
+    sc2.ray_off = np.insert(sc.ray_off, 1, sc.ray_off[1]).astype(np.int32)
+    sc2.amp = np.ones(4, np.float32)
+    np.testing.assert_allclose(R.if_cube(sc2), base, atol=1e-12)
