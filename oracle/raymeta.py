@@ -87,17 +87,19 @@ def slope(radar):
     return radar.bandwidth / radar.t_chirp
 
 
-def fast_time(radar):
-    return np.arange(radar.n_samples) / radar.f_s
+def fast_time(radar, samples=None):
+    n = np.arange(radar.n_samples) if samples is None else np.asarray(samples)
+    return n / radar.f_s
 
 
-def if_signal(tau, weight, radar, ray_block=4096):
+def if_signal(tau, weight, radar, ray_block=4096, samples=None):
     """Eq. 2 for one chirp and antenna pair:
     s(t_n) = sum_i A_i exp(2 pi i (mu t_n tau_i + f_c tau_i)), summed over
-    rays in blocks of ``ray_block`` (a memory bound, not a reordering)."""
+    rays in blocks of ``ray_block`` (a memory bound, not a reordering); at
+    every sample, or only at the sample indices ``samples``."""
     mu = slope(radar)
-    t = fast_time(radar)
-    s = np.zeros(radar.n_samples, dtype=np.complex128)
+    t = fast_time(radar, samples)
+    s = np.zeros(t.shape[0], dtype=np.complex128)
     for b in range(0, tau.shape[0], ray_block):
         tb = tau[b:b + ray_block, None]
         wb = weight[b:b + ray_block, None].astype(np.float64)
@@ -115,20 +117,22 @@ def ray_weights(scene, span=None):
     return w
 
 
-def if_cube(scene, span=None, chirps=None, pairs=None):
-    """The IF cube s[q, j, n] for antenna pairs q and chirps j (Eqs. 1, 2, 6, 7)."""
+def if_cube(scene, span=None, chirps=None, pairs=None, samples=None):
+    """The IF cube s[q, j, n] for antenna pairs q and chirps j (Eqs. 1, 2, 6, 7),
+    at every sample n or at the indices ``samples``."""
     radar = scene.radar
     chirps = range(radar.n_chirps) if chirps is None else chirps
     pairs = range(scene.n_pairs) if pairs is None else pairs
     w = ray_weights(scene, span)
-    out = np.zeros((len(pairs), len(chirps), radar.n_samples), dtype=np.complex128)
+    ns = radar.n_samples if samples is None else len(samples)
+    out = np.zeros((len(pairs), len(chirps), ns), dtype=np.complex128)
     for jj, j in enumerate(chirps):
         p = hit_positions(scene.verts[j], scene.tris, scene.mesh_tri_off, scene.hit_mesh, scene.hit_tri,
                           scene.hit_u, scene.hit_v)
         d, pf, pl = path_lengths(p, scene.ray_off, scene.x_tx, scene.x_rx)
         for qq, q in enumerate(pairs):
             l = displaced_lengths(d, pf, pl, scene.x_tx, scene.x_rx, scene.tx_virt[q], scene.rx_virt[q])
-            out[qq, jj] = if_signal(delays(l), w, radar)
+            out[qq, jj] = if_signal(delays(l), w, radar, samples=samples)
     return out
 
 

@@ -7,9 +7,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libyee.so")
+RAYMETA_LIB = os.path.join(HERE, "libraymeta.so")
 
-SOURCES = ["yee_runtime.hip"]
-HEADERS = ["yee_kernels.hpp", "yee_adjoint.hpp", os.path.join("..", "..", "include", "yee.h")]
+# library -> its HIP sources (each library is one translation unit)
+LIBRARIES = {
+    LIB: ["yee_runtime.hip"],
+    RAYMETA_LIB: ["raymeta.hip"],
+}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -31,11 +35,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, extra_flags=()) -> str:
-    """Compile every source into ``libyee.so`` (always recompiles)."""
-    out_tmp = LIB + ".tmp"
+def build_one(lib: str, sources, verbose: bool = False, extra_flags=()) -> str:
+    out_tmp = lib + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", out_tmp]
+           *[os.path.join(CSRC, s) for s in sources], "-o", out_tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,7 +46,14 @@ def build(verbose: bool = False, extra_flags=()) -> str:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
     if verbose and r.stderr.strip():
         print(r.stderr)
-    os.replace(out_tmp, LIB)
+    os.replace(out_tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False, extra_flags=()) -> str:
+    """Compile every library (always recompiles); returns the Yee library's path."""
+    for lib, sources in LIBRARIES.items():
+        build_one(lib, sources, verbose, extra_flags)
     return LIB
 
 

@@ -1,0 +1,190 @@
+"""GPU parity of the ray-meta-data IF path (through the C ABI of
+libraymeta) against the FP64 oracle on the same seeded inputs.
+
+Tolerances:
+  * IF cube (Eqs. 1-3, 6, 7): relative L2 <= 1e-5 per (pair, chirp) block
+    against the FP64 oracle.  The kernel forms each ray's phase in FP64,
+    reduces it modulo one cycle, and runs an FP32 phasor recurrence over runs
+    of 8 samples: per-term errors of a few 1e-7 rad, far inside the gate.
+  * Range-Doppler (Eq. 4): relative L2 <= 1e-5 against numpy's FP64 FFT of
+    the same (GPU) input: FP32 radix-2 rounding grows like log2(N) eps.
+  * Span masks (Eq. 5): bit-exact (0/1 times the float32 pattern weight).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import raymeta as R
+from paper_2305_14176_amd import rayscene as S
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def RM():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2305_14176_amd import raymeta
+    raymeta.load()
+    return raymeta
+
+
+def _blocks_rel(got, ref):
+    num = np.sqrt(np.sum(np.abs(got - ref) ** 2, axis=-1))
+    den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=-1))
+    return num / den
+
+
+def _cube(RM, sc, **kw):
+    ds = RM.DeviceScene(sc)
+    return ds, RM.if_cube(ds, **kw).cpu().numpy()
+
+
+@pytest.mark.parametrize("n_rays,n_samples,n_chirps,amp", [
+    (4096, 256, 6, False),
+    (1000, 512, 3, True),        # ragged ray count (not a multiple of 64 or 256)
+    (777, 300, 2, True),         # ragged sample count: part of the last lane run unused
+    (2048, 1000, 2, False),      # two 512-sample passes per wave, the second ragged
+    (1, 64, 2, False),           # a single ray
+])
+def test_if_cube_small(RM, n_rays, n_samples, n_chirps, amp):
+    sc = S.small_scene(n_rays=n_rays, n_chirps=n_chirps, n_samples=n_samples)
+    if amp:
+        sc.amp = S.random_amplitudes(sc, 5)
+    _say(f"[gpu] raymeta if_cube rays={n_rays} samples={n_samples} chirps={n_chirps} pairs={sc.n_pairs}")
+    ds, got = _cube(RM, sc)
+    ref = R.if_cube(sc)
+    err = _blocks_rel(got, ref)
+    _say(f"[gpu]   worst block rel L2 {err.max():.2e}")
+    assert err.max() <= TOL, err.max()
+
+
+def test_if_cube_max_samples_and_chirp_window(RM):
+    """RMD_MAX_SAMPLES samples; a chirp window [2, 5) of a 6-chirp scene."""
+    sc = S.small_scene(n_rays=600, n_chirps=6, n_samples=RM.MAX_SAMPLES)
+    _say("[gpu] raymeta max samples, chirp window")
+    ds = RM.DeviceScene(sc)
+    got = RM.if_cube(ds, chirps=[2, 3, 4]).cpu().numpy()
+    ref = R.if_cube(sc, chirps=[2, 3, 4])
+    assert _blocks_rel(got, ref).max() <= TOL
+
+
+def test_bad_and_empty_rays_contribute_nothing(RM):
+    """Rays with no hits or with out-of-range meta data add nothing (the
+    kernel checks every index before using it); rmd_check_scene counts them."""
+    sc = S.small_scene(n_rays=300, n_chirps=2, n_samples=128)
+    ref = R.if_cube(sc)
+    # ray 7: mesh ID out of range; ray 8: triangle index out of range;
+    # ray 9: a vertex index out of range (through a corrupted triangle)
+    bad = S.small_scene(n_rays=300, n_chirps=2, n_samples=128)
+    bad.hit_mesh = bad.hit_mesh.copy()
+    bad.hit_tri = bad.hit_tri.copy()
+    bad.tris = bad.tris.copy()
+    k9 = sc.ray_off[9]
+    t9 = sc.mesh_tri_off[sc.hit_mesh[k9]] + sc.hit_tri[k9]
+    users = np.nonzero((sc.mesh_tri_off[sc.hit_mesh] + sc.hit_tri) == t9)[0]
+    owners = set(int(i) for i in np.searchsorted(sc.ray_off, users, side="right") - 1)
+    bad.tris[t9, 1] = bad.n_verts + 5
+    bad.hit_mesh[bad.ray_off[7]] = 99
+    bad.hit_tri[bad.ray_off[8]] = 1 << 20
+    _say("[gpu] raymeta bad meta data")
+    ds = RM.DeviceScene(bad)
+    assert RM.check_scene(ds) == len({7, 8} | owners)
+    got = RM.if_cube(ds).cpu().numpy()
+    ref_kept = R.if_cube(sc, span=None) - sum(
+        R.if_cube(_one_ray(sc, i)) for i in [7, 8] + sorted(owners))
+    assert _blocks_rel(got, ref_kept).max() <= TOL
+    assert RM.check_scene(RM.DeviceScene(sc)) == 0
+    # an empty ray in the middle
+    sc2 = S.small_scene(n_rays=300, n_chirps=2, n_samples=128)
+    sc2.ray_off = np.insert(sc2.ray_off, 5, sc2.ray_off[5]).astype(np.int32)
+    sc2.amp = np.ones(301, np.float32)
+    got2 = RM.if_cube(RM.DeviceScene(sc2)).cpu().numpy()
+    assert _blocks_rel(got2, ref).max() <= TOL
+
+
+def _one_ray(sc, i):
+    """The scene restricted to ray i (for subtracting single contributions)."""
+    b, e = sc.ray_off[i], sc.ray_off[i + 1]
+    return S.RayScene("one", sc.radar, sc.mesh_tri_off, sc.tris, sc.verts, np.array([0, e - b], np.int32),
+                      sc.hit_mesh[b:e], sc.hit_tri[b:e], sc.hit_u[b:e], sc.hit_v[b:e], sc.x_tx, sc.x_rx,
+                      sc.tx_virt, sc.rx_virt, None)
+
+
+def test_range_doppler_matches_fft(RM):
+    import torch
+    sc = S.small_scene(n_rays=2000, n_chirps=16, n_samples=256)
+    _say("[gpu] raymeta range-Doppler")
+    ds = RM.DeviceScene(sc)
+    s = RM.if_cube(ds)
+    got = RM.range_doppler(s).cpu().numpy()
+    ref = np.fft.fft2(s.cpu().numpy().astype(np.complex128), axes=(-2, -1))
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say(f"[gpu]   rel L2 {err:.2e}")
+    assert err <= TOL
+    # in place, and the full configuration's shape (128 chirps x 512 samples)
+    x = (torch.randn(3, 128, 512, dtype=torch.complex64, device="cuda"))
+    ref = np.fft.fft2(x.cpu().numpy().astype(np.complex128), axes=(-2, -1))
+    RM.range_doppler(x, out=x)
+    assert np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref) <= TOL
+    # degenerate lines: one chirp, and the largest line length
+    for shape in [(2, 1, 64), (1, 2, RM.MAX_FFT)]:
+        y = torch.randn(*shape, dtype=torch.complex64, device="cuda")
+        ref = np.fft.fft2(y.cpu().numpy().astype(np.complex128), axes=(-2, -1))
+        out = RM.range_doppler(y).cpu().numpy()
+        assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= TOL, shape
+
+
+@pytest.mark.parametrize("rule", [
+    dict(meshes=[0], mode=R.SPAN_ANY),
+    dict(meshes=[0], mode=R.SPAN_NONE),
+    dict(meshes=[1, 2], mode=R.SPAN_ALL),
+    dict(meshes=[0, 1, 2], mode=R.SPAN_ANY, min_hits=2),
+    dict(meshes=[2], mode=R.SPAN_ANY, max_hits=1),
+])
+def test_span_weights_exact(RM, rule):
+    sc = S.small_scene(n_rays=3000, n_chirps=2, n_samples=64)
+    sc.amp = S.random_amplitudes(sc, 8)
+    ds = RM.DeviceScene(sc)
+    got = RM.span_weights(ds, **rule).cpu().numpy()
+    ref = (R.span_mask(sc, **rule) * sc.amp.astype(np.float64)).astype(np.float32)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_span_decomposition_sums_to_whole(RM):
+    """Eq. 5 on the GPU: the IF of complementary spans adds up to the whole,
+    and each span matches the oracle's span signal."""
+    sc = S.small_scene(n_rays=2500, n_chirps=3, n_samples=256)
+    ds = RM.DeviceScene(sc)
+    whole = RM.if_cube(ds).cpu().numpy()
+    parts = []
+    for mode in (R.SPAN_ANY, R.SPAN_NONE):
+        w = RM.span_weights(ds, meshes=[1], mode=mode)
+        parts.append(RM.if_cube(ds, weights=w).cpu().numpy())
+        ref = R.if_cube(sc, span=dict(meshes=[1], mode=mode))
+        assert _blocks_rel(parts[-1], ref).max() <= TOL
+    assert _blocks_rel(parts[0] + parts[1], whole).max() <= 2 * TOL
+
+
+@pytest.mark.timeout(600)
+def test_full_size_sampled(RM):
+    """The full scene (8 meshes x 4096 triangles, 2^20 rays, 12 antenna pairs,
+    512 samples) over chirps [0, 2) in the launch shape the benchmark times,
+    against the oracle at 16 sampled fast-time indices of every block."""
+    sc = S.pedestrian_scene()
+    _say(f"[gpu] raymeta full size: {sc.n_rays} rays, {sc.n_hits} hits, {sc.n_pairs} pairs")
+    ds = RM.DeviceScene(sc.with_chirps(0, 2))
+    syn = RM.Synthesizer(ds, chirp_count=2)
+    got = syn.run(0, ds.amp).cpu().numpy()
+    sel = [0, 1, 7, 8, 63, 64, 100, 255, 256, 300, 383, 448, 500, 509, 510, 511]
+    ref = R.if_cube(sc, chirps=[0, 1], samples=sel)
+    err = _blocks_rel(got[:, :, sel], ref)
+    _say(f"[gpu]   worst sampled block rel L2 {err.max():.2e}")
+    assert err.max() <= TOL

@@ -270,3 +270,12 @@ def test_empty_ray_contributes_nothing():
     sc2.ray_off = np.insert(sc.ray_off, 1, sc.ray_off[1]).astype(np.int32)
     sc2.amp = np.ones(4, np.float32)
     np.testing.assert_allclose(R.if_cube(sc2), base, atol=1e-12)
+
+
+def test_sampled_evaluation_matches_full():
+    """Selected fast-time samples (used for full-size parity) equal the same
+    entries of the full evaluation."""
+    sc = S.small_scene(n_rays=90, n_chirps=2, n_samples=64)
+    full = R.if_cube(sc)
+    sel = [0, 5, 63, 17]
+    np.testing.assert_allclose(R.if_cube(sc, samples=sel), full[:, :, sel], rtol=0, atol=1e-12)
