@@ -229,6 +229,75 @@ def adjoint_benchmark(checkpoint_every=64):
     return out
 
 
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak (it counts packed two-wide FP32 ops)
+FP32_UNPACKED_TFLOPS = 78.6       # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (one FMA) x 2.4 GHz
+FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply (6) and a complex add (2)
+
+
+def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
+    """IF cube from ray meta data (Eqs. 1-7) on the full pedestrian scene:
+    2^20 rays, 8 meshes x 4096 triangles, 12 antenna pairs, 128 chirps x 512
+    samples; then the range-Doppler map of the cube (Eq. 4)."""
+    import torch
+    from paper_2305_14176_amd import raymeta as RM
+    from paper_2305_14176_amd import rayscene as RS
+    sc = RS.pedestrian_scene()
+    ds = RM.DeviceScene(sc, device="cuda:0")
+    syn = RM.Synthesizer(ds)
+    stream = torch.cuda.current_stream()
+    syn.run(0, ds.amp)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        syn.run(0, ds.amp)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    r = sc.radar
+    terms = sc.n_rays * sc.n_pairs * r.n_chirps * r.n_samples
+    spec = torch.empty_like(syn.out)
+    RM.range_doppler(syn.out, out=spec)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(20):
+        RM.range_doppler(syn.out, out=spec)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    rd_ms = ev0.elapsed_time(ev1) / 20
+    tflops = terms * FLOPS_PER_TERM / (ms / 1e3) / 1e12
+    out = {
+        "workload": f"{sc.name}: {sc.n_hits} hits, {sc.n_pairs} antenna pairs (3 TX x 4 RX), "
+                    f"{r.n_chirps} chirps x {r.n_samples} samples, 77 GHz, B = 1 GHz, T_c = 51.2 us, f_s = 10 MHz",
+        "dtype": "f64 geometry and phase, f32 phasor recurrence, f64 partition sums",
+        "metric": "IF terms/s (ray x antenna pair x chirp x sample)",
+        "value": round(terms / (ms / 1e3), 1),
+        "unit": "terms/s",
+        "ms_per_cube": round(ms, 3),
+        "cubes_per_s": round(1e3 / ms, 3),
+        "reps": reps,
+        "range_doppler_ms": round(rd_ms, 4),
+        "roofline": {"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "unpacked_peak": FP32_UNPACKED_TFLOPS,
+                     "frac_of_unpacked": round(tflops / FP32_UNPACKED_TFLOPS, 4),
+                     "traffic": None, "algorithmic_flops_per_launch": terms * FLOPS_PER_TERM,
+                     "kernel": "rmd::synth_kernel<1> (+ rmd::reduce_kernel)", "kernel_ms_avg": round(ms, 3)},
+    }
+    if cpu:
+        from oracle import raymeta as R
+        small = sc.with_rays(cpu_rays)
+        t0 = time.perf_counter()
+        R.if_cube(small, chirps=[0])
+        dt = time.perf_counter() - t0
+        n = cpu_rays * sc.n_pairs * r.n_samples
+        out["cpu_baseline"] = {"value": round(n / dt, 1), "unit": "terms/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the first {cpu_rays} rays, chirp 0, all {sc.n_pairs} pairs and "
+                                         f"{r.n_samples} samples (numpy FP64, single-threaded), {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +311,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient measurement")
     ap.add_argument("--no-precisions", action="store_true", help="skip the FP16-storage and FP64 configurations")
+    ap.add_argument("--no-if-synthesis", action="store_true", help="skip the ray-meta-data IF measurement")
+    ap.add_argument("--if-only", action="store_true",
+                    help="run only the ray-meta-data IF measurement and print its JSON object")
+    ap.add_argument("--if-reps", type=int, default=5)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: a few untimed steps, then a plain device copy of "
                          "COPY_MIB MiB (the known-size kernel the HBM counters are scaled by)")
@@ -255,6 +328,11 @@ def main():
     import torch
     from paper_2305_14176_amd import workloads as W
     from paper_2305_14176_amd.solver import YeeSolver
+
+    if args.if_only:
+        print(json.dumps({"if_synthesis": if_synthesis_benchmark(reps=args.if_reps,
+                                                                 cpu=not args.no_cpu_baseline)}))
+        return
 
     wl = W.cpml_block_lattice(n=args.n, steps=args.steps)
     if args.profile_run:
@@ -325,6 +403,8 @@ def main():
     }
     if not args.no_precisions:
         out["precision_modes"] = precision_benchmark()
+    if not args.no_if_synthesis:
+        out["if_synthesis"] = if_synthesis_benchmark(reps=args.if_reps, cpu=not args.no_cpu_baseline)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark()
     if not args.no_serving:

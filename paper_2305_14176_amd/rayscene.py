@@ -91,6 +91,14 @@ class RayScene:
     def n_verts(self) -> int:
         return int(self.verts.shape[1])
 
+    def with_rays(self, k: int) -> "RayScene":
+        """The same scene restricted to its first k rays."""
+        e = int(self.ray_off[k])
+        return RayScene(self.name + f"[rays :{k}]", self.radar, self.mesh_tri_off, self.tris, self.verts,
+                        self.ray_off[:k + 1].copy(), self.hit_mesh[:e], self.hit_tri[:e], self.hit_u[:e],
+                        self.hit_v[:e], self.x_tx, self.x_rx, self.tx_virt, self.rx_virt,
+                        None if self.amp is None else self.amp[:k])
+
     def with_chirps(self, j0: int, j1: int) -> "RayScene":
         """The same scene restricted to chirps [j0, j1)."""
         r = Radar(**{**self.radar.__dict__, "n_chirps": j1 - j0})
