@@ -2,9 +2,13 @@
 // for gfx950.  The C ABI is declared in include/raymeta.h.
 //
 // Kernels:
-//   synth_kernel   Eqs. 6, 7, 1, 2 fused: per workgroup one antenna pair, one
-//                  chirp and one partition of the rays; FP64 geometry per ray,
-//                  then an FP32 phasor recurrence over fast time.
+//   geometry_kernel Eq. 6 for every hit of a ray and the pair-independent
+//                  part of its path (FP64), once per ray and chirp.
+//   synth_kernel   Eqs. 7, 1, 2: per workgroup one antenna pair, one chirp and
+//                  one partition of the rays; the antenna legs and phases per
+//                  ray in FP64, then the sum over rays as float32 MFMA
+//                  products of phasor tiles (fast time factored into 32 rows
+//                  x 16 columns).
 //   reduce_kernel  sums the partitions' partial cubes in FP64, fixed order.
 //   fft_kernel     radix-2 FFT of lines held in LDS (Eq. 4, one axis a pass).
 //   span_kernel    Eq. 5 rule masks, one thread per ray.
@@ -25,21 +29,15 @@ namespace rmd {
 constexpr int kWave = 64;
 constexpr int kWaves = 4;                 // waves per synthesis workgroup
 constexpr int kThreads = kWave * kWaves;
-constexpr int kRun = 8;                   // consecutive fast-time samples per lane
-constexpr int kBlock = kWave * kRun;      // samples one wave covers per pass (512)
-constexpr int kHiBits = 16;               // bits of the split per-lane phase step
-constexpr double kC0 = 299792458.0;
+constexpr int kRows = 32;                 // MFMA tile rows m: fast-time steps of kCols samples
+constexpr int kCols = 16;                 // MFMA tile columns k: consecutive samples
+constexpr int kBlock = kRows * kCols;     // samples of one pass (512)
+constexpr int kGroup = 16;                // rays per operand table
+constexpr int kTab = 4 * kRows + 4;       // floats per table row: A' (64), B' (64), pad against bank conflicts
+static_assert(kWaves * kGroup * kTab >= kWaves * 2 * kBlock, "wave sums must fit in the table memory");
 
-// One ray's contribution for one (pair, chirp), as the synthesis loop reads it.
-//   phi    f_c tau modulo 1 (cycles): phase at t = 0
-//   th_hi  kRun * theta modulo 1, rounded down to kHiBits fraction bits, with
-//   th_lo  the rest: theta = mu tau / f_s is the phase step per sample (cycles)
-//   w      weight (0: the ray contributes nothing)
-//   cz, sz cos and sin of 2 pi theta;  c2 = 2 cos(2 pi theta)
-struct alignas(16) Rec {
-    float phi, th_hi, th_lo, w;
-    float cz, sz, c2, pad;
-};
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr double kC0 = 299792458.0;
 
 struct SynthArgs {
     const int32_t* mesh_tri_off;
@@ -52,11 +50,12 @@ struct SynthArgs {
     const float* hit_v;
     const double* pairs;
     const float* weights;
+    double* geo;                // [7][chirp_count][n_rays]: inner path, first hit xyz, last hit xyz
     float2* partial;            // [n_parts][n_pairs][chirp_count][n_samples]
     int64_t n_hits;
     int32_t n_meshes, n_tris, n_verts, n_rays;
-    int32_t n_pairs, chirp0, chirp_count, n_samples;
-    int32_t n_parts, rays_per_part;
+    int32_t n_pairs, chirp0, chirp_count, n_samples;   // chirps [chirp0, chirp0 + chirp_count) of one batch
+    int32_t n_parts, rays_per_part, n_passes;
     double cyc_per_m;           // f_c / c: carrier cycles per metre of path (Eq. 1 into Eq. 2)
     double step_per_m;          // mu / (c f_s): beat cycles per sample per metre (Eqs. 1-3)
 };
@@ -91,161 +90,241 @@ __device__ inline bool hit_point(const SynthArgs& a, const double* __restrict__ 
     return true;
 }
 
-// Path length of ray i for pair q on chirp j's snapshot: inner path over the
-// hits plus the two displaced antenna legs.  Returns false when the ray has no
-// usable path (no hits, or out-of-range meta data).
-__device__ bool ray_length(const SynthArgs& a, int ray, int j, const double* __restrict__ pq, double& len) {
+// The part of ray i's path that does not depend on the antenna pair, on the
+// snapshot of chirp chirp0 + jj (Eq. 6 for every hit): the inner length from
+// the first to the last hit and those two hit points.  One thread per (ray,
+// chirp); the pair loop of the synthesis then only adds the two antenna legs.
+// A ray with no usable path (no hits, or out-of-range meta data) stores an
+// inner length of -1.
+__global__ void geometry_kernel(SynthArgs a) {
+    const int ray = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jj = blockIdx.y;
+    if (ray >= a.n_rays) return;
+    const int64_t plane = (int64_t)a.chirp_count * a.n_rays;
+    double* g = a.geo + (int64_t)jj * a.n_rays + ray;
     const int32_t b = a.ray_off[ray], e = a.ray_off[ray + 1];
-    if (b < 0 || e > a.n_hits || e <= b) return false;
-    const double* v = a.verts + (int64_t)j * a.n_verts * 3;
-    double fx, fy, fz, lx, ly, lz;
-    if (!hit_point(a, v, b, fx, fy, fz)) return false;
-    lx = fx; ly = fy; lz = fz;
-    double inner = 0.0;
-    for (int64_t k = b + 1; k < e; ++k) {
-        double x, y, z;
-        if (!hit_point(a, v, k, x, y, z)) return false;
-        inner += dist3(x, y, z, lx, ly, lz);
-        lx = x; ly = y; lz = z;
+    const double* v = a.verts + (int64_t)(a.chirp0 + jj) * a.n_verts * 3;
+    double fx = 0, fy = 0, fz = 0, lx = 0, ly = 0, lz = 0, inner = -1.0;
+    if (b >= 0 && e <= a.n_hits && e > b && hit_point(a, v, b, fx, fy, fz)) {
+        lx = fx; ly = fy; lz = fz;
+        inner = 0.0;
+        for (int64_t k = b + 1; k < e; ++k) {
+            double x, y, z;
+            if (!hit_point(a, v, k, x, y, z)) { inner = -1.0; break; }
+            inner += dist3(x, y, z, lx, ly, lz);
+            lx = x; ly = y; lz = z;
+        }
     }
-    len = dist3(fx, fy, fz, pq[0], pq[1], pq[2]) + inner + dist3(lx, ly, lz, pq[3], pq[4], pq[5]);
-    return true;
+    g[0] = inner;
+    g[plane] = fx;
+    g[2 * plane] = fy;
+    g[3 * plane] = fz;
+    g[4 * plane] = lx;
+    g[5 * plane] = ly;
+    g[6 * plane] = lz;
 }
 
-__device__ Rec make_record(const SynthArgs& a, int ray, int j, const double* __restrict__ pq) {
-    Rec r;
-    r.phi = r.th_hi = r.th_lo = r.w = r.sz = r.pad = 0.f;
-    r.cz = 1.f;
-    r.c2 = 2.f;
-    double len;
-    if (ray >= a.n_rays || !ray_length(a, ray, j, pq, len)) return r;
-    const double wt = a.weights ? (double)a.weights[ray] : 1.0;
-    const double ph = len * a.cyc_per_m;              // f_c tau, cycles
-    double th = len * a.step_per_m;                   // mu tau / f_s, cycles per sample
-    th -= floor(th);
-    double thr = kRun * th;
-    thr -= floor(thr);
-    const double hi = floor(thr * (double)(1 << kHiBits)) * (1.0 / (double)(1 << kHiBits));
-    double sn, cs;
-    sincospi(2.0 * th, &sn, &cs);
-    r.phi = (float)(ph - floor(ph));
-    r.th_hi = (float)hi;                              // exact: kHiBits fraction bits
-    r.th_lo = (float)(thr - hi);
-    r.w = (float)wt;
-    r.cz = (float)cs;
-    r.sz = (float)sn;
-    r.c2 = (float)(2.0 * cs);
-    return r;
+// Pair-independent geometry of one ray on one batch chirp (see
+// geometry_kernel) and its weight; w = 0 marks a ray that contributes nothing
+// (outside the partition, or without a usable path).
+struct Geo {
+    double inner, fx, fy, fz, lx, ly, lz;
+    float w;
+};
+
+__device__ inline Geo load_geo(const SynthArgs& a, int ray, int r1, int jj) {
+    Geo g{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0f};
+    if (ray >= r1) return g;
+    const int64_t plane = (int64_t)a.chirp_count * a.n_rays;
+    const double* p = a.geo + (int64_t)jj * a.n_rays + ray;
+    g.inner = p[0];
+    g.fx = p[plane];
+    g.fy = p[2 * plane];
+    g.fz = p[3 * plane];
+    g.lx = p[4 * plane];
+    g.ly = p[5 * plane];
+    g.lz = p[6 * plane];
+    g.w = a.weights ? a.weights[ray] : 1.0f;
+    return g;
 }
 
-// Workgroup (pair q, chirp j, partition p): the rays of partition p are taken
-// 64 at a time, one per lane, round-robin over the workgroup's waves.  Lane l
-// of a wave first builds its ray's record (FP64 geometry) into the wave's LDS
-// slice; the wave then walks the 64 records.  For each record, lane l owns the
-// kRun consecutive samples n = 512 b + kRun l + r of each pass b: it evaluates
-// the phasor at its first sample with the hardware sin/cos (argument in
-// revolutions), its second by one complex multiply, and the rest with the
-// two-term recurrence p_{r+1} = 2 cos(2 pi theta) p_r - p_{r-1}.  Sums of a
-// 64-ray group are added into a second accumulator, which keeps the float32
-// sums short.  Waves combine through LDS in a fixed order.
-template <int NB>
+// Phases of a ray for pair pq, in cycles modulo 1: the path length is the
+// inner path plus |p^f - x'_tx| + |p^l - x'_rx| (Eq. 7 with the traced pair's
+// legs cancelled exactly); Eq. 1 turns it into the delay, Eq. 2 into
+// phi = f_c tau and theta = mu tau / f_s (the phase step per sample).
+struct Phases {
+    double phi, theta;
+    float w;
+};
+
+__device__ inline Phases ray_phases(const SynthArgs& a, const Geo& g, const double* __restrict__ pq) {
+    Phases p{0.0, 0.0, 0.0f};
+    if (!(g.inner >= 0.0) || g.w == 0.0f) return p;
+    const double len = g.inner + dist3(g.fx, g.fy, g.fz, pq[0], pq[1], pq[2]) +
+                       dist3(g.lx, g.ly, g.lz, pq[3], pq[4], pq[5]);
+    const double ph = len * a.cyc_per_m;              // f_c tau
+    const double th = len * a.step_per_m;             // mu tau / f_s
+    p.phi = ph - floor(ph);
+    p.theta = th - floor(th);
+    p.w = g.w;
+    return p;
+}
+
+__device__ inline double frac1(double x) { return x - floor(x); }
+
+// e^{2 pi i x} for x in [0, 1) revolutions, hardware sine and cosine.
+__device__ inline float2 cis(double x) {
+    const float xf = (float)x;
+    return make_float2(__builtin_amdgcn_cosf(xf), __builtin_amdgcn_sinf(xf));
+}
+
+__device__ inline float2 cmul(float2 p, float2 z) {
+    return make_float2(fmaf(p.x, z.x, -p.y * z.y), fmaf(p.x, z.y, p.y * z.x));
+}
+
+// Workgroup (pair q, pass b, partition p, chirp j).  Fast time is split as
+// n = 512 b + 16 m + k (pass b, row m < 32, column k < 16), so that
+//   s[n] = sum_i A[m][i] B[i][k],  A[m][i] = w_i e^{2 pi i (phi_i + (32 b + m) 16 theta_i)},
+//                                 B[i][k] = e^{2 pi i k theta_i}:
+// a complex 32 x 16 product over the rays.  Its real embedding is one
+// 32 x 32 x 2 float32 MFMA per ray: the K = 2 operand pair of ray i is
+// A' = (Re A, Im A) and B' = ([Re B | Im B], [-Im B | Re B]), which puts Re s
+// in result columns 0-15 and Im s in columns 16-31.  Operand lane layout:
+// A'[m][c] in lane m + 32 c, B'[c][col] in lane col + 32 c.
+//
+// Each wave takes the partition's rays 64 at a time (one ray per lane;
+// super-groups round-robin over the waves):
+//   phases  lane l derives ray l's phases in FP64 (antenna legs, Eq. 1, the
+//           reductions modulo one cycle) and the float32 phasor steps between
+//           rows and columns;
+// then, for each group of kGroup = 16 of these rays,
+//   build   the four lanes r, r + 16, r + 32, r + 48 fetch ray r's phases
+//           from its owner lane (cross-lane shuffles); quarter h of the wave
+//           forms A rows [8 h, 8 h + 8) and B columns [4 h, 4 h + 4) from one
+//           exact anchor each (phase reduced in FP64) and complex-multiply
+//           steps, and writes them into the ray's row of the wave's LDS table;
+//   sum     lanes run over tile elements: per ray one LDS read of the lane's
+//           A' and B' values and one MFMA.
+// The geometry of the next super-group is loaded before the groups run, so its
+// global loads are in flight while the MFMAs run.  The MFMA accumulates one
+// group; group sums are added into a second accumulator, which keeps the
+// float32 sums short.  Waves combine through LDS in a fixed order.
 __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
-    __shared__ Rec rec[kWaves][kWave];
-    __shared__ float2 red[kWaves - 1][NB * kBlock];
+    __shared__ float4 lds_raw[kWaves * kGroup * kTab / 4];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int g = blockIdx.x;
     const int q = g % a.n_pairs;
     g /= a.n_pairs;
+    const int pass = g % a.n_passes;
+    g /= a.n_passes;
     const int part = g % a.n_parts;
     const int jj = g / a.n_parts;
-    const int j = a.chirp0 + jj;
     const double* pq = a.pairs + 6 * q;
+    float* tab = reinterpret_cast<float*>(lds_raw) + wave * kGroup * kTab;
 
-    float2 tot[NB][kRun];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int r = 0; r < kRun; ++r) tot[b][r] = make_float2(0.f, 0.f);
+    constexpr int kSplit = kWave / kGroup;           // lanes per ray in the build phase
+    constexpr int kRowsPer = kRows / kSplit;         // A rows per lane (8)
+    constexpr int kColsPer = kCols / kSplit;         // B columns per lane (4)
+    const int ri = lane & (kGroup - 1);              // build: ray of the group
+    const int h = lane / kGroup;                     // build: quarter of the rows and columns
+    const int ma = pass * kRows + h * kRowsPer;      // first A row of the lane (global row index)
+    const int ka = h * kColsPer;                     // first B column of the lane
+    float* row = tab + ri * kTab;
 
-    float lf[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) lf[b] = (float)(b * kWave + lane);   // first sample / kRun
-
+    f32x16 tot = {};
     const int r0 = part * a.rays_per_part;
     const int r1 = min(a.n_rays, r0 + a.rays_per_part);
-    for (int base = r0 + wave * kWave; base < r1; base += kThreads) {
-        rec[wave][lane] = make_record(a, base + lane, j, pq);
-        __builtin_amdgcn_wave_barrier();
-        float2 acc[NB][kRun];
+    Geo gn = load_geo(a, r0 + wave * kWave + lane, r1, jj);
+    for (int sbase = r0 + wave * kWave; sbase < r1; sbase += kThreads) {
+        const Phases own = ray_phases(a, gn, pq);
+        gn = load_geo(a, sbase + kThreads + lane, r1, jj);      // next super-group, in flight meanwhile
+        const float2 own_s16 = cis(frac1(kCols * own.theta));   // step between rows
+        const float2 own_s1 = cis(own.theta);                   // step between columns
+        for (int gq = 0; gq < kSplit && sbase + gq * kGroup < r1; ++gq) {
+            const int src = gq * kGroup + ri;
+            const double phi = __shfl(own.phi, src);
+            const double theta = __shfl(own.theta, src);
+            const float w = __shfl(own.w, src);
+            const float2 s16 = make_float2(__shfl(own_s16.x, src), __shfl(own_s16.y, src));
+            const float2 s1 = make_float2(__shfl(own_s1.x, src), __shfl(own_s1.y, src));
+            {                                        // A rows ma + t
+                float2 p = cis(frac1(phi + (double)ma * frac1(kCols * theta)));
+                p.x *= w;
+                p.y *= w;
+                float re[kRowsPer], im[kRowsPer];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < kRun; ++r) acc[b][r] = make_float2(0.f, 0.f);
-        const int cnt = min(kWave, r1 - base);
-        for (int i = 0; i < cnt; ++i) {
-            const Rec e = rec[wave][i];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const float x = __builtin_amdgcn_fractf(lf[b] * e.th_hi);   // exact product
-                const float ph = x + fmaf(lf[b], e.th_lo, e.phi);    // revolutions, [0, 2.01)
-                float c0 = __builtin_amdgcn_cosf(ph);
-                float s0 = __builtin_amdgcn_sinf(ph);
-                float c1 = c0 * e.cz - s0 * e.sz;
-                float s1 = c0 * e.sz + s0 * e.cz;
-                acc[b][0].x = fmaf(e.w, c0, acc[b][0].x);
-                acc[b][0].y = fmaf(e.w, s0, acc[b][0].y);
-                acc[b][1].x = fmaf(e.w, c1, acc[b][1].x);
-                acc[b][1].y = fmaf(e.w, s1, acc[b][1].y);
-#pragma unroll
-                for (int r = 2; r < kRun; ++r) {
-                    const float c2 = fmaf(e.c2, c1, -c0);
-                    const float s2 = fmaf(e.c2, s1, -s0);
-                    acc[b][r].x = fmaf(e.w, c2, acc[b][r].x);
-                    acc[b][r].y = fmaf(e.w, s2, acc[b][r].y);
-                    c0 = c1; s0 = s1; c1 = c2; s1 = s2;
+                for (int t = 0; t < kRowsPer; ++t) {
+                    re[t] = p.x;
+                    im[t] = p.y;
+                    p = cmul(p, s16);
                 }
+                const int o = h * kRowsPer;
+                *reinterpret_cast<float4*>(row + o) = make_float4(re[0], re[1], re[2], re[3]);
+                *reinterpret_cast<float4*>(row + o + 4) = make_float4(re[4], re[5], re[6], re[7]);
+                *reinterpret_cast<float4*>(row + kRows + o) = make_float4(im[0], im[1], im[2], im[3]);
+                *reinterpret_cast<float4*>(row + kRows + o + 4) = make_float4(im[4], im[5], im[6], im[7]);
             }
+            {                                        // B columns ka + t
+                float2 p = cis(frac1((double)ka * theta));
+                float re[kColsPer], im[kColsPer];
+#pragma unroll
+                for (int t = 0; t < kColsPer; ++t) {
+                    re[t] = p.x;
+                    im[t] = p.y;
+                    p = cmul(p, s1);
+                }
+                float* bq = row + 2 * kRows + ka;
+                *reinterpret_cast<float4*>(bq) = make_float4(re[0], re[1], re[2], re[3]);
+                *reinterpret_cast<float4*>(bq + kCols) = make_float4(im[0], im[1], im[2], im[3]);
+                *reinterpret_cast<float4*>(bq + 2 * kCols) = make_float4(-im[0], -im[1], -im[2], -im[3]);
+                *reinterpret_cast<float4*>(bq + 3 * kCols) = make_float4(re[0], re[1], re[2], re[3]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // All kGroup rows are written in every group; rows of rays at or
+            // past the partition end hold A' = 0, so the loop needs no count.
+            f32x16 acc = {};
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) {
+                const float av = tab[i * kTab + lane];
+                const float bv = tab[i * kTab + 2 * kRows + lane];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+            }
+            tot += acc;
+            __builtin_amdgcn_wave_barrier();
         }
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < kRun; ++r) {
-                tot[b][r].x += acc[b][r].x;
-                tot[b][r].y += acc[b][r].y;
-            }
-        __builtin_amdgcn_wave_barrier();
     }
 
-    // Combine the waves: waves 1.. publish, wave 0 adds in wave order.
-    if (wave > 0) {
+    // Result layout of the 32 x 32 MFMA: register r of lane l holds row
+    // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.  Row m, column col is
+    // sample 16 m + col % 16 of the pass, real part for col < 16, imaginary
+    // otherwise.  The wave sums reuse the table memory.
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(lds_raw);
+    const int c = lane >> 5, col = lane & 31;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < kRun; ++r) red[wave - 1][b * kBlock + lane * kRun + r] = tot[b][r];
+    for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * c + (r & 3);
+        const int n = kCols * m + (col & (kCols - 1));
+        red[wave * 2 * kBlock + 2 * n + (col >> 4)] = tot[r];
     }
     __syncthreads();
-    if (wave == 0) {
-        float2* out = a.partial +
-                      (((int64_t)part * a.n_pairs + q) * a.chirp_count + jj) * (int64_t)a.n_samples;
+    float2* out = a.partial + (((int64_t)part * a.n_pairs + q) * a.chirp_count + jj) * (int64_t)a.n_samples;
+    const int n_end = min(a.n_samples - pass * kBlock, kBlock);
+    for (int n = threadIdx.x; n < n_end; n += kThreads) {
+        float re = 0.f, im = 0.f;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int r = 0; r < kRun; ++r) {
-                float2 v = tot[b][r];
-                for (int w = 0; w < kWaves - 1; ++w) {
-                    const float2 o = red[w][b * kBlock + lane * kRun + r];
-                    v.x += o.x;
-                    v.y += o.y;
-                }
-                const int n = b * kBlock + lane * kRun + r;
-                if (n < a.n_samples) out[n] = v;
-            }
+        for (int w = 0; w < kWaves; ++w) {
+            re += red[w * 2 * kBlock + 2 * n];
+            im += red[w * 2 * kBlock + 2 * n + 1];
+        }
+        out[pass * kBlock + n] = make_float2(re, im);
     }
 }
 
-__global__ void reduce_kernel(const float2* __restrict__ partial, float2* __restrict__ s, int64_t count,
-                              int n_parts) {
+__global__ void reduce_kernel(const float2* __restrict__ partial, float2* __restrict__ s, int n_pairs, int nb,
+                              int n_samples, int n_parts, int n_chirps_out, int c0) {
+    const int64_t count = (int64_t)n_pairs * nb * n_samples;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     double re = 0.0, im = 0.0;
@@ -254,7 +333,10 @@ __global__ void reduce_kernel(const float2* __restrict__ partial, float2* __rest
         re += v.x;
         im += v.y;
     }
-    s[i] = make_float2((float)re, (float)im);
+    const int n = (int)(i % n_samples);
+    const int64_t qj = i / n_samples;
+    const int jj = (int)(qj % nb), q = (int)(qj / nb);
+    s[((int64_t)q * n_chirps_out + c0 + jj) * n_samples + n] = make_float2((float)re, (float)im);
 }
 
 // Radix-2 decimation-in-time FFT of `lines` lines of length L = 2^logL, M
@@ -379,17 +461,35 @@ rmd_status check_scene_desc(const rmd_scene* sc) {
     return RMD_OK;
 }
 
-// Ray partitions: enough workgroups to fill the device several times over,
-// each wave keeping at least four 64-ray groups.
-void partition(int n_rays, int64_t pairs_chirps, int& n_parts, int& rays_per_part) {
+// Work plan of one IF cube.  Chirps are processed in batches whose per-ray
+// geometry (7 doubles per ray and chirp) fits in kGeoBudget bytes, at most
+// kMaxBatch chirps.  Within a batch the rays are split into partitions so that
+// the (pair, chirp, partition) workgroups fill the device several times over,
+// each wave keeping at least four 64-ray super-groups.
+constexpr int64_t kGeoBudget = int64_t(1) << 30;
+constexpr int kMaxBatch = 16;
+
+struct Plan {
+    int batch, parts, rays_per_part;
+    int64_t geo_bytes, partial_bytes;
+};
+
+Plan plan(int n_rays, int n_pairs, int chirp_count, int n_samples) {
+    Plan p{};
+    const int64_t per_chirp = (int64_t)n_rays * 7 * (int64_t)sizeof(double);
+    p.batch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)chirp_count, kMaxBatch, kGeoBudget / per_chirp}));
+    const int64_t blocks = (int64_t)n_pairs * p.batch;
     const int64_t target = 8192;
-    int64_t p = (target + pairs_chirps - 1) / pairs_chirps;
+    int64_t np = (target + blocks - 1) / blocks;
     const int64_t max_p = std::max<int64_t>(1, n_rays / (rmd::kThreads * 4));
-    p = std::max<int64_t>(1, std::min(p, max_p));
-    int64_t rpp = (n_rays + p - 1) / p;
+    np = std::max<int64_t>(1, std::min(np, max_p));
+    int64_t rpp = (n_rays + np - 1) / np;
     rpp = (rpp + rmd::kThreads - 1) / rmd::kThreads * rmd::kThreads;
-    n_parts = (int)((n_rays + rpp - 1) / rpp);
-    rays_per_part = (int)rpp;
+    p.parts = (int)((n_rays + rpp - 1) / rpp);
+    p.rays_per_part = (int)rpp;
+    p.geo_bytes = (per_chirp * p.batch + 255) / 256 * 256;
+    p.partial_bytes = (int64_t)p.parts * blocks * n_samples * (int64_t)sizeof(float2);
+    return p;
 }
 
 rmd::SynthArgs synth_args(const rmd_scene* sc) {
@@ -447,9 +547,8 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
     if (!radar || !bytes) return fail(RMD_EINVAL, "radar and bytes must not be NULL");
     if (n_pairs <= 0 || chirp_count <= 0 || radar->n_samples <= 0 || radar->n_samples > RMD_MAX_SAMPLES)
         return fail(RMD_EINVAL, "n_pairs, chirp_count must be positive; n_samples in [1, RMD_MAX_SAMPLES]");
-    int parts, rpp;
-    partition(scene->n_rays, (int64_t)n_pairs * chirp_count, parts, rpp);
-    *bytes = (int64_t)parts * n_pairs * chirp_count * radar->n_samples * (int64_t)sizeof(float2);
+    const Plan p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
+    *bytes = p.geo_bytes + p.partial_bytes;
     return RMD_OK;
 }
 
@@ -466,36 +565,39 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
         return fail(RMD_EINVAL, "chirp range outside [0, n_chirps)");
     if (!(radar->f_s > 0) || !(radar->t_chirp > 0) || !std::isfinite(radar->f_c) || !std::isfinite(radar->bandwidth))
         return fail(RMD_EINVAL, "radar parameters must be finite, f_s and t_chirp positive");
-    const int64_t groups = (int64_t)n_pairs * chirp_count;
-    int parts, rpp;
-    partition(scene->n_rays, groups, parts, rpp);
-    if (groups * parts > INT32_MAX) return fail(RMD_EINVAL, "too many (pair, chirp) blocks");
+    const Plan p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
+    if ((int64_t)n_pairs * p.batch * p.parts * 2 > INT32_MAX) return fail(RMD_EINVAL, "too many (pair, chirp) blocks");
 
     rmd::SynthArgs a = synth_args(scene);
     a.pairs = pairs;
     a.weights = weights;
-    a.partial = static_cast<float2*>(workspace);
+    a.geo = static_cast<double*>(workspace);
+    a.partial = reinterpret_cast<float2*>(static_cast<char*>(workspace) + p.geo_bytes);
     a.n_pairs = n_pairs;
-    a.chirp0 = chirp0;
-    a.chirp_count = chirp_count;
     a.n_samples = radar->n_samples;
-    a.n_parts = parts;
-    a.rays_per_part = rpp;
+    a.n_parts = p.parts;
+    a.rays_per_part = p.rays_per_part;
+    a.n_passes = (radar->n_samples + rmd::kBlock - 1) / rmd::kBlock;
     const double mu = radar->bandwidth / radar->t_chirp;               // Eq. 3
     a.cyc_per_m = radar->f_c / rmd::kC0;
     a.step_per_m = mu / (rmd::kC0 * radar->f_s);
-    const dim3 grid((unsigned)(groups * parts));
-    if (radar->n_samples <= rmd::kBlock)
-        hipLaunchKernelGGL(rmd::synth_kernel<1>, grid, dim3(rmd::kThreads), 0, stream, a);
-    else
-        hipLaunchKernelGGL(rmd::synth_kernel<2>, grid, dim3(rmd::kThreads), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "synth_kernel launch");
-    const int64_t count = groups * radar->n_samples;
-    hipLaunchKernelGGL(rmd::reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
-                       static_cast<const float2*>(workspace), reinterpret_cast<float2*>(s), count, parts);
-    e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "reduce_kernel launch");
+    // Chirp batches: geometry of the batch, then the synthesis and the
+    // partition sums of the batch (the partition count is the same for every
+    // batch: a shorter last batch uses part of the buffers).
+    for (int c0 = 0; c0 < chirp_count; c0 += p.batch) {
+        const int nb = std::min(p.batch, chirp_count - c0);
+        a.chirp0 = chirp0 + c0;
+        a.chirp_count = nb;
+        hipLaunchKernelGGL(rmd::geometry_kernel, dim3((scene->n_rays + 255) / 256, nb), dim3(256), 0, stream, a);
+        const dim3 grid((unsigned)((int64_t)n_pairs * a.n_passes * nb * p.parts));
+        hipLaunchKernelGGL(rmd::synth_kernel, grid, dim3(rmd::kThreads), 0, stream, a);
+        const int64_t count = (int64_t)n_pairs * nb * radar->n_samples;
+        hipLaunchKernelGGL(rmd::reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                           a.partial, reinterpret_cast<float2*>(s), n_pairs, nb, radar->n_samples, p.parts,
+                           chirp_count, c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "IF cube launch");
+    }
     return RMD_OK;
 }
 

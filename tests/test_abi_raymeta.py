@@ -43,22 +43,34 @@ def _radar(**kw):
     return RM.radar_struct(r)
 
 
-def test_workspace_bytes_partitions():
+def _plan(n_rays, n_pairs, chirps, n_samples):
+    """The documented work plan: chirp batches of at most 16 whose per-ray
+    geometry (7 doubles per ray and chirp) fits in 1 GiB; ray partitions so
+    that about 8192 workgroups run per batch, each wave keeping >= 4 groups
+    of 64 rays (256-ray granules)."""
+    batch = max(1, min(chirps, 16, (1 << 30) // (n_rays * 56)))
+    blocks = n_pairs * batch
+    np_ = max(1, min(-(-8192 // blocks), max(1, n_rays // 1024)))
+    rpp = -(-n_rays // np_)
+    rpp = -(-rpp // 256) * 256
+    parts = -(-n_rays // rpp)
+    geo = -(-(n_rays * 56 * batch) // 256) * 256
+    return batch, parts, geo + parts * blocks * n_samples * 8
+
+
+def test_workspace_bytes_plan():
     lib = RM.load()
     out = C.c_int64()
-    sc = _fake_scene()
-    # full cube: 12 pairs x 128 chirps; a few partitions of the 2^20 rays
-    assert lib.rmd_workspace_bytes(C.byref(sc), C.byref(_radar()), 12, 128, C.byref(out)) == 0
-    per_part = 12 * 128 * 512 * 8
-    assert out.value % per_part == 0 and 1 <= out.value // per_part <= 16
-    # two chirps: many more partitions, each at least 4 x 256 rays
-    assert lib.rmd_workspace_bytes(C.byref(sc), C.byref(_radar()), 12, 2, C.byref(out)) == 0
-    parts = out.value // (12 * 2 * 512 * 8)
-    assert parts > 16 and (1 << 20) / parts >= 1024
-    # tiny scene: one partition
-    small = _fake_scene(n_rays=100)
-    assert lib.rmd_workspace_bytes(C.byref(small), C.byref(_radar()), 1, 1, C.byref(out)) == 0
-    assert out.value == 512 * 8
+    for n_rays, pairs, chirps, ns in [(1 << 20, 12, 128, 512), (1 << 20, 12, 2, 512), (100, 1, 1, 512),
+                                      (777, 4, 3, 300), (1 << 24, 12, 128, 512)]:
+        sc = _fake_scene(n_rays=n_rays)
+        assert lib.rmd_workspace_bytes(C.byref(sc), C.byref(_radar(n_samples=ns)), pairs, chirps,
+                                       C.byref(out)) == 0
+        batch, parts, nbytes = _plan(n_rays, pairs, chirps, ns)
+        assert out.value == nbytes, (n_rays, pairs, chirps, ns)
+        assert parts * -(-n_rays // parts) >= n_rays
+    # full cube: 16-chirp batches of 2^20 rays (940 MB of geometry) and 43 partitions
+    assert _plan(1 << 20, 12, 128, 512)[:2] == (16, 43)
 
 
 @pytest.mark.parametrize("kw", [

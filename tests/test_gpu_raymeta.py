@@ -76,6 +76,19 @@ def test_if_cube_max_samples_and_chirp_window(RM):
     assert _blocks_rel(got, ref).max() <= TOL
 
 
+def test_if_cube_several_chirp_batches(RM):
+    """40 chirps run as geometry batches of 16, 16 and 8 chirps, each with its
+    own partition sums, written into one cube; and a window starting mid-batch."""
+    sc = S.small_scene(n_rays=300, n_chirps=40, n_samples=64)
+    _say("[gpu] raymeta 40 chirps (three batches)")
+    ds = RM.DeviceScene(sc)
+    got = RM.if_cube(ds).cpu().numpy()
+    ref = R.if_cube(sc)
+    assert _blocks_rel(got, ref).max() <= TOL
+    got = RM.if_cube(ds, chirps=list(range(5, 38))).cpu().numpy()
+    assert _blocks_rel(got, ref[:, 5:38]).max() <= TOL
+
+
 def test_bad_and_empty_rays_contribute_nothing(RM):
     """Rays with no hits or with out-of-range meta data add nothing (the
     kernel checks every index before using it); rmd_check_scene counts them."""
