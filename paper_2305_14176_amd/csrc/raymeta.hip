@@ -32,9 +32,21 @@ constexpr int kThreads = kWave * kWaves;
 constexpr int kRows = 32;                 // MFMA tile rows m: fast-time steps of kCols samples
 constexpr int kCols = 16;                 // MFMA tile columns k: consecutive samples
 constexpr int kBlock = kRows * kCols;     // samples of one pass (512)
-constexpr int kGroup = 16;                // rays per operand table
-constexpr int kTab = 4 * kRows + 4;       // floats per table row: A' (64), B' (64), pad against bank conflicts
-static_assert(kWaves * kGroup * kTab >= kWaves * 2 * kBlock, "wave sums must fit in the table memory");
+constexpr int kGroup = 16;                // rays per operand table (two MFMA blocks of 8)
+constexpr int kBlockRays = 8;             // rays per 32 x 32 x 16 fp16 MFMA (K = 2 components x 8 rays)
+constexpr int kSlotWords = 4;             // one lane's operand: 8 fp16 values
+// Word offset of lane slot L in an operand block, padded by one slot every 8
+// slots so that the build's scattered 4-byte writes spread over the banks.
+__host__ __device__ constexpr int slot_word(int L) { return kSlotWords * (L + (L >> 3)); }
+constexpr int kBlockWords = slot_word(kWave);               // 288 words per block
+constexpr int kArrayWords = (kGroup / kBlockRays) * kBlockWords;
+constexpr int kTableWords = 4 * kArrayWords;                // A hi, A lo, B hi, B lo
+static_assert(kWaves * kTableWords >= kWaves * 2 * kBlock, "wave sums must fit in the table memory");
+static_assert(kRows / (kWave / kGroup) == 8 && kCols / (kWave / kGroup) == 4,
+              "the build's step trees are written for 8 rows and 4 columns per lane");
+
+typedef __fp16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr double kC0 = 299792458.0;
@@ -182,15 +194,32 @@ __device__ inline float2 cmul(float2 p, float2 z) {
     return make_float2(fmaf(p.x, z.x, -p.y * z.y), fmaf(p.x, z.y, p.y * z.x));
 }
 
+// Split two float32 values into fp16 high parts (rounded toward zero) and
+// fp16 low parts (the rounded remainders): x = hi + lo to about 2^-21 |x|.
+// Returns the packed pairs (x in the low half, y in the high half).
+__device__ inline void split2(float x, float y, uint32_t& hi, uint32_t& lo) {
+    const f16x2 h = __builtin_amdgcn_cvt_pkrtz(x, y);
+    const f16x2 l = __builtin_amdgcn_cvt_pkrtz(x - (float)h.x, y - (float)h.y);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
+}
+
 // Workgroup (pair q, pass b, partition p, chirp j).  Fast time is split as
 // n = 512 b + 16 m + k (pass b, row m < 32, column k < 16), so that
 //   s[n] = sum_i A[m][i] B[i][k],  A[m][i] = w_i e^{2 pi i (phi_i + (32 b + m) 16 theta_i)},
 //                                 B[i][k] = e^{2 pi i k theta_i}:
-// a complex 32 x 16 product over the rays.  Its real embedding is one
-// 32 x 32 x 2 float32 MFMA per ray: the K = 2 operand pair of ray i is
-// A' = (Re A, Im A) and B' = ([Re B | Im B], [-Im B | Re B]), which puts Re s
-// in result columns 0-15 and Im s in columns 16-31.  Operand lane layout:
-// A'[m][c] in lane m + 32 c, B'[c][col] in lane col + 32 c.
+// a complex 32 x 16 product over the rays, in real form a 32 x 32 product
+// with two K entries per ray: A' = (Re A, Im A) and B' = ([Re B | Im B],
+// [-Im B | Re B]), which puts Re s in result columns 0-15 and Im s in
+// columns 16-31.
+//
+// The product runs on the fp16 matrix path: every operand value is split into
+// fp16 high and low parts (split2), and A'B' is formed as hi hi + hi lo + lo hi
+// with float32 accumulation (the dropped lo lo term is below 2^-21 of the
+// product).  One 32 x 32 x 16 MFMA takes 8 rays (K = 2 components x 8); its
+// operand layout puts A'[m][kk] in lane m + 32 (kk / 8), element kk % 8, and
+// B'[kk][col] in lane col + 32 (kk / 8), element kk % 8, with kk = 2 r + c for
+// ray r of the block and component c.
 //
 // Each wave takes the partition's rays 64 at a time (one ray per lane;
 // super-groups round-robin over the waves):
@@ -202,15 +231,17 @@ __device__ inline float2 cmul(float2 p, float2 z) {
 //           from its owner lane (cross-lane shuffles); quarter h of the wave
 //           forms A rows [8 h, 8 h + 8) and B columns [4 h, 4 h + 4) from one
 //           exact anchor each (phase reduced in FP64) and complex-multiply
-//           steps, and writes them into the ray's row of the wave's LDS table;
-//   sum     lanes run over tile elements: per ray one LDS read of the lane's
-//           A' and B' values and one MFMA.
+//           steps (depth <= 3), splits them, and writes them into the
+//           operand slots of the wave's LDS table;
+//   sum     lanes run over operand slots: per 8-ray block four 16-byte LDS
+//           reads and three MFMAs.
 // The geometry of the next super-group is loaded before the groups run, so its
-// global loads are in flight while the MFMAs run.  The MFMA accumulates one
-// group; group sums are added into a second accumulator, which keeps the
-// float32 sums short.  Waves combine through LDS in a fixed order.
+// global loads are in flight while the groups are summed.  The MFMA
+// accumulates one group; group sums are added into a second accumulator,
+// which keeps the float32 sums short.  Waves combine through LDS in a fixed
+// order.
 __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
-    __shared__ float4 lds_raw[kWaves * kGroup * kTab / 4];
+    __shared__ uint4 lds_raw[kWaves * kTableWords / 4];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int g = blockIdx.x;
@@ -221,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
     const int part = g % a.n_parts;
     const int jj = g / a.n_parts;
     const double* pq = a.pairs + 6 * q;
-    float* tab = reinterpret_cast<float*>(lds_raw) + wave * kGroup * kTab;
+    uint32_t* tw = reinterpret_cast<uint32_t*>(lds_raw) + wave * kTableWords;
 
     constexpr int kSplit = kWave / kGroup;           // lanes per ray in the build phase
     constexpr int kRowsPer = kRows / kSplit;         // A rows per lane (8)
@@ -230,7 +261,17 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
     const int h = lane / kGroup;                     // build: quarter of the rows and columns
     const int ma = pass * kRows + h * kRowsPer;      // first A row of the lane (global row index)
     const int ka = h * kColsPer;                     // first B column of the lane
-    float* row = tab + ri * kTab;
+    // build: where ray ri's operand values go (block, lane half, word in the slot)
+    const int bk = ri / kBlockRays;
+    const int hh = (ri % kBlockRays) / 4;
+    const int rr = ri % 4;
+    uint32_t* ahi = tw + bk * kBlockWords + rr;
+    uint32_t* alo = ahi + kArrayWords;
+    uint32_t* bhi = ahi + 2 * kArrayWords;
+    uint32_t* blo = ahi + 3 * kArrayWords;
+    const int la = h * kRowsPer + 32 * hh;           // slot of row h * 8 (+ t)
+    const int lb = h * kColsPer + 32 * hh;           // slot of column h * 4 (+ t) ...
+    const int lb2 = lb + kCols;                      // ... and of column 16 + h * 4 (+ t)
 
     f32x16 tot = {};
     const int r0 = part * a.rays_per_part;
@@ -248,47 +289,59 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
             const float w = __shfl(own.w, src);
             const float2 s16 = make_float2(__shfl(own_s16.x, src), __shfl(own_s16.y, src));
             const float2 s1 = make_float2(__shfl(own_s1.x, src), __shfl(own_s1.y, src));
-            {                                        // A rows ma + t
-                float2 p = cis(frac1(phi + (double)ma * frac1(kCols * theta)));
-                p.x *= w;
-                p.y *= w;
-                float re[kRowsPer], im[kRowsPer];
+            {                                        // A rows ma + t: p_t = p_0 s^t by a depth-3 tree
+                float2 p0 = cis(frac1(phi + (double)ma * frac1(kCols * theta)));
+                p0.x *= w;
+                p0.y *= w;
+                const float2 s2 = cmul(s16, s16), s4 = cmul(s2, s2);
+                float2 pt[kRowsPer];
+                pt[0] = p0;
+                pt[1] = cmul(p0, s16);
+                pt[2] = cmul(p0, s2);
+                pt[3] = cmul(pt[1], s2);
 #pragma unroll
-                for (int t = 0; t < kRowsPer; ++t) {
-                    re[t] = p.x;
-                    im[t] = p.y;
-                    p = cmul(p, s16);
+                for (int t = 4; t < kRowsPer; ++t) pt[t] = cmul(pt[t - 4], s4);
+#pragma unroll
+                for (int t = 0; t < kRowsPer; ++t) {     // A'[m][0] = Re, A'[m][1] = Im
+                    uint32_t hi, lo;
+                    split2(pt[t].x, pt[t].y, hi, lo);
+                    ahi[slot_word(la + t)] = hi;
+                    alo[slot_word(la + t)] = lo;
                 }
-                const int o = h * kRowsPer;
-                *reinterpret_cast<float4*>(row + o) = make_float4(re[0], re[1], re[2], re[3]);
-                *reinterpret_cast<float4*>(row + o + 4) = make_float4(re[4], re[5], re[6], re[7]);
-                *reinterpret_cast<float4*>(row + kRows + o) = make_float4(im[0], im[1], im[2], im[3]);
-                *reinterpret_cast<float4*>(row + kRows + o + 4) = make_float4(im[4], im[5], im[6], im[7]);
             }
-            {                                        // B columns ka + t
-                float2 p = cis(frac1((double)ka * theta));
-                float re[kColsPer], im[kColsPer];
+            {                                        // B columns ka + t: q_t = q_0 s1^t by a depth-2 tree
+                const float2 q0 = cis(frac1((double)ka * theta));
+                const float2 s1sq = cmul(s1, s1);
+                float2 qt[kColsPer];
+                qt[0] = q0;
+                qt[1] = cmul(q0, s1);
+                qt[2] = cmul(q0, s1sq);
+                qt[3] = cmul(qt[1], s1sq);
 #pragma unroll
                 for (int t = 0; t < kColsPer; ++t) {
-                    re[t] = p.x;
-                    im[t] = p.y;
-                    p = cmul(p, s1);
+                    uint32_t hi, lo;
+                    split2(qt[t].x, qt[t].y, hi, lo);
+                    // column k: (B'[0][k], B'[1][k]) = (Re, -Im); column 16 + k: (Im, Re)
+                    bhi[slot_word(lb + t)] = hi ^ 0x80000000u;
+                    blo[slot_word(lb + t)] = lo ^ 0x80000000u;
+                    bhi[slot_word(lb2 + t)] = (hi >> 16) | (hi << 16);
+                    blo[slot_word(lb2 + t)] = (lo >> 16) | (lo << 16);
                 }
-                float* bq = row + 2 * kRows + ka;
-                *reinterpret_cast<float4*>(bq) = make_float4(re[0], re[1], re[2], re[3]);
-                *reinterpret_cast<float4*>(bq + kCols) = make_float4(im[0], im[1], im[2], im[3]);
-                *reinterpret_cast<float4*>(bq + 2 * kCols) = make_float4(-im[0], -im[1], -im[2], -im[3]);
-                *reinterpret_cast<float4*>(bq + 3 * kCols) = make_float4(re[0], re[1], re[2], re[3]);
             }
             __builtin_amdgcn_wave_barrier();
-            // All kGroup rows are written in every group; rows of rays at or
-            // past the partition end hold A' = 0, so the loop needs no count.
+            // Every slot is written in every group; rays at or past the
+            // partition end have A' = 0.
             f32x16 acc = {};
 #pragma unroll
-            for (int i = 0; i < kGroup; ++i) {
-                const float av = tab[i * kTab + lane];
-                const float bv = tab[i * kTab + 2 * kRows + lane];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+            for (int b = 0; b < kGroup / kBlockRays; ++b) {
+                const uint32_t* base = tw + b * kBlockWords + slot_word(lane);
+                const f16x8 a_hi = *reinterpret_cast<const f16x8*>(base);
+                const f16x8 a_lo = *reinterpret_cast<const f16x8*>(base + kArrayWords);
+                const f16x8 b_hi = *reinterpret_cast<const f16x8*>(base + 2 * kArrayWords);
+                const f16x8 b_lo = *reinterpret_cast<const f16x8*>(base + 3 * kArrayWords);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, b_hi, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, b_lo, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_lo, b_hi, acc, 0, 0, 0);
             }
             tot += acc;
             __builtin_amdgcn_wave_barrier();
