@@ -199,7 +199,7 @@ __device__ inline float2 cmul(float2 p, float2 z) {
 // Returns the packed pairs (x in the low half, y in the high half).
 __device__ inline void split2(float x, float y, uint32_t& hi, uint32_t& lo) {
     const f16x2 h = __builtin_amdgcn_cvt_pkrtz(x, y);
-    const f16x2 l = __builtin_amdgcn_cvt_pkrtz(x - (float)h.x, y - (float)h.y);
+    const f16x2 l = __builtin_amdgcn_cvt_pkrtz(fmaf((float)h.x, -1.0f, x), fmaf((float)h.y, -1.0f, y));
     hi = __builtin_bit_cast(uint32_t, h);
     lo = __builtin_bit_cast(uint32_t, l);
 }
@@ -231,14 +231,14 @@ __device__ inline void split2(float x, float y, uint32_t& hi, uint32_t& lo) {
 //           from its owner lane (cross-lane shuffles); quarter h of the wave
 //           forms A rows [8 h, 8 h + 8) and B columns [4 h, 4 h + 4) from one
 //           exact anchor each (phase reduced in FP64) and complex-multiply
-//           steps (depth <= 3), splits them, and writes them into the
+//           steps (at most 7), splits them, and writes them into the
 //           operand slots of the wave's LDS table;
 //   sum     lanes run over operand slots: per 8-ray block four 16-byte LDS
 //           reads and three MFMAs.
 // The geometry of the next super-group is loaded before the groups run, so its
 // global loads are in flight while the groups are summed.  The MFMA
-// accumulates one group; group sums are added into a second accumulator,
-// which keeps the float32 sums short.  Waves combine through LDS in a fixed
+// accumulates one super-group (64 rays); super-group sums are added into a
+// second accumulator, which keeps the float32 sums short.  Waves combine through LDS in a fixed
 // order.
 __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
     __shared__ uint4 lds_raw[kWaves * kTableWords / 4];
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
         gn = load_geo(a, sbase + kThreads + lane, r1, jj);      // next super-group, in flight meanwhile
         const float2 own_s16 = cis(frac1(kCols * own.theta));   // step between rows
         const float2 own_s1 = cis(own.theta);                   // step between columns
+        f32x16 acc[kGroup / kBlockRays] = {};   // one chain per block: consecutive MFMAs are independent
         for (int gq = 0; gq < kSplit && sbase + gq * kGroup < r1; ++gq) {
             const int src = gq * kGroup + ri;
             const double phi = __shfl(own.phi, src);
@@ -289,38 +290,26 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
             const float w = __shfl(own.w, src);
             const float2 s16 = make_float2(__shfl(own_s16.x, src), __shfl(own_s16.y, src));
             const float2 s1 = make_float2(__shfl(own_s1.x, src), __shfl(own_s1.y, src));
-            {                                        // A rows ma + t: p_t = p_0 s^t by a depth-3 tree
-                float2 p0 = cis(frac1(phi + (double)ma * frac1(kCols * theta)));
-                p0.x *= w;
-                p0.y *= w;
-                const float2 s2 = cmul(s16, s16), s4 = cmul(s2, s2);
-                float2 pt[kRowsPer];
-                pt[0] = p0;
-                pt[1] = cmul(p0, s16);
-                pt[2] = cmul(p0, s2);
-                pt[3] = cmul(pt[1], s2);
-#pragma unroll
-                for (int t = 4; t < kRowsPer; ++t) pt[t] = cmul(pt[t - 4], s4);
+            {                                        // A rows ma + t: p_t = p_0 s^t
+                float2 p = cis(frac1(phi + (double)ma * frac1(kCols * theta)));
+                p.x *= w;
+                p.y *= w;
 #pragma unroll
                 for (int t = 0; t < kRowsPer; ++t) {     // A'[m][0] = Re, A'[m][1] = Im
                     uint32_t hi, lo;
-                    split2(pt[t].x, pt[t].y, hi, lo);
+                    split2(p.x, p.y, hi, lo);
                     ahi[slot_word(la + t)] = hi;
                     alo[slot_word(la + t)] = lo;
+                    p = cmul(p, s16);
                 }
             }
-            {                                        // B columns ka + t: q_t = q_0 s1^t by a depth-2 tree
-                const float2 q0 = cis(frac1((double)ka * theta));
-                const float2 s1sq = cmul(s1, s1);
-                float2 qt[kColsPer];
-                qt[0] = q0;
-                qt[1] = cmul(q0, s1);
-                qt[2] = cmul(q0, s1sq);
-                qt[3] = cmul(qt[1], s1sq);
+            {                                        // B columns ka + t: q_t = q_0 s1^t
+                float2 qv = cis(frac1((double)ka * theta));
 #pragma unroll
                 for (int t = 0; t < kColsPer; ++t) {
                     uint32_t hi, lo;
-                    split2(qt[t].x, qt[t].y, hi, lo);
+                    split2(qv.x, qv.y, hi, lo);
+                    qv = cmul(qv, s1);
                     // column k: (B'[0][k], B'[1][k]) = (Re, -Im); column 16 + k: (Im, Re)
                     bhi[slot_word(lb + t)] = hi ^ 0x80000000u;
                     blo[slot_word(lb + t)] = lo ^ 0x80000000u;
@@ -331,21 +320,26 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
             __builtin_amdgcn_wave_barrier();
             // Every slot is written in every group; rays at or past the
             // partition end have A' = 0.
-            f32x16 acc = {};
+            constexpr int kB = kGroup / kBlockRays;
+            f16x8 a_hi[kB], a_lo[kB], b_hi[kB], b_lo[kB];
 #pragma unroll
-            for (int b = 0; b < kGroup / kBlockRays; ++b) {
+            for (int b = 0; b < kB; ++b) {
                 const uint32_t* base = tw + b * kBlockWords + slot_word(lane);
-                const f16x8 a_hi = *reinterpret_cast<const f16x8*>(base);
-                const f16x8 a_lo = *reinterpret_cast<const f16x8*>(base + kArrayWords);
-                const f16x8 b_hi = *reinterpret_cast<const f16x8*>(base + 2 * kArrayWords);
-                const f16x8 b_lo = *reinterpret_cast<const f16x8*>(base + 3 * kArrayWords);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, b_hi, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi, b_lo, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_lo, b_hi, acc, 0, 0, 0);
+                a_hi[b] = *reinterpret_cast<const f16x8*>(base);
+                a_lo[b] = *reinterpret_cast<const f16x8*>(base + kArrayWords);
+                b_hi[b] = *reinterpret_cast<const f16x8*>(base + 2 * kArrayWords);
+                b_lo[b] = *reinterpret_cast<const f16x8*>(base + 3 * kArrayWords);
             }
-            tot += acc;
+#pragma unroll
+            for (int b = 0; b < kB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi[b], b_hi[b], acc[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < kB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_hi[b], b_lo[b], acc[b], 0, 0, 0);
+#pragma unroll
+            for (int b = 0; b < kB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a_lo[b], b_hi[b], acc[b], 0, 0, 0);
             __builtin_amdgcn_wave_barrier();
         }
+#pragma unroll
+        for (int b = 0; b < kGroup / kBlockRays; ++b) tot += acc[b];
     }
 
     // Result layout of the 32 x 32 MFMA: register r of lane l holds row
