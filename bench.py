@@ -230,6 +230,7 @@ def adjoint_benchmark(checkpoint_every=64):
 
 
 FP32_MFMA_PEAK_TFLOPS = 157.3     # published MI355X dense FP32 matrix peak
+FP16_MFMA_PEAK_TFLOPS = 2500.0    # published MI355X dense fp16 matrix peak
 FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply-add, four real multiply-adds
 
 
@@ -269,8 +270,8 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
     out = {
         "workload": f"{sc.name}: {sc.n_hits} hits, {sc.n_pairs} antenna pairs (3 TX x 4 RX), "
                     f"{r.n_chirps} chirps x {r.n_samples} samples, 77 GHz, B = 1 GHz, T_c = 51.2 us, f_s = 10 MHz",
-        "dtype": "f64 geometry and phases, f32 phasor tables and MFMA products (f32 accumulation), "
-                 "f64 partition sums",
+        "dtype": "f64 geometry and phases, f32 phasors split into fp16 hi/lo parts, products as "
+                 "hi*hi + hi*lo + lo*hi fp16 MFMAs with f32 accumulation, f64 partition sums",
         "metric": "IF terms/s (ray x antenna pair x chirp x sample)",
         "value": round(terms / (ms / 1e3), 1),
         "unit": "terms/s",
@@ -280,6 +281,9 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
         "range_doppler_ms": round(rd_ms, 4),
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4),
+                     "peak_basis": "dense FP32 matrix peak: the result has FP32-class accuracy",
+                     "fp16_matrix_tflops": round(3 * tflops, 2),
+                     "fp16_matrix_frac": round(3 * tflops / FP16_MFMA_PEAK_TFLOPS, 4),
                      "traffic": None, "algorithmic_flops_per_launch": terms * FLOPS_PER_TERM,
                      "kernel": "rmd::synth_kernel (timed with rmd::geometry_kernel and rmd::reduce_kernel: "
                                "one IF cube)",
