@@ -35,10 +35,11 @@ constexpr int kBlock = kRows * kCols;     // samples of one pass (512)
 constexpr int kGroup = 16;                // rays per operand table (two MFMA blocks of 8)
 constexpr int kBlockRays = 8;             // rays per 32 x 32 x 16 fp16 MFMA (K = 2 components x 8 rays)
 constexpr int kSlotWords = 4;             // one lane's operand: 8 fp16 values
-// Word offset of lane slot L in an operand block, padded by one slot every 8
-// slots so that the build's scattered 4-byte writes spread over the banks.
-__host__ __device__ constexpr int slot_word(int L) { return kSlotWords * (L + (L >> 3)); }
-constexpr int kBlockWords = slot_word(kWave);               // 288 words per block
+// Word offset of lane slot L in an operand block.  Slots are permuted within
+// each run of 8 (XOR with the run index) so that the build's scattered 4-byte
+// writes spread over the LDS banks; the block needs no padding.
+__host__ __device__ constexpr int slot_word(int L) { return kSlotWords * (L ^ ((L >> 3) & 7)); }
+constexpr int kBlockWords = kSlotWords * kWave;             // 256 words per block
 constexpr int kArrayWords = (kGroup / kBlockRays) * kBlockWords;
 constexpr int kTableWords = 4 * kArrayWords;                // A hi, A lo, B hi, B lo
 static_assert(kWaves * kTableWords >= kWaves * 2 * kBlock, "wave sums must fit in the table memory");

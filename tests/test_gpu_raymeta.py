@@ -201,3 +201,20 @@ def test_full_size_sampled(RM):
     err = _blocks_rel(got[:, :, sel], ref)
     _say(f"[gpu]   worst sampled block rel L2 {err.max():.2e}")
     assert err.max() <= TOL
+
+
+def test_if_cube_bitwise_reproducible_and_null_weights(RM):
+    """Partition sums and wave combination run in a fixed order, so two runs
+    agree bit for bit; NULL weights mean w = 1 for every ray."""
+    import torch
+    sc = S.small_scene(n_rays=5000, n_chirps=4, n_samples=512)
+    sc.amp = None
+    ds = RM.DeviceScene(sc)
+    syn = RM.Synthesizer(ds)
+    a = syn.run(0, None).clone()
+    b = syn.run(0, None).clone()
+    assert torch.equal(a, b)
+    ones = torch.ones(sc.n_rays, dtype=torch.float32, device=ds.device)
+    c = syn.run(0, ones).clone()
+    assert torch.equal(a, c)
+    assert _blocks_rel(a.cpu().numpy(), R.if_cube(sc)).max() <= TOL
