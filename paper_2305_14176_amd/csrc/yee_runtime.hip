@@ -407,9 +407,11 @@ void default_launch(yee_ctx* c) {
   const auto& d = c->d;
   c->V = c->vpl ? c->vpl : default_samples_per_lane(d);
   const int wpr = waves_per_row(d.nx, c->V);
-  // rows per tile: workgroups of at most 12 waves, so that two fit a CU;
-  // measured best for the 256^3 grid: two rows of four waves plus the halo row
-  c->ty = c->ty_req ? c->ty_req : std::max(1, std::min({7, d.ny, 12 / wpr - 1}));
+  // rows per tile: workgroups of at most 12 waves, so that two fit a CU, and
+  // within the kernel's wave limit for V samples per lane; measured best for
+  // the 256^3 grid: two rows of four waves plus the halo row
+  c->ty = c->ty_req ? c->ty_req
+                    : std::max(1, std::min({7, d.ny, 12 / wpr - 1, yee::max_block_waves(c->V) / wpr - 1}));
   for (;;) {
     if (c->kz_req > 0) {
       c->kz = std::min(c->kz_req, d.nz);

@@ -111,6 +111,7 @@ def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
     ((160, 48, 48), 4, 16, 0),
     ((512, 9, 12), 1, 1, 0),    # widest rows (automatic: eight waves), one plane per chunk
     ((512, 9, 12), 1, 2, 2),    # widest rows, two samples per lane
+    ((512, 9, 12), 0, 0, 4),    # four samples per lane: automatic rows within its 8-wave limit
 ])
 def test_random_init_fp32_launch_shapes(solver_cls, shape, ty, kz, vpl):
     nx, ny, nz = shape
