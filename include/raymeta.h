@@ -93,8 +93,11 @@ const char* rmd_last_error(void);
 rmd_status rmd_check_scene(const rmd_scene* scene, int32_t n_chirps, void* workspace,
                            int64_t* n_bad_rays, hipStream_t stream);
 
-/* Bytes of device workspace rmd_if_cube needs for these sizes (partial sums
- * of the ray partitions, complex64 per pair, chirp and sample). */
+/* Bytes of device workspace rmd_if_cube needs for these sizes.  Chirps are
+ * processed in batches of up to 16 whose per-ray geometry (7 float64 per ray
+ * and chirp: inner path length, first and last hit point) fits in 1 GiB; the
+ * workspace holds one batch's geometry and its partition sums (complex64 per
+ * ray partition, pair, chirp and sample). */
 rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs,
                                int32_t chirp_count, int64_t* bytes);
 
@@ -108,8 +111,10 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
  *   chirps   [chirp0, chirp0 + chirp_count) of the scene's n_chirps.
  *   s        output [n_pairs][chirp_count][n_samples] complex64.
  *   workspace at least rmd_workspace_bytes(...) bytes, 256-byte aligned.
- * Phases are formed in float64 and reduced modulo one cycle before the
- * float32 recurrence over fast time; partition sums are added in float64. */
+ * Phases are formed in float64 and reduced modulo one cycle; the phasors are
+ * float32, split into fp16 high and low parts for the matrix products
+ * (float32 accumulation, about 2^-21 relative); partition sums are added in
+ * float64 in a fixed order, so repeated calls give identical results. */
 rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
                        const float* weights, int32_t chirp0, int32_t chirp_count, float* s,
                        void* workspace, int64_t workspace_bytes, hipStream_t stream);
