@@ -24,8 +24,10 @@
  *   - Every call is asynchronous on the given stream (0 = the null stream)
  *     unless it says otherwise; inputs must stay valid until the stream has
  *     run the work.
- *   - Every call returns an rmd_status; on failure nothing was launched and
- *     rmd_last_error() holds a message (thread-local).
+ *   - Every call returns an rmd_status and, on failure, leaves a message in
+ *     rmd_last_error() (thread-local).  Argument errors (RMD_EINVAL) are found
+ *     before anything is launched; RMD_EHIP from rmd_if_cube can follow
+ *     launches of earlier chirp batches already queued on the stream.
  *   - Complex values are interleaved float pairs (re, im).
  */
 #ifndef RAYMETA_H
