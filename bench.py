@@ -77,7 +77,7 @@ def cpu_baseline(wl, budget_s=15.0, max_steps=5):
 
 
 def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=32, max_slots=32,
-                      hbm_budget=4 << 30, sample=16):
+                      hbm_budget=4 << 30, sample=16, max_active_cells="default"):
     """Serving sweep: Poisson arrivals at `load` x the plain one-at-a-time capacity.
 
     Requests follow the serving workload (cubic sides from {32, 48, 64, 96, 128,
@@ -90,6 +90,9 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     from paper_2305_14176_amd import workloads as W
     from paper_2305_14176_amd.serving import BatchServer, Request, serve_one_at_a_time
 
+    if max_active_cells == "default":
+        from paper_2305_14176_amd.serving import DEFAULT_ACTIVE_CELLS
+        max_active_cells = DEFAULT_ACTIVE_CELLS
     gaps, wls = W.serving_sweep(n_requests, seed=seed)
     cells = [w.cells * w.steps for w in wls]
 
@@ -100,7 +103,8 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     t0 = time.perf_counter()
     serve_one_at_a_time(make(np.zeros(n_requests))[:sample])
     cap = sample / (time.perf_counter() - t0)
-    srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay)
+    srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay,
+                      max_active_cells=max_active_cells)
     t0 = time.perf_counter()
     srv.serve(make(np.zeros(n_requests))[:sample])
     cap_b = sample / (time.perf_counter() - t0)
@@ -110,7 +114,8 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     for load in loads:
         arrivals = np.asarray(gaps) / (load * cap)
         plain = serve_one_at_a_time(make(arrivals))
-        srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay)
+        srv = BatchServer(max_slots=max_slots, hbm_budget=hbm_budget, steps_per_replay=steps_per_replay,
+                          max_active_cells=max_active_cells)
         batched = srv.serve(make(arrivals))
         srv.close()
         runs[load] = (plain, batched, srv.replays)
@@ -127,6 +132,7 @@ def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=
     out = {"requests": n_requests, "plain_capacity_req_per_s": round(cap, 3),
            "batched_capacity_req_per_s": round(cap_b, 3),
            "steps_per_replay": steps_per_replay, "max_slots": max_slots, "hbm_budget_bytes": hbm_budget,
+           "max_active_cells": max_active_cells,
            "workload": "serving_request: side in {32,48,64,96,128,160}, 500-3000 steps, CPML 8, FP32"}
     for load, (plain, batched, replays) in runs.items():
         out[f"load_{load}"] = {"arrival_rate_req_per_s": round(load * cap, 3), "batched": stats(batched),

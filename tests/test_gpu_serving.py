@@ -115,3 +115,27 @@ def test_admission_by_budget_and_slots():
     lib.yee_batch_destroy(b)
     for s in (small, big, other, third):
         s.close()
+
+
+def test_active_cell_cap_queues_and_keeps_results():
+    """A cell cap smaller than two of the grids: requests wait for room (one
+    larger than the cap still runs when it is alone), and every result equals
+    the request run alone."""
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    specs = [(48, 40, 301, 0.0), (64, 30, 302, 0.0), (32, 50, 303, 0.0), (96, 20, 304, 0.0)]
+    keep = ("Ez",)
+    _say("[gpu] serving: cell cap")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(specs), keep_fields=keep)}
+    cap = 64 ** 3 + 32 ** 3        # below 96^3, and below 48^3 + 64^3 + 32^3
+    srv = BatchServer(max_slots=8, hbm_budget=2 << 30, steps_per_replay=8, keep_fields=keep,
+                      max_active_cells=cap)
+    done = srv.serve(_requests(specs))
+    by_id = {r.rid: r for r in done}
+    assert sorted(by_id) == sorted(alone)
+    # with the cap, the 96^3 request cannot start before the others have finished
+    big = by_id[3]
+    assert big.admitted >= max(by_id[i].finished for i in (0, 1, 2)) - 1e-9
+    for rid, a in alone.items():
+        np.testing.assert_array_equal(by_id[rid].series, a.series, err_msg=f"series of request {rid}")
+        np.testing.assert_array_equal(by_id[rid].fields["Ez"], a.fields["Ez"])
+    srv.close()
