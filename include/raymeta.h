@@ -48,6 +48,7 @@ typedef int32_t rmd_status;
 
 #define RMD_MAX_SAMPLES 1024   /* n_samples limit of rmd_if_cube */
 #define RMD_MAX_FFT     4096   /* line length limit of rmd_range_doppler */
+#define RMD_MAX_RAYS    (1 << 30)   /* n_rays limit (32-bit ray indices with partition headroom) */
 
 /* FMCW parameters (Section II.A, Eq. 3). */
 typedef struct {

@@ -503,6 +503,7 @@ rmd_status check_scene_desc(const rmd_scene* sc) {
     if (sc->n_meshes <= 0 || sc->n_tris <= 0 || sc->n_verts <= 0 || sc->n_rays <= 0 || sc->n_hits < 0)
         return fail(RMD_EINVAL, "scene sizes must be positive (n_hits >= 0)");
     if (sc->n_hits > INT32_MAX) return fail(RMD_EINVAL, "n_hits above 2^31 - 1 (32-bit ray offsets)");
+    if (sc->n_rays > RMD_MAX_RAYS) return fail(RMD_EINVAL, "n_rays above RMD_MAX_RAYS");
     if (!sc->mesh_tri_off || !sc->tris || !sc->verts || !sc->ray_off || !sc->hit_mesh || !sc->hit_tri ||
         !sc->hit_u || !sc->hit_v)
         return fail(RMD_EINVAL, "a scene array pointer is NULL");

@@ -21,6 +21,7 @@ RMD_OK = 0
 STATUS_NAMES = {0: "RMD_OK", -1: "RMD_EINVAL", -3: "RMD_EHIP", -8: "RMD_ESCENE"}
 MAX_SAMPLES = 1024
 MAX_FFT = 4096
+MAX_RAYS = 1 << 30
 SPAN_ANY, SPAN_NONE, SPAN_ALL = 0, 1, 2
 
 # Every symbol include/raymeta.h declares (checked by the CPU test suite).

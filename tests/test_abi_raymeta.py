@@ -87,7 +87,8 @@ def test_scene_descriptor_checks():
     lib = RM.load()
     out = C.c_int64()
     r = _radar()
-    for bad in (_fake_scene(n_rays=0), _fake_scene(n_hits=-1), _fake_scene(n_hits=1 << 31)):
+    for bad in (_fake_scene(n_rays=0), _fake_scene(n_hits=-1), _fake_scene(n_hits=1 << 31),
+                _fake_scene(n_rays=RM.MAX_RAYS + 1, n_hits=1 << 30)):
         assert lib.rmd_workspace_bytes(C.byref(bad), C.byref(r), 1, 1, C.byref(out)) == -1
     sc = _fake_scene()
     sc.hit_v = None
