@@ -93,6 +93,18 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _device_array(x, dtype, n, name, device):
+    """Check that a tensor handed to the library is a contiguous device array
+    of `n` elements of `dtype` on `device` (the kernels read exactly n)."""
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.dtype != dtype or not x.is_contiguous() or x.numel() != n or x.device != device:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} elements on {device}; "
+                         f"got {x.dtype}, {tuple(x.shape)}, contiguous={x.is_contiguous()}, on {x.device}")
+    return C.c_void_p(x.data_ptr())
+
+
 def radar_struct(radar) -> Radar:
     return Radar(radar.f_c, radar.bandwidth, radar.t_chirp, radar.f_s, radar.n_samples, radar.n_chirps)
 
@@ -107,6 +119,22 @@ class DeviceScene:
         self.scene = scene
         self.radar = scene.radar
         self.device = torch.device(device)
+        # The kernels range-check every index they read, but trust these sizes.
+        nh, nr = scene.n_hits, scene.n_rays
+        checks = [
+            (np.shape(scene.ray_off) == (nr + 1,), "ray_off must have n_rays + 1 entries"),
+            (all(np.shape(x) == (nh,) for x in (scene.hit_tri, scene.hit_u, scene.hit_v)),
+             "hit_mesh, hit_tri, hit_u and hit_v must have the same length"),
+            (np.ndim(scene.tris) == 2 and np.shape(scene.tris)[1] == 3, "tris must be [n_tris][3]"),
+            (np.ndim(scene.verts) == 3 and np.shape(scene.verts)[0] == scene.radar.n_chirps
+             and np.shape(scene.verts)[2] == 3, "verts must be [n_chirps][n_verts][3]"),
+            (np.shape(scene.tx_virt) == np.shape(scene.rx_virt) and np.shape(scene.tx_virt)[1:] == (3,),
+             "tx_virt and rx_virt must be [n_pairs][3]"),
+            (scene.amp is None or np.shape(scene.amp) == (nr,), "amp must have n_rays entries"),
+        ]
+        for ok, msg in checks:
+            if not ok:
+                raise ValueError(msg)
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(self.device)   # noqa: E731
         self.mesh_tri_off = t(scene.mesh_tri_off, np.int32)
         self.tris = t(scene.tris, np.int32)
@@ -156,6 +184,9 @@ class Synthesizer:
         import torch
         self.ds = ds
         self.pairs = ds.pairs if pairs is None else torch.as_tensor(np.asarray(pairs, np.float64)).to(ds.device)
+        if self.pairs.dim() != 2 or self.pairs.shape[1] != 6:
+            raise ValueError("pairs must be [n_pairs][6]: x'_tx then x'_rx of each pair")
+        self.pairs = self.pairs.contiguous()
         self.n_pairs = int(self.pairs.shape[0])
         self.chirp_count = chirp_count or ds.radar.n_chirps
         self.radar = radar_struct(ds.radar)
@@ -168,7 +199,9 @@ class Synthesizer:
     def run(self, chirp0: int = 0, weights=None, stream=None):
         """s[q, j - chirp0, n] for chirps [chirp0, chirp0 + chirp_count); returns
         the (reused) output tensor, valid once the stream has run."""
-        wptr = None if weights is None else C.c_void_p(weights.data_ptr())
+        import torch
+        wptr = None if weights is None else _device_array(weights, torch.float32, self.ds.scene.n_rays, "weights",
+                                                          self.ds.device)
         check(load().rmd_if_cube(C.byref(self.ds.desc), C.byref(self.radar), self.n_pairs,
                                  C.c_void_p(self.pairs.data_ptr()), wptr, chirp0, self.chirp_count,
                                  C.c_void_p(self.out.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
@@ -188,8 +221,13 @@ def if_cube(ds: DeviceScene, weights=None, chirps: Optional[Sequence[int]] = Non
 def range_doppler(s, out=None, stream=None):
     """Eq. 4 on a complex64 cube [pair][chirp][sample] (new tensor unless ``out``)."""
     import torch
-    assert s.dtype == torch.complex64 and s.is_contiguous() and s.dim() == 3
+    if not (isinstance(s, torch.Tensor) and s.dtype == torch.complex64 and s.is_contiguous() and s.dim() == 3
+            and s.is_cuda):
+        raise ValueError("s must be a contiguous complex64 device tensor [pair][chirp][sample]")
     out = torch.empty_like(s) if out is None else out
+    _device_array(out, torch.complex64, s.numel(), "out", s.device)
+    if out.shape != s.shape:
+        raise ValueError("out must have the shape of s")
     check(load().rmd_range_doppler(C.c_void_p(s.data_ptr()), C.c_void_p(out.data_ptr()), s.shape[0], s.shape[1],
                                    s.shape[2], _stream(stream)), "rmd_range_doppler")
     return out
@@ -203,7 +241,9 @@ def span_weights(ds: DeviceScene, meshes=(), mode=SPAN_ANY, min_hits=1, max_hits
     in_set[list(meshes)] = 1
     in_set = torch.from_numpy(in_set).to(ds.device)
     rule = SpanRule(mode, min_hits, max_hits)
-    a = ds.amp if amp == "scene" else amp
+    a = ds.amp if (isinstance(amp, str) and amp == "scene") else amp
+    if a is not None:
+        _device_array(a, torch.float32, ds.scene.n_rays, "amp", ds.device)
     w = torch.empty(ds.scene.n_rays, dtype=torch.float32, device=ds.device)
     check(load().rmd_span_weights(C.byref(ds.desc), C.c_void_p(in_set.data_ptr()), C.byref(rule),
                                   None if a is None else C.c_void_p(a.data_ptr()), C.c_void_p(w.data_ptr()),
