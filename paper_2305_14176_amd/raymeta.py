@@ -137,6 +137,7 @@ class DeviceScene:
                 raise ValueError(msg)
         t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).to(self.device)   # noqa: E731
         self.mesh_tri_off = t(scene.mesh_tri_off, np.int32)
+        self.device = self.mesh_tri_off.device          # with its index ("cuda" -> "cuda:0")
         self.tris = t(scene.tris, np.int32)
         self.verts = t(scene.verts, np.float64)
         self.ray_off = t(scene.ray_off, np.int32)

@@ -154,3 +154,27 @@ def test_scene_generator_is_seeded_and_consistent():
     assert np.diff(full.mesh_tri_off).tolist() == [4096] * 8 and full.n_pairs == 12
     counts = np.bincount(np.diff(full.ray_off), minlength=5)[1:] / full.n_rays
     np.testing.assert_allclose(counts, [0.6, 0.25, 0.1, 0.05], atol=0.03)
+
+
+def test_binding_validates_before_the_library():
+    """Shape and tensor checks in the binding fire on the host (device "cpu":
+    no call here reaches a kernel)."""
+    import torch
+    sc = S.small_scene(n_rays=50, n_chirps=2, n_samples=64)
+    bad = S.small_scene(n_rays=50, n_chirps=2, n_samples=64)
+    bad.hit_u = bad.hit_u[:-1]
+    with pytest.raises(ValueError, match="same length"):
+        RM.DeviceScene(bad, device="cpu")
+    bad = S.small_scene(n_rays=50, n_chirps=2, n_samples=64)
+    bad.verts = bad.verts[:1]
+    with pytest.raises(ValueError, match="verts"):
+        RM.DeviceScene(bad, device="cpu")
+    ds = RM.DeviceScene(sc, device="cpu")
+    with pytest.raises(ValueError, match="pairs"):
+        RM.Synthesizer(ds, pairs=np.zeros((3, 5)))
+    syn = RM.Synthesizer(ds)
+    for w in (torch.ones(49), torch.ones(50, dtype=torch.float64), torch.ones(100)[::2]):
+        with pytest.raises(ValueError, match="weights"):
+            syn.run(0, w)
+    with pytest.raises(ValueError, match="amp"):
+        RM.span_weights(ds, meshes=[0], amp=torch.ones(7))
