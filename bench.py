@@ -198,40 +198,49 @@ def precision_benchmark(steps=100, warmup=10):
 def adjoint_benchmark(checkpoint_every=64):
     """Gradient of the 128^3 design workload (FP32 fields, FP64 gradient):
     forward run with checkpoints, backward run (recompute + reverse steps),
-    against the same N plain steps."""
+    against the same N plain steps; then the same gradient with the E history
+    of every segment kept from the forward run (no recompute)."""
     import torch
     from paper_2305_14176_amd import workloads as W
     from paper_2305_14176_amd.adjoint import DesignProblem
     wl = W.adjoint_design()
     d0, d1 = wl.design
     box = (d0, d1, d0, d1, d0, d1)
-    prob = DesignProblem(wl, box, checkpoint_every=checkpoint_every)
-    eps0 = prob.initial_design
-    prob.forward(eps0)
-    prob.gradient()              # warm-up of both passes
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    prob.forward(eps0)           # synchronizes (returns J to the host)
-    t1 = time.perf_counter()
-    g = prob.gradient()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    prob.solver.reset()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    prob.solver.step(prob.n_steps)
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    nbox = g.numel()
-    fwd, bwd, plain = t1 - t0, t2 - t1, t4 - t3
-    out = {"workload": f"{wl.name}: design [{d0},{d1})^3, {prob.n_steps} steps, {len(wl.probes)} Ez probes, "
+
+    def timed(history_segments):
+        prob = DesignProblem(wl, box, checkpoint_every=checkpoint_every, history_segments=history_segments)
+        eps0 = prob.initial_design
+        prob.forward(eps0)
+        prob.gradient()              # warm-up of both passes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.forward(eps0)           # synchronizes (returns J to the host)
+        t1 = time.perf_counter()
+        g = prob.gradient()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prob.solver.reset()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        prob.solver.step(prob.n_steps)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        res = (t1 - t0, t2 - t1, t4 - t3, g.numel(), prob.run.footprint, prob.n_steps)
+        prob.close()
+        return res
+
+    fwd, bwd, plain, nbox, ws, n_steps = timed(1)
+    out = {"workload": f"{wl.name}: design [{d0},{d1})^3, {n_steps} steps, {len(wl.probes)} Ez probes, "
                        f"checkpoint every {checkpoint_every}",
            "dtype": "f32 fields, f64 gradient",
            "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
            "gradient_ms": round((fwd + bwd) * 1e3, 2), "plain_forward_ms": round(plain * 1e3, 2),
            "gradient_over_plain": round((fwd + bwd) / plain, 3),
-           "design_cells": nbox, "workspace_bytes": prob.run.footprint}
-    prob.close()
+           "design_cells": nbox, "workspace_bytes": ws}
+    fwd, bwd, plain, _, ws, _ = timed(0)
+    out["all_history_kept"] = {"forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
+                               "gradient_ms": round((fwd + bwd) * 1e3, 2),
+                               "gradient_over_plain": round((fwd + bwd) / plain, 3), "workspace_bytes": ws}
     return out
 
 

@@ -253,8 +253,9 @@ yee_status yee_batch_info(const yee_batch* batch, int32_t* active_slots, int64_t
  *
  * The caller owns the adjoint's device workspace (yee_adjoint_footprint()
  * bytes, 256-byte aligned): (N/K + 1) checkpoints of the context state,
- * K + 1 copies of E over the box, 12 adjoint arrays of the grid's size and
- * N x n_probes doubles.
+ * K + 1 copies of E over the box per kept history segment (one unless
+ * yee_adjoint_set_history() asks for more), 12 adjoint arrays of the grid's
+ * size and N x n_probes doubles.
  * ------------------------------------------------------------------------ */
 typedef struct yee_adjoint yee_adjoint;
 
@@ -263,6 +264,16 @@ typedef struct yee_adjoint yee_adjoint;
 yee_status yee_adjoint_create(yee_ctx* ctx, int64_t n_steps, int32_t checkpoint_every,
                               const int32_t* box, yee_adjoint** out);
 void yee_adjoint_destroy(yee_adjoint* adj);
+
+/* How many segments (the newest) keep the E history of the box from the
+ * forward run: 1 by default, the checkpoint-recompute schedule above; 0 keeps
+ * all of them, and the backward run then recomputes nothing.  Every kept
+ * segment adds (K + 1) x 3 x box cells x element bytes to the workspace (FP32
+ * 128^3 with a 64^3 box and K = 64: 204 MB per segment, 3.3 GB for 16).  The
+ * gradient does not depend on it: recomputed and kept histories are the same
+ * values.  Call before yee_adjoint_footprint(); YEE_ESTATE once bound,
+ * YEE_EINVAL outside [0, number of segments]. */
+yee_status yee_adjoint_set_history(yee_adjoint* adj, int32_t segments);
 yee_status yee_adjoint_footprint(const yee_adjoint* adj, int64_t* bytes);
 yee_status yee_adjoint_bind_workspace(yee_adjoint* adj, void* device_ptr, int64_t bytes);
 

@@ -27,7 +27,7 @@ EXPORTED = (
     "yee_read_dft", "yee_set_launch", "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
     "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
     "yee_batch_info", "yee_adjoint_create", "yee_adjoint_destroy", "yee_adjoint_footprint",
-    "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward",
+    "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward", "yee_adjoint_set_history",
 )
 
 
@@ -107,6 +107,7 @@ def load():
         "yee_batch_info": (I32, [VP, P(I32), P(I64)]),
         "yee_adjoint_create": (I32, [VP, I64, I32, P(I32), P(VP)]),
         "yee_adjoint_destroy": (None, [VP]),
+        "yee_adjoint_set_history": (I32, [VP, I32]),
         "yee_adjoint_footprint": (I32, [VP, P(I64)]),
         "yee_adjoint_bind_workspace": (I32, [VP, VP, I64]),
         "yee_adjoint_forward": (I32, [VP, P(D), VP]),

@@ -55,9 +55,15 @@ def design_workload(wl: Workload, box: Sequence[int]) -> Tuple[Workload, np.ndar
 
 
 class AdjointRun:
-    """One forward run with checkpoints and its reverse-time gradient."""
+    """One forward run with checkpoints and its reverse-time gradient.
 
-    def __init__(self, solver: YeeSolver, n_steps: int, box: Sequence[int], checkpoint_every: int = 64):
+    ``history_segments``: how many of the newest segments keep the E history
+    of the box from the forward run (1: checkpoint-recompute; 0: all, and the
+    backward run recomputes nothing, for (K + 1) x 3 x box cells of memory per
+    segment)."""
+
+    def __init__(self, solver: YeeSolver, n_steps: int, box: Sequence[int], checkpoint_every: int = 64,
+                 history_segments: int = 1):
         self.solver = solver
         self.lib = solver.lib
         self.box = tuple(int(v) for v in box)
@@ -68,6 +74,8 @@ class AdjointRun:
         _lib.check(self.lib.yee_adjoint_create(solver.ctx, self.n_steps, int(checkpoint_every), b, C.byref(h)),
                    "yee_adjoint_create")
         self.handle = h
+        if history_segments != 1:
+            _lib.check(self.lib.yee_adjoint_set_history(h, int(history_segments)), "yee_adjoint_set_history")
         nb = C.c_int64()
         _lib.check(self.lib.yee_adjoint_footprint(h, C.byref(nb)), "yee_adjoint_footprint")
         self.footprint = nb.value
@@ -107,12 +115,12 @@ class DesignProblem:
     """A workload whose box cells carry free eps_r values (the design)."""
 
     def __init__(self, wl: Workload, box: Sequence[int], n_steps: int = None, checkpoint_every: int = 64,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", history_segments: int = 1):
         self.wl, self.block = design_workload(wl, box)
         self.box = tuple(int(v) for v in box)
         self.n_steps = int(wl.steps if n_steps is None else n_steps)
         self.solver = YeeSolver(self.wl, device=device, series_len=self.n_steps)
-        self.run = AdjointRun(self.solver, self.n_steps, self.box, checkpoint_every)
+        self.run = AdjointRun(self.solver, self.n_steps, self.box, checkpoint_every, history_segments)
         self.generation = 0
 
     @property

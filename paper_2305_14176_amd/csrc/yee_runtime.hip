@@ -1054,7 +1054,8 @@ struct yee_adjoint {
   Region ckpt, hist, u, hb, pe[2], ph[2], phist, jout, dcoef, inj;
   size_t ckpt_bytes = 0;  // one checkpoint: fields | psi_E | psi_H
   size_t ucomp = 0;       // bytes of one adjoint component array
-  int32_t hist_seg = -1;  // segment whose E history the workspace holds
+  int32_t H = 1;          // history slots: segments whose E history is kept
+  std::vector<int32_t> slot_seg;  // segment held by each history slot (-1: none)
   bool have_forward = false;
   std::vector<yee::InjDev> inj_host;
   std::vector<double> dcoef_host;
@@ -1073,7 +1074,7 @@ void adj_layout(yee_adjoint* A) {
   };
   A->ckpt_bytes = align256(6 * c->comp_bytes) + 2 * align256(c->psi_e.bytes);
   take(A->ckpt, (size_t)(A->S + 1) * A->ckpt_bytes);
-  take(A->hist, (size_t)(A->K + 1) * 3 * A->nbox * c->tsize);
+  take(A->hist, (size_t)A->H * (A->K + 1) * 3 * A->nbox * c->tsize);
   A->ucomp = align256((size_t)d.nz * d.ny * c->px * c->csize);
   take(A->u, 3 * A->ucomp);
   take(A->hb, 3 * A->ucomp);
@@ -1107,8 +1108,8 @@ yee_status adj_checkpoint(yee_adjoint* A, int q, bool save, hipStream_t s) {
   return YEE_OK;
 }
 
-// E of the box cells at the current step into history slot m.
-yee_status adj_store(yee_adjoint* A, int m, hipStream_t s) {
+// E of the box cells at the current step into entry m of history slot `slot`.
+yee_status adj_store(yee_adjoint* A, int slot, int m, hipStream_t s) {
   yee_ctx* c = A->c;
   const int cur = (int)(c->n & 1);
   const int4 lo = {A->box[0], A->box[2], A->box[4], 0};
@@ -1117,14 +1118,14 @@ yee_status adj_store(yee_adjoint* A, int m, hipStream_t s) {
   const uint64_t hs = A->nbox;
   if (c->d.precision == YEE_F64) {
     const double* f = reinterpret_cast<const double*>(c->ws + c->fields[cur].off);
-    double* slot = reinterpret_cast<double*>(A->ws + A->hist.off) + (size_t)m * 3 * hs;
+    double* dst = reinterpret_cast<double*>(A->ws + A->hist.off) + ((size_t)slot * (A->K + 1) + m) * 3 * hs;
     hipLaunchKernelGGL(yee::adj_store_kernel<double>, grid, block, 0, s, f, (uint64_t)(c->comp_bytes / 8),
-                       c->d.ny, c->px, lo, A->bx, A->by, slot, hs);
+                       c->d.ny, c->px, lo, A->bx, A->by, dst, hs);
   } else {
     const float* f = reinterpret_cast<const float*>(c->ws + c->fields[cur].off);
-    float* slot = reinterpret_cast<float*>(A->ws + A->hist.off) + (size_t)m * 3 * hs;
+    float* dst = reinterpret_cast<float*>(A->ws + A->hist.off) + ((size_t)slot * (A->K + 1) + m) * 3 * hs;
     hipLaunchKernelGGL(yee::adj_store_kernel<float>, grid, block, 0, s, f, (uint64_t)(c->comp_bytes / 4),
-                       c->d.ny, c->px, lo, A->bx, A->by, slot, hs);
+                       c->d.ny, c->px, lo, A->bx, A->by, dst, hs);
   }
   HIP_TRY(hipGetLastError());
   return YEE_OK;
@@ -1144,7 +1145,7 @@ yee_status adj_gather(yee_adjoint* A, int64_t s0, int64_t count, hipStream_t s) 
 }
 
 template <class T, class C>
-yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int m, int pin, int pout, bool e_side) {
+yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int slot, int m, int pin, int pout, bool e_side) {
   using namespace yee;
   yee_ctx* c = A->c;
   const auto& d = c->d;
@@ -1165,7 +1166,7 @@ yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int m, int pin, int pout,
   a.nsxy = c->nsx * c->nsy;
   a.pec_plane = reinterpret_cast<const int32_t*>(c->ws + c->pecplane.off);
   a.pec_mask = reinterpret_cast<const uint8_t*>(c->ws + c->pecmask.off);
-  const T* h0 = reinterpret_cast<const T*>(A->ws + A->hist.off);
+  const T* h0 = reinterpret_cast<const T*>(A->ws + A->hist.off) + (size_t)slot * (A->K + 1) * 3 * A->nbox;
   a.hstride = A->nbox;
   a.hist_n = h0 + (size_t)m * 3 * A->nbox;
   a.hist_np1 = h0 + (size_t)(m + 1) * 3 * A->nbox;
@@ -1190,9 +1191,11 @@ yee::AdjArgs<T, C> adj_args(yee_adjoint* A, int64_t n, int m, int pin, int pout,
   return a;
 }
 
-// One reverse step of forward step n (n0 <= n < n0 + K, history slot m = n - n0).
+// One reverse step of forward step n (n0 <= n < n0 + K: entry m = n - n0 of
+// history slot `slot`).
 template <class C>
-yee_status adj_reverse_step(yee_adjoint* A, int64_t n, int m, int& pe, int& ph, double* grad, hipStream_t s) {
+yee_status adj_reverse_step(yee_adjoint* A, int64_t n, int slot, int m, int& pe, int& ph, double* grad,
+                            hipStream_t s) {
   using namespace yee;
   yee_ctx* c = A->c;
   const auto& d = c->d;
@@ -1212,12 +1215,12 @@ yee_status adj_reverse_step(yee_adjoint* A, int64_t n, int m, int& pe, int& ph, 
   }
   const dim3 grid((d.nx + kAdjBX - 1) / kAdjBX, (d.ny + kAdjBY - 1) / kAdjBY, d.nz);
   const dim3 block(kAdjBX, kAdjBY);
-  AdjArgs<C, C> ah = adj_args<C, C>(A, n, m, pe, pe ^ 1, false);
+  AdjArgs<C, C> ah = adj_args<C, C>(A, n, slot, m, pe, pe ^ 1, false);
   ah.yrow_h = ninj > 0 ? yrow + (size_t)n * np : nullptr;
   hipLaunchKernelGGL(adj_h_kernel<C>, grid, block, 0, s, ah);
   HIP_TRY(hipGetLastError());
   pe ^= 1;
-  AdjArgs<C, C> ae = adj_args<C, C>(A, n, m, ph, ph ^ 1, true);
+  AdjArgs<C, C> ae = adj_args<C, C>(A, n, slot, m, ph, ph ^ 1, true);
   ae.yrow_e = (ninj > 0 && n > 0) ? yrow + (size_t)(n - 1) * np : nullptr;
   ae.grad = grad;
   hipLaunchKernelGGL((adj_e_kernel<C, C>), grid, block, 0, s, ae);
@@ -1258,8 +1261,20 @@ yee_status yee_adjoint_create(yee_ctx* c, int64_t n_steps, int32_t checkpoint_ev
   A->by = box[3] - box[2];
   A->bz = box[5] - box[4];
   A->nbox = (size_t)A->bx * A->by * A->bz;
+  A->slot_seg.assign(1, -1);
   adj_layout(A);
   *out = A;
+  return YEE_OK;
+}
+
+yee_status yee_adjoint_set_history(yee_adjoint* A, int32_t segments) {
+  if (!A) return fail(YEE_EINVAL, "NULL argument");
+  if (A->bound) return fail(YEE_ESTATE, "set the history before binding the workspace");
+  if (segments < 0 || segments > A->S)
+    return fail(YEE_EINVAL, "history of %d segments: must be 0 (all) to %d", segments, A->S);
+  A->H = segments == 0 ? A->S : segments;
+  A->slot_seg.assign((size_t)A->H, -1);
+  adj_layout(A);
   return YEE_OK;
 }
 
@@ -1279,7 +1294,7 @@ yee_status yee_adjoint_bind_workspace(yee_adjoint* A, void* dev, int64_t bytes) 
   A->ws = static_cast<unsigned char*>(dev);
   A->bound = true;
   A->have_forward = false;
-  A->hist_seg = -1;
+  A->slot_seg.assign((size_t)A->H, -1);
   return YEE_OK;
 }
 
@@ -1293,15 +1308,19 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
   A->have_forward = false;
   yee_status st = YEE_OK;
   int64_t gathered = 0;
+  // the newest H segments keep the E history of the box from this run
+  const int32_t kept0 = A->S - A->H;
+  A->slot_seg.assign((size_t)A->H, -1);
   for (int32_t seg = 0; seg < A->S; ++seg) {
     const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
-    const bool last = seg == A->S - 1;
+    const bool keep = seg >= kept0;
+    const int slot = seg - kept0;
     if ((st = adj_checkpoint(A, seg, true, s))) return st;
-    if (last && (st = adj_store(A, 0, s))) return st;
+    if (keep && (st = adj_store(A, slot, 0, s))) return st;
     for (int64_t n = n0; n < n1; ++n) {
       if ((st = launch_one_step(c, s))) return st;
       c->n += 1;
-      if (last && (st = adj_store(A, (int)(c->n - n0), s))) return st;
+      if (keep && (st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       if (c->n - gathered >= d.series_len) {
         if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
         gathered = c->n;
@@ -1367,7 +1386,7 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(objective, A->ws + A->jout.off, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  A->hist_seg = A->S - 1;
+  for (int32_t q = 0; q < A->H; ++q) A->slot_seg[q] = kept0 + q;
   A->have_forward = true;
   return YEE_OK;
 }
@@ -1384,20 +1403,26 @@ yee_status yee_adjoint_backward(yee_adjoint* A, double* grad, void* stream) {
   yee_status st = YEE_OK;
   for (int32_t seg = A->S - 1; seg >= 0; --seg) {
     const int64_t n0 = (int64_t)seg * A->K, n1 = std::min(A->N, n0 + A->K);
-    if (A->hist_seg != seg) {
+    int slot = -1;
+    for (int32_t q = 0; q < A->H; ++q)
+      if (A->slot_seg[q] == seg) slot = q;
+    if (slot < 0) {
+      // recompute the segment from its checkpoint into slot 0, whose segment
+      // (newer than this one) has been walked already
+      slot = 0;
       c->n = n0;
       if ((st = adj_checkpoint(A, seg, false, s))) return st;
-      if ((st = adj_store(A, 0, s))) return st;
+      if ((st = adj_store(A, slot, 0, s))) return st;
       for (int64_t n = n0; n < n1; ++n) {
         if ((st = launch_one_step(c, s, false))) return st;
         c->n += 1;
-        if ((st = adj_store(A, (int)(c->n - n0), s))) return st;
+        if ((st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       }
-      A->hist_seg = seg;
+      A->slot_seg[slot] = seg;
     }
     for (int64_t n = n1 - 1; n >= n0; --n) {
-      st = c->csize == 8 ? adj_reverse_step<double>(A, n, (int)(n - n0), pe, ph, grad, s)
-                         : adj_reverse_step<float>(A, n, (int)(n - n0), pe, ph, grad, s);
+      st = c->csize == 8 ? adj_reverse_step<double>(A, n, slot, (int)(n - n0), pe, ph, grad, s)
+                         : adj_reverse_step<float>(A, n, slot, (int)(n - n0), pe, ph, grad, s);
       if (st) return st;
     }
   }

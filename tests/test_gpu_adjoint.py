@@ -224,6 +224,34 @@ def test_adjoint_leaves_context_as_plain_steps():
         s.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_kept_history_gives_the_same_gradient(prec):
+    """Keeping the E history of 3 or of all segments from the forward run
+    (fewer or no recomputed segments) gives bitwise the gradient of the
+    checkpoint-recompute schedule, also on a second backward call."""
+    from paper_2305_14176_amd.adjoint import AdjointRun
+    from paper_2305_14176_amd.solver import YeeSolver
+    wl = _case(prec, "e", seed=16, steps=70)
+    _say(f"[gpu] adjoint kept history {prec}")
+    ref_j, ref_g = _gpu_gradient(wl, BOX_IN, 16)          # 5 segments, 4 recomputed
+    base = None
+    for hist in (3, 0):
+        s = YeeSolver(wl, series_len=wl.steps)
+        run = AdjointRun(s, wl.steps, BOX_IN, checkpoint_every=16, history_segments=hist)
+        if base is None:
+            base = run.footprint
+        else:
+            assert run.footprint > base
+        j = run.forward()
+        g1 = run.backward().cpu().numpy()
+        g2 = run.backward().cpu().numpy()
+        run.close()
+        s.close()
+        assert j == ref_j
+        np.testing.assert_array_equal(g1, ref_g)
+        np.testing.assert_array_equal(g2, ref_g)
+
+
 def test_adjoint_error_states():
     from paper_2305_14176_amd import _lib
     from paper_2305_14176_amd.solver import YeeSolver
@@ -238,6 +266,10 @@ def test_adjoint_error_states():
     box = (C.c_int32 * 6)(*BOX_IN)
     assert lib.yee_adjoint_create(s.ctx, 0, 4, box, C.byref(h)) == -1
     assert lib.yee_adjoint_create(s.ctx, 10, 4, box, C.byref(h)) == 0
+    assert lib.yee_adjoint_set_history(h, 4) == -1                     # 3 segments of 4 steps
+    assert lib.yee_adjoint_set_history(h, -1) == -1
+    assert lib.yee_adjoint_set_history(h, 3) == 0
+    assert lib.yee_adjoint_set_history(h, 1) == 0
     jv = C.c_double()
     assert lib.yee_adjoint_forward(h, C.byref(jv), None) == -4          # workspace not bound
     nb = C.c_int64()
@@ -247,6 +279,7 @@ def test_adjoint_error_states():
     ptr = (ws.data_ptr() + 255) & ~255
     assert lib.yee_adjoint_bind_workspace(h, C.c_void_p(ptr), nb.value - 1) == -2
     assert lib.yee_adjoint_bind_workspace(h, C.c_void_p(ptr), nb.value) == 0
+    assert lib.yee_adjoint_set_history(h, 0) == -4                     # already bound
     g = torch.empty(18 * 16 * 15, dtype=torch.float64, device="cuda")
     assert lib.yee_adjoint_backward(h, C.c_void_p(g.data_ptr()), None) == -4   # no forward run
     s.step(1)
