@@ -40,7 +40,10 @@ constexpr int kMaxBlockWaves = 16;   // 1024 threads
 
 // Waves a workgroup may hold at V samples per lane (bounds the registers the
 // compiler may give each lane).
-__host__ __device__ constexpr int max_block_waves(int V) { return V >= 4 ? 8 : 16; }
+// Waves per workgroup the kernel is built for.  The bound also caps registers:
+// at 16 waves a kernel gets 128 VGPRs, and the two-sample kernels spill there
+// (FP16 storage: 9 VGPRs, FP64: 348); built for 12 waves they get up to 170.
+__host__ __device__ constexpr int max_block_waves(int V) { return V >= 4 ? 8 : (V == 2 ? 12 : 16); }
 constexpr int kMaxSources = 8;
 
 // psi auxiliaries (E side in place; H side ping-ponged).  The two of one

@@ -106,7 +106,7 @@ def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
     ((256, 40, 33), 0, 0, 0),
     ((256, 40, 33), 3, 5, 0),
     ((256, 21, 19), 7, 3, 4),   # four samples per lane, one wave per row
-    ((300, 17, 26), 4, 4, 2),   # two samples per lane, ragged row
+    ((300, 17, 26), 3, 4, 2),   # two samples per lane, ragged row (12 waves, the two-sample limit)
     ((300, 17, 26), 0, 0, 0),   # automatic: one sample per lane, five waves per row
     ((160, 48, 48), 4, 16, 0),
     ((512, 9, 12), 1, 1, 0),    # widest rows (automatic: eight waves), one plane per chunk
