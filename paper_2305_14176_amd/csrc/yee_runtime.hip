@@ -399,8 +399,12 @@ int step_slots(const yee_ctx* c, int threads, size_t lds) {
 // 2-byte storage one-sample loads would be half-width).  Measured at
 // 512 x 512 x 256: FP32 1.04 ms per step with one sample, 1.35 with two;
 // FP16 storage 1.08 with two, 1.10 with one.
+// Samples per lane when the caller does not choose: one up to 256-sample rows;
+// past that two for FP32 and FP16 storage (512 x 512 x 256: 0.88 against
+// 1.10 ms in FP32, 0.69 against 1.01 ms in FP16 storage), but one for FP64,
+// whose two-sample kernel spills (300 x 256 x 128: 0.43 against 1.10 ms).
 int default_samples_per_lane(const yee_grid_desc& d) {
-  return (d.nx <= 4 * yee::kWave || d.precision == YEE_F32) ? 1 : 2;
+  return (d.nx <= 4 * yee::kWave || d.precision == YEE_F64) ? 1 : 2;
 }
 
 void default_launch(yee_ctx* c) {

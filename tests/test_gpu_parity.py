@@ -87,7 +87,8 @@ def test_plain_pec_box_fp64_full():
     ((37, 29, 23), (4, 3, 5), "ragged rows"),
     ((100, 21, 18), (6, 2, 0), "no z layer"),
     ((200, 12, 30), (10, 5, 7), "four waves per row"),
-    ((300, 9, 11), (6, 2, 3), "rows past 256: two samples per lane"),
+    ((300, 9, 11), (6, 2, 3), "rows past 256: one sample per lane, five waves per row"),
+    ((512, 6, 9), (6, 2, 3), "widest rows: eight waves per row, 16-wave workgroups"),
     ((2, 2, 2), (0, 0, 0), "smallest grid"),
 ])
 def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
@@ -102,14 +103,26 @@ def test_random_init_fp64_cpml(solver_cls, shape, cpml, v):
     _check_fields(s, sim, TOL["f64"])
 
 
+def test_fp64_two_samples_per_lane(solver_cls):
+    """FP64 with two samples per lane (not the automatic choice: chosen
+    explicitly), rows of 300 samples."""
+    wl = W.cpml_block_lattice(n=300, ny=9, nz=11, steps=8, precision="f64", cpml=0, nprobes=0, nfreq=0, block=4)
+    wl.cpml_cells = (6, 2, 3)
+    wl.cpml_kappa_max = 2.0
+    wl.cpml_alpha_max = 0.05
+    s, sim = _run_both(solver_cls, wl, 8, init_seed=13, samples_per_lane=2)
+    _check_fields(s, sim, TOL["f64"])
+
+
 @pytest.mark.parametrize("shape,ty,kz,vpl", [
     ((256, 40, 33), 0, 0, 0),
     ((256, 40, 33), 3, 5, 0),
     ((256, 21, 19), 7, 3, 4),   # four samples per lane, one wave per row
     ((300, 17, 26), 3, 4, 2),   # two samples per lane, ragged row (12 waves, the two-sample limit)
-    ((300, 17, 26), 0, 0, 0),   # automatic: one sample per lane, five waves per row
+    ((300, 17, 26), 0, 0, 0),   # automatic: two samples per lane, three waves per row
     ((160, 48, 48), 4, 16, 0),
-    ((512, 9, 12), 1, 1, 0),    # widest rows (automatic: eight waves), one plane per chunk
+    ((512, 9, 12), 1, 1, 0),    # widest rows (automatic: two samples per lane), one plane per chunk
+    ((512, 9, 12), 0, 0, 1),    # widest rows, one sample per lane: eight waves, 16-wave workgroups
     ((512, 9, 12), 1, 2, 2),    # widest rows, two samples per lane
     ((512, 9, 12), 0, 0, 4),    # four samples per lane: automatic rows within its 8-wave limit
 ])
