@@ -245,7 +245,12 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
     __shared__ uint4 lds_raw[kWaves * kTableWords / 4];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    int g = blockIdx.x;
+    // XCD-aware order: consecutive workgroup ids are dealt round-robin to the
+    // 8 XCDs, so give each XCD a contiguous run of (pair, pass, partition,
+    // chirp) blocks.  The pairs of one partition and chirp, which read the
+    // same ray geometry, then run side by side on one XCD and share its L2.
+    int g = (gridDim.x & 7) ? (int)blockIdx.x
+                            : (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3));
     const int q = g % a.n_pairs;
     g /= a.n_pairs;
     const int pass = g % a.n_passes;
