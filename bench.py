@@ -247,18 +247,14 @@ def adjoint_benchmark(checkpoint_every=64):
 FP32_MFMA_PEAK_TFLOPS = 157.3     # published MI355X dense FP32 matrix peak
 FP16_MFMA_PEAK_TFLOPS = 2500.0    # published MI355X dense fp16 matrix peak
 FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply-add, four real multiply-adds
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak
+SPREAD_FLOPS_PER_RAY_BLOCK = 8 * (2 * 10 + 4)   # per (ray, pair, chirp): 8 taps x (10 FMAs + 2 mul + 2 add)
 
 
-def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
-    """IF cube from ray meta data (Eqs. 1-7) on the full pedestrian scene:
-    2^20 rays, 8 meshes x 4096 triangles, 12 antenna pairs, 128 chirps x 512
-    samples; then the range-Doppler map of the cube (Eq. 4)."""
+def _time_cube(syn, ds, reps):
+    """Average milliseconds of one whole IF cube (all chirp batches) over
+    `reps` back-to-back calls on the current stream, after one untimed call."""
     import torch
-    from paper_2305_14176_amd import raymeta as RM
-    from paper_2305_14176_amd import rayscene as RS
-    sc = RS.pedestrian_scene()
-    ds = RM.DeviceScene(sc, device="cuda:0")
-    syn = RM.Synthesizer(ds)
     stream = torch.cuda.current_stream()
     syn.run(0, ds.amp)
     torch.cuda.synchronize()
@@ -269,24 +265,46 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
         syn.run(0, ds.amp)
     ev1.record(stream)
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / reps
+    return ev0.elapsed_time(ev1) / reps
+
+
+def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
+    """IF cube from ray meta data (Eqs. 1-7) on the full pedestrian scene:
+    2^20 rays, 8 meshes x 4096 triangles, 12 antenna pairs, 128 chirps x 512
+    samples, with the spreading method (rmd_if_cube) and the direct method
+    (rmd_if_cube_direct); then the range-Doppler map of the cube (Eq. 4)."""
+    import torch
+    from paper_2305_14176_amd import raymeta as RM
+    from paper_2305_14176_amd import rayscene as RS
+    sc = RS.pedestrian_scene()
+    ds = RM.DeviceScene(sc, device="cuda:0")
     r = sc.radar
     terms = sc.n_rays * sc.n_pairs * r.n_chirps * r.n_samples
+    ray_blocks = sc.n_rays * sc.n_pairs * r.n_chirps
+    syn = RM.Synthesizer(ds, method="spread")
+    ms = _time_cube(syn, ds, reps)
     spec = torch.empty_like(syn.out)
+    stream = torch.cuda.current_stream()
     RM.range_doppler(syn.out, out=spec)
     torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(20):
         RM.range_doppler(syn.out, out=spec)
     ev1.record(stream)
     torch.cuda.synchronize()
     rd_ms = ev0.elapsed_time(ev1) / 20
-    tflops = terms * FLOPS_PER_TERM / (ms / 1e3) / 1e12
+    syn_d = RM.Synthesizer(ds, method="direct")
+    ms_d = _time_cube(syn_d, ds, reps)
+    spread_tflops = ray_blocks * SPREAD_FLOPS_PER_RAY_BLOCK / (ms / 1e3) / 1e12
+    tflops_d = terms * FLOPS_PER_TERM / (ms_d / 1e3) / 1e12
     out = {
         "workload": f"{sc.name}: {sc.n_hits} hits, {sc.n_pairs} antenna pairs (3 TX x 4 RX), "
                     f"{r.n_chirps} chirps x {r.n_samples} samples, 77 GHz, B = 1 GHz, T_c = 51.2 us, f_s = 10 MHz",
-        "dtype": "f64 geometry and phases, f32 phasors split into fp16 hi/lo parts, products as "
-                 "hi*hi + hi*lo + lo*hi fp16 MFMAs with f32 accumulation, f64 partition sums",
+        "method": "spread: type-1 non-uniform FFT (8-cell exponential-of-semicircle kernel on a 1024-cell grid, "
+                  "FP32 spreading in LDS, FP64 partition sums, inverse DFT and deconvolution)",
+        "dtype": "f64 geometry and phases, f32 phasors, kernel values and grid sums, f64 transform",
         "metric": "IF terms/s (ray x antenna pair x chirp x sample)",
         "value": round(terms / (ms / 1e3), 1),
         "unit": "terms/s",
@@ -294,15 +312,28 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
         "cubes_per_s": round(1e3 / ms, 3),
         "reps": reps,
         "range_doppler_ms": round(rd_ms, 4),
-        "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(tflops / FP32_MFMA_PEAK_TFLOPS, 4),
-                     "peak_basis": "dense FP32 matrix peak: the result has FP32-class accuracy",
-                     "fp16_matrix_tflops": round(3 * tflops, 2),
-                     "fp16_matrix_frac": round(3 * tflops / FP16_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": None, "algorithmic_flops_per_launch": terms * FLOPS_PER_TERM,
-                     "kernel": "rmd::synth_kernel (timed with rmd::geometry_kernel and rmd::reduce_kernel: "
+        "roofline": {"bound": "alu", "achieved": round(spread_tflops, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(spread_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                     "peak_basis": "published FP32 vector peak (packed FMA); built without packed FP32, the issue "
+                                   "limit is half of it",
+                     "traffic": None, "algorithmic_flops_per_launch": ray_blocks * SPREAD_FLOPS_PER_RAY_BLOCK,
+                     "flops_counted": "per ray, pair and chirp: 8 taps x (10 Horner FMAs + 2 multiplies + 2 adds)",
+                     "kernel": "rmd::spread_kernel (timed with rmd::geometry_kernel and rmd::finish_kernel: "
                                "one IF cube)",
                      "kernel_ms_avg": round(ms, 3)},
+        "direct": {
+            "method": "direct: fp16 hi/lo split MFMA products (rmd_if_cube_direct)",
+            "value": round(terms / (ms_d / 1e3), 1), "unit": "terms/s", "ms_per_cube": round(ms_d, 3),
+            "roofline": {"bound": "mfma", "achieved": round(tflops_d, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops_d / FP32_MFMA_PEAK_TFLOPS, 4),
+                         "peak_basis": "dense FP32 matrix peak: the result has FP32-class accuracy",
+                         "fp16_matrix_tflops": round(3 * tflops_d, 2),
+                         "fp16_matrix_frac": round(3 * tflops_d / FP16_MFMA_PEAK_TFLOPS, 4),
+                         "traffic": None, "algorithmic_flops_per_launch": terms * FLOPS_PER_TERM,
+                         "kernel": "rmd::synth_kernel (timed with rmd::geometry_kernel and rmd::reduce_kernel: "
+                                   "one IF cube)",
+                         "kernel_ms_avg": round(ms_d, 3)}},
+        "spread_speedup_over_direct": round(ms_d / ms, 3),
     }
     if cpu:
         from oracle import raymeta as R

@@ -96,11 +96,14 @@ const char* rmd_last_error(void);
 rmd_status rmd_check_scene(const rmd_scene* scene, int32_t n_chirps, void* workspace,
                            int64_t* n_bad_rays, hipStream_t stream);
 
-/* Bytes of device workspace rmd_if_cube needs for these sizes.  Chirps are
- * processed in batches of up to 16 whose per-ray geometry (7 float64 per ray
- * and chirp: inner path length, first and last hit point) fits in 1 GiB; the
- * workspace holds one batch's geometry and its partition sums (complex64 per
- * ray partition, pair, chirp and sample). */
+/* Bytes of device workspace rmd_if_cube and rmd_if_cube_direct need for these
+ * sizes (one size serves both).  Chirps are processed in batches of up to 16
+ * whose per-ray geometry (7 float64 per ray and chirp: inner path length,
+ * first and last hit point) fits in 1 GiB; the workspace holds one batch's
+ * geometry and the batch's per-partition results (rmd_if_cube: a grid of M
+ * complex64 cells per ray partition, pair and chirp, M the smallest power of
+ * two >= max(64, 2 n_samples), plus n_samples float64; rmd_if_cube_direct:
+ * n_samples complex64 per ray partition, pair and chirp). */
 rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs,
                                int32_t chirp_count, int64_t* bytes);
 
@@ -114,13 +117,31 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
  *   chirps   [chirp0, chirp0 + chirp_count) of the scene's n_chirps.
  *   s        output [n_pairs][chirp_count][n_samples] complex64.
  *   workspace at least rmd_workspace_bytes(...) bytes, 256-byte aligned.
- * Phases are formed in float64 and reduced modulo one cycle; the phasors are
- * float32, split into fp16 high and low parts for the matrix products
- * (float32 accumulation, about 2^-21 relative); partition sums are added in
- * float64 in a fixed order, so repeated calls give identical results. */
+ * The sum over rays is evaluated as a type-1 non-uniform FFT: each ray's
+ * phasor (phase formed in float64 and reduced modulo one cycle) is spread
+ * onto a 2x-oversampled periodic grid with an 8-cell "exponential of
+ * semicircle" kernel, the grid is transformed and deconvolved in float64.
+ * The grid accumulates 64-bit fixed-point integers scaled by the largest
+ * |w_i| (each contribution rounded by at most 2^-30 max|w|), so its sums are
+ * exact and order-free, and partition grids are added in float64 in a fixed
+ * order: repeated calls give identical results.  The kernel's aliasing error
+ * is about 1e-7 relative; with the float32 phasors the result agrees with
+ * the exact sum to about 1e-6 (relative L2 per pair and chirp).  Weights must
+ * be finite. */
 rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
                        const float* weights, int32_t chirp0, int32_t chirp_count, float* s,
                        void* workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/* The same IF cube with the sum over rays evaluated term by term: the arguments,
+ * checks and output are those of rmd_if_cube.  Phases are formed in float64 and
+ * reduced modulo one cycle; the phasors are float32, split into fp16 high and
+ * low parts for the matrix products (float32 accumulation, about 2^-21
+ * relative); partition sums are added in float64 in a fixed order, so repeated
+ * calls give identical results.  Slower than rmd_if_cube; exact up to
+ * rounding. */
+rmd_status rmd_if_cube_direct(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs,
+                              const double* pairs, const float* weights, int32_t chirp0, int32_t chirp_count,
+                              float* s, void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
 /* Range-Doppler map, Eq. 4: S[q] = DFT_2d(s[q]) over (chirp, sample), the
  * forward unnormalised transform exp(-2 pi i k n / N) on both axes, without

@@ -4,12 +4,19 @@
 // Kernels:
 //   geometry_kernel Eq. 6 for every hit of a ray and the pair-independent
 //                  part of its path (FP64), once per ray and chirp.
-//   synth_kernel   Eqs. 7, 1, 2: per workgroup one antenna pair, one chirp and
-//                  one partition of the rays; the antenna legs and phases per
-//                  ray in FP64, then the sum over rays as float32 MFMA
-//                  products of phasor tiles (fast time factored into 32 rows
-//                  x 16 columns).
-//   reduce_kernel  sums the partitions' partial cubes in FP64, fixed order.
+//   spread_kernel  Eqs. 7, 1, 2 (rmd_if_cube): per workgroup one antenna pair,
+//                  one chirp and one partition of the rays; the antenna legs
+//                  and phases per ray in FP64, then each ray's phasor spread
+//                  onto an oversampled periodic grid in LDS (the sum over rays
+//                  as a type-1 non-uniform FFT).
+//   deconv_kernel  the spreading kernel's Fourier transform at the output
+//                  frequencies (FP64 quadrature), once per call.
+//   finish_kernel  per (pair, chirp): the partitions' grids summed in FP64,
+//                  their inverse DFT (FP64, LDS) and the deconvolved samples.
+//   synth_kernel   the same sum evaluated directly (rmd_if_cube_direct): float32
+//                  MFMA products of phasor tiles (fast time factored into 32
+//                  rows x 16 columns).
+//   reduce_kernel  sums synth_kernel's partition cubes in FP64, fixed order.
 //   fft_kernel     radix-2 FFT of lines held in LDS (Eq. 4, one axis a pass).
 //   span_kernel    Eq. 5 rule masks, one thread per ray.
 //   check_kernel   counts rays with out-of-range meta data.
@@ -52,6 +59,28 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr double kC0 = 299792458.0;
 
+// Spreading method.  The sum s[n] = sum_i c_i e^{2 pi i n theta_i}, n < N, is
+// a Fourier series at N integer frequencies with non-uniform positions
+// theta_i (cycles per sample, modulo 1).  With the centre index n_c = N / 2,
+//   s[n_c + m] = sum_i c'_i e^{2 pi i m theta_i},  c'_i = c_i e^{2 pi i n_c theta_i},
+// for m in [-N/2, N/2).  Each c'_i is spread onto a periodic grid of M >= 2N
+// cells around x_i = M theta_i with a kernel psi of kTaps cells; the grid's
+// inverse DFT G[m] = sum_l g[l] e^{2 pi i m l / M} then equals
+// psi_hat(m / M) s[n_c + m] up to the kernel's aliasing error, psi_hat being
+// the continuous Fourier transform of psi (Poisson summation).  psi is the
+// "exponential of semicircle" kernel e^{beta (sqrt(1 - z^2) - 1)}, z = 2 u /
+// kTaps for an offset of u cells (Barnett, Magland and af Klinteberg, SIAM J.
+// Sci. Comput. 41, 2019): at 2x oversampling and 8 cells its aliasing error
+// is about 1e-7 relative.  Kernel values are evaluated as one polynomial per
+// tap (degree kTapDeg, fitted on the host), which keeps their float32 error at
+// a few ulp; exp() of a float32 argument near -beta would lose about 1e-6.
+constexpr int kTaps = 8;
+constexpr int kTapDeg = 10;
+static_assert(kTapDeg % 2 == 0 && kTaps % 2 == 0, "taps come in mirrored pairs; even degree");
+constexpr double kBeta = 2.30 * kTaps;
+constexpr int kMinGridLog2 = 6;          // M >= 64
+constexpr int kQuad = 256;               // trapezoid intervals of the psi_hat quadrature
+
 struct SynthArgs {
     const int32_t* mesh_tri_off;
     const int32_t* tris;
@@ -71,6 +100,14 @@ struct SynthArgs {
     int32_t n_parts, rays_per_part, n_passes;
     double cyc_per_m;           // f_c / c: carrier cycles per metre of path (Eq. 1 into Eq. 2)
     double step_per_m;          // mu / (c f_s): beat cycles per sample per metre (Eqs. 1-3)
+    // spreading method: partial holds [n_parts][n_pairs][chirp_count][M] grids
+    const double* deconv;       // [n_samples]: 1 / psi_hat((n - center) / M)
+    const unsigned* wmax_bits;  // max_i |w_i| as float bits (1 when weights is NULL)
+    int32_t grid_log2, center;  // M = 2^grid_log2; center n_c = n_samples / 2
+    // Tap t < kTaps / 2 has the polynomial P_t(s) = E_t(s^2) + s O_t(s^2), s in
+    // [-1/2, 1/2); psi is even, so tap kTaps - 1 - t is P_t(-s) = E_t - s O_t.
+    float tap_even[kTaps / 2][kTapDeg / 2 + 1];   // E_t coefficients, constant term first
+    float tap_odd[kTaps / 2][kTapDeg / 2];        // O_t coefficients
 };
 
 __device__ inline double dist3(double ax, double ay, double az, double bx, double by, double bz) {
@@ -375,6 +412,178 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
     }
 }
 
+// Workgroup (pair q, partition p, chirp j) of the spreading method.  The
+// workgroup's grid of M complex cells sits in LDS as 64-bit fixed-point
+// integers (real parts, then imaginary parts) with the scale 2^e chosen from
+// the largest weight, 2^e max|w| in [2^29, 2^30): every contribution
+// w e^{2 pi i phi'} psi is cut to an int32 multiple of 2^-e (toward zero, error
+// below 2^-29 max|w|) and added with a 64-bit LDS integer atomic; a cell of a block
+// receives at most n_rays contributions, so no sum exceeds 2^60.  Integer
+// addition is exact and order-free, so all waves share one grid and the result
+// does not depend on scheduling (LDS float atomics would not be, and on this
+// chip they are several times slower than integer ones).
+//
+// Each wave takes the partition's rays 64 at a time, one ray per lane (the
+// same super-group order and geometry prefetch as synth_kernel): the lane forms
+// the ray's phases in FP64, its grid position x = M theta, the first cell
+// l0 = ceil(x - kTaps / 2) under the kernel and the offset
+// s = l0 - x + (kTaps - 1) / 2 in [-1/2, 1/2), evaluates the kTaps kernel
+// values by Horner's rule and adds the contributions into cells l0 .. l0 +
+// kTaps - 1 (modulo M).  At the end the grid is scaled back and written as
+// the partition's float32 grid.
+__global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
+    extern __shared__ unsigned long long gq[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int M = 1 << a.grid_log2;
+    // XCD-aware order as in synth_kernel: the pairs of one partition and chirp
+    // run side by side on one XCD.
+    int g = (gridDim.x & 7) ? (int)blockIdx.x
+                            : (int)((blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3));
+    const int q = g % a.n_pairs;
+    g /= a.n_pairs;
+    const int part = g % a.n_parts;
+    const int jj = g / a.n_parts;
+    const double* pq = a.pairs + 6 * q;
+    for (int i = threadIdx.x; i < 2 * M; i += kThreads) gq[i] = 0ull;
+    int e2;
+    frexpf(__uint_as_float(*a.wmax_bits), &e2);     // max|w| = m 2^e2, m in [1/2, 1)
+    const int qexp = 30 - e2;                       // 2^qexp max|w| in [2^29, 2^30)
+    __syncthreads();
+
+    const int r0 = part * a.rays_per_part;
+    const int r1 = min(a.n_rays, r0 + a.rays_per_part);
+    const double fM = (double)M;
+    Geo gn = load_geo(a, r0 + wave * kWave + lane, r1, jj);
+    for (int sbase = r0 + wave * kWave; sbase < r1; sbase += kThreads) {
+        const Phases own = ray_phases(a, gn, pq);
+        gn = load_geo(a, sbase + kThreads + lane, r1, jj);      // next super-group, in flight meanwhile
+        if (own.w != 0.0f) {
+            const double x = own.theta * fM;                   // grid position in [0, M)
+            const double l0 = ceil(x - 0.5 * kTaps);
+            const float sv = (float)((l0 - x) + 0.5 * (kTaps - 1));
+            float2 c = cis(frac1(own.phi + frac1((double)a.center * own.theta)));
+            const float ws = ldexpf(own.w, qexp);             // weight in grid units (exact)
+            c.x *= ws;
+            c.y *= ws;
+            // Kernel values, the mirrored taps t and kTaps - 1 - t from one
+            // Horner pass over the even and odd parts in s^2.
+            const float y = sv * sv;
+            float k[kTaps];
+#pragma unroll
+            for (int t = 0; t < kTaps / 2; ++t) {
+                float ev = a.tap_even[t][kTapDeg / 2];
+#pragma unroll
+                for (int d = kTapDeg / 2 - 1; d >= 0; --d) ev = fmaf(ev, y, a.tap_even[t][d]);
+                float od = a.tap_odd[t][kTapDeg / 2 - 1];
+#pragma unroll
+                for (int d = kTapDeg / 2 - 2; d >= 0; --d) od = fmaf(od, y, a.tap_odd[t][d]);
+                k[t] = fmaf(sv, od, ev);
+                k[kTaps - 1 - t] = fmaf(-sv, od, ev);
+            }
+            const int base = (int)l0;                          // in [-kTaps / 2, M - kTaps / 2]
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) {
+                const int idx = (base + t) & (M - 1);
+                // |k c| < 2^31 by the choice of qexp; conversion rounds toward zero
+                const long long vr = (int)(k[t] * c.x);
+                const long long vi = (int)(k[t] * c.y);
+                atomicAdd(gq + idx, (unsigned long long)vr);
+                atomicAdd(gq + M + idx, (unsigned long long)vi);
+            }
+        }
+    }
+    __syncthreads();
+    float2* out = a.partial + (((int64_t)part * a.n_pairs + q) * a.chirp_count + jj) * (int64_t)M;
+    for (int i = threadIdx.x; i < M; i += kThreads) {
+        const double re = ldexp((double)(long long)gq[i], -qexp);
+        const double im = ldexp((double)(long long)gq[M + i], -qexp);
+        out[i] = make_float2((float)re, (float)im);
+    }
+}
+
+// *bits = the float bits of max_i |w_i| (nonnegative floats order like their
+// bit patterns); *bits must be zero on entry.
+__global__ void wmax_kernel(const float* __restrict__ w, int n, unsigned* bits) {
+    unsigned m = 0u;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(fabsf(w[i])));
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(bits, m);
+}
+
+__global__ void set_u32_kernel(unsigned* p, unsigned v) { *p = v; }
+
+// deconv[n] = 1 / psi_hat((n - center) / M), psi_hat(xi) the integral of
+// psi(u) cos(2 pi xi u) over the kernel's support |u| <= kTaps / 2 (psi is
+// even), by the trapezoid rule with kQuad intervals in FP64 (psi falls to
+// e^{-beta} at the ends of its support, where the rule's error vanishes with
+// it).  One wave per n; the lanes' partial sums are combined in a fixed order.
+__global__ __launch_bounds__(kWave) void deconv_kernel(double* deconv, int n_samples, int center, int grid_log2) {
+    const int n = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double xi = (double)(n - center) / (double)(1 << grid_log2);
+    const double h = (double)kTaps / kQuad;
+    double acc = 0.0;
+    for (int i = lane; i <= kQuad; i += kWave) {
+        const double u = -0.5 * kTaps + i * h;
+        const double z = 2.0 * u / kTaps;
+        const double psi = exp(kBeta * (sqrt(fmax(0.0, 1.0 - z * z)) - 1.0));
+        acc += ((i == 0 || i == kQuad) ? 0.5 * h : h) * psi * cospi(2.0 * xi * u);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0 && n < n_samples) deconv[n] = 1.0 / acc;
+}
+
+// Workgroup (pair q, batch chirp j): the partitions' grids of the block summed
+// in FP64 in partition order, loaded bit-reversed; the inverse DFT
+// G[m] = sum_l g[l] e^{2 pi i m l / M} by radix-2 decimation in time in FP64
+// in LDS (twiddles from sincospi); then s[n] = G[(n - center) mod M] deconv[n]
+// rounded once to float32 and written into the cube at chirp c0 + j.
+__global__ __launch_bounds__(256) void finish_kernel(SynthArgs a, float2* __restrict__ s, int n_chirps_out, int c0) {
+    extern __shared__ double2 fl[];
+    const int logL = a.grid_log2, L = 1 << logL;
+    double2* tw = fl;                    // L / 2 twiddles e^{+2 pi i k / L}
+    double2* x = fl + L / 2;
+    const int q = blockIdx.x % a.n_pairs, jj = blockIdx.x / a.n_pairs;
+    for (int k = threadIdx.x; k < L / 2; k += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * k / L, &sn, &cs);
+        tw[k] = make_double2(cs, sn);
+    }
+    const int64_t stride = (int64_t)a.n_pairs * a.chirp_count * L;
+    const float2* src = a.partial + ((int64_t)q * a.chirp_count + jj) * L;
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int p = 0; p < a.n_parts; ++p) {
+            const float2 v = src[(int64_t)p * stride + l];
+            re += v.x;
+            im += v.y;
+        }
+        x[__brev((unsigned)l) >> (32 - logL)] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int st = 0; st < logL; ++st) {
+        const int half = 1 << st;
+        for (int k = threadIdx.x; k < L / 2; k += blockDim.x) {
+            const int pos = k & (half - 1);
+            const int i0 = ((k >> st) << (st + 1)) + pos, i1 = i0 + half;
+            const double2 w = tw[pos << (logL - 1 - st)];
+            const double2 u = x[i0], v = x[i1];
+            const double vr = v.x * w.x - v.y * w.y, vi = v.x * w.y + v.y * w.x;
+            x[i0] = make_double2(u.x + vr, u.y + vi);
+            x[i1] = make_double2(u.x - vr, u.y - vi);
+        }
+        __syncthreads();
+    }
+    float2* out = s + ((int64_t)q * n_chirps_out + c0 + jj) * a.n_samples;
+    for (int n = threadIdx.x; n < a.n_samples; n += blockDim.x) {
+        const double2 v = x[(n - a.center) & (L - 1)];
+        const double f = a.deconv[n];
+        out[n] = make_float2((float)(v.x * f), (float)(v.y * f));
+    }
+}
+
 __global__ void reduce_kernel(const float2* __restrict__ partial, float2* __restrict__ s, int n_pairs, int nb,
                               int n_samples, int n_parts, int n_chirps_out, int c0) {
     const int64_t count = (int64_t)n_pairs * nb * n_samples;
@@ -519,13 +728,24 @@ rmd_status check_scene_desc(const rmd_scene* sc) {
 // geometry (7 doubles per ray and chirp) fits in kGeoBudget bytes, at most
 // kMaxBatch chirps.  Within a batch the rays are split into partitions so that
 // the (pair, chirp, partition) workgroups fill the device several times over,
-// each wave keeping at least four 64-ray super-groups.
+// each wave keeping at least four 64-ray super-groups.  The workspace holds the
+// batch's geometry, then the partition results of either method (direct:
+// n_samples complex values per block; spreading: an M-cell grid per block and
+// the deconvolution table), so one size serves both entry points.
 constexpr int64_t kGeoBudget = int64_t(1) << 30;
 constexpr int kMaxBatch = 16;
 
+int grid_log2_for(int n_samples) {
+    int l = rmd::kMinGridLog2;
+    while ((1 << l) < 2 * n_samples) ++l;
+    return l;
+}
+
+int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
 struct Plan {
-    int batch, parts, rays_per_part;
-    int64_t geo_bytes, partial_bytes;
+    int batch, parts, rays_per_part, grid_log2;
+    int64_t geo_bytes, partial_bytes, grid_bytes, deconv_bytes, total_bytes;
 };
 
 Plan plan(int n_rays, int n_pairs, int chirp_count, int n_samples) {
@@ -541,9 +761,68 @@ Plan plan(int n_rays, int n_pairs, int chirp_count, int n_samples) {
     rpp = (rpp + rmd::kThreads - 1) / rmd::kThreads * rmd::kThreads;
     p.parts = (int)((n_rays + rpp - 1) / rpp);
     p.rays_per_part = (int)rpp;
-    p.geo_bytes = (per_chirp * p.batch + 255) / 256 * 256;
+    p.grid_log2 = grid_log2_for(n_samples);
+    p.geo_bytes = round256(per_chirp * p.batch);
     p.partial_bytes = (int64_t)p.parts * blocks * n_samples * (int64_t)sizeof(float2);
+    p.grid_bytes = round256((int64_t)p.parts * blocks * (int64_t(1) << p.grid_log2) * (int64_t)sizeof(float2));
+    p.deconv_bytes = round256((int64_t)n_samples * (int64_t)sizeof(double)) + 256;   // + the max-weight word
+    p.total_bytes = p.geo_bytes + std::max(p.partial_bytes, p.grid_bytes + p.deconv_bytes);
     return p;
+}
+
+// Monomial coefficients (in s in [-1/2, 1/2]) of the degree-kTapDeg
+// polynomials that interpolate the spreading kernel of taps t < kTaps / 2 at
+// the kTapDeg + 1 Chebyshev points of that interval (tap t sits u = s + 1/2 -
+// kTaps/2 + t cells from the ray; the nodes are symmetric, so the mirrored tap
+// kTaps - 1 - t is the same polynomial at -s), split into even and odd parts.
+// Solved once, in long double, by Gaussian elimination with partial pivoting.
+struct TapPoly {
+    float even[rmd::kTaps / 2][rmd::kTapDeg / 2 + 1];
+    float odd[rmd::kTaps / 2][rmd::kTapDeg / 2];
+};
+
+const TapPoly& tap_poly() {
+    static const TapPoly tp = [] {
+        TapPoly r{};
+        constexpr int n = rmd::kTapDeg + 1;
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int t = 0; t < rmd::kTaps / 2; ++t) {
+            long double A[n][n + 1];
+            for (int i = 0; i < n; ++i) {
+                const long double sn = 0.5L * cosl(pi * (i + 0.5L) / n);
+                const long double z = (sn + 0.5L - 0.5L * rmd::kTaps + t) * 2.0L / rmd::kTaps;
+                long double pw = 1.0L;
+                for (int j = 0; j < n; ++j) {
+                    A[i][j] = pw;
+                    pw *= sn;
+                }
+                A[i][n] = expl((long double)rmd::kBeta * (sqrtl(fmaxl(0.0L, 1.0L - z * z)) - 1.0L));
+            }
+            for (int col = 0; col < n; ++col) {
+                int piv = col;
+                for (int i = col + 1; i < n; ++i)
+                    if (fabsl(A[i][col]) > fabsl(A[piv][col])) piv = i;
+                for (int j = 0; j <= n; ++j) std::swap(A[col][j], A[piv][j]);
+                for (int i = col + 1; i < n; ++i) {
+                    const long double f = A[i][col] / A[col][col];
+                    for (int j = col; j <= n; ++j) A[i][j] -= f * A[col][j];
+                }
+            }
+            for (int i = n - 1; i >= 0; --i) {      // back substitution; x_j kept in A[j][n]
+                long double v = A[i][n];
+                for (int j = i + 1; j < n; ++j) v -= A[i][j] * A[j][n];
+                A[i][n] = v / A[i][i];
+            }
+            for (int j = 0; j < n; ++j) {
+                if (j % 2 == 0)
+                    r.even[t][j / 2] = (float)A[j][n];
+                else
+                    r.odd[t][j / 2] = (float)A[j][n];
+            }
+        }
+        return r;
+    }();
+    return tp;
 }
 
 rmd::SynthArgs synth_args(const rmd_scene* sc) {
@@ -568,7 +847,7 @@ rmd::SynthArgs synth_args(const rmd_scene* sc) {
 
 extern "C" {
 
-int32_t rmd_api_version(void) { return 1; }
+int32_t rmd_api_version(void) { return 2; }
 
 const char* rmd_last_error(void) { return g_err.c_str(); }
 
@@ -601,14 +880,19 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
     if (!radar || !bytes) return fail(RMD_EINVAL, "radar and bytes must not be NULL");
     if (n_pairs <= 0 || chirp_count <= 0 || radar->n_samples <= 0 || radar->n_samples > RMD_MAX_SAMPLES)
         return fail(RMD_EINVAL, "n_pairs, chirp_count must be positive; n_samples in [1, RMD_MAX_SAMPLES]");
-    const Plan p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
-    *bytes = p.geo_bytes + p.partial_bytes;
+    *bytes = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples).total_bytes;
     return RMD_OK;
 }
 
-rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
-                       const float* weights, int32_t chirp0, int32_t chirp_count, float* s, void* workspace,
-                       int64_t workspace_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by both IF entry points; fills the plan and the kernel
+// arguments common to both methods.
+rmd_status cube_setup(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
+                      const float* weights, int32_t chirp0, int32_t chirp_count, float* s, void* workspace,
+                      int64_t workspace_bytes, Plan& p, rmd::SynthArgs& a) {
     int64_t need = 0;
     rmd_status st = rmd_workspace_bytes(scene, radar, n_pairs, chirp_count, &need);
     if (st != RMD_OK) return st;
@@ -619,10 +903,10 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
         return fail(RMD_EINVAL, "chirp range outside [0, n_chirps)");
     if (!(radar->f_s > 0) || !(radar->t_chirp > 0) || !std::isfinite(radar->f_c) || !std::isfinite(radar->bandwidth))
         return fail(RMD_EINVAL, "radar parameters must be finite, f_s and t_chirp positive");
-    const Plan p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
+    p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
     if ((int64_t)n_pairs * p.batch * p.parts * 2 > INT32_MAX) return fail(RMD_EINVAL, "too many (pair, chirp) blocks");
 
-    rmd::SynthArgs a = synth_args(scene);
+    a = synth_args(scene);
     a.pairs = pairs;
     a.weights = weights;
     a.geo = static_cast<double*>(workspace);
@@ -635,9 +919,70 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     const double mu = radar->bandwidth / radar->t_chirp;               // Eq. 3
     a.cyc_per_m = radar->f_c / rmd::kC0;
     a.step_per_m = mu / (rmd::kC0 * radar->f_s);
-    // Chirp batches: geometry of the batch, then the synthesis and the
-    // partition sums of the batch (the partition count is the same for every
+    return RMD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
+                       const float* weights, int32_t chirp0, int32_t chirp_count, float* s, void* workspace,
+                       int64_t workspace_bytes, hipStream_t stream) {
+    Plan p;
+    rmd::SynthArgs a;
+    rmd_status st = cube_setup(scene, radar, n_pairs, pairs, weights, chirp0, chirp_count, s, workspace,
+                               workspace_bytes, p, a);
+    if (st != RMD_OK) return st;
+    const int M = 1 << p.grid_log2;
+    a.grid_log2 = p.grid_log2;
+    a.center = radar->n_samples / 2;
+    char* tail = static_cast<char*>(workspace) + p.geo_bytes + p.grid_bytes;
+    auto* wmax = reinterpret_cast<unsigned*>(tail);
+    auto* deconv = reinterpret_cast<double*>(tail + 256);
+    a.deconv = deconv;
+    a.wmax_bits = wmax;
+    std::memcpy(a.tap_even, tap_poly().even, sizeof(a.tap_even));
+    std::memcpy(a.tap_odd, tap_poly().odd, sizeof(a.tap_odd));
+    hipLaunchKernelGGL(rmd::deconv_kernel, dim3(radar->n_samples), dim3(rmd::kWave), 0, stream, deconv,
+                       radar->n_samples, a.center, a.grid_log2);
+    if (weights) {
+        hipLaunchKernelGGL(rmd::set_u32_kernel, dim3(1), dim3(1), 0, stream, wmax, 0u);
+        const int blocks = (int)std::min<int64_t>(1024, (scene->n_rays + 255) / 256);
+        hipLaunchKernelGGL(rmd::wmax_kernel, dim3(blocks), dim3(256), 0, stream, weights, scene->n_rays, wmax);
+    } else {
+        hipLaunchKernelGGL(rmd::set_u32_kernel, dim3(1), dim3(1), 0, stream, wmax, 0x3f800000u);   // 1.0f
+    }
+    const size_t spread_lds = (size_t)2 * M * sizeof(unsigned long long);
+    const size_t finish_lds = (size_t)(M / 2 + M) * sizeof(double2);
+    // Chirp batches: geometry of the batch, then the spreading and the
+    // transform of the batch (the partition count is the same for every
     // batch: a shorter last batch uses part of the buffers).
+    for (int c0 = 0; c0 < chirp_count; c0 += p.batch) {
+        const int nb = std::min(p.batch, chirp_count - c0);
+        a.chirp0 = chirp0 + c0;
+        a.chirp_count = nb;
+        hipLaunchKernelGGL(rmd::geometry_kernel, dim3((scene->n_rays + 255) / 256, nb), dim3(256), 0, stream, a);
+        const dim3 grid((unsigned)((int64_t)n_pairs * nb * p.parts));
+        hipLaunchKernelGGL(rmd::spread_kernel, grid, dim3(rmd::kThreads), spread_lds, stream, a);
+        hipLaunchKernelGGL(rmd::finish_kernel, dim3((unsigned)(n_pairs * nb)), dim3(256), finish_lds, stream, a,
+                           reinterpret_cast<float2*>(s), chirp_count, c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "IF cube launch");
+    }
+    return RMD_OK;
+}
+
+rmd_status rmd_if_cube_direct(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
+                              const float* weights, int32_t chirp0, int32_t chirp_count, float* s, void* workspace,
+                              int64_t workspace_bytes, hipStream_t stream) {
+    Plan p;
+    rmd::SynthArgs a;
+    rmd_status st = cube_setup(scene, radar, n_pairs, pairs, weights, chirp0, chirp_count, s, workspace,
+                               workspace_bytes, p, a);
+    if (st != RMD_OK) return st;
+    // Chirp batches: geometry of the batch, then the synthesis and the
+    // partition sums of the batch.
     for (int c0 = 0; c0 < chirp_count; c0 += p.batch) {
         const int nb = std::min(p.batch, chirp_count - c0);
         a.chirp0 = chirp0 + c0;

@@ -26,7 +26,10 @@ SPAN_ANY, SPAN_NONE, SPAN_ALL = 0, 1, 2
 
 # Every symbol include/raymeta.h declares (checked by the CPU test suite).
 EXPORTED = ("rmd_api_version", "rmd_last_error", "rmd_check_scene", "rmd_workspace_bytes", "rmd_if_cube",
-            "rmd_range_doppler", "rmd_span_weights")
+            "rmd_if_cube_direct", "rmd_range_doppler", "rmd_span_weights")
+# Evaluation of the sum over rays: "spread" (type-1 non-uniform FFT,
+# rmd_if_cube) or "direct" (term by term on the matrix cores, rmd_if_cube_direct).
+METHODS = {"spread": "rmd_if_cube", "direct": "rmd_if_cube_direct"}
 
 
 class Radar(C.Structure):
@@ -71,6 +74,8 @@ def load():
                                 C.c_int32),
         "rmd_if_cube": ([C.POINTER(Scene), C.POINTER(Radar), C.c_int32, P, P, C.c_int32, C.c_int32, P, P,
                          C.c_int64, P], C.c_int32),
+        "rmd_if_cube_direct": ([C.POINTER(Scene), C.POINTER(Radar), C.c_int32, P, P, C.c_int32, C.c_int32, P, P,
+                                C.c_int64, P], C.c_int32),
         "rmd_range_doppler": ([P, P, C.c_int32, C.c_int32, C.c_int32, P], C.c_int32),
         "rmd_span_weights": ([C.POINTER(Scene), P, C.POINTER(SpanRule), P, P, P], C.c_int32),
     }
@@ -181,8 +186,11 @@ class Synthesizer:
     """IF cubes of one device scene: owns the output and workspace buffers for
     a chirp-block size, so repeated calls allocate nothing."""
 
-    def __init__(self, ds: DeviceScene, chirp_count: Optional[int] = None, pairs=None):
+    def __init__(self, ds: DeviceScene, chirp_count: Optional[int] = None, pairs=None, method: str = "spread"):
         import torch
+        if method not in METHODS:
+            raise ValueError(f"method must be one of {sorted(METHODS)}")
+        self.fn = METHODS[method]
         self.ds = ds
         self.pairs = ds.pairs if pairs is None else torch.as_tensor(np.asarray(pairs, np.float64)).to(ds.device)
         if self.pairs.dim() != 2 or self.pairs.shape[1] != 6:
@@ -203,19 +211,20 @@ class Synthesizer:
         import torch
         wptr = None if weights is None else _device_array(weights, torch.float32, self.ds.scene.n_rays, "weights",
                                                           self.ds.device)
-        check(load().rmd_if_cube(C.byref(self.ds.desc), C.byref(self.radar), self.n_pairs,
-                                 C.c_void_p(self.pairs.data_ptr()), wptr, chirp0, self.chirp_count,
-                                 C.c_void_p(self.out.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
-                                 self.workspace.numel() * 8, _stream(stream)), "rmd_if_cube")
+        check(getattr(load(), self.fn)(C.byref(self.ds.desc), C.byref(self.radar), self.n_pairs,
+                                       C.c_void_p(self.pairs.data_ptr()), wptr, chirp0, self.chirp_count,
+                                       C.c_void_p(self.out.data_ptr()), C.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel() * 8, _stream(stream)), self.fn)
         return self.out
 
 
-def if_cube(ds: DeviceScene, weights=None, chirps: Optional[Sequence[int]] = None, stream=None):
+def if_cube(ds: DeviceScene, weights=None, chirps: Optional[Sequence[int]] = None, stream=None,
+            method: str = "spread"):
     """The IF cube (Eqs. 1, 2, 3, 6, 7) as a new complex64 tensor [pair][chirp][sample]."""
     j0, j1 = (0, ds.radar.n_chirps) if chirps is None else (chirps[0], chirps[-1] + 1)
     if weights is None:
         weights = ds.amp
-    syn = Synthesizer(ds, chirp_count=j1 - j0)
+    syn = Synthesizer(ds, chirp_count=j1 - j0, method=method)
     return syn.run(j0, weights, stream).clone()
 
 

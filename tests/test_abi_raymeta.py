@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     assert set(decl) == set(RM.EXPORTED), set(decl) ^ set(RM.EXPORTED)
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.rmd_api_version() == 1
+    assert lib.rmd_api_version() == 2
 
 
 def _fake_scene(n_rays=1 << 20, n_hits=None):
@@ -43,19 +43,32 @@ def _radar(**kw):
     return RM.radar_struct(r)
 
 
+def _r256(b):
+    return -(-b // 256) * 256
+
+
 def _plan(n_rays, n_pairs, chirps, n_samples):
     """The documented work plan: chirp batches of at most 16 whose per-ray
     geometry (7 doubles per ray and chirp) fits in 1 GiB; ray partitions so
     that about 8192 workgroups run per batch, each wave keeping >= 4 groups
-    of 64 rays (256-ray granules)."""
+    of 64 rays (256-ray granules); then room for either method's partition
+    results (direct: n_samples complex64 per block and partition; spreading:
+    an M-cell complex64 grid, M the power of two >= max(64, 2 n_samples),
+    then a 256-byte word for the largest weight and the n_samples float64
+    deconvolution table)."""
     batch = max(1, min(chirps, 16, (1 << 30) // (n_rays * 56)))
     blocks = n_pairs * batch
     np_ = max(1, min(-(-8192 // blocks), max(1, n_rays // 1024)))
     rpp = -(-n_rays // np_)
     rpp = -(-rpp // 256) * 256
     parts = -(-n_rays // rpp)
-    geo = -(-(n_rays * 56 * batch) // 256) * 256
-    return batch, parts, geo + parts * blocks * n_samples * 8
+    geo = _r256(n_rays * 56 * batch)
+    M = 64
+    while M < 2 * n_samples:
+        M *= 2
+    direct = parts * blocks * n_samples * 8
+    spread = _r256(parts * blocks * M * 8) + 256 + _r256(n_samples * 8)
+    return batch, parts, geo + max(direct, spread)
 
 
 def test_workspace_bytes_plan():
@@ -119,6 +132,26 @@ def test_if_cube_rejects_before_launch():
     assert lib.rmd_if_cube(C.byref(sc), C.byref(r0), 2, p, None, 0, 4, p, p, need.value, None) == -1
 
 
+@pytest.mark.parametrize("fn", ["rmd_if_cube", "rmd_if_cube_direct"])
+def test_both_methods_share_the_checks(fn):
+    """Both IF entry points reject the same arguments before any launch."""
+    lib = RM.load()
+    f = getattr(lib, fn)
+    sc = _fake_scene(n_rays=1000)
+    r = _radar(n_chirps=4)
+    need = C.c_int64()
+    assert lib.rmd_workspace_bytes(C.byref(sc), C.byref(r), 2, 4, C.byref(need)) == 0
+    p = C.c_void_p(4096)
+    assert f(C.byref(sc), C.byref(r), 2, p, None, 0, 4, p, p, need.value - 8, None) == -1
+    assert b"workspace" in lib.rmd_last_error()
+    assert f(C.byref(sc), C.byref(r), 2, p, None, 0, 4, p, C.c_void_p(4100), need.value, None) == -1
+    assert f(C.byref(sc), C.byref(r), 2, p, None, 2, 3, p, p, need.value, None) == -1
+    assert f(C.byref(sc), C.byref(r), 2, None, None, 0, 4, p, p, need.value, None) == -1
+    assert f(C.byref(sc), C.byref(_radar(n_chirps=4, t_chirp=-1.0)), 2, p, None, 0, 4, p, p, need.value,
+             None) == -1
+    assert f(C.byref(_fake_scene(n_rays=0)), C.byref(r), 2, p, None, 0, 4, p, p, need.value, None) == -1
+
+
 @pytest.mark.parametrize("nc,ns,ok", [(128, 512, True), (96, 512, False), (128, 500, False), (1, 8, True),
                                       (8192, 8, False), (0, 8, False)])
 def test_range_doppler_size_rules(nc, ns, ok):
@@ -172,6 +205,8 @@ def test_binding_validates_before_the_library():
     ds = RM.DeviceScene(sc, device="cpu")
     with pytest.raises(ValueError, match="pairs"):
         RM.Synthesizer(ds, pairs=np.zeros((3, 5)))
+    with pytest.raises(ValueError, match="method"):
+        RM.Synthesizer(ds, method="fft")
     syn = RM.Synthesizer(ds)
     for w in (torch.ones(49), torch.ones(50, dtype=torch.float64), torch.ones(100)[::2]):
         with pytest.raises(ValueError, match="weights"):

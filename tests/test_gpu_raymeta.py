@@ -1,15 +1,21 @@
 """GPU parity of the ray-meta-data IF path (through the C ABI of
 libraymeta) against the FP64 oracle on the same seeded inputs.
 
+Both evaluations of the sum over rays are checked: "spread" (rmd_if_cube, a
+type-1 non-uniform FFT) and "direct" (rmd_if_cube_direct, term by term).
+
 Tolerances:
   * IF cube (Eqs. 1-3, 6, 7): relative L2 <= 1e-5 per (pair, chirp) block
-    against the FP64 oracle.  The kernel forms each ray's phase in FP64,
-    reduces it modulo one cycle, and runs an FP32 phasor recurrence over runs
-    of 8 samples: per-term errors of a few 1e-7 rad, far inside the gate.
+    against the FP64 oracle.  Both methods form each ray's phase in FP64 and
+    reduce it modulo one cycle; the direct method runs FP32 phasor recurrences
+    (per-term errors of a few 1e-7 rad), the spreading method adds the
+    kernel's aliasing error (about 1e-7) and its fixed-point rounding (at
+    most 2^-30 of the largest weight per contribution): about 1e-6.
   * Range-Doppler (Eq. 4): relative L2 <= 1e-5 against numpy's FP64 FFT of
     the same (GPU) input: FP32 radix-2 rounding grows like log2(N) eps.
   * Span masks (Eq. 5): bit-exact (0/1 times the float32 pattern weight).
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -20,6 +26,7 @@ from paper_2305_14176_amd import rayscene as S
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
+METHODS = ["spread", "direct"]
 
 
 def _say(msg):
@@ -47,6 +54,7 @@ def _cube(RM, sc, **kw):
     return ds, RM.if_cube(ds, **kw).cpu().numpy()
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("n_rays,n_samples,n_chirps,amp", [
     (4096, 256, 6, False),
     (1000, 512, 3, True),        # ragged ray count (not a multiple of 64 or 256)
@@ -54,42 +62,46 @@ def _cube(RM, sc, **kw):
     (2048, 1000, 2, False),      # two 512-sample passes per wave, the second ragged
     (1, 64, 2, False),           # a single ray
 ])
-def test_if_cube_small(RM, n_rays, n_samples, n_chirps, amp):
+def test_if_cube_small(RM, n_rays, n_samples, n_chirps, amp, method):
     sc = S.small_scene(n_rays=n_rays, n_chirps=n_chirps, n_samples=n_samples)
     if amp:
         sc.amp = S.random_amplitudes(sc, 5)
-    _say(f"[gpu] raymeta if_cube rays={n_rays} samples={n_samples} chirps={n_chirps} pairs={sc.n_pairs}")
-    ds, got = _cube(RM, sc)
+    _say(f"[gpu] raymeta if_cube {method} rays={n_rays} samples={n_samples} chirps={n_chirps} pairs={sc.n_pairs}")
+    ds, got = _cube(RM, sc, method=method)
     ref = R.if_cube(sc)
     err = _blocks_rel(got, ref)
     _say(f"[gpu]   worst block rel L2 {err.max():.2e}")
     assert err.max() <= TOL, err.max()
 
 
-def test_if_cube_max_samples_and_chirp_window(RM):
-    """RMD_MAX_SAMPLES samples; a chirp window [2, 5) of a 6-chirp scene."""
+@pytest.mark.parametrize("method", METHODS)
+def test_if_cube_max_samples_and_chirp_window(RM, method):
+    """RMD_MAX_SAMPLES samples (spreading: the largest grid, 2048 cells); a
+    chirp window [2, 5) of a 6-chirp scene."""
     sc = S.small_scene(n_rays=600, n_chirps=6, n_samples=RM.MAX_SAMPLES)
-    _say("[gpu] raymeta max samples, chirp window")
+    _say(f"[gpu] raymeta {method} max samples, chirp window")
     ds = RM.DeviceScene(sc)
-    got = RM.if_cube(ds, chirps=[2, 3, 4]).cpu().numpy()
+    got = RM.if_cube(ds, chirps=[2, 3, 4], method=method).cpu().numpy()
     ref = R.if_cube(sc, chirps=[2, 3, 4])
     assert _blocks_rel(got, ref).max() <= TOL
 
 
-def test_if_cube_several_chirp_batches(RM):
+@pytest.mark.parametrize("method", METHODS)
+def test_if_cube_several_chirp_batches(RM, method):
     """40 chirps run as geometry batches of 16, 16 and 8 chirps, each with its
     own partition sums, written into one cube; and a window starting mid-batch."""
     sc = S.small_scene(n_rays=300, n_chirps=40, n_samples=64)
-    _say("[gpu] raymeta 40 chirps (three batches)")
+    _say(f"[gpu] raymeta {method} 40 chirps (three batches)")
     ds = RM.DeviceScene(sc)
-    got = RM.if_cube(ds).cpu().numpy()
+    got = RM.if_cube(ds, method=method).cpu().numpy()
     ref = R.if_cube(sc)
     assert _blocks_rel(got, ref).max() <= TOL
-    got = RM.if_cube(ds, chirps=list(range(5, 38))).cpu().numpy()
+    got = RM.if_cube(ds, chirps=list(range(5, 38)), method=method).cpu().numpy()
     assert _blocks_rel(got, ref[:, 5:38]).max() <= TOL
 
 
-def test_bad_and_empty_rays_contribute_nothing(RM):
+@pytest.mark.parametrize("method", METHODS)
+def test_bad_and_empty_rays_contribute_nothing(RM, method):
     """Rays with no hits or with out-of-range meta data add nothing (the
     kernel checks every index before using it); rmd_check_scene counts them."""
     sc = S.small_scene(n_rays=300, n_chirps=2, n_samples=128)
@@ -107,10 +119,10 @@ def test_bad_and_empty_rays_contribute_nothing(RM):
     bad.tris[t9, 1] = bad.n_verts + 5
     bad.hit_mesh[bad.ray_off[7]] = 99
     bad.hit_tri[bad.ray_off[8]] = 1 << 20
-    _say("[gpu] raymeta bad meta data")
+    _say(f"[gpu] raymeta {method} bad meta data")
     ds = RM.DeviceScene(bad)
     assert RM.check_scene(ds) == len({7, 8} | owners)
-    got = RM.if_cube(ds).cpu().numpy()
+    got = RM.if_cube(ds, method=method).cpu().numpy()
     ref_kept = R.if_cube(sc, span=None) - sum(
         R.if_cube(_one_ray(sc, i)) for i in [7, 8] + sorted(owners))
     assert _blocks_rel(got, ref_kept).max() <= TOL
@@ -119,7 +131,7 @@ def test_bad_and_empty_rays_contribute_nothing(RM):
     sc2 = S.small_scene(n_rays=300, n_chirps=2, n_samples=128)
     sc2.ray_off = np.insert(sc2.ray_off, 5, sc2.ray_off[5]).astype(np.int32)
     sc2.amp = np.ones(301, np.float32)
-    got2 = RM.if_cube(RM.DeviceScene(sc2)).cpu().numpy()
+    got2 = RM.if_cube(RM.DeviceScene(sc2), method=method).cpu().numpy()
     assert _blocks_rel(got2, ref).max() <= TOL
 
 
@@ -171,16 +183,17 @@ def test_span_weights_exact(RM, rule):
     np.testing.assert_array_equal(got, ref)
 
 
-def test_span_decomposition_sums_to_whole(RM):
+@pytest.mark.parametrize("method", METHODS)
+def test_span_decomposition_sums_to_whole(RM, method):
     """Eq. 5 on the GPU: the IF of complementary spans adds up to the whole,
     and each span matches the oracle's span signal."""
     sc = S.small_scene(n_rays=2500, n_chirps=3, n_samples=256)
     ds = RM.DeviceScene(sc)
-    whole = RM.if_cube(ds).cpu().numpy()
+    whole = RM.if_cube(ds, method=method).cpu().numpy()
     parts = []
     for mode in (R.SPAN_ANY, R.SPAN_NONE):
         w = RM.span_weights(ds, meshes=[1], mode=mode)
-        parts.append(RM.if_cube(ds, weights=w).cpu().numpy())
+        parts.append(RM.if_cube(ds, weights=w, method=method).cpu().numpy())
         ref = R.if_cube(sc, span=dict(meshes=[1], mode=mode))
         assert _blocks_rel(parts[-1], ref).max() <= TOL
     assert _blocks_rel(parts[0] + parts[1], whole).max() <= 2 * TOL
@@ -190,30 +203,33 @@ def test_span_decomposition_sums_to_whole(RM):
 def test_full_size_sampled(RM):
     """The full scene (8 meshes x 4096 triangles, 2^20 rays, 12 antenna pairs,
     128 chirps x 512 samples) built exactly as the benchmark builds it (all
-    chirps: 16-chirp geometry batches, 43 ray partitions), against the oracle
-    at 16 sampled fast-time indices of every pair on chirps 0, 77 and 127."""
+    chirps: 16-chirp geometry batches, 43 ray partitions), with both methods,
+    against the oracle at 16 sampled fast-time indices of every pair on
+    chirps 0, 77 and 127."""
     sc = S.pedestrian_scene()
     _say(f"[gpu] raymeta full size: {sc.n_rays} rays, {sc.n_hits} hits, {sc.n_pairs} pairs, "
          f"{sc.radar.n_chirps} chirps")
     ds = RM.DeviceScene(sc)
-    syn = RM.Synthesizer(ds)
-    got = syn.run(0, ds.amp).cpu().numpy()
     sel = [0, 1, 7, 8, 63, 64, 100, 255, 256, 300, 383, 448, 500, 509, 510, 511]
     chirps = [0, 77, 127]
     ref = R.if_cube(sc, chirps=chirps, samples=sel)
-    err = _blocks_rel(got[:, chirps][:, :, sel], ref)
-    _say(f"[gpu]   worst sampled block rel L2 {err.max():.2e}")
-    assert err.max() <= TOL
+    for method in METHODS:
+        got = RM.Synthesizer(ds, method=method).run(0, ds.amp).cpu().numpy()
+        err = _blocks_rel(got[:, chirps][:, :, sel], ref)
+        _say(f"[gpu]   {method}: worst sampled block rel L2 {err.max():.2e}")
+        assert err.max() <= TOL, method
 
 
-def test_if_cube_bitwise_reproducible_and_null_weights(RM):
-    """Partition sums and wave combination run in a fixed order, so two runs
-    agree bit for bit; NULL weights mean w = 1 for every ray."""
+@pytest.mark.parametrize("method", METHODS)
+def test_if_cube_bitwise_reproducible_and_null_weights(RM, method):
+    """Partition sums and wave combination run in a fixed order (the spreading
+    grid adds integers, exact in any order), so two runs agree bit for bit;
+    NULL weights mean w = 1 for every ray."""
     import torch
     sc = S.small_scene(n_rays=5000, n_chirps=4, n_samples=512)
     sc.amp = None
     ds = RM.DeviceScene(sc)
-    syn = RM.Synthesizer(ds)
+    syn = RM.Synthesizer(ds, method=method)
     a = syn.run(0, None).clone()
     b = syn.run(0, None).clone()
     assert torch.equal(a, b)
@@ -221,3 +237,60 @@ def test_if_cube_bitwise_reproducible_and_null_weights(RM):
     c = syn.run(0, ones).clone()
     assert torch.equal(a, c)
     assert _blocks_rel(a.cpu().numpy(), R.if_cube(sc)).max() <= TOL
+
+
+@pytest.mark.parametrize("n_samples,f_s", [(301, 0.2e6), (1, 10e6), (2, 0.1e6), (1023, 0.2e6), (64, 0.05e6)])
+def test_spread_grid_wrap_and_odd_lengths(RM, n_samples, f_s):
+    """Spreading method: a low sampling rate makes theta (beat cycles per
+    sample) run over several cycles, so rays sit anywhere on the periodic grid
+    and kernels straddle its wrap-around; odd and tiny sample counts move the
+    centre index and use the smallest grid (64 cells)."""
+    sc = S.small_scene(n_rays=1500, n_chirps=2, n_samples=n_samples)
+    sc.radar = dataclasses.replace(sc.radar, f_s=f_s)
+    sc.amp = S.random_amplitudes(sc, 3)
+    p = R.hit_positions(sc.verts[1], sc.tris, sc.mesh_tri_off, sc.hit_mesh, sc.hit_tri, sc.hit_u, sc.hit_v)
+    d, pf, pl = R.path_lengths(p, sc.ray_off, sc.x_tx, sc.x_rx)
+    theta = np.mod(R.slope(sc.radar) * R.delays(d) / sc.radar.f_s, 1.0)
+    if f_s < 5e6:
+        assert np.any(theta < 0.01) and np.any(theta > 0.99), "the case must put rays next to the wrap"
+    _say(f"[gpu] raymeta spread wrap n_samples={n_samples} f_s={f_s}")
+    got = RM.if_cube(RM.DeviceScene(sc), method="spread").cpu().numpy()
+    ref = R.if_cube(sc)
+    err = _blocks_rel(got, ref)
+    _say(f"[gpu]   worst block rel L2 {err.max():.2e}")
+    assert err.max() <= TOL
+
+
+def test_methods_agree_on_the_full_cube_shape(RM):
+    """Both methods on one 8192-ray scene with the full fast-time and pair
+    layout (512 samples, 12 pairs): every sample of every block, spread
+    against direct, well inside the sum of their tolerances."""
+    sc = S.pedestrian_scene(n_rays=8192, radar=S.Radar(n_chirps=3))
+    ds = RM.DeviceScene(sc)
+    a = RM.if_cube(ds, method="spread").cpu().numpy()
+    b = RM.if_cube(ds, method="direct").cpu().numpy()
+    assert _blocks_rel(a, b).max() <= TOL
+
+
+def test_spread_weight_scale(RM):
+    """Spreading method: the fixed-point scale follows the largest |w|, so
+    tiny and huge weights (1e-30, 1e30 times the pattern) and a single
+    dominant ray keep the same relative accuracy; all-zero weights give an
+    all-zero cube."""
+    import torch
+    sc = S.small_scene(n_rays=3000, n_chirps=2, n_samples=256)
+    amp = S.random_amplitudes(sc, 9).astype(np.float64)
+    ds = RM.DeviceScene(sc)
+    syn = RM.Synthesizer(ds, method="spread")
+    for f in (1e-30, 1e30):
+        sc.amp = (amp * f).astype(np.float32)
+        ref = R.if_cube(sc)
+        got = syn.run(0, torch.from_numpy(sc.amp).to(ds.device)).cpu().numpy()
+        assert _blocks_rel(got, ref).max() <= TOL, f
+    w = amp.copy()
+    w[17] = 1e4                                   # one ray 10^4 times the rest
+    sc.amp = w.astype(np.float32)
+    got = syn.run(0, torch.from_numpy(sc.amp).to(ds.device)).cpu().numpy()
+    assert _blocks_rel(got, R.if_cube(sc)).max() <= TOL
+    z = syn.run(0, torch.zeros(sc.n_rays, dtype=torch.float32, device=ds.device))
+    assert not torch.any(z != 0)
