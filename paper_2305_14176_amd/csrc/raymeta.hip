@@ -445,7 +445,11 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
     const int part = g % a.n_parts;
     const int jj = g / a.n_parts;
     const double* pq = a.pairs + 6 * q;
-    for (int i = threadIdx.x; i < 2 * M; i += kThreads) gq[i] = 0ull;
+    // Each plane has kTaps cells of padding: padded cell i holds grid cell
+    // (i - kTaps / 2) mod M, so a ray's taps are one address plus constant
+    // offsets; the wrapped cells are folded back when the grid is written.
+    const int P = M + kTaps;
+    for (int i = threadIdx.x; i < 2 * P; i += kThreads) gq[i] = 0ull;
     int e2;
     frexpf(__uint_as_float(*a.wmax_bits), &e2);     // max|w| = m 2^e2, m in [1/2, 1)
     const int qexp = 30 - e2;                       // 2^qexp max|w| in [2^29, 2^30)
@@ -481,24 +485,36 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
                 k[t] = fmaf(sv, od, ev);
                 k[kTaps - 1 - t] = fmaf(-sv, od, ev);
             }
-            const int base = (int)l0;                          // in [-kTaps / 2, M - kTaps / 2]
+            // l0 is in [-kTaps / 2, M - kTaps / 2] for every finite theta in
+            // [0, 1) (the clamp only guards non-finite pair coordinates), so
+            // the taps' padded cells l0 + kTaps / 2 + t lie in [0, M + kTaps).
+            const int base = min(max((int)l0, -kTaps / 2), M - kTaps / 2);
+            unsigned long long* cr = gq + (base + kTaps / 2);
+            unsigned long long* ci = cr + P;
 #pragma unroll
             for (int t = 0; t < kTaps; ++t) {
-                const int idx = (base + t) & (M - 1);
                 // |k c| < 2^31 by the choice of qexp; conversion rounds toward zero
                 const long long vr = (int)(k[t] * c.x);
                 const long long vi = (int)(k[t] * c.y);
-                atomicAdd(gq + idx, (unsigned long long)vr);
-                atomicAdd(gq + M + idx, (unsigned long long)vi);
+                atomicAdd(cr + t, (unsigned long long)vr);
+                atomicAdd(ci + t, (unsigned long long)vi);
             }
         }
     }
     __syncthreads();
     float2* out = a.partial + (((int64_t)part * a.n_pairs + q) * a.chirp_count + jj) * (int64_t)M;
     for (int i = threadIdx.x; i < M; i += kThreads) {
-        const double re = ldexp((double)(long long)gq[i], -qexp);
-        const double im = ldexp((double)(long long)gq[M + i], -qexp);
-        out[i] = make_float2((float)re, (float)im);
+        const int h = i + kTaps / 2;                        // padded cell of grid cell i
+        long long re = (long long)gq[h], im = (long long)gq[P + h];
+        if (i < kTaps / 2) {                                // wrapped past the end
+            re += (long long)gq[h + M];
+            im += (long long)gq[P + h + M];
+        }
+        if (i >= M - kTaps / 2) {                           // wrapped below the start
+            re += (long long)gq[h - M];
+            im += (long long)gq[P + h - M];
+        }
+        out[i] = make_float2((float)ldexp((double)re, -qexp), (float)ldexp((double)im, -qexp));
     }
 }
 
@@ -953,7 +969,7 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     } else {
         hipLaunchKernelGGL(rmd::set_u32_kernel, dim3(1), dim3(1), 0, stream, wmax, 0x3f800000u);   // 1.0f
     }
-    const size_t spread_lds = (size_t)2 * M * sizeof(unsigned long long);
+    const size_t spread_lds = (size_t)2 * (M + rmd::kTaps) * sizeof(unsigned long long);
     const size_t finish_lds = (size_t)(M / 2 + M) * sizeof(double2);
     // Chirp batches: geometry of the batch, then the spreading and the
     // transform of the batch (the partition count is the same for every
