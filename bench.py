@@ -248,7 +248,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3     # published MI355X dense FP32 matrix peak
 FP16_MFMA_PEAK_TFLOPS = 2500.0    # published MI355X dense fp16 matrix peak
 FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply-add, four real multiply-adds
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak
-SPREAD_FLOPS_PER_RAY_BLOCK = 8 * (2 * 10 + 4)   # per (ray, pair, chirp): 8 taps x (10 FMAs + 2 mul + 2 add)
+SPREAD_FLOPS_PER_RAY_BLOCK = 2 * 44 + 16 + 16   # per (ray, pair, chirp): 44 FMAs (8 taps), 16 mul, 16 grid adds
 
 
 def _time_cube(syn, ds, reps):
@@ -303,8 +303,9 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
         "workload": f"{sc.name}: {sc.n_hits} hits, {sc.n_pairs} antenna pairs (3 TX x 4 RX), "
                     f"{r.n_chirps} chirps x {r.n_samples} samples, 77 GHz, B = 1 GHz, T_c = 51.2 us, f_s = 10 MHz",
         "method": "spread: type-1 non-uniform FFT (8-cell exponential-of-semicircle kernel on a 1024-cell grid, "
-                  "FP32 spreading in LDS, FP64 partition sums, inverse DFT and deconvolution)",
-        "dtype": "f64 geometry and phases, f32 phasors, kernel values and grid sums, f64 transform",
+                  "64-bit fixed-point spreading with integer LDS atomics, FP64 partition sums, inverse DFT and "
+                  "deconvolution)",
+        "dtype": "f64 geometry and phases, f32 phasors and kernel values, i64 grid sums, f64 transform",
         "metric": "IF terms/s (ray x antenna pair x chirp x sample)",
         "value": round(terms / (ms / 1e3), 1),
         "unit": "terms/s",
@@ -317,7 +318,8 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
                      "peak_basis": "published FP32 vector peak (packed FMA); built without packed FP32, the issue "
                                    "limit is half of it",
                      "traffic": None, "algorithmic_flops_per_launch": ray_blocks * SPREAD_FLOPS_PER_RAY_BLOCK,
-                     "flops_counted": "per ray, pair and chirp: 8 taps x (10 Horner FMAs + 2 multiplies + 2 adds)",
+                     "flops_counted": "per ray, pair and chirp: 8 kernel values (44 FMAs), 16 multiplies, 16 grid "
+                                      "additions; the FP64 antenna legs, conversions and atomics are not counted",
                      "kernel": "rmd::spread_kernel (timed with rmd::geometry_kernel and rmd::finish_kernel: "
                                "one IF cube)",
                      "kernel_ms_avg": round(ms, 3)},
