@@ -79,6 +79,7 @@ constexpr int kTapDeg = 10;
 static_assert(kTapDeg % 2 == 0 && kTaps % 2 == 0, "taps come in mirrored pairs; even degree");
 constexpr double kBeta = 2.30 * kTaps;
 constexpr int kMinGridLog2 = 6;          // M >= 64
+constexpr int kGridCopies = 2;           // spreading grids per workgroup (lanes split by parity)
 constexpr int kQuad = 256;               // trapezoid intervals of the psi_hat quadrature
 
 struct SynthArgs {
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void synth_kernel(SynthArgs a) {
 // w e^{2 pi i phi'} psi is cut to an int32 multiple of 2^-e (toward zero, error
 // below 2^-29 max|w|) and added with a 64-bit LDS integer atomic; a cell of a block
 // receives at most n_rays contributions, so no sum exceeds 2^60.  Integer
-// addition is exact and order-free, so all waves share one grid and the result
+// addition is exact and order-free, so all waves share the grid and the result
 // does not depend on scheduling (LDS float atomics would not be, and on this
 // chip they are several times slower than integer ones).
 //
@@ -448,8 +449,13 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
     // Each plane has kTaps cells of padding: padded cell i holds grid cell
     // (i - kTaps / 2) mod M, so a ray's taps are one address plus constant
     // offsets; the wrapped cells are folded back when the grid is written.
+    // Even and odd lanes add into separate copies of the grid (2P + 1 cells
+    // apart, so equal cells of the two copies sit in different banks): rays
+    // of one target share cells, and two copies halve the lanes of one
+    // atomic instruction that can meet on the same address.
     const int P = M + kTaps;
-    for (int i = threadIdx.x; i < 2 * P; i += kThreads) gq[i] = 0ull;
+    const int CS = 2 * P + 1;
+    for (int i = threadIdx.x; i < kGridCopies * CS; i += kThreads) gq[i] = 0ull;
     int e2;
     frexpf(__uint_as_float(*a.wmax_bits), &e2);     // max|w| = m 2^e2, m in [1/2, 1)
     const int qexp = 30 - e2;                       // 2^qexp max|w| in [2^29, 2^30)
@@ -489,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
             // [0, 1) (the clamp only guards non-finite pair coordinates), so
             // the taps' padded cells l0 + kTaps / 2 + t lie in [0, M + kTaps).
             const int base = min(max((int)l0, -kTaps / 2), M - kTaps / 2);
-            unsigned long long* cr = gq + (base + kTaps / 2);
+            unsigned long long* cr = gq + (lane & (kGridCopies - 1)) * CS + (base + kTaps / 2);
             unsigned long long* ci = cr + P;
 #pragma unroll
             for (int t = 0; t < kTaps; ++t) {
@@ -505,14 +511,20 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
     float2* out = a.partial + (((int64_t)part * a.n_pairs + q) * a.chirp_count + jj) * (int64_t)M;
     for (int i = threadIdx.x; i < M; i += kThreads) {
         const int h = i + kTaps / 2;                        // padded cell of grid cell i
-        long long re = (long long)gq[h], im = (long long)gq[P + h];
-        if (i < kTaps / 2) {                                // wrapped past the end
-            re += (long long)gq[h + M];
-            im += (long long)gq[P + h + M];
-        }
-        if (i >= M - kTaps / 2) {                           // wrapped below the start
-            re += (long long)gq[h - M];
-            im += (long long)gq[P + h - M];
+        long long re = 0, im = 0;
+#pragma unroll
+        for (int cp = 0; cp < kGridCopies; ++cp) {
+            const unsigned long long* g0 = gq + cp * CS;
+            re += (long long)g0[h];
+            im += (long long)g0[P + h];
+            if (i < kTaps / 2) {                            // wrapped past the end
+                re += (long long)g0[h + M];
+                im += (long long)g0[P + h + M];
+            }
+            if (i >= M - kTaps / 2) {                       // wrapped below the start
+                re += (long long)g0[h - M];
+                im += (long long)g0[P + h - M];
+            }
         }
         out[i] = make_float2((float)ldexp((double)re, -qexp), (float)ldexp((double)im, -qexp));
     }
@@ -969,7 +981,8 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     } else {
         hipLaunchKernelGGL(rmd::set_u32_kernel, dim3(1), dim3(1), 0, stream, wmax, 0x3f800000u);   // 1.0f
     }
-    const size_t spread_lds = (size_t)2 * (M + rmd::kTaps) * sizeof(unsigned long long);
+    const size_t spread_lds =
+        (size_t)rmd::kGridCopies * (2 * (M + rmd::kTaps) + 1) * sizeof(unsigned long long);
     const size_t finish_lds = (size_t)(M / 2 + M) * sizeof(double2);
     // Chirp batches: geometry of the batch, then the spreading and the
     // transform of the batch (the partition count is the same for every
