@@ -94,6 +94,8 @@ struct SynthArgs {
     const double* pairs;
     const float* weights;
     double* geo;                // [7][chirp_count][n_rays]: inner path, first hit xyz, last hit xyz
+    int4* hit_rec;              // [n_hits]: vertex indices i1, i2, i3 and the bits of u (i1 < 0: bad hit)
+    float* hit_rec_v;           // [n_hits]: v
     float2* partial;            // [n_parts][n_pairs][chirp_count][n_samples]
     int64_t n_hits;
     int32_t n_meshes, n_tris, n_verts, n_rays;
@@ -141,12 +143,51 @@ __device__ inline bool hit_point(const SynthArgs& a, const double* __restrict__ 
     return true;
 }
 
+// Each hit resolved once per call: the vertex indices of its triangle and its
+// barycentric coordinates, or i1 = -1 if any index of the hit is out of range.
+__global__ void resolve_kernel(SynthArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_hits) return;
+    int4 r = make_int4(-1, 0, 0, 0);
+    const int32_t m = a.hit_mesh[k];
+    if (m >= 0 && m < a.n_meshes) {
+        const int32_t t0 = a.mesh_tri_off[m], t1 = a.mesh_tri_off[m + 1];
+        const int32_t b = a.hit_tri[k];
+        if (b >= 0 && t0 >= 0 && t1 <= a.n_tris && b < t1 - t0) {
+            const int32_t t = t0 + b;
+            const int32_t i1 = a.tris[3 * t], i2 = a.tris[3 * t + 1], i3 = a.tris[3 * t + 2];
+            if ((unsigned)i1 < (unsigned)a.n_verts && (unsigned)i2 < (unsigned)a.n_verts &&
+                (unsigned)i3 < (unsigned)a.n_verts)
+                r = make_int4(i1, i2, i3, __float_as_int(a.hit_u[k]));
+        }
+    }
+    a.hit_rec[k] = r;
+    a.hit_rec_v[k] = a.hit_v[k];
+}
+
+// Eq. 6 for a resolved hit on the snapshot `v`.
+__device__ inline void rec_point(const int4 r, float hv, const double* __restrict__ v, double& px, double& py,
+                                 double& pz) {
+    const double u = __int_as_float(r.w), w = hv;
+    const double g = 1.0 - u - w;
+    const double* v1 = v + 3 * (int64_t)r.x;
+    const double* v2 = v + 3 * (int64_t)r.y;
+    const double* v3 = v + 3 * (int64_t)r.z;
+    px = g * v1[0] + u * v2[0] + w * v3[0];
+    py = g * v1[1] + u * v2[1] + w * v3[1];
+    pz = g * v1[2] + u * v2[2] + w * v3[2];
+}
+
 // The part of ray i's path that does not depend on the antenna pair, on the
 // snapshot of chirp chirp0 + jj (Eq. 6 for every hit): the inner length from
 // the first to the last hit and those two hit points.  One thread per (ray,
-// chirp); the pair loop of the synthesis then only adds the two antenna legs.
-// A ray with no usable path (no hits, or out-of-range meta data) stores an
-// inner length of -1.
+// chirp).  The hits' records are loaded kHitRun at a time before any vertex,
+// so the common rays (up to kHitRun hits) wait for two dependent loads, not
+// for one chain per hit.  The pair loop of the synthesis then only adds the
+// two antenna legs.  A ray with no usable path (no hits, or out-of-range meta
+// data) stores an inner length of -1.
+constexpr int kHitRun = 4;
+
 __global__ void geometry_kernel(SynthArgs a) {
     const int ray = blockIdx.x * blockDim.x + threadIdx.x;
     const int jj = blockIdx.y;
@@ -156,15 +197,38 @@ __global__ void geometry_kernel(SynthArgs a) {
     const int32_t b = a.ray_off[ray], e = a.ray_off[ray + 1];
     const double* v = a.verts + (int64_t)(a.chirp0 + jj) * a.n_verts * 3;
     double fx = 0, fy = 0, fz = 0, lx = 0, ly = 0, lz = 0, inner = -1.0;
-    if (b >= 0 && e <= a.n_hits && e > b && hit_point(a, v, b, fx, fy, fz)) {
-        lx = fx; ly = fy; lz = fz;
+    if (b >= 0 && e <= a.n_hits && e > b) {
         inner = 0.0;
-        for (int64_t k = b + 1; k < e; ++k) {
-            double x, y, z;
-            if (!hit_point(a, v, k, x, y, z)) { inner = -1.0; break; }
-            inner += dist3(x, y, z, lx, ly, lz);
-            lx = x; ly = y; lz = z;
+        for (int64_t k0 = b; k0 < e && inner >= 0.0; k0 += kHitRun) {
+            int4 r[kHitRun];
+            float hv[kHitRun];
+#pragma unroll
+            for (int c = 0; c < kHitRun; ++c) {
+                r[c] = make_int4(0, 0, 0, 0);
+                hv[c] = 0.0f;
+                if (k0 + c < e) {
+                    r[c] = a.hit_rec[k0 + c];
+                    hv[c] = a.hit_rec_v[k0 + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kHitRun; ++c) {
+                if (k0 + c >= e) break;
+                if (r[c].x < 0) {
+                    inner = -1.0;
+                    break;
+                }
+                double x, y, z;
+                rec_point(r[c], hv[c], v, x, y, z);
+                if (k0 + c == b) {
+                    fx = x; fy = y; fz = z;
+                } else {
+                    inner += dist3(x, y, z, lx, ly, lz);
+                }
+                lx = x; ly = y; lz = z;
+            }
         }
+        if (inner < 0.0) fx = fy = fz = lx = ly = lz = 0.0;
     }
     g[0] = inner;
     g[plane] = fx;
@@ -773,10 +837,10 @@ int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
 
 struct Plan {
     int batch, parts, rays_per_part, grid_log2;
-    int64_t geo_bytes, partial_bytes, grid_bytes, deconv_bytes, total_bytes;
+    int64_t geo_bytes, rec_bytes, partial_bytes, grid_bytes, deconv_bytes, total_bytes;
 };
 
-Plan plan(int n_rays, int n_pairs, int chirp_count, int n_samples) {
+Plan plan(int n_rays, int64_t n_hits, int n_pairs, int chirp_count, int n_samples) {
     Plan p{};
     const int64_t per_chirp = (int64_t)n_rays * 7 * (int64_t)sizeof(double);
     p.batch = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)chirp_count, kMaxBatch, kGeoBudget / per_chirp}));
@@ -791,10 +855,11 @@ Plan plan(int n_rays, int n_pairs, int chirp_count, int n_samples) {
     p.rays_per_part = (int)rpp;
     p.grid_log2 = grid_log2_for(n_samples);
     p.geo_bytes = round256(per_chirp * p.batch);
+    p.rec_bytes = round256(n_hits * (int64_t)sizeof(int4)) + round256(n_hits * (int64_t)sizeof(float));
     p.partial_bytes = (int64_t)p.parts * blocks * n_samples * (int64_t)sizeof(float2);
     p.grid_bytes = round256((int64_t)p.parts * blocks * (int64_t(1) << p.grid_log2) * (int64_t)sizeof(float2));
     p.deconv_bytes = round256((int64_t)n_samples * (int64_t)sizeof(double)) + 256;   // + the max-weight word
-    p.total_bytes = p.geo_bytes + std::max(p.partial_bytes, p.grid_bytes + p.deconv_bytes);
+    p.total_bytes = p.geo_bytes + p.rec_bytes + std::max(p.partial_bytes, p.grid_bytes + p.deconv_bytes);
     return p;
 }
 
@@ -908,7 +973,7 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
     if (!radar || !bytes) return fail(RMD_EINVAL, "radar and bytes must not be NULL");
     if (n_pairs <= 0 || chirp_count <= 0 || radar->n_samples <= 0 || radar->n_samples > RMD_MAX_SAMPLES)
         return fail(RMD_EINVAL, "n_pairs, chirp_count must be positive; n_samples in [1, RMD_MAX_SAMPLES]");
-    *bytes = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples).total_bytes;
+    *bytes = plan(scene->n_rays, scene->n_hits, n_pairs, chirp_count, radar->n_samples).total_bytes;
     return RMD_OK;
 }
 
@@ -931,14 +996,17 @@ rmd_status cube_setup(const rmd_scene* scene, const rmd_radar* radar, int32_t n_
         return fail(RMD_EINVAL, "chirp range outside [0, n_chirps)");
     if (!(radar->f_s > 0) || !(radar->t_chirp > 0) || !std::isfinite(radar->f_c) || !std::isfinite(radar->bandwidth))
         return fail(RMD_EINVAL, "radar parameters must be finite, f_s and t_chirp positive");
-    p = plan(scene->n_rays, n_pairs, chirp_count, radar->n_samples);
+    p = plan(scene->n_rays, scene->n_hits, n_pairs, chirp_count, radar->n_samples);
     if ((int64_t)n_pairs * p.batch * p.parts * 2 > INT32_MAX) return fail(RMD_EINVAL, "too many (pair, chirp) blocks");
 
     a = synth_args(scene);
     a.pairs = pairs;
     a.weights = weights;
     a.geo = static_cast<double*>(workspace);
-    a.partial = reinterpret_cast<float2*>(static_cast<char*>(workspace) + p.geo_bytes);
+    a.hit_rec = reinterpret_cast<int4*>(static_cast<char*>(workspace) + p.geo_bytes);
+    a.hit_rec_v = reinterpret_cast<float*>(static_cast<char*>(workspace) + p.geo_bytes +
+                                           round256(scene->n_hits * (int64_t)sizeof(int4)));
+    a.partial = reinterpret_cast<float2*>(static_cast<char*>(workspace) + p.geo_bytes + p.rec_bytes);
     a.n_pairs = n_pairs;
     a.n_samples = radar->n_samples;
     a.n_parts = p.parts;
@@ -947,6 +1015,15 @@ rmd_status cube_setup(const rmd_scene* scene, const rmd_radar* radar, int32_t n_
     const double mu = radar->bandwidth / radar->t_chirp;               // Eq. 3
     a.cyc_per_m = radar->f_c / rmd::kC0;
     a.step_per_m = mu / (rmd::kC0 * radar->f_s);
+    return RMD_OK;
+}
+
+// Resolves the hits into a.hit_rec once per call (both methods).
+rmd_status resolve_hits(const rmd::SynthArgs& a, hipStream_t stream) {
+    if (a.n_hits > 0)
+        hipLaunchKernelGGL(rmd::resolve_kernel, dim3((unsigned)((a.n_hits + 255) / 256)), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "resolve_kernel launch");
     return RMD_OK;
 }
 
@@ -962,10 +1039,12 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     rmd_status st = cube_setup(scene, radar, n_pairs, pairs, weights, chirp0, chirp_count, s, workspace,
                                workspace_bytes, p, a);
     if (st != RMD_OK) return st;
+    st = resolve_hits(a, stream);
+    if (st != RMD_OK) return st;
     const int M = 1 << p.grid_log2;
     a.grid_log2 = p.grid_log2;
     a.center = radar->n_samples / 2;
-    char* tail = static_cast<char*>(workspace) + p.geo_bytes + p.grid_bytes;
+    char* tail = static_cast<char*>(workspace) + p.geo_bytes + p.rec_bytes + p.grid_bytes;
     auto* wmax = reinterpret_cast<unsigned*>(tail);
     auto* deconv = reinterpret_cast<double*>(tail + 256);
     a.deconv = deconv;
@@ -1009,6 +1088,8 @@ rmd_status rmd_if_cube_direct(const rmd_scene* scene, const rmd_radar* radar, in
     rmd::SynthArgs a;
     rmd_status st = cube_setup(scene, radar, n_pairs, pairs, weights, chirp0, chirp_count, s, workspace,
                                workspace_bytes, p, a);
+    if (st != RMD_OK) return st;
+    st = resolve_hits(a, stream);
     if (st != RMD_OK) return st;
     // Chirp batches: geometry of the batch, then the synthesis and the
     // partition sums of the batch.

@@ -47,11 +47,12 @@ def _r256(b):
     return -(-b // 256) * 256
 
 
-def _plan(n_rays, n_pairs, chirps, n_samples):
+def _plan(n_rays, n_pairs, chirps, n_samples, n_hits=None):
     """The documented work plan: chirp batches of at most 16 whose per-ray
     geometry (7 doubles per ray and chirp) fits in 1 GiB; ray partitions so
     that about 8192 workgroups run per batch, each wave keeping >= 4 groups
-    of 64 rays (256-ray granules); then room for either method's partition
+    of 64 rays (256-ray granules); the hits' resolved records (16 + 4 bytes
+    per hit); then room for either method's partition
     results (direct: n_samples complex64 per block and partition; spreading:
     an M-cell complex64 grid, M the power of two >= max(64, 2 n_samples),
     then a 256-byte word for the largest weight and the n_samples float64
@@ -63,12 +64,14 @@ def _plan(n_rays, n_pairs, chirps, n_samples):
     rpp = -(-rpp // 256) * 256
     parts = -(-n_rays // rpp)
     geo = _r256(n_rays * 56 * batch)
+    n_hits = int(n_rays * 1.75) if n_hits is None else n_hits
+    rec = _r256(n_hits * 16) + _r256(n_hits * 4)
     M = 64
     while M < 2 * n_samples:
         M *= 2
     direct = parts * blocks * n_samples * 8
     spread = _r256(parts * blocks * M * 8) + 256 + _r256(n_samples * 8)
-    return batch, parts, geo + max(direct, spread)
+    return batch, parts, geo + rec + max(direct, spread)
 
 
 def test_workspace_bytes_plan():
