@@ -100,7 +100,9 @@ rmd_status rmd_check_scene(const rmd_scene* scene, int32_t n_chirps, void* works
  * sizes (one size serves both).  Chirps are processed in batches of up to 16
  * whose per-ray geometry (7 float64 per ray and chirp: inner path length,
  * first and last hit point) fits in 1 GiB; the workspace holds one batch's
- * geometry and the batch's per-partition results (rmd_if_cube: a grid of M
+ * geometry, every hit resolved to its triangle's vertex indices and
+ * barycentric coordinates (20 bytes per hit, once per call), and the batch's
+ * per-partition results (rmd_if_cube: a grid of M
  * complex64 cells per ray partition, pair and chirp, M the smallest power of
  * two >= max(64, 2 n_samples), plus n_samples float64; rmd_if_cube_direct:
  * n_samples complex64 per ray partition, pair and chirp). */
