@@ -595,13 +595,20 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SynthArgs a) {
 }
 
 // *bits = the float bits of max_i |w_i| (nonnegative floats order like their
-// bit patterns); *bits must be zero on entry.
-__global__ void wmax_kernel(const float* __restrict__ w, int n, unsigned* bits) {
+// bit patterns); *bits must be zero on entry.  256 threads per block; one
+// atomic per block.
+__global__ __launch_bounds__(256) void wmax_kernel(const float* __restrict__ w, int n, unsigned* bits) {
+    __shared__ unsigned wave_max[256 / kWave];
     unsigned m = 0u;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         m = max(m, __float_as_uint(fabsf(w[i])));
     for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(bits, m);
+    if ((threadIdx.x & (kWave - 1)) == 0) wave_max[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 256 / kWave; ++k) m = max(m, wave_max[k]);
+        atomicMax(bits, m);
+    }
 }
 
 __global__ void set_u32_kernel(unsigned* p, unsigned v) { *p = v; }
@@ -632,7 +639,10 @@ __global__ __launch_bounds__(kWave) void deconv_kernel(double* deconv, int n_sam
 // G[m] = sum_l g[l] e^{2 pi i m l / M} by radix-2 decimation in time in FP64
 // in LDS (twiddles from sincospi); then s[n] = G[(n - center) mod M] deconv[n]
 // rounded once to float32 and written into the cube at chirp c0 + j.
-__global__ __launch_bounds__(256) void finish_kernel(SynthArgs a, float2* __restrict__ s, int n_chirps_out, int c0) {
+constexpr int kFinishThreads = 1024;     // one grid cell per thread at M = 1024
+
+__global__ __launch_bounds__(kFinishThreads) void finish_kernel(SynthArgs a, float2* __restrict__ s, int n_chirps_out,
+                                                              int c0) {
     extern __shared__ double2 fl[];
     const int logL = a.grid_log2, L = 1 << logL;
     double2* tw = fl;                    // L / 2 twiddles e^{+2 pi i k / L}
@@ -647,6 +657,7 @@ __global__ __launch_bounds__(256) void finish_kernel(SynthArgs a, float2* __rest
     const float2* src = a.partial + ((int64_t)q * a.chirp_count + jj) * L;
     for (int l = threadIdx.x; l < L; l += blockDim.x) {
         double re = 0.0, im = 0.0;
+#pragma unroll 4
         for (int p = 0; p < a.n_parts; ++p) {
             const float2 v = src[(int64_t)p * stride + l];
             re += v.x;
@@ -1073,8 +1084,8 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
         hipLaunchKernelGGL(rmd::geometry_kernel, dim3((scene->n_rays + 255) / 256, nb), dim3(256), 0, stream, a);
         const dim3 grid((unsigned)((int64_t)n_pairs * nb * p.parts));
         hipLaunchKernelGGL(rmd::spread_kernel, grid, dim3(rmd::kThreads), spread_lds, stream, a);
-        hipLaunchKernelGGL(rmd::finish_kernel, dim3((unsigned)(n_pairs * nb)), dim3(256), finish_lds, stream, a,
-                           reinterpret_cast<float2*>(s), chirp_count, c0);
+        hipLaunchKernelGGL(rmd::finish_kernel, dim3((unsigned)(n_pairs * nb)), dim3(rmd::kFinishThreads), finish_lds,
+                           stream, a, reinterpret_cast<float2*>(s), chirp_count, c0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "IF cube launch");
     }
