@@ -2,20 +2,23 @@
 // for gfx950.  The C ABI is declared in include/raymeta.h.
 //
 // Kernels:
+//   resolve_kernel each hit's triangle and vertex indices range-checked and
+//                  reduced to a record, once per call.
 //   geometry_kernel Eq. 6 for every hit of a ray and the pair-independent
 //                  part of its path (FP64), once per ray and chirp.
 //   spread_kernel  Eqs. 7, 1, 2 (rmd_if_cube): per workgroup one antenna pair,
 //                  one chirp and one partition of the rays; the antenna legs
 //                  and phases per ray in FP64, then each ray's phasor spread
 //                  onto an oversampled periodic grid in LDS (the sum over rays
-//                  as a type-1 non-uniform FFT).
+//                  as a type-1 non-uniform FFT), in 64-bit fixed point.
+//   wmax_kernel    the largest weight (sets the fixed-point scale).
 //   deconv_kernel  the spreading kernel's Fourier transform at the output
 //                  frequencies (FP64 quadrature), once per call.
 //   finish_kernel  per (pair, chirp): the partitions' grids summed in FP64,
 //                  their inverse DFT (FP64, LDS) and the deconvolved samples.
-//   synth_kernel   the same sum evaluated directly (rmd_if_cube_direct): float32
-//                  MFMA products of phasor tiles (fast time factored into 32
-//                  rows x 16 columns).
+//   synth_kernel   the same sum evaluated directly (rmd_if_cube_direct): MFMA
+//                  products of phasor tiles split into fp16 high and low parts
+//                  (fast time factored into 32 rows x 16 columns).
 //   reduce_kernel  sums synth_kernel's partition cubes in FP64, fixed order.
 //   fft_kernel     radix-2 FFT of lines held in LDS (Eq. 4, one axis a pass).
 //   span_kernel    Eq. 5 rule masks, one thread per ray.
