@@ -185,6 +185,30 @@ yee_status yee_read_series(yee_ctx* ctx, int64_t first, int64_t count, double* h
 /* DFT accumulators into re[n_probes][nf], im[n_probes][nf].  Synchronizes. */
 yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
 
+/* Port voltages and scattering parameters from two runs' probe DFTs (the
+ * "S-parameter accumulators" are the running DFTs above; this combines them on
+ * the host, in FP64, with no GPU work).  Port q is the probe list
+ * port_probe[port_off[q] .. port_off[q+1]) with weights port_weight (a line
+ * integral of E when the weights are cell lengths):
+ *     V_q(f) = sum_i port_weight[i] X_{port_probe[i]}(f).
+ * The two-run method (Sheen, Ali, Abouzahra and Kong, IEEE Trans. Microwave
+ * Theory Tech. 38, 1990): the reference run (dft_ref: the uniform structure)
+ * carries the incident wave, the device run (dft_dut) the total field; with
+ * the source in front of port 0,
+ *     S_00 = (V_0^dut - V_0^ref) / V_0^ref,   S_q0 = V_q^dut / V_q^ref (q > 0),
+ * each referred to its own port position.
+ *   dft_*_re/im  [n_probes][n_freq] host arrays, as yee_read_dft writes them.
+ *   v_ref_re/im, v_dut_re/im  [n_ports][n_freq] outputs, or NULL.
+ *   s_re, s_im   [n_ports][n_freq] outputs.
+ * YEE_EINVAL for non-positive sizes, NULL required arrays, a non-increasing
+ * port_off or a probe index outside [0, n_probes).  A zero reference voltage
+ * gives IEEE infinities or NaNs in s. */
+yee_status yee_sparams(int32_t n_probes, int32_t n_freq, const double* dft_ref_re, const double* dft_ref_im,
+                       const double* dft_dut_re, const double* dft_dut_im, int32_t n_ports,
+                       const int32_t* port_off, const int32_t* port_probe, const double* port_weight,
+                       double* v_ref_re, double* v_ref_im, double* v_dut_re, double* v_dut_im, double* s_re,
+                       double* s_im);
+
 /* Launch shape of the fused step kernel: y-rows per workgroup tile, planes
  * per z-chunk and x samples per lane (1, 2 or 4); 0 keeps the automatic
  * choice (one sample per lane up to 256 samples per row, and in FP32 up to

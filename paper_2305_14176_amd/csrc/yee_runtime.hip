@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -819,6 +820,43 @@ yee_status yee_read_dft(yee_ctx* c, double* re, double* im, void* stream) {
   for (size_t q = 0; q < cnt; ++q) {
     re[q] = buf[2 * q];
     im[q] = buf[2 * q + 1];
+  }
+  return YEE_OK;
+}
+
+yee_status yee_sparams(int32_t n_probes, int32_t n_freq, const double* dft_ref_re, const double* dft_ref_im,
+                       const double* dft_dut_re, const double* dft_dut_im, int32_t n_ports,
+                       const int32_t* port_off, const int32_t* port_probe, const double* port_weight,
+                       double* v_ref_re, double* v_ref_im, double* v_dut_re, double* v_dut_im, double* s_re,
+                       double* s_im) {
+  if (n_probes <= 0 || n_freq <= 0 || n_ports <= 0) return fail(YEE_EINVAL, "sizes must be positive");
+  if (!dft_ref_re || !dft_ref_im || !dft_dut_re || !dft_dut_im || !port_off || !port_probe || !port_weight ||
+      !s_re || !s_im)
+    return fail(YEE_EINVAL, "NULL argument");
+  if (port_off[0] != 0) return fail(YEE_EINVAL, "port_off[0] must be 0");
+  for (int32_t q = 0; q < n_ports; ++q) {
+    if (port_off[q + 1] <= port_off[q]) return fail(YEE_EINVAL, "every port needs at least one probe");
+    for (int32_t i = port_off[q]; i < port_off[q + 1]; ++i)
+      if (port_probe[i] < 0 || port_probe[i] >= n_probes) return fail(YEE_EINVAL, "port probe index out of range");
+  }
+  using cd = std::complex<double>;
+  for (int32_t q = 0; q < n_ports; ++q) {
+    for (int32_t f = 0; f < n_freq; ++f) {
+      cd vr = 0.0, vd = 0.0;
+      for (int32_t i = port_off[q]; i < port_off[q + 1]; ++i) {
+        const size_t x = (size_t)port_probe[i] * n_freq + f;
+        vr += port_weight[i] * cd(dft_ref_re[x], dft_ref_im[x]);
+        vd += port_weight[i] * cd(dft_dut_re[x], dft_dut_im[x]);
+      }
+      const size_t o = (size_t)q * n_freq + f;
+      if (v_ref_re) v_ref_re[o] = vr.real();
+      if (v_ref_im) v_ref_im[o] = vr.imag();
+      if (v_dut_re) v_dut_re[o] = vd.real();
+      if (v_dut_im) v_dut_im[o] = vd.imag();
+      const cd sq = (q == 0 ? vd - vr : vd) / vr;
+      s_re[o] = sq.real();
+      s_im[o] = sq.imag();
+    }
   }
   return YEE_OK;
 }

@@ -13,6 +13,8 @@ Workloads (no public dataset is involved; every input is synthetic):
   * ``plain_pec_box``          32^3 FP64 PEC box, centred 8^3 eps_r = 4 block,
                                Gaussian-derivative Ez source (t0 = 40 dt, tau = 12 dt),
                                4 seeded Ez probes, 200 steps.
+  * ``waveguide_ports``        12 x 12 x 140 PEC waveguide, CPML on the z faces, for
+                               two-run S-parameters (reference, PEC short, dielectric slab)
   * ``cpml_block_lattice``     256^3 FP32, 10-cell CPML on all faces, 8^3-cell block
                                lattice eps_r ~ U[1, 10), sigma ~ U[0, 0.1) S/m,
                                modulated-Gaussian Ez source at 10 GHz (dx = 0.5 mm),
@@ -270,6 +272,37 @@ def fp16_substrate(nx: int = 512, ny: int = 512, nz: int = 256, steps: int = 200
 
 
 SERVING_SIDES = (32, 48, 64, 96, 128, 160)
+
+
+def waveguide_ports(kind: str = "ref", precision: str = "f32", steps: int = 6000, n: int = 12, nz: int = 140,
+                    cpml: int = 10) -> Workload:
+    """A rectangular PEC waveguide along z (n x n cells of 0.5 mm, CPML only on
+    the z faces) fed by a centred Ez point source, for two-run S-parameters.
+    The source excites TM11 (cutoff 35.3 GHz for n = 12) and, by symmetry, no
+    TM21/TM12; the next excited modes (TM13, TM31) are cut off below 79 GHz, so
+    44-66 GHz carries one mode.  Port 0 is the Ez probe on the axis at k = 60,
+    port 1 the one at k = 110.
+      kind "ref":   the uniform guide (the incident wave);
+      kind "short": a PEC plane (tangential E = 0) across the guide at k = 90;
+      kind "slab":  a lossless eps_r = 2.5 slab filling k in [80, 88)."""
+    d = 0.5e-3
+    wl = Workload(f"waveguide_{kind}_{n}x{n}x{nz}", n, n, nz, d, d, d, precision=precision,
+                  cpml_cells=(0, 0, cpml))
+    tau, f0 = 30e-12, 55e9
+    wl.sources = [SourceSpec(2, n // 2, n // 2, cpml + 4, "mod_gauss", 1.0, 4 * tau, tau, f0, unit="s")]
+    wl.probes = [(2, n // 2, n // 2, 60), (2, n // 2, n // 2, 110)]
+    wl.freqs = np.linspace(44e9, 66e9, 12)
+    wl.steps = steps
+    if kind == "short":
+        wl.pec_planes = [(90, np.full((n, n), 3, np.int32))]
+    elif kind == "slab":
+        seg = np.zeros(nz, np.int32)
+        seg[80:88] = 1
+        wl.seg_z, wl.nsz = seg, 2
+        wl.eps_blk, wl.sig_blk = np.array([1.0, 2.5]), np.zeros(2)
+    elif kind != "ref":
+        raise ValueError(f"unknown waveguide kind {kind!r}")
+    return wl
 
 
 def serving_request(seed: int, side: Optional[int] = None, steps: Optional[int] = None) -> Workload:
