@@ -15,6 +15,10 @@ time-stepping scheme.  The oracle therefore writes out the textbook scheme
 Roden & Gedney 2000 CPML).  Every point those sources leave open is an
 explicit argument of :class:`oracle.yee.Simulation`.
 
+``oracle.sparams`` combines probe DFTs into port voltages and two-run
+scattering parameters (Sheen, Ali, Abouzahra and Kong 1990), pinned on FDTD
+runs of a PEC waveguide against the Yee grid's own TM11 dispersion.
+
 ``oracle.raymeta`` is the oracle of the paper's own method (Section II,
 Eqs. 1-7: hit update, path lengths, antenna displacement, delays, IF
 synthesis, range-Doppler transform and span masks), written from the paper's
