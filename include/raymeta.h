@@ -124,7 +124,7 @@ rmd_status rmd_workspace_bytes(const rmd_scene* scene, const rmd_radar* radar, i
  * onto a 2x-oversampled periodic grid with an 8-cell "exponential of
  * semicircle" kernel, the grid is transformed and deconvolved in float64.
  * The grid accumulates 64-bit fixed-point integers scaled by the largest
- * |w_i| (each contribution rounded by at most 2^-30 max|w|), so its sums are
+ * |w_i| (each contribution cut toward zero by less than 2^-29 max|w|), so its sums are
  * exact and order-free, and partition grids are added in float64 in a fixed
  * order: repeated calls give identical results.  The kernel's aliasing error
  * is about 1e-7 relative; with the float32 phasors the result agrees with

@@ -9,8 +9,8 @@ Tolerances:
     against the FP64 oracle.  Both methods form each ray's phase in FP64 and
     reduce it modulo one cycle; the direct method runs FP32 phasor recurrences
     (per-term errors of a few 1e-7 rad), the spreading method adds the
-    kernel's aliasing error (about 1e-7) and its fixed-point rounding (at
-    most 2^-30 of the largest weight per contribution): about 1e-6.
+    kernel's aliasing error (about 1e-7) and its fixed-point rounding (below
+    2^-29 of the largest weight per contribution): about 1e-6.
   * Range-Doppler (Eq. 4): relative L2 <= 1e-5 against numpy's FP64 FFT of
     the same (GPU) input: FP32 radix-2 rounding grows like log2(N) eps.
   * Span masks (Eq. 5): bit-exact (0/1 times the float32 pattern weight).
