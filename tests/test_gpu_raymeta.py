@@ -205,7 +205,8 @@ def test_full_size_sampled(RM):
     128 chirps x 512 samples) built exactly as the benchmark builds it (all
     chirps: 16-chirp geometry batches, 43 ray partitions), with both methods,
     against the oracle at 16 sampled fast-time indices of every pair on
-    chirps 0, 77 and 127."""
+    chirps 0, 77 and 127, and the two methods against each other on the
+    whole cube."""
     sc = S.pedestrian_scene()
     _say(f"[gpu] raymeta full size: {sc.n_rays} rays, {sc.n_hits} hits, {sc.n_pairs} pairs, "
          f"{sc.radar.n_chirps} chirps")
@@ -213,11 +214,19 @@ def test_full_size_sampled(RM):
     sel = [0, 1, 7, 8, 63, 64, 100, 255, 256, 300, 383, 448, 500, 509, 510, 511]
     chirps = [0, 77, 127]
     ref = R.if_cube(sc, chirps=chirps, samples=sel)
+    cubes = {}
     for method in METHODS:
         got = RM.Synthesizer(ds, method=method).run(0, ds.amp).cpu().numpy()
         err = _blocks_rel(got[:, chirps][:, :, sel], ref)
         _say(f"[gpu]   {method}: worst sampled block rel L2 {err.max():.2e}")
         assert err.max() <= TOL, method
+        cubes[method] = got
+    # The two methods are independent evaluations of the same sum (a
+    # non-uniform FFT and an exact matrix product): every sample of every
+    # (pair, chirp) block of the full cube must agree.
+    err = _blocks_rel(cubes["spread"], cubes["direct"])
+    _say(f"[gpu]   spread vs direct, all 12 x 128 blocks of 512 samples: worst rel L2 {err.max():.2e}")
+    assert err.max() <= TOL
 
 
 @pytest.mark.parametrize("method", METHODS)
