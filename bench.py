@@ -251,6 +251,49 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak
 SPREAD_FLOPS_PER_RAY_BLOCK = 2 * 44 + 16 + 16   # per (ray, pair, chirp): 44 FMAs (8 taps), 16 mul, 16 grid adds
 
 
+def sparams_benchmark():
+    """Two-run S-parameters on the PEC-waveguide workloads (12 x 12 x 140
+    cells, 6000 FP32 steps each): the GPU time of every run (HIP events on the
+    launch stream), the host time of the extraction from the probe DFTs
+    (yee_sparams), and the physical checks: the PEC short reflects fully
+    (|S11| = 1) and the lossless slab conserves power (|S11|^2 + |S21|^2 = 1),
+    over 44-66 GHz."""
+    import numpy as np
+    import torch
+    from paper_2305_14176_amd import sparams as L
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.solver import YeeSolver
+    ports = [([0], [1.0]), ([1], [1.0])]
+    dft, run_ms = {}, {}
+    for kind in ("ref", "short", "slab"):
+        wl = W.waveguide_ports(kind, precision="f32")
+        s = YeeSolver(wl, device="cuda:0")
+        stream = torch.cuda.current_stream()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.step(wl.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        run_ms[kind] = round(ev0.elapsed_time(ev1), 3)
+        dft[kind] = s.dft()
+        s.close()
+    t0 = time.perf_counter()
+    _, _, s_short = L.sparams(dft["ref"], dft["short"], ports)
+    _, _, s_slab = L.sparams(dft["ref"], dft["slab"], ports)
+    host_us = (time.perf_counter() - t0) / 2 * 1e6
+    wl = W.waveguide_ports("ref")
+    return {
+        "workload": f"{wl.name}: PEC waveguide, CPML on the z faces, {wl.steps} FP32 steps, "
+                    f"{len(wl.freqs)} frequencies 44-66 GHz, ports = Ez probes at k = 60 and 110",
+        "run_ms": run_ms,
+        "steps_per_s": round(wl.steps / (run_ms["ref"] / 1e3), 1),
+        "extraction_us_host": round(host_us, 1),
+        "short_max_abs_s11_minus_1": round(float(np.abs(np.abs(s_short[0]) - 1).max()), 5),
+        "slab_max_power_error": round(float(np.abs(np.abs(s_slab[0]) ** 2 + np.abs(s_slab[1]) ** 2 - 1).max()), 5),
+    }
+
+
 def _time_cube(syn, ds, reps):
     """Average milliseconds of one whole IF cube (all chirp batches) over
     `reps` back-to-back calls on the current stream, after one untimed call."""
@@ -362,6 +405,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serving-requests", type=int, default=64)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient measurement")
+    ap.add_argument("--no-sparams", action="store_true", help="skip the S-parameter measurement")
     ap.add_argument("--no-precisions", action="store_true", help="skip the FP16-storage and FP64 configurations")
     ap.add_argument("--no-if-synthesis", action="store_true", help="skip the ray-meta-data IF measurement")
     ap.add_argument("--if-only", action="store_true",
@@ -459,6 +503,8 @@ def main():
         out["if_synthesis"] = if_synthesis_benchmark(reps=args.if_reps, cpu=not args.no_cpu_baseline)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_benchmark()
+    if not args.no_sparams:
+        out["sparams"] = sparams_benchmark()
     if not args.no_serving:
         del solver
         torch.cuda.empty_cache()
