@@ -218,6 +218,25 @@ yee_status yee_sparams(int32_t n_probes, int32_t n_freq, const double* dft_ref_r
  * not depend on the launch shape. */
 yee_status yee_set_launch(yee_ctx* ctx, int32_t tile_rows, int32_t chunk_planes, int32_t samples_per_lane);
 
+/* Steps per sweep of yee_step.  A two-step sweep reads the fields and CPML
+ * auxiliaries once and writes them once for two leapfrog steps (time
+ * blocking): each workgroup recomputes the first step on a halo of two rows
+ * and two planes around its tile.  Every sample is computed by the same
+ * instruction sequence as in a single step, so results are bitwise equal to
+ * single steps.  steps_per_sweep: 0 automatic (two-step sweeps where they
+ * apply: FP32 or FP16 storage, nx <= 256, a probe ring of at least 2 steps;
+ * single steps otherwise and for the last step of an odd count), 1 single
+ * steps only, 2 two-step sweeps (YEE_EINVAL where they do not apply).
+ * tile_rows (1..9, the workgroup holds tile_rows + 3 waves) and
+ * chunk_planes set the sweep's tile; 0 = automatic (9 rows, the shortest
+ * chunk that lets every tile be resident at once). */
+yee_status yee_set_time_blocking(yee_ctx* ctx, int32_t steps_per_sweep, int32_t tile_rows, int32_t chunk_planes);
+
+/* The launch yee_step will use (after yee_bind_workspace): steps per sweep
+ * (1 or 2), tile rows, planes per chunk and x samples per lane. */
+yee_status yee_launch_info(const yee_ctx* ctx, int32_t* steps_per_sweep, int32_t* tile_rows, int32_t* chunk_planes,
+                           int32_t* samples_per_lane);
+
 /* ------------------------------------------------------------------------
  * Batched stepper for serving many grids (continuous batching).
  *

@@ -14,6 +14,12 @@ LIBRARIES = {
     LIB: ["yee_runtime.hip"],
     RAYMETA_LIB: ["raymeta.hip"],
 }
+# per-library flags: the Yee kernels write every fused multiply-add explicitly,
+# so that one sample's update is the same instruction sequence in every kernel
+LIBRARY_FLAGS = {
+    LIB: ["-ffp-contract=off"],
+    RAYMETA_LIB: [],
+}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -37,7 +43,7 @@ def hipcc() -> str:
 
 def build_one(lib: str, sources, verbose: bool = False, extra_flags=()) -> str:
     out_tmp = lib + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *extra_flags, "-I", os.path.join(ROOT, "include"),
+    cmd = [hipcc(), *HIPCC_FLAGS, *LIBRARY_FLAGS.get(lib, []), *extra_flags, "-I", os.path.join(ROOT, "include"),
            *[os.path.join(CSRC, s) for s in sources], "-o", out_tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -24,7 +24,8 @@ EXPORTED = (
     "yee_set_materials", "yee_upload_materials", "yee_add_pec_plane", "yee_add_source",
     "yee_add_probe", "yee_set_dft_freqs", "yee_footprint", "yee_bind_workspace", "yee_reset",
     "yee_set_field", "yee_step", "yee_steps_done", "yee_read_field", "yee_read_series",
-    "yee_read_dft", "yee_sparams", "yee_set_launch", "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
+    "yee_read_dft", "yee_sparams", "yee_set_launch", "yee_set_time_blocking", "yee_launch_info",
+    "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
     "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
     "yee_batch_info", "yee_adjoint_create", "yee_adjoint_destroy", "yee_adjoint_footprint",
     "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward", "yee_adjoint_set_history",
@@ -98,6 +99,8 @@ def load():
         "yee_sparams": (I32, [I32, I32, P(D), P(D), P(D), P(D), I32, P(I32), P(I32), P(D),
                               P(D), P(D), P(D), P(D), P(D), P(D)]),
         "yee_set_launch": (I32, [VP, I32, I32, I32]),
+        "yee_set_time_blocking": (I32, [VP, I32, I32, I32]),
+        "yee_launch_info": (I32, [VP, P(I32), P(I32), P(I32), P(I32)]),
         "yee_batch_footprint": (I32, [I32, P(I64)]),
         "yee_batch_create": (I32, [I32, I64, I32, P(VP)]),
         "yee_batch_destroy": (None, [VP]),

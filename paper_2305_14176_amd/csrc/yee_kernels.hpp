@@ -76,7 +76,12 @@ struct StepArgs {
   const T* fin;             // E^n, H^{n-1/2}: component c (Ex..Hz) at fin + c * cstride
   T* fout;                  // E^{n+1}, H^{n+1/2}
   uint64_t cstride;         // elements between components
-  C* pse;                   // E-side psi, updated in place
+  C* pse;                   // E-side psi (single step: updated in place; two-step sweep: old)
+  C* pse_out;               // E-side psi, new (two-step sweep only)
+  C* pse_mid;               // two-step sweep: auxiliaries after the first step (E side)
+  C* psh_mid;               //                                              (H side)
+  const C* psbase;          // two-step sweep: lowest of the six auxiliary regions
+  uint32_t psi_span;        //                 bytes from psbase to the end of the highest
   const C* psh_in;          // H-side psi, old
   C* psh_out;               // H-side psi, new
   uint32_t psoff[6];        // element offset of the pair array holding each psi auxiliary
@@ -91,6 +96,7 @@ struct StepArgs {
   const int4* probe;        // (comp, i, j, k)
   double* series;           // probe ring [series_len][nprobe]
   int32_t nprobe, series_slot;
+  int32_t series_slot2;     // ring slot of the second step of a two-step sweep
   const SrcDev* src;        // soft sources
   int32_t nsrc;
   int64_t n;                // index of the step being taken
@@ -118,6 +124,29 @@ struct Conv<_Float16, float> {
   static __device__ __forceinline__ float ld(_Float16 v, float dec) { return static_cast<float>(v) * dec; }
   static __device__ __forceinline__ _Float16 st(float v, float enc) { return static_cast<_Float16>(v * enc); }
 };
+
+// ---------------------------------------------------------------------------
+// Per-sample arithmetic of one step, shared by every kernel that advances the
+// fields (single step, two steps per sweep, batched).  The library is built
+// with -ffp-contract=off, so each operation below is exactly the instruction
+// written: the same sample gets the same bits whichever kernel computes it.
+// ---------------------------------------------------------------------------
+// forward or backward difference (hi - lo) / dw
+template <class C>
+__device__ __forceinline__ C fdiff(C hi, C lo, C inv) { return (hi - lo) * inv; }
+// CPML (Roden & Gedney 2000): psi <- b psi + a d, evaluated as
+// psi - (1 - b) psi + a d; returns d / kappa + psi
+template <class C>
+__device__ __forceinline__ C cpml_term(C& psi, C d, C omb, C a, C kinv) {
+  psi = fma(a, d, fma(-omb, psi, psi));
+  return fma(kinv, d, psi);
+}
+// H half step: h - (dt/mu0) (p - q)
+template <class C>
+__device__ __forceinline__ C h_new(C h, C p, C q, C dtm) { return fma(-dtm, p - q, h); }
+// E half step (Taflove & Hagness ch. 3): Ca e + Cb (p - q)
+template <class C>
+__device__ __forceinline__ C e_new(C e, C p, C q, C ca, C cb) { return fma(ca, e, cb * (p - q)); }
 
 template <class T, int V>
 struct alignas(sizeof(T) * V) VecT {
@@ -589,31 +618,27 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         C dEz_dy[V], dEy_dz[V], dEx_dz[V], dEz_dx[V], dEy_dx[V], dEx_dy[V];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          dEz_dy[e] = (ezu[e] - e0[2][e]) * idy;
-          dEy_dz[e] = (e1[1][e] - e0[1][e]) * idz;
-          dEx_dz[e] = (e1[0][e] - e0[0][e]) * idz;
-          dEz_dx[e] = (ezr[e] - e0[2][e]) * idx_;
-          dEy_dx[e] = (eyr[e] - e0[1][e]) * idx_;
-          dEx_dy[e] = (exu[e] - e0[0][e]) * idy;
+          dEz_dy[e] = fdiff(ezu[e], e0[2][e], idy);
+          dEy_dz[e] = fdiff(e1[1][e], e0[1][e], idz);
+          dEx_dz[e] = fdiff(e1[0][e], e0[0][e], idz);
+          dEz_dx[e] = fdiff(ezr[e], e0[2][e], idx_);
+          dEy_dx[e] = fdiff(eyr[e], e0[1][e], idx_);
+          dEx_dy[e] = fdiff(exu[e], e0[0][e], idy);
         }
         if (iny) {
           const C ob = typ[3 * (ty + 1) + r], av = typ[4 * (ty + 1) + r], kv = typ[5 * (ty + 1) + r];
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            ph[PHXY][e] = ph[PHXY][e] - ob * ph[PHXY][e] + av * dEz_dy[e];
-            ph[PHZY][e] = ph[PHZY][e] - ob * ph[PHZY][e] + av * dEx_dy[e];
-            dEz_dy[e] = kv * dEz_dy[e] + ph[PHXY][e];
-            dEx_dy[e] = kv * dEx_dy[e] + ph[PHZY][e];
+            dEz_dy[e] = cpml_term(ph[PHXY][e], dEz_dy[e], ob, av, kv);
+            dEx_dy[e] = cpml_term(ph[PHZY][e], dEx_dy[e], ob, av, kv);
           }
         }
         if (inz) {
           const C ob = tzp[3 * nk1 + kq], av = tzp[4 * nk1 + kq], kv = tzp[5 * nk1 + kq];
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            ph[PHXZ][e] = ph[PHXZ][e] - ob * ph[PHXZ][e] + av * dEy_dz[e];
-            ph[PHYZ][e] = ph[PHYZ][e] - ob * ph[PHYZ][e] + av * dEx_dz[e];
-            dEy_dz[e] = kv * dEy_dz[e] + ph[PHXZ][e];
-            dEx_dz[e] = kv * dEx_dz[e] + ph[PHYZ][e];
+            dEy_dz[e] = cpml_term(ph[PHXZ][e], dEy_dz[e], ob, av, kv);
+            dEx_dz[e] = cpml_term(ph[PHYZ][e], dEx_dz[e], ob, av, kv);
           }
         }
         if (wave_inx) {
@@ -622,17 +647,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
             // lanes outside the layer read (1 - b, a, 1/kappa) = (0, 0, 1) and psi 0
             const int i = xl + e;
             const C ob = txp[3 * RL + i], av = txp[4 * RL + i], kv = txp[5 * RL + i];
-            ph[PHYX][e] = ph[PHYX][e] - ob * ph[PHYX][e] + av * dEz_dx[e];
-            ph[PHZX][e] = ph[PHZX][e] - ob * ph[PHZX][e] + av * dEy_dx[e];
-            dEz_dx[e] = kv * dEz_dx[e] + ph[PHYX][e];
-            dEy_dx[e] = kv * dEy_dx[e] + ph[PHZX][e];
+            dEz_dx[e] = cpml_term(ph[PHYX][e], dEz_dx[e], ob, av, kv);
+            dEy_dx[e] = cpml_term(ph[PHZX][e], dEy_dx[e], ob, av, kv);
           }
         }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          hx[e] = to_storage<T, C>(h0[0][e] - dtm * (dEz_dy[e] - dEy_dz[e]), a.enc[3], a.dec[3]);
-          hy[e] = HALO ? C(0) : to_storage<T, C>(h0[1][e] - dtm * (dEx_dz[e] - dEz_dx[e]), a.enc[4], a.dec[4]);
-          hz[e] = to_storage<T, C>(h0[2][e] - dtm * (dEy_dx[e] - dEx_dy[e]), a.enc[5], a.dec[5]);
+          hx[e] = to_storage<T, C>(h_new(h0[0][e], dEz_dy[e], dEy_dz[e], dtm), a.enc[3], a.dec[3]);
+          hy[e] = HALO ? C(0) : to_storage<T, C>(h_new(h0[1][e], dEx_dz[e], dEz_dx[e], dtm), a.enc[4], a.dec[4]);
+          hz[e] = to_storage<T, C>(h_new(h0[2][e], dEy_dx[e], dEx_dy[e], dtm), a.enc[5], a.dec[5]);
         }
         // new H-side psi of the own rows
         if (upd) {
@@ -690,31 +713,27 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           C dHz_dy[V], dHy_dz[V], dHx_dz[V], dHz_dx[V], dHy_dx[V], dHx_dy[V];
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            dHz_dy[e] = (hz[e] - hzd[e]) * idy;
-            dHy_dz[e] = (hy[e] - hyp[e]) * idz;
-            dHx_dz[e] = (hx[e] - hxp[e]) * idz;
-            dHz_dx[e] = (hz[e] - hzl[e]) * idx_;
-            dHy_dx[e] = (hy[e] - hyl[e]) * idx_;
-            dHx_dy[e] = (hx[e] - hxd[e]) * idy;
+            dHz_dy[e] = fdiff(hz[e], hzd[e], idy);
+            dHy_dz[e] = fdiff(hy[e], hyp[e], idz);
+            dHx_dz[e] = fdiff(hx[e], hxp[e], idz);
+            dHz_dx[e] = fdiff(hz[e], hzl[e], idx_);
+            dHy_dx[e] = fdiff(hy[e], hyl[e], idx_);
+            dHx_dy[e] = fdiff(hx[e], hxd[e], idy);
           }
           if (iny) {
             const C ob = typ[0 * (ty + 1) + r], av = typ[1 * (ty + 1) + r], kv = typ[2 * (ty + 1) + r];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              pe[PEXY][e] = pe[PEXY][e] - ob * pe[PEXY][e] + av * dHz_dy[e];
-              pe[PEZY][e] = pe[PEZY][e] - ob * pe[PEZY][e] + av * dHx_dy[e];
-              dHz_dy[e] = kv * dHz_dy[e] + pe[PEXY][e];
-              dHx_dy[e] = kv * dHx_dy[e] + pe[PEZY][e];
+              dHz_dy[e] = cpml_term(pe[PEXY][e], dHz_dy[e], ob, av, kv);
+              dHx_dy[e] = cpml_term(pe[PEZY][e], dHx_dy[e], ob, av, kv);
             }
           }
           if (inz) {
             const C ob = tzp[0 * nk1 + kq], av = tzp[1 * nk1 + kq], kv = tzp[2 * nk1 + kq];
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              pe[PEXZ][e] = pe[PEXZ][e] - ob * pe[PEXZ][e] + av * dHy_dz[e];
-              pe[PEYZ][e] = pe[PEYZ][e] - ob * pe[PEYZ][e] + av * dHx_dz[e];
-              dHy_dz[e] = kv * dHy_dz[e] + pe[PEXZ][e];
-              dHx_dz[e] = kv * dHx_dz[e] + pe[PEYZ][e];
+              dHy_dz[e] = cpml_term(pe[PEXZ][e], dHy_dz[e], ob, av, kv);
+              dHx_dz[e] = cpml_term(pe[PEYZ][e], dHx_dz[e], ob, av, kv);
             }
           }
           if (wave_inx) {
@@ -722,10 +741,8 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
             for (int e = 0; e < V; ++e) {
               const int i = xl + e;
               const C ob = txp[0 * RL + i], av = txp[1 * RL + i], kv = txp[2 * RL + i];
-              pe[PEYX][e] = pe[PEYX][e] - ob * pe[PEYX][e] + av * dHz_dx[e];
-              pe[PEZX][e] = pe[PEZX][e] - ob * pe[PEZX][e] + av * dHy_dx[e];
-              dHz_dx[e] = kv * dHz_dx[e] + pe[PEYX][e];
-              dHy_dx[e] = kv * dHy_dx[e] + pe[PEZX][e];
+              dHz_dx[e] = cpml_term(pe[PEYX][e], dHz_dx[e], ob, av, kv);
+              dHy_dx[e] = cpml_term(pe[PEZX][e], dHy_dx[e], ob, av, kv);
             }
           }
           const bool ux = j > 0 && k > 0;     // uniform: Ex off the outer faces
@@ -740,9 +757,9 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
               if (m & 2) { cay = C(0); cby = C(0); }
               if (m & 4) { caz = C(0); cbz = C(0); }
             }
-            exo[e] = cax * e0[0][e] + cbx * (dHz_dy[e] - dHy_dz[e]);
-            eyo[e] = cay * e0[1][e] + cby * (dHx_dz[e] - dHz_dx[e]);
-            ezo[e] = caz * e0[2][e] + cbz * (dHy_dx[e] - dHx_dy[e]);
+            exo[e] = e_new(e0[0][e], dHz_dy[e], dHy_dz[e], cax, cbx);
+            eyo[e] = e_new(e0[1][e], dHx_dz[e], dHz_dx[e], cay, cby);
+            ezo[e] = e_new(e0[2][e], dHy_dx[e], dHx_dy[e], caz, cbz);
           }
           if (!ux) {
 #pragma unroll
@@ -924,7 +941,7 @@ batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __res
     const int64_t n = slots[s].base_n + q;
     if (n < slots[s].n_end) {
       StepArgs<T, C> a = slots[s].a;
-      const int par = (int)(n & 1);
+      const int par = (int)((n - slots[s].base_n) & 1);   // set[0]: the state at the replay's start
       a.fin = slots[s].set[par];
       a.fout = const_cast<T*>(slots[s].set[par ^ 1]);
       a.psh_in = slots[s].psh[par];

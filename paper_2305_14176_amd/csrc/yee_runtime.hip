@@ -24,6 +24,7 @@
 #include "../../include/yee.h"
 #include "yee_adjoint.hpp"
 #include "yee_kernels.hpp"
+#include "yee_tb.hpp"
 
 namespace {
 
@@ -73,6 +74,11 @@ struct yee_ctx {
   size_t csize = 0; // compute element size
   int ty = 0, kz = 0, vpl = 0;  // launch shape (0 = automatic)
   int ty_req = 0, kz_req = 0;   // as requested by yee_set_launch
+  // two steps per sweep: requested mode (0 automatic, 1 single steps only,
+  // 2 required), its launch shape (0 = automatic) and whether it applies
+  int tb_req = 0, tb_ty_req = 0, tb_kz_req = 0;
+  int tb_ty = 0, tb_kz = 0, tb_V = 0, tb_wpr = 1;
+  bool tb_ok = false;
   size_t lds_limit = 65536;  // per-workgroup LDS, queried at bind time
 
   // host-side configuration
@@ -89,7 +95,7 @@ struct yee_ctx {
   bool bound = false;
   unsigned char* ws = nullptr;
   int64_t ws_bytes = 0;
-  Region fields[2], psi_e, psi_h[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
+  Region fields[2], psi_e[2], psi_h[2], psi_mid[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
       srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
@@ -97,6 +103,10 @@ struct yee_ctx {
   size_t prof_len = 0;     // elements of one profile array (max axis length)
   int64_t n = 0;           // steps taken
   int64_t folded = 0;      // steps folded into the DFT
+  // current buffers: a single step and a two-step sweep both write the other
+  // field set and H-side auxiliary set (cur); the E-side auxiliaries are
+  // updated in place by a single step and ping-ponged by a sweep (pecur)
+  int cur = 0, pecur = 0;
 };
 
 struct yee_batch {
@@ -171,9 +181,13 @@ void layout(yee_ctx* c) {
   c->psi_off[3] = c->psi_off[4] = (uint32_t)(ypair + zpair);
   const size_t psin = ypair + zpair + xpair;
   const size_t psib = psin * c->csize;
-  take(c->psi_e, psib);
+  take(c->psi_e[0], psib);
+  take(c->psi_e[1], psib);
   take(c->psi_h[0], psib);
   take(c->psi_h[1], psib);
+  // auxiliaries after the first step of a two-step sweep (E side, H side)
+  take(c->psi_mid[0], psib);
+  take(c->psi_mid[1], psib);
   const size_t np = c->probes.size(), nf = c->freqs.size();
   take(c->series, (size_t)d.series_len * np * sizeof(double));
   take(c->dft, np * nf * 2 * sizeof(double));
@@ -266,11 +280,16 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   using namespace yee;
   const auto& d = c->d;
   StepArgs<T, C> a{};
-  const int cur = (int)(c->n & 1), nxt = cur ^ 1;
+  const int cur = c->cur, nxt = cur ^ 1;
   a.fin = reinterpret_cast<const T*>(c->ws + c->fields[cur].off);
   a.fout = reinterpret_cast<T*>(c->ws + c->fields[nxt].off);
   a.cstride = c->comp_bytes / sizeof(T);
-  a.pse = reinterpret_cast<C*>(c->ws + c->psi_e.off);
+  a.pse = reinterpret_cast<C*>(c->ws + c->psi_e[c->pecur].off);
+  a.pse_out = reinterpret_cast<C*>(c->ws + c->psi_e[c->pecur ^ 1].off);
+  a.pse_mid = reinterpret_cast<C*>(c->ws + c->psi_mid[0].off);
+  a.psh_mid = reinterpret_cast<C*>(c->ws + c->psi_mid[1].off);
+  a.psbase = reinterpret_cast<const C*>(c->ws + c->psi_e[0].off);
+  a.psi_span = (uint32_t)(c->psi_mid[1].off + c->psi_mid[1].bytes - c->psi_e[0].off);
   a.psh_in = reinterpret_cast<const C*>(c->ws + c->psi_h[cur].off);
   a.psh_out = reinterpret_cast<C*>(c->ws + c->psi_h[nxt].off);
   for (int q = 0; q < 6; ++q) a.psoff[q] = c->psi_off[q];
@@ -287,6 +306,7 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   a.series = reinterpret_cast<double*>(c->ws + c->series.off);
   a.nprobe = record ? (int32_t)c->probes.size() : 0;
   a.series_slot = (int32_t)(c->n % d.series_len);
+  a.series_slot2 = (int32_t)((c->n + 1) % d.series_len);
   a.src = reinterpret_cast<const SrcDev*>(c->ws + c->srcr.off);
   a.nsrc = (int32_t)c->src.size();
   a.n = c->n;
@@ -308,7 +328,7 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   a.ny_tiles = (d.ny + ty - 1) / ty;
   a.ntiles = a.ny_tiles * ((d.nz + kz - 1) / kz);
 
-  a.psi_bytes = (uint32_t)c->psi_e.bytes;
+  a.psi_bytes = (uint32_t)c->psi_e[0].bytes;
   a.coef_bytes = (uint32_t)c->coef.bytes;
   return a;
 }
@@ -343,6 +363,46 @@ yee_status launch_one_step(yee_ctx* c, hipStream_t s, bool record = true) {
     case YEE_F32: return launch_step_v<float, float>(c, s, record);
     default: return launch_step_v<_Float16, float>(c, s, record);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per sweep (yee_tb.hpp): FP32 arithmetic (FP32 or FP16 storage),
+// rows of at most 256 samples (one wave per row).
+// ---------------------------------------------------------------------------
+constexpr int kTbMaxRow = 4 * yee::kWave;
+
+size_t tb_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
+  return yee::tb_lds_bytes_for(ty, V, c->tb_wpr, kz);
+}
+
+// Most tile rows of a two-step workgroup (ty + 3 rows of wpr waves each).
+int tb_max_rows(int V, int wpr) { return yee::tb_block_waves(V) / wpr - 3; }
+
+template <class T, class C, int V, int WPR>
+yee_status launch_tb(yee_ctx* c, hipStream_t s, bool record) {
+  using namespace yee;
+  const StepArgs<T, C> a = fill_args<T, C>(c, V, c->tb_ty, c->tb_kz, record);
+  const int grid = ((a.ntiles + 7) / 8) * 8;
+  const size_t lds = tb_lds_bytes(c, c->tb_ty, V, c->tb_kz);
+  if (lds > c->lds_limit) return fail(YEE_EINVAL, "two-step tile needs %zu bytes of LDS (limit %zu)", lds, c->lds_limit);
+  if (c->tb_ty < 1 || c->tb_ty > tb_max_rows(V, WPR))
+    return fail(YEE_EINVAL, "two-step tile of %d rows exceeds the workgroup", c->tb_ty);
+  hipLaunchKernelGGL((tb_kernel<T, C, V, WPR>), dim3(grid), dim3(kWave * WPR * (c->tb_ty + 3)), lds, s, a);
+  HIP_TRY(hipGetLastError());
+  return YEE_OK;
+}
+
+// rows of at most 64, 128 and 256 samples: one wave of one or two samples per
+// lane, or two waves of two
+template <class T>
+yee_status launch_tb_v(yee_ctx* c, hipStream_t s, bool record) {
+  if (c->tb_V == 1) return launch_tb<T, float, 1, 1>(c, s, record);
+  if (c->tb_wpr == 1) return launch_tb<T, float, 2, 1>(c, s, record);
+  return launch_tb<T, float, 2, 2>(c, s, record);
+}
+
+yee_status launch_two_steps(yee_ctx* c, hipStream_t s, bool record = true) {
+  return c->d.precision == YEE_F32 ? launch_tb_v<float>(c, s, record) : launch_tb_v<_Float16>(c, s, record);
 }
 
 yee_status fold_dft(yee_ctx* c, hipStream_t s) {
@@ -408,6 +468,79 @@ int default_samples_per_lane(const yee_grid_desc& d) {
   return (d.nx <= 4 * yee::kWave || d.precision == YEE_F64) ? 1 : 2;
 }
 
+// Workgroups of the two-step kernel that fit one CU at once.
+template <class T, int V, int WPR>
+int tb_blocks_per_cu(int threads, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, yee::tb_kernel<T, float, V, WPR>, threads, lds) != hipSuccess)
+    n = 1;
+  return std::max(1, n);
+}
+
+int tb_slots(const yee_ctx* c, int threads, size_t lds) {
+  int dev_id = 0, cus = 0;
+  if (hipGetDevice(&dev_id) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus < 1)
+    cus = 1;
+  int per_cu = 1;
+  const bool f32 = c->d.precision == YEE_F32;
+  if (c->tb_V == 1) per_cu = f32 ? tb_blocks_per_cu<float, 1, 1>(threads, lds) : tb_blocks_per_cu<_Float16, 1, 1>(threads, lds);
+  else if (c->tb_wpr == 1) per_cu = f32 ? tb_blocks_per_cu<float, 2, 1>(threads, lds) : tb_blocks_per_cu<_Float16, 2, 1>(threads, lds);
+  else per_cu = f32 ? tb_blocks_per_cu<float, 2, 2>(threads, lds) : tb_blocks_per_cu<_Float16, 2, 2>(threads, lds);
+  return per_cu * cus;
+}
+
+// Whether yee_step advances two steps per sweep, and its launch shape.  The
+// sweep takes FP32 arithmetic (FP32 or FP16 storage) and rows of at most 256
+// samples; with probes the ring must hold both steps.  Tile rows: the count
+// whose tiles, with chunks sized so that every tile is resident at once, do
+// the least work per workgroup (a tile computes 4 ty + 6 row-stages on each of
+// kz + 3 planes); for 256^3 that is four rows, 64 y-tiles of 64-plane chunks,
+// one workgroup per CU.
+// Whether the automatic mode (steps_per_sweep 0) takes two-step sweeps.
+constexpr bool kTbAutomatic = false;
+
+void tb_default_launch(yee_ctx* c) {
+  const auto& d = c->d;
+  c->tb_ok = false;
+  if (c->tb_req == 1 || (c->tb_req == 0 && !kTbAutomatic)) return;
+  if (d.precision == YEE_F64 || d.nx > kTbMaxRow || (!c->probes.empty() && d.series_len < 2)) return;
+  c->tb_V = d.nx <= yee::kWave ? 1 : 2;
+  c->tb_wpr = d.nx <= 2 * yee::kWave ? 1 : 2;
+  const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+  const int min_chunk = cells <= (int64_t(1) << 18) ? 2 : (cells <= (int64_t(1) << 20) ? 4 : kMinChunk);
+  const int tymax = std::min(tb_max_rows(c->tb_V, c->tb_wpr), d.ny);
+  int best_ty = 0, best_kz = 0;
+  double best = 0.0;
+  for (int ty = (c->tb_ty_req ? c->tb_ty_req : 1); ty <= (c->tb_ty_req ? c->tb_ty_req : tymax); ++ty) {
+    const int ny_tiles = (d.ny + ty - 1) / ty;
+    int kz;
+    int slots = 1;
+    if (c->tb_kz_req > 0) {
+      kz = std::min(c->tb_kz_req, d.nz);
+    } else {
+      slots = tb_slots(c, (ty + 3) * c->tb_wpr * yee::kWave, tb_lds_bytes(c, ty, c->tb_V, d.nz));
+      const int chunks = std::max(1, slots / ny_tiles);
+      kz = std::min(d.nz, std::max(min_chunk, (d.nz + chunks - 1) / chunks));
+    }
+    if (tb_lds_bytes(c, ty, c->tb_V, kz) > c->lds_limit) continue;
+    if (c->tb_kz_req == 0) {
+      // a tile's work, times the rounds of resident workgroups the launch takes
+      const int64_t tiles = (int64_t)ny_tiles * ((d.nz + kz - 1) / kz);
+      const double rounds = (double)((tiles + slots - 1) / slots);
+      const double cost = rounds * (4.0 * ty + 6.0) * (std::min(kz, d.nz) + 3.0);
+      if (best_ty == 0 || cost < best) { best = cost; best_ty = ty; best_kz = kz; }
+    } else if (best_ty == 0) {
+      best_ty = ty;
+      best_kz = kz;
+    }
+  }
+  if (best_ty == 0) return;
+  c->tb_ty = best_ty;
+  c->tb_kz = best_kz;
+  c->tb_ok = true;
+}
+
 void default_launch(yee_ctx* c) {
   const auto& d = c->d;
   c->V = c->vpl ? c->vpl : default_samples_per_lane(d);
@@ -444,6 +577,7 @@ void default_launch(yee_ctx* c) {
     if (c->ty == 1 || step_lds_bytes(c, c->ty, c->V, c->kz) <= c->lds_limit) break;
     --c->ty;
   }
+  tb_default_launch(c);
 }
 
 template <class T>
@@ -531,6 +665,20 @@ yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out) {
   if (6 * ((uint64_t)(d.nz + 1) * d.ny * c->px * c->tsize + 256) >= (1ull << 31)) {
     delete c;
     return fail(YEE_EINVAL, "grid too large: a set of six components must stay below 2 GiB");
+  }
+  // ... and the six CPML auxiliary regions (E and H side: two sets each and the
+  // values after the first step of a two-step sweep, laid out consecutively)
+  // under one resource whose out-of-range marker is 2^31: their total must
+  // stay below it
+  {
+    size_t pl[6];
+    psi_lengths(c, pl);
+    const uint64_t psib = align256((2 * (pl[0] + pl[1] + pl[3])) * c->csize);
+    if (6 * psib >= (1ull << 31)) {
+      delete c;
+      return fail(YEE_EINVAL, "CPML layers too thick: the six auxiliary regions (%llu bytes) must stay below 2 GiB",
+                  (unsigned long long)(6 * psib));
+    }
   }
   c->dt = d.courant / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz)));
   c->segx.assign(d.nx, 0);
@@ -671,6 +819,39 @@ yee_status yee_set_launch(yee_ctx* c, int32_t tile_rows, int32_t chunk_planes, i
   return YEE_OK;
 }
 
+yee_status yee_set_time_blocking(yee_ctx* c, int32_t steps_per_sweep, int32_t tile_rows, int32_t chunk_planes) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (steps_per_sweep < 0 || steps_per_sweep > 2) return fail(YEE_EINVAL, "steps_per_sweep must be 0, 1 or 2");
+  const int tb_wpr = c->d.nx <= 2 * yee::kWave ? 1 : 2;
+  const int tb_rows = tb_max_rows(c->d.nx <= yee::kWave ? 1 : 2, tb_wpr);
+  if (tile_rows < 0 || tile_rows > tb_rows || chunk_planes < 0)
+    return fail(YEE_EINVAL, "tile_rows must be 0..%d for rows of %d samples, chunk_planes >= 0", tb_rows, c->d.nx);
+  const auto& d = c->d;
+  if (steps_per_sweep == 2 && (d.precision == YEE_F64 || d.nx > kTbMaxRow))
+    return fail(YEE_EINVAL, "two steps per sweep take FP32 or FP16 storage and rows of at most %d samples", kTbMaxRow);
+  if (steps_per_sweep == 2 && !c->probes.empty() && d.series_len < 2)
+    return fail(YEE_EINVAL, "two steps per sweep need a probe ring of at least 2 steps");
+  c->tb_req = steps_per_sweep;
+  c->tb_ty_req = tile_rows;
+  c->tb_kz_req = chunk_planes;
+  if (c->bound) {
+    tb_default_launch(c);
+    if (steps_per_sweep == 2 && !c->tb_ok) return fail(YEE_EINVAL, "the two-step tile does not fit the device's LDS");
+  }
+  return YEE_OK;
+}
+
+yee_status yee_launch_info(const yee_ctx* c, int32_t* steps_per_sweep, int32_t* tile_rows, int32_t* chunk_planes,
+                           int32_t* samples_per_lane) {
+  if (!c || !steps_per_sweep || !tile_rows || !chunk_planes || !samples_per_lane) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  *steps_per_sweep = c->tb_ok ? 2 : 1;
+  *tile_rows = c->tb_ok ? c->tb_ty : c->ty;
+  *chunk_planes = c->tb_ok ? c->tb_kz : c->kz;
+  *samples_per_lane = c->tb_ok ? c->tb_V : c->V;
+  return YEE_OK;
+}
+
 yee_status yee_reset(yee_ctx* c, void* stream) {
   if (!c) return fail(YEE_EINVAL, "NULL context");
   if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
@@ -718,6 +899,8 @@ yee_status yee_reset(yee_ctx* c, void* stream) {
   HIP_TRY(hipStreamSynchronize(s));
   c->n = 0;
   c->folded = 0;
+  c->cur = 0;
+  c->pecur = 0;
   return YEE_OK;
 }
 
@@ -744,7 +927,7 @@ yee_status yee_set_field(yee_ctx* c, int32_t comp, const double* host, void* str
           o[(k * d.ny + j) * c->px + i] = static_cast<_Float16>(host[(k * d.ny + j) * d.nx + i] * (double)enc);
   }
   hipStream_t s = (hipStream_t)stream;
-  const int cur = (int)(c->n & 1);
+  const int cur = c->cur;
   HIP_TRY(hipMemcpyAsync(c->ws + c->fields[cur].off + comp * c->comp_bytes, buf.data(), buf.size(),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -756,13 +939,21 @@ yee_status yee_step(yee_ctx* c, int64_t n_steps, void* stream) {
   if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
   if (n_steps < 0) return fail(YEE_EINVAL, "n_steps < 0");
   hipStream_t s = (hipStream_t)stream;
-  for (int64_t q = 0; q < n_steps; ++q) {
-    yee_status st = launch_one_step(c, s);
-    if (st) return st;
-    c->n += 1;
-    if (c->n - c->folded >= c->d.series_len) {
-      if ((st = fold_dft(c, s))) return st;
+  yee_status st = YEE_OK;
+  for (int64_t left = n_steps; left > 0;) {
+    const int k = (c->tb_ok && left >= 2) ? 2 : 1;
+    // the probe ring holds series_len steps: fold before a launch would
+    // overwrite samples not yet in the DFT
+    if (c->n + k - c->folded > c->d.series_len && (st = fold_dft(c, s))) return st;
+    if (k == 2) {
+      if ((st = launch_two_steps(c, s))) return st;
+      c->pecur ^= 1;
+    } else if ((st = launch_one_step(c, s))) {
+      return st;
     }
+    c->n += k;
+    c->cur ^= 1;
+    left -= k;
   }
   return fold_dft(c, s);
 }
@@ -780,7 +971,7 @@ yee_status yee_read_field(yee_ctx* c, int32_t comp, double* host, void* stream) 
   const auto& d = c->d;
   std::vector<unsigned char> buf((size_t)d.nz * d.ny * c->px * c->tsize);
   hipStream_t s = (hipStream_t)stream;
-  const int cur = (int)(c->n & 1);
+  const int cur = c->cur;
   HIP_TRY(hipMemcpyAsync(buf.data(), c->ws + c->fields[cur].off + comp * c->comp_bytes, buf.size(),
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1010,10 +1201,11 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
     BatchDesc& d = desc[nact++];
     sl.kz = std::min(c->d.nz, kz_all);
     d.a = fill_args<float, float>(c, 1, sl.ty, sl.kz);
-    d.set[0] = reinterpret_cast<const float*>(c->ws + c->fields[0].off);
-    d.set[1] = reinterpret_cast<const float*>(c->ws + c->fields[1].off);
-    d.psh[0] = reinterpret_cast<float*>(c->ws + c->psi_h[0].off);
-    d.psh[1] = reinterpret_cast<float*>(c->ws + c->psi_h[1].off);
+    // set[0] holds the state at the start of the replay (the context's current buffers)
+    d.set[0] = reinterpret_cast<const float*>(c->ws + c->fields[c->cur].off);
+    d.set[1] = reinterpret_cast<const float*>(c->ws + c->fields[c->cur ^ 1].off);
+    d.psh[0] = reinterpret_cast<float*>(c->ws + c->psi_h[c->cur].off);
+    d.psh[1] = reinterpret_cast<float*>(c->ws + c->psi_h[c->cur ^ 1].off);
     d.base_n = c->n;
     d.n_end = sl.n_end;
     d.series_len = c->d.series_len;
@@ -1049,7 +1241,9 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
   for (int32_t q : order) {
     auto& sl = b->slots[q];
     yee_ctx* c = sl.ctx;
-    c->n = std::min(sl.n_end, c->n + b->K);
+    const int64_t taken = std::min(sl.n_end, c->n + b->K) - c->n;
+    c->n += taken;
+    c->cur ^= (int)(taken & 1);
     yee_status st = fold_dft(c, s);
     if (st) return st;
   }
@@ -1126,14 +1320,14 @@ void adj_layout(yee_adjoint* A) {
     r.bytes = bytes;
     off += align256(std::max<size_t>(bytes, 1));
   };
-  A->ckpt_bytes = align256(6 * c->comp_bytes) + 2 * align256(c->psi_e.bytes);
+  A->ckpt_bytes = align256(6 * c->comp_bytes) + 2 * align256(c->psi_e[0].bytes);
   take(A->ckpt, (size_t)(A->S + 1) * A->ckpt_bytes);
   take(A->hist, (size_t)A->H * (A->K + 1) * 3 * A->nbox * c->tsize);
   A->ucomp = align256((size_t)d.nz * d.ny * c->px * c->csize);
   take(A->u, 3 * A->ucomp);
   take(A->hb, 3 * A->ucomp);
-  for (int q = 0; q < 2; ++q) take(A->pe[q], c->psi_e.bytes);
-  for (int q = 0; q < 2; ++q) take(A->ph[q], c->psi_e.bytes);
+  for (int q = 0; q < 2; ++q) take(A->pe[q], c->psi_e[0].bytes);
+  for (int q = 0; q < 2; ++q) take(A->ph[q], c->psi_e[0].bytes);
   take(A->phist, (size_t)A->N * c->probes.size() * sizeof(double));
   take(A->jout, sizeof(double));
   take(A->dcoef, (size_t)c->nsx * c->nsy * c->nsz * 2 * sizeof(double));
@@ -1149,12 +1343,12 @@ yee_status adj_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // Checkpoint slot q <-> the context's current state (fields, psi_E, psi_H).
 yee_status adj_checkpoint(yee_adjoint* A, int q, bool save, hipStream_t s) {
   yee_ctx* c = A->c;
-  const int cur = (int)(c->n & 1);
+  const int cur = c->cur;
   unsigned char* slot = A->ws + A->ckpt.off + (size_t)q * A->ckpt_bytes;
   unsigned char* parts[3] = {slot, slot + align256(6 * c->comp_bytes),
-                             slot + align256(6 * c->comp_bytes) + align256(c->psi_e.bytes)};
-  unsigned char* live[3] = {c->ws + c->fields[cur].off, c->ws + c->psi_e.off, c->ws + c->psi_h[cur].off};
-  const size_t bytes[3] = {6 * c->comp_bytes, c->psi_e.bytes, c->psi_e.bytes};
+                             slot + align256(6 * c->comp_bytes) + align256(c->psi_e[0].bytes)};
+  unsigned char* live[3] = {c->ws + c->fields[cur].off, c->ws + c->psi_e[c->pecur].off, c->ws + c->psi_h[cur].off};
+  const size_t bytes[3] = {6 * c->comp_bytes, c->psi_e[0].bytes, c->psi_e[0].bytes};
   for (int p = 0; p < 3; ++p) {
     yee_status st = save ? adj_copy(parts[p], live[p], bytes[p], s) : adj_copy(live[p], parts[p], bytes[p], s);
     if (st) return st;
@@ -1165,7 +1359,7 @@ yee_status adj_checkpoint(yee_adjoint* A, int q, bool save, hipStream_t s) {
 // E of the box cells at the current step into entry m of history slot `slot`.
 yee_status adj_store(yee_adjoint* A, int slot, int m, hipStream_t s) {
   yee_ctx* c = A->c;
-  const int cur = (int)(c->n & 1);
+  const int cur = c->cur;
   const int4 lo = {A->box[0], A->box[2], A->box[4], 0};
   const dim3 grid((A->bx + yee::kAdjBX - 1) / yee::kAdjBX, (A->by + yee::kAdjBY - 1) / yee::kAdjBY, A->bz);
   const dim3 block(yee::kAdjBX, yee::kAdjBY);
@@ -1374,6 +1568,7 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
     for (int64_t n = n0; n < n1; ++n) {
       if ((st = launch_one_step(c, s))) return st;
       c->n += 1;
+      c->cur ^= 1;
       if (keep && (st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       if (c->n - gathered >= d.series_len) {
         if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
@@ -1470,6 +1665,7 @@ yee_status yee_adjoint_backward(yee_adjoint* A, double* grad, void* stream) {
       for (int64_t n = n0; n < n1; ++n) {
         if ((st = launch_one_step(c, s, false))) return st;
         c->n += 1;
+        c->cur ^= 1;
         if ((st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       }
       A->slot_seg[slot] = seg;

@@ -27,7 +27,8 @@ class YeeSolver:
     """A configured, bound and reset context for one workload on one device."""
 
     def __init__(self, wl: Workload, device: str = "cuda:0", series_len: Optional[int] = None,
-                 tile_rows: int = 0, chunk_planes: int = 0, samples_per_lane: int = 0, stream=None):
+                 tile_rows: int = 0, chunk_planes: int = 0, samples_per_lane: int = 0, stream=None,
+                 steps_per_sweep: int = 0, sweep_rows: int = 0, sweep_planes: int = 0):
         import torch
         self.torch = torch
         self.lib = _lib.load()
@@ -67,6 +68,8 @@ class YeeSolver:
         _lib.check(self.lib.yee_bind_workspace(ctx, C.c_void_p(aligned), self.footprint), "yee_bind_workspace")
         if tile_rows or chunk_planes or samples_per_lane:
             _lib.check(self.lib.yee_set_launch(ctx, tile_rows, chunk_planes, samples_per_lane), "yee_set_launch")
+        if steps_per_sweep or sweep_rows or sweep_planes:
+            self.set_time_blocking(steps_per_sweep, sweep_rows, sweep_planes)
         self.stream = stream
         self.reset()
 
@@ -126,6 +129,18 @@ class YeeSolver:
         """Launch shape of the fused step kernel (0 = automatic)."""
         _lib.check(self.lib.yee_set_launch(self.ctx, int(tile_rows), int(chunk_planes), int(samples_per_lane)),
                    "yee_set_launch")
+
+    def set_time_blocking(self, steps_per_sweep: int = 0, tile_rows: int = 0, chunk_planes: int = 0):
+        """Steps per sweep of yee_step (0 automatic, 1 single steps, 2 two-step
+        sweeps) and the two-step launch shape (0 = automatic)."""
+        _lib.check(self.lib.yee_set_time_blocking(self.ctx, int(steps_per_sweep), int(tile_rows), int(chunk_planes)),
+                   "yee_set_time_blocking")
+
+    def launch_info(self) -> dict:
+        """The launch yee_step uses: steps per sweep, tile rows, chunk planes, samples per lane."""
+        v = [C.c_int32() for _ in range(4)]
+        _lib.check(self.lib.yee_launch_info(self.ctx, *[C.byref(x) for x in v]), "yee_launch_info")
+        return dict(zip(("steps_per_sweep", "tile_rows", "chunk_planes", "samples_per_lane"), (x.value for x in v)))
 
     def step(self, n: int):
         _lib.check(self.lib.yee_step(self.ctx, int(n), self._s()), "yee_step")
