@@ -78,9 +78,7 @@ struct StepArgs {
   uint64_t cstride;         // elements between components
   C* pse;                   // E-side psi (single step: updated in place; two-step sweep: old)
   C* pse_out;               // E-side psi, new (two-step sweep only)
-  C* pse_mid;               // two-step sweep: auxiliaries after the first step (E side)
-  C* psh_mid;               //                                              (H side)
-  const C* psbase;          // two-step sweep: lowest of the six auxiliary regions
+  const C* psbase;          // two-step sweep: lowest of the four auxiliary regions
   uint32_t psi_span;        //                 bytes from psbase to the end of the highest
   const C* psh_in;          // H-side psi, old
   C* psh_out;               // H-side psi, new

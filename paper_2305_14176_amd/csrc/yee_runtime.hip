@@ -95,7 +95,7 @@ struct yee_ctx {
   bool bound = false;
   unsigned char* ws = nullptr;
   int64_t ws_bytes = 0;
-  Region fields[2], psi_e[2], psi_h[2], psi_mid[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
+  Region fields[2], psi_e[2], psi_h[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
       srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
@@ -185,9 +185,6 @@ void layout(yee_ctx* c) {
   take(c->psi_e[1], psib);
   take(c->psi_h[0], psib);
   take(c->psi_h[1], psib);
-  // auxiliaries after the first step of a two-step sweep (E side, H side)
-  take(c->psi_mid[0], psib);
-  take(c->psi_mid[1], psib);
   const size_t np = c->probes.size(), nf = c->freqs.size();
   take(c->series, (size_t)d.series_len * np * sizeof(double));
   take(c->dft, np * nf * 2 * sizeof(double));
@@ -286,10 +283,8 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   a.cstride = c->comp_bytes / sizeof(T);
   a.pse = reinterpret_cast<C*>(c->ws + c->psi_e[c->pecur].off);
   a.pse_out = reinterpret_cast<C*>(c->ws + c->psi_e[c->pecur ^ 1].off);
-  a.pse_mid = reinterpret_cast<C*>(c->ws + c->psi_mid[0].off);
-  a.psh_mid = reinterpret_cast<C*>(c->ws + c->psi_mid[1].off);
   a.psbase = reinterpret_cast<const C*>(c->ws + c->psi_e[0].off);
-  a.psi_span = (uint32_t)(c->psi_mid[1].off + c->psi_mid[1].bytes - c->psi_e[0].off);
+  a.psi_span = (uint32_t)(c->psi_h[1].off + c->psi_h[1].bytes - c->psi_e[0].off);
   a.psh_in = reinterpret_cast<const C*>(c->ws + c->psi_h[cur].off);
   a.psh_out = reinterpret_cast<C*>(c->ws + c->psi_h[nxt].off);
   for (int q = 0; q < 6; ++q) a.psoff[q] = c->psi_off[q];
@@ -372,7 +367,7 @@ yee_status launch_one_step(yee_ctx* c, hipStream_t s, bool record = true) {
 constexpr int kTbMaxRow = 4 * yee::kWave;
 
 size_t tb_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
-  return yee::tb_lds_bytes_for(ty, V, c->tb_wpr, kz);
+  return yee::tb_lds_bytes_for(ty, V, c->tb_wpr, kz, c->d.cpml_cells[0]);
 }
 
 // Most tile rows of a two-step workgroup (ty + 3 rows of wpr waves each).
@@ -525,10 +520,15 @@ void tb_default_launch(yee_ctx* c) {
     }
     if (tb_lds_bytes(c, ty, c->tb_V, kz) > c->lds_limit) continue;
     if (c->tb_kz_req == 0) {
-      // a tile's work, times the rounds of resident workgroups the launch takes
+      // a tile's work times the tiles each CU runs (resident workgroups share
+      // their CU, so a CU's work is what counts)
+      int dev_id = 0, cus = 1;
+      if (hipGetDevice(&dev_id) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess || cus < 1)
+        cus = 1;
       const int64_t tiles = (int64_t)ny_tiles * ((d.nz + kz - 1) / kz);
-      const double rounds = (double)((tiles + slots - 1) / slots);
-      const double cost = rounds * (4.0 * ty + 6.0) * (std::min(kz, d.nz) + 3.0);
+      const double per_cu = (double)((tiles + cus - 1) / cus);
+      const double cost = per_cu * (4.0 * ty + 6.0) * (std::min(kz, d.nz) + 3.0);
       if (best_ty == 0 || cost < best) { best = cost; best_ty = ty; best_kz = kz; }
     } else if (best_ty == 0) {
       best_ty = ty;
@@ -666,18 +666,17 @@ yee_status yee_create(const yee_grid_desc* desc, yee_ctx** out) {
     delete c;
     return fail(YEE_EINVAL, "grid too large: a set of six components must stay below 2 GiB");
   }
-  // ... and the six CPML auxiliary regions (E and H side: two sets each and the
-  // values after the first step of a two-step sweep, laid out consecutively)
-  // under one resource whose out-of-range marker is 2^31: their total must
-  // stay below it
+  // ... and the four CPML auxiliary regions (E and H side, two sets each, laid
+  // out consecutively) under one resource whose out-of-range marker is 2^31:
+  // their total must stay below it
   {
     size_t pl[6];
     psi_lengths(c, pl);
     const uint64_t psib = align256((2 * (pl[0] + pl[1] + pl[3])) * c->csize);
-    if (6 * psib >= (1ull << 31)) {
+    if (4 * psib >= (1ull << 31)) {
       delete c;
-      return fail(YEE_EINVAL, "CPML layers too thick: the six auxiliary regions (%llu bytes) must stay below 2 GiB",
-                  (unsigned long long)(6 * psib));
+      return fail(YEE_EINVAL, "CPML layers too thick: the four auxiliary regions (%llu bytes) must stay below 2 GiB",
+                  (unsigned long long)(4 * psib));
     }
   }
   c->dt = d.courant / (kC0 * std::sqrt(1.0 / (d.dx * d.dx) + 1.0 / (d.dy * d.dy) + 1.0 / (d.dz * d.dz)));

@@ -104,15 +104,21 @@ __device__ __forceinline__ void st_pair_f32(rsrc_t r, uint32_t vo, uint32_t so, 
 //   seam  [5][ty+4]        two waves per row: the values x neighbours take from
 //                          the row's other wave that no row above holds (Ey of
 //                          E^n and E^{n+1} by parity, Hy of H^{n+3/2})
+//   PX[2] [ty+3][4][2Lx]   x-layer auxiliaries after the first step (H: YX, ZX;
+//                          E: YX, ZX) by plane parity
+//   HO    [ty+3][8][64V]   y- and z-layer auxiliaries after the first step (H: XY,
+//                          ZY, XZ, YZ; E: XY, ZY, XZ, YZ); each row's slots are
+//                          read and rewritten by that row's waves only
 //   src   [2][kMaxSources] waveform values of the two steps
 //   tzp   [6][kz+3]        z profiles of the tile's planes (E side 1-b, a, 1/kappa; H side)
 //   txp   [6][64V]         x profiles
 //   typ   [6][ty+3]        y profiles of the tile's rows
 //   int32 tzs, tzl [kz+3]  z block offset, PEC plane index; uint8 tfl [ty+3][kz+3] row flags
-__host__ __device__ inline size_t tb_lds_bytes_for(int ty, int V, int wpr, int kz) {
+__host__ __device__ inline size_t tb_lds_bytes_for(int ty, int V, int wpr, int kz, int Lx) {
   const size_t rl = (size_t)kWave * V * wpr;
   const size_t nr = (size_t)ty + 4, nw = (size_t)ty + 3, npl = (size_t)kz + 3;
-  size_t b = (2 * nr * 2 * rl + 2 * nw * 3 * rl + nr * 2 * rl + 5 * nr + 2 * kMaxSources + 6 * npl + 6 * rl + 6 * nw) * 4;
+  size_t b = (2 * nr * 2 * rl + 2 * nw * 3 * rl + nr * 2 * rl + 5 * nr + 2 * nw * 4 * 2 * (size_t)Lx + nw * 8 * rl +
+              2 * kMaxSources + 6 * npl + 6 * rl + 6 * nw) * 4;
   b += 2 * npl * 4 + nw * npl;
   return (b + 15) & ~size_t(15);
 }
@@ -142,7 +148,10 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
   C* HA0 = X0 + 2 * NR * 2 * RL;
   C* Hb = HA0 + 2 * NW * 3 * RL;
   C* seam = Hb + NR * 2 * RL;            // [5][NR]: Ey^n by parity, Ey^{n+1} by parity, Hy^{n+3/2}
-  C* ldsS = seam + 5 * NR;
+  const int XW = 2 * Lx;
+  C* PX = seam + 5 * NR;                 // [2][NW][4][XW]
+  C* HO = PX + 2 * NW * 4 * XW;          // [NW][8][RL]
+  C* ldsS = HO + NW * 8 * RL;
   C* tzp = ldsS + 2 * kMaxSources;
   C* txp = tzp + 6 * npl;
   C* typ = txp + 6 * RL;
@@ -216,26 +225,27 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
   const uint32_t vrow = (rowA && lane_ok) ? ((uint32_t)jc * (uint32_t)px + (uint32_t)xl) * TB : kOut;
   const uint32_t vxc = (rowA && lane_ok) ? (uint32_t)xl * 2 * CB : kOut;   // y/z-slab pairs
   uint32_t vxs[V], vcf[V];
+  int xs_slot[V];   // the sample's place in the x layer, or -1
   bool lane_inx = false;
 #pragma unroll
   for (int e = 0; e < V; ++e) {
     const int i = xl + e;
     const bool inx = rowA && i < nx && (i < Lx || i >= nx - Lx);
     lane_inx = lane_inx || inx;
-    vxs[e] = inx ? (uint32_t)(i < Lx ? i : i - nx + 2 * Lx) * 2 * CB : kOut;
+    xs_slot[e] = inx ? (i < Lx ? i : i - nx + 2 * Lx) : -1;
+    vxs[e] = inx ? (uint32_t)xs_slot[e] * 2 * CB : kOut;
     vcf[e] = (rowA && i < nx) ? (uint32_t)(a.seg[i] + a.seg[px + jc] * a.nsx) * (uint32_t)sizeof(Coef2<C>) : kOut;
   }
   const uint32_t plane_b = plane * TB;
   const uint32_t cs_b = (uint32_t)(a.cstride * TB);
   const rsrc_t rin = make_rsrc(a.fin, 6 * cs_b);
   const rsrc_t rout = make_rsrc(a.fout, 6 * cs_b);
-  // the six auxiliary regions (E and H side: old, new, after the first step)
-  // under one resource based at the lowest of them (the host keeps their span
-  // below 2 GiB)
+  // the four auxiliary regions (E and H side, old and new) under one resource
+  // based at the lowest of them (the host keeps their span below 2 GiB)
   const char* psb = reinterpret_cast<const char*>(a.psbase);
   auto pof = [&](const C* r) __attribute__((always_inline)) { return (uint32_t)(reinterpret_cast<const char*>(r) - psb); };
-  const uint32_t pe_in = pof(a.pse), pe_out = pof(a.pse_out), pe_mid = pof(a.pse_mid);
-  const uint32_t ph_in = pof(a.psh_in), ph_out = pof(a.psh_out), ph_mid = pof(a.psh_mid);
+  const uint32_t pe_in = pof(a.pse), pe_out = pof(a.pse_out);
+  const uint32_t ph_in = pof(a.psh_in), ph_out = pof(a.psh_out);
   const rsrc_t rpsi = make_rsrc(psb, a.psi_span);
   const rsrc_t rcoef = make_rsrc(a.coef, a.coef_bytes);
   const C idx_ = a.inv_d[0], idy = a.inv_d[1], idz = a.inv_d[2];
@@ -512,11 +522,45 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
     return pm;
   };
 
+  // x-layer auxiliaries between the two steps: through LDS (H side in slots
+  // 0, 1; E side in 2, 3), each lane reading back what it wrote
+  auto px_put = [&](int pr, int c0, const C (&v0)[V], const C (&v1)[V]) __attribute__((always_inline)) {
+    C* b = PX + pr * (NW * 4 * XW) + wv * 4 * XW;
+#pragma unroll
+    for (int e = 0; e < V; ++e)
+      if (xs_slot[e] >= 0) {
+        b[c0 * XW + xs_slot[e]] = v0[e];
+        b[(c0 + 1) * XW + xs_slot[e]] = v1[e];
+      }
+  };
+  auto px_get = [&](int pr, int c0, C (&v0)[V], C (&v1)[V]) __attribute__((always_inline)) {
+    const C* b = PX + pr * (NW * 4 * XW) + wv * 4 * XW;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      v0[e] = xs_slot[e] >= 0 ? b[c0 * XW + xs_slot[e]] : C(0);
+      v1[e] = xs_slot[e] >= 0 ? b[(c0 + 1) * XW + xs_slot[e]] : C(0);
+    }
+  };
+
+  // y- and z-layer auxiliaries between the two steps (slot c0: H side at 0,
+  // E side at 4)
+  C* const myHO = HO + wv * 8 * RL + xl;
+  auto ho_put = [&](int c0, int k, const Aux& u) __attribute__((always_inline)) {
+    if (iny) { lds_put<C, V>(myHO + c0 * RL, u.y0); lds_put<C, V>(myHO + (c0 + 1) * RL, u.y1); }
+    if (in_z(k)) { lds_put<C, V>(myHO + (c0 + 2) * RL, u.z0); lds_put<C, V>(myHO + (c0 + 3) * RL, u.z1); }
+  };
+  auto ho_get = [&](int c0, int k, Aux& u) __attribute__((always_inline)) {
+    if (iny) { lds_get<C, V>(myHO + c0 * RL, u.y0); lds_get<C, V>(myHO + (c0 + 1) * RL, u.y1); }
+    if (in_z(k)) { lds_get<C, V>(myHO + (c0 + 2) * RL, u.z0); lds_get<C, V>(myHO + (c0 + 3) * RL, u.z1); }
+  };
+
   // Memory operations are ordered by need: gfx9 counts outstanding vector
   // loads and stores in one in-order counter, so waiting for a load also waits
-  // for everything issued before it.  Each stage's small loads (auxiliaries,
-  // coefficients) are issued right before the barrier that precedes it; the
-  // plane prefetch goes out after stage A's and is first waited for at stage C.
+  // for everything issued before it.  The old H-side auxiliaries of plane p
+  // are loaded before the first barrier, the E-side ones after stage A, then
+  // the plane prefetch.  Between the two steps the auxiliaries stay in LDS: the
+  // y- and z-layer ones of plane p in the row's slots once the second step of
+  // plane p-1 has read its own, the x-layer ones by plane parity.
   auto march = [&](auto role) __attribute__((always_inline)) {
     constexpr int R = decltype(role)::value;
     constexpr bool BOTTOM = R == 0, TOP = R == 2, MID = R == 1;
@@ -549,10 +593,8 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
 #pragma unroll
     for (int e = 0; e < V; ++e) e0y[e] = e0[1][e];
     if (seam_lo) *seamEy(0, pbeg & 1) = e0[1][0];
-    // old H-side auxiliaries of the first plane
-    Aux uA;
-    aux_zero(uA);
-    if (rowA && pbeg < nz) aux_load(ph_in, pbeg, PHXY, PHXZ, PHYX, uA);
+    // old auxiliaries of the first plane (H side for stage A, E side for B)
+    Aux uA, uB;
 
     for (int p = pbeg; p <= k1; ++p) {
       const int q = p - pbeg;
@@ -561,6 +603,10 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
       const bool doB = !BOTTOM && doA && p >= k0 - 1;
       const bool doC = MID && rowC && p >= k0 && p >= 1;
       const bool doD = MID && rowD && p >= k0 + 1;
+      // old H-side auxiliaries of plane p (their wait also covers the last
+      // plane's stores)
+      aux_zero(uA);
+      if (doA) aux_load(ph_in, p, PHXY, PHXZ, PHYX, uA);
       __syncthreads();   // E^n(p) rows published
 
       // ---- stage A: H^{n+1/2}(p) of rows j0-2 .. j0+ty ----
@@ -576,14 +622,12 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         C eys = C(0), ezs = C(0);
         if constexpr (WPR == 2) { eys = *seamEy(0, par); ezs = rowX0[par * (NR * 2 * RL) + XS]; }
         h_half(ex, e0y, ez, exu, ezu, e1[0], e1[1], h0[0], h0[1], h0[2], in_z(p), q, uA, hA, eys, ezs);
-        // (stage C takes plane p at the next plane)
-        if constexpr (MID) { if (rowC && p >= k0 - 1 && p < k1) aux_store(ph_mid, p, PHXY, PHXZ, PHYX, uA); }
+        // stage C takes plane p at the next plane
+        if constexpr (MID) { if (rowC && p < k1) px_put(par, 0, uA.x0, uA.x1); }
       }
-      // stage B's small loads, then the plane prefetch E^n(p+2), H^{n-1/2}(p+1)
-      Aux uB;
-      aux_zero(uB);
       Coef2<C> cfB[V];
       int plB = -1;
+      aux_zero(uB);
       if constexpr (!BOTTOM) {
         if (doB) {
           aux_load(pe_in, p, PEXY, PEXZ, PEYX, uB);
@@ -592,6 +636,7 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         }
       }
       __builtin_amdgcn_sched_barrier(0);
+      // ---- the plane prefetch: E^n(p+2), H^{n-1/2}(p+1) (the zero plane past the top) ----
       load_E(vrow, min(p + 2, nz), e2);
       load_H(min(p + 1, nz), h1);
       if constexpr (TOP) load_ExEz(vtop, min(p + 1, nz), tp1);
@@ -628,7 +673,7 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
                  hzs);
           if constexpr (MID) {
             if (rowD && p >= k0 && p < k1) {   // stage D takes plane p at the next plane
-              aux_store(pe_mid, p, PEXY, PEXZ, PEYX, uB);
+              px_put(par, 2, uB.x0, uB.x1);
               record(p, q, eB, hA, a.series_slot);
             }
           }
@@ -637,22 +682,20 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         lds_put<C, V>(myX(par) + RL, eB[0]);
         if (seam_lo) *seamEy(1, par) = eB[1][0];
       }
-      // stage C's auxiliaries (after the first step of plane p-1)
-      Aux uC;
-      aux_zero(uC);
-      if constexpr (MID) { if (doC) aux_load(ph_mid, p - 1, PHXY, PHXZ, PHYX, uC); }
       __syncthreads();
 
       // ---- stage C: H^{n+3/2}(p-1) of rows j0-1 .. j0+ty-1 ----
       C hC[3][V];
-      Aux uD;
-      aux_zero(uD);
       Coef2<C> cfD[V];
       int plD = -1;
       if constexpr (MID) {
 #pragma unroll
         for (int e = 0; e < V; ++e) { hC[0][e] = C(0); hC[1][e] = C(0); hC[2][e] = C(0); }
         if (doC) {
+          Aux uC;
+          aux_zero(uC);
+          ho_get(0, p - 1, uC);
+          px_get(par ^ 1, 0, uC.x0, uC.x1);
           C ex[V], ez[V], exu[V], ezu[V], exz[V], hx[V], hy[V], hz[V];
           lds_get<C, V>(myX(par ^ 1), ez);              // E^{n+1}(p-1)
           lds_get<C, V>(myX(par ^ 1) + RL, ex);
@@ -667,12 +710,12 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
           h_half(ex, eByp, ez, exu, ezu, exz, eB[1], hx, hy, hz, in_z(p - 1), q - 1, uC, hC, eys, ezs);
           if (doD) aux_store(ph_out, p - 1, PHXY, PHXZ, PHYX, uC);
         }
+        // plane p's first-step H-side auxiliaries replace plane p-1's
+        if (rowC && p < k1 && doA) ho_put(0, p, uA);
         lds_put<C, V>(myHb, hC[2]);
         lds_put<C, V>(myHb + RL, hC[0]);
         if (seam_hi) *seamHy = hC[1][V - 1];
-        // stage D's small loads
         if (doD) {
-          aux_load(pe_mid, p - 1, PEXY, PEXZ, PEYX, uD);
           load_coef(q - 1, cfD);
           plD = uniform(tzl[q - 1]);
         }
@@ -687,7 +730,11 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         lds_get<C, V>(myX(par ^ 1) + RL, ex);
 #pragma unroll
         for (int e = 0; e < V; ++e) { eD[0][e] = ex[e]; eD[1][e] = eByp[e]; eD[2][e] = ez[e]; }
+        Aux uD;
         if (doD) {
+          aux_zero(uD);
+          ho_get(4, p - 1, uD);
+          px_get(par ^ 1, 2, uD.x0, uD.x1);
           const uint32_t pmD = load_mask(plD);
           C hxd[V], hzd[V];
           lds_get<C, V>(myHb - RL, hxd);                // row j-1
@@ -696,13 +743,11 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
           if constexpr (WPR == 2) { hys = *seamHy; hzs = rowHb[XS - 1]; }
           e_half(ex, eByp, ez, hC[0], hC[1], hC[2], hxd, hzd, hCp[0], hCp[1], p - 1, in_z(p - 1), q - 1, cfD, plD,
                  pmD, 1, uD, eD, hys, hzs);
-          aux_store(pe_out, p - 1, PEXY, PEXZ, PEYX, uD);
           record(p - 1, q - 1, eD, hC, a.series_slot2);
         }
-        // next plane's old H-side auxiliaries, issued before this plane's
-        // field stores so that stage A's wait for them leaves the stores in flight
-        aux_zero(uA);
-        if (rowA && p + 1 < nz && p + 1 <= k1) aux_load(ph_in, p + 1, PHXY, PHXZ, PHYX, uA);
+        // plane p's first-step E-side auxiliaries replace plane p-1's
+        if (rowD && p >= k0 && p < k1) ho_put(4, p, uB);
+        if (doD) aux_store(pe_out, p - 1, PEXY, PEXZ, PEYX, uD);
         // the field stores are issued at every plane (every lane out of range
         // where nothing is owned), so each iteration issues the same operations
         const uint32_t vst = doD ? vrow : kOut;
@@ -713,9 +758,6 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         st_row<T, C, V>(rout, vst, so + 3 * cs_b, hC[0], a.enc[3]);
         st_row<T, C, V>(rout, vst, so + 4 * cs_b, hC[1], a.enc[4]);
         st_row<T, C, V>(rout, vst, so + 5 * cs_b, hC[2], a.enc[5]);
-      } else {
-        aux_zero(uA);
-        if (rowA && p + 1 < nz && p + 1 <= k1) aux_load(ph_in, p + 1, PHXY, PHXZ, PHYX, uA);
       }
 
       // ---- publish E^n(p+1) for the next stage A; advance the window ----

@@ -89,7 +89,7 @@ def _check_bitwise(one, two, steps):
     ((100, 21, 18), (6, 2, 0), 8, None),         # two samples per lane, no z layer
     ((200, 30, 40), (10, 5, 7), 11, None),       # four samples per lane, several y-tiles and chunks
     ((256, 20, 33), (10, 10, 10), 6, {"sweep_rows": 3, "sweep_planes": 4}),
-    ((256, 20, 33), (10, 10, 10), 6, {"sweep_rows": 5, "sweep_planes": 64}),   # one chunk taller than the grid
+    ((256, 20, 33), (10, 10, 10), 6, {"sweep_rows": 4, "sweep_planes": 64}),   # one chunk taller than the grid
     ((64, 12, 9), (0, 0, 0), 7, {"sweep_rows": 1, "sweep_planes": 1}),          # PEC box, one-row tiles
     ((2, 2, 2), (0, 0, 0), 5, None),             # smallest grid
 ])
