@@ -132,8 +132,18 @@ yee_status yee_upload_materials(yee_ctx* ctx, void* stream);
 
 /* PEC mask on the z-plane k (0 < k < nz): mask[j * nx + i] bit 0 holds Ex,
  * bit 1 Ey, bit 2 Ez of sample (i, j, k) at Ca = Cb = 0 (the sample stays 0).
- * Only before yee_bind_workspace(). */
+ * A plane given again is merged (OR).  Only before yee_bind_workspace(). */
 yee_status yee_add_pec_plane(yee_ctx* ctx, int32_t k, const uint8_t* mask);
+
+/* Volume PEC mask: mask[(k * ny + j) * nx + i] bit 0 holds Ex, bit 1 Ey,
+ * bit 2 Ez of sample (i, j, k) at Ca = Cb = 0 (the update leaves 0 there; a
+ * source on the sample still adds after it), for every k in [0, nz)
+ * (Ez of plane 0 lies inside the box; Ex and Ey of plane 0 are on the PEC
+ * face anyway).  Other bits set: YEE_EINVAL.  The mask is merged (OR) with
+ * plane masks of yee_add_pec_plane(); the device holds ny * nx bytes per
+ * z-plane with a set bit and none for the others.  Only before
+ * yee_bind_workspace(). */
+yee_status yee_set_pec_mask(yee_ctx* ctx, const uint8_t* mask);
 
 /* Soft source (see yee_source).  Only before yee_bind_workspace(). */
 yee_status yee_add_source(yee_ctx* ctx, const yee_source* src);
@@ -163,7 +173,10 @@ yee_status yee_bind_workspace(yee_ctx* ctx, void* device_ptr, int64_t bytes);
 yee_status yee_reset(yee_ctx* ctx, void* stream);
 
 /* Overwrite one component (initial E^0 or H^{-1/2}) from host[nz][ny][nx].
- * Synchronizes the stream.  In YEE_F16S the values are rounded to storage. */
+ * Synchronizes the stream.  In YEE_F16S the values are rounded to storage;
+ * a finite value with |x 2^fp16_exp| > 65504 returns YEE_EOVERFLOW and
+ * nothing is written.  Non-finite values are stored as given (and reported
+ * by yee_status_flags()). */
 yee_status yee_set_field(yee_ctx* ctx, int32_t component, const double* host, void* stream);
 
 /* Advance n_steps leapfrog steps (E^n, H^{n-1/2}) -> (E^{n+1}, H^{n+1/2}).
@@ -184,6 +197,42 @@ yee_status yee_read_series(yee_ctx* ctx, int64_t first, int64_t count, double* h
 
 /* DFT accumulators into re[n_probes][nf], im[n_probes][nf].  Synchronizes. */
 yee_status yee_read_dft(yee_ctx* ctx, double* re, double* im, void* stream);
+
+/* Health of the run: folds the probe samples not yet in the DFT, then scans
+ * the current fields, the probe ring and the DFT accumulators, and writes the
+ * context's sticky flags (cleared by yee_reset(), saved with the state):
+ *   YEE_FLAG_NONFINITE  a NaN or infinity (FP16 storage: a NaN) is in the
+ *                       fields, the probe ring or the DFT now, or was in a
+ *                       probe sample folded into the DFT since the reset;
+ *   YEE_FLAG_OVERFLOW   FP16 storage holds an infinity: some update produced
+ *                       |x 2^fp16_exp| >= 65520, which rounds past the
+ *                       largest finite fp16 (65504).
+ * Returns YEE_EOVERFLOW if YEE_FLAG_OVERFLOW is set, else YEE_ENUMERIC if
+ * YEE_FLAG_NONFINITE is set, else YEE_OK (flags are written in every case).
+ * Reads the field set once (about the traffic of a third of a step);
+ * synchronizes the stream. */
+#define YEE_FLAG_NONFINITE 1u
+#define YEE_FLAG_OVERFLOW 2u
+yee_status yee_status_flags(yee_ctx* ctx, uint32_t* flags, void* stream);
+
+/* Saved state (checkpoint/restart of a run): the current fields, CPML
+ * auxiliaries, probe ring, DFT accumulators, status flags and the step and
+ * fold counters, in one device buffer of yee_state_bytes() bytes (any
+ * alignment) that the caller owns.  Materials, sources, probe positions and
+ * frequencies are configuration, not state: a state loads into any bound
+ * context of the same shape (grid, precision, CPML thickness, FP16
+ * exponents, probe and frequency counts, ring length), which then continues
+ * exactly as the saved one would have (fields and probe series bitwise; the
+ * DFT sums in another order where the fold points differ).
+ * yee_save_state: asynchronous on `stream` (a header kernel and device
+ * copies); YEE_ENOMEM if bytes is too small.
+ * yee_load_state: reads and checks the header (synchronizes the stream), then
+ * queues the copies on `stream`; YEE_EINVAL for a buffer that is not a saved
+ * state or is of another shape, YEE_ESTATE while the context is admitted to
+ * a batch.  The source must stay valid until the stream passes the copies. */
+yee_status yee_state_bytes(const yee_ctx* ctx, int64_t* bytes);
+yee_status yee_save_state(yee_ctx* ctx, void* device_dst, int64_t bytes, void* stream);
+yee_status yee_load_state(yee_ctx* ctx, const void* device_src, int64_t bytes, void* stream);
 
 /* Port voltages and scattering parameters from two runs' probe DFTs (the
  * "S-parameter accumulators" are the running DFTs above; this combines them on

@@ -16,15 +16,17 @@ YEE_OK = 0
 STATUS_NAMES = {0: "YEE_OK", -1: "YEE_EINVAL", -2: "YEE_ENOMEM", -3: "YEE_EHIP", -4: "YEE_ESTATE",
                 -5: "YEE_ENUMERIC", -6: "YEE_EAGAIN", -7: "YEE_EOVERFLOW"}
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2}
+FLAG_NONFINITE = 1     # YEE_FLAG_NONFINITE
+FLAG_OVERFLOW = 2      # YEE_FLAG_OVERFLOW
 WAVEFORMS = {"gauss_deriv": 0, "mod_gauss": 1}
 
 # Every symbol include/yee.h declares (checked by the CPU test suite).
 EXPORTED = (
     "yee_last_error", "yee_api_version", "yee_create", "yee_destroy", "yee_time_step",
-    "yee_set_materials", "yee_upload_materials", "yee_add_pec_plane", "yee_add_source",
+    "yee_set_materials", "yee_upload_materials", "yee_add_pec_plane", "yee_set_pec_mask", "yee_add_source",
     "yee_add_probe", "yee_set_dft_freqs", "yee_footprint", "yee_bind_workspace", "yee_reset",
     "yee_set_field", "yee_step", "yee_steps_done", "yee_read_field", "yee_read_series",
-    "yee_read_dft", "yee_sparams", "yee_set_launch", "yee_set_time_blocking", "yee_launch_info",
+    "yee_read_dft", "yee_status_flags", "yee_state_bytes", "yee_save_state", "yee_load_state", "yee_sparams", "yee_set_launch", "yee_set_time_blocking", "yee_launch_info",
     "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
     "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
     "yee_batch_info", "yee_adjoint_create", "yee_adjoint_destroy", "yee_adjoint_footprint",
@@ -84,6 +86,7 @@ def load():
         "yee_set_materials": (I32, [VP, I32, I32, I32, P(I32), P(I32), P(I32), P(D), P(D)]),
         "yee_upload_materials": (I32, [VP, VP]),
         "yee_add_pec_plane": (I32, [VP, I32, P(C.c_uint8)]),
+        "yee_set_pec_mask": (I32, [VP, P(C.c_uint8)]),
         "yee_add_source": (I32, [VP, P(SourceDesc)]),
         "yee_add_probe": (I32, [VP, I32, I32, I32, I32, P(I32)]),
         "yee_set_dft_freqs": (I32, [VP, P(D), I32]),
@@ -96,6 +99,10 @@ def load():
         "yee_read_field": (I32, [VP, I32, P(D), VP]),
         "yee_read_series": (I32, [VP, I64, I64, P(D), VP]),
         "yee_read_dft": (I32, [VP, P(D), P(D), VP]),
+        "yee_status_flags": (I32, [VP, P(C.c_uint32), VP]),
+        "yee_state_bytes": (I32, [VP, P(I64)]),
+        "yee_save_state": (I32, [VP, VP, I64, VP]),
+        "yee_load_state": (I32, [VP, VP, I64, VP]),
         "yee_sparams": (I32, [I32, I32, P(D), P(D), P(D), P(D), I32, P(I32), P(I32), P(D),
                               P(D), P(D), P(D), P(D), P(D), P(D)]),
         "yee_set_launch": (I32, [VP, I32, I32, I32]),

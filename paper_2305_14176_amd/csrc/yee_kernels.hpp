@@ -959,10 +959,15 @@ batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __res
 // samples of the chunk, partial sums meet in a butterfly of lane shuffles.
 // X_p(f) += sum_n y_p[n] exp(-i 2 pi f n dt) dt for n = n_first .. n_first+count-1.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kFlagNonFinite = 1u;   // a NaN or infinity was found
+constexpr uint32_t kFlagOverflow = 2u;    // FP16 storage overflowed (an infinity)
+
+// The wave of frequency 0 also checks the probe's samples and sets bit 0 of
+// *flags when one is not finite.
 __global__ void __launch_bounds__(256)
 dft_fold_kernel(const double* __restrict__ series, int nprobe, int series_len, int64_t n_first,
                 int count, const double* __restrict__ freqs, int nf, double dt,
-                double2* __restrict__ acc) {
+                double2* __restrict__ acc, uint32_t* __restrict__ flags) {
   const int wid = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wid >= nprobe * nf) return;
@@ -970,9 +975,11 @@ dft_fold_kernel(const double* __restrict__ series, int nprobe, int series_len, i
   const int m = wid % nf;
   const double fdt = freqs[m] * dt;
   double re = 0.0, im = 0.0;
+  bool bad = false;
   for (int s = lane; s < count; s += kWave) {
     const int64_t n = n_first + s;                  // 1-based step number
     const double y = series[(size_t)((n - 1) % series_len) * nprobe + p];
+    bad |= !isfinite(y);
     double ph = fdt * (double)n;                    // cycles
     ph -= floor(ph);
     double sn, cs;
@@ -985,12 +992,69 @@ dft_fold_kernel(const double* __restrict__ series, int nprobe, int series_len, i
     re += __shfl_xor(re, o, kWave);
     im += __shfl_xor(im, o, kWave);
   }
+  if (m == 0 && __ballot(bad) != 0 && lane == 0) atomicOr(flags, kFlagNonFinite);
   if (lane == 0) {
     double2 v = acc[wid];
     v.x += re * dt;
     v.y += im * dt;
     acc[wid] = v;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Status scan: ORs into *flags what it finds in two ranges of 16-byte words,
+// a field set in its storage format (kind 0 FP64, 1 FP32, 2 FP16) and a run
+// of FP64 values (probe ring and DFT accumulators):
+//   kFlagNonFinite  a NaN or an infinity (FP16 storage: a NaN),
+//   kFlagOverflow   an infinity in FP16 storage, i.e. a value whose scaled
+//                   magnitude rounded past the largest finite fp16 (65504).
+// Classification works on the bit patterns (exponent field all ones).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t classify_word(uint4 w, int kind) {
+  uint32_t f = 0u;
+  const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+  if (kind == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; q += 2)
+      f |= ((u[q + 1] & 0x7ff00000u) == 0x7ff00000u) ? kFlagNonFinite : 0u;   // high word of each double
+  } else if (kind == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f |= ((u[q] & 0x7f800000u) == 0x7f800000u) ? kFlagNonFinite : 0u;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t b = (u[q] >> (16 * h)) & 0xffffu;
+        if ((b & 0x7c00u) == 0x7c00u) f |= (b & 0x03ffu) ? kFlagNonFinite : kFlagOverflow;
+      }
+  }
+  return f;
+}
+
+__global__ void __launch_bounds__(256)
+status_scan_kernel(const uint4* __restrict__ fld, size_t nfld, int kind, const uint4* __restrict__ dbl,
+                   size_t ndbl, uint32_t* __restrict__ flags) {
+  uint32_t f = 0u;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfld; i += stride)
+    f |= classify_word(fld[i], kind);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ndbl; i += stride)
+    f |= classify_word(dbl[i], 0);
+  const uint64_t b0 = __ballot((f & kFlagNonFinite) != 0u);
+  const uint64_t b1 = __ballot((f & kFlagOverflow) != 0u);
+  if ((threadIdx.x & (kWave - 1)) == 0 && (b0 | b1))
+    atomicOr(flags, (b0 ? kFlagNonFinite : 0u) | (b1 ? kFlagOverflow : 0u));
+}
+
+// Writes a saved state's header: 32 64-bit words passed by value (no host
+// staging buffer has to outlive the launch).
+struct StateHeader {
+  int64_t w[32];
+};
+
+__global__ void state_header_kernel(StateHeader h, int64_t* __restrict__ dst) {
+  if (threadIdx.x < 32) dst[threadIdx.x] = h.w[threadIdx.x];
 }
 
 }  // namespace yee

@@ -95,7 +95,7 @@ struct yee_ctx {
   bool bound = false;
   unsigned char* ws = nullptr;
   int64_t ws_bytes = 0;
-  Region fields[2], psi_e[2], psi_h[2], series, dft, segr, coef, prof, pecplane, pecmask, rowflag,
+  Region fields[2], psi_e[2], psi_h[2], series, dft, stat, segr, coef, prof, pecplane, pecmask, rowflag,
       srcr, prober, freqr;
   size_t comp_bytes = 0;   // one component array
   size_t psi_len[6] = {};  // elements of each psi array (same for E and H side)
@@ -107,6 +107,7 @@ struct yee_ctx {
   // field set and H-side auxiliary set (cur); the E-side auxiliaries are
   // updated in place by a single step and ping-ponged by a sweep (pecur)
   int cur = 0, pecur = 0;
+  bool in_batch = false;   // admitted to a batch (yee_load_state refuses)
 };
 
 struct yee_batch {
@@ -188,6 +189,7 @@ void layout(yee_ctx* c) {
   const size_t np = c->probes.size(), nf = c->freqs.size();
   take(c->series, (size_t)d.series_len * np * sizeof(double));
   take(c->dft, np * nf * 2 * sizeof(double));
+  take(c->stat, sizeof(uint32_t));   // status flags (yee_status_flags), last of the state run
   take(c->segr, ((size_t)c->px + d.ny + d.nz) * 4);
   take(c->coef, (size_t)c->nsx * c->nsy * c->nsz * 2 * c->csize);
   c->prof_len = std::max({d.nx, d.ny, d.nz}) + 1;
@@ -410,7 +412,8 @@ yee_status fold_dft(yee_ctx* c, hipStream_t s) {
     hipLaunchKernelGGL(yee::dft_fold_kernel, dim3(blocks), dim3(256), 0, s,
                        reinterpret_cast<const double*>(c->ws + c->series.off), np, c->d.series_len,
                        c->folded + 1, (int)count, reinterpret_cast<const double*>(c->ws + c->freqr.off),
-                       nf, c->dt, reinterpret_cast<double2*>(c->ws + c->dft.off));
+                       nf, c->dt, reinterpret_cast<double2*>(c->ws + c->dft.off),
+                       reinterpret_cast<uint32_t*>(c->ws + c->stat.off));
     HIP_TRY(hipGetLastError());
   }
   c->folded = c->n;
@@ -727,17 +730,45 @@ yee_status yee_upload_materials(yee_ctx* c, void* stream) {
   return upload_materials_impl(c, (hipStream_t)stream);
 }
 
+namespace {
+
+// The mask of z-plane k ([ny][px] bytes), added (all clear) on first use.
+std::vector<uint8_t>& pec_plane_mask(yee_ctx* c, int k) {
+  auto it = std::find(c->pec_k.begin(), c->pec_k.end(), k);
+  if (it != c->pec_k.end()) return c->pec_masks[(size_t)(it - c->pec_k.begin())];
+  c->pec_k.push_back(k);
+  c->pec_masks.emplace_back((size_t)c->d.ny * c->px, (uint8_t)0);
+  return c->pec_masks.back();
+}
+
+}  // namespace
+
 yee_status yee_add_pec_plane(yee_ctx* c, int32_t k, const uint8_t* mask) {
   if (!c || !mask) return fail(YEE_EINVAL, "NULL argument");
   if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
   if (k <= 0 || k >= c->d.nz) return fail(YEE_EINVAL, "PEC plane k = %d not in (0, nz)", k);
-  if (std::find(c->pec_k.begin(), c->pec_k.end(), k) != c->pec_k.end())
-    return fail(YEE_EINVAL, "PEC plane %d given twice", k);
-  c->pec_k.push_back(k);
-  std::vector<uint8_t> m((size_t)c->d.ny * c->px, 0);
+  std::vector<uint8_t>& m = pec_plane_mask(c, k);
   for (int j = 0; j < c->d.ny; ++j)
-    for (int i = 0; i < c->d.nx; ++i) m[(size_t)j * c->px + i] = mask[(size_t)j * c->d.nx + i] & 7;
-  c->pec_masks.push_back(std::move(m));
+    for (int i = 0; i < c->d.nx; ++i) m[(size_t)j * c->px + i] |= mask[(size_t)j * c->d.nx + i] & 7;
+  return YEE_OK;
+}
+
+yee_status yee_set_pec_mask(yee_ctx* c, const uint8_t* mask) {
+  if (!c || !mask) return fail(YEE_EINVAL, "NULL argument");
+  if (c->bound) return fail(YEE_ESTATE, "configuration is frozen once the workspace is bound");
+  const auto& d = c->d;
+  const size_t plane = (size_t)d.nx * d.ny;
+  for (size_t q = 0; q < plane * d.nz; ++q)
+    if (mask[q] & ~7u) return fail(YEE_EINVAL, "mask byte %zu has bits other than 0..2 set", q);
+  // one plane mask per z-plane that holds a set bit, merged with planes
+  // already given by yee_add_pec_plane
+  for (int k = 0; k < d.nz; ++k) {
+    const uint8_t* mk = mask + (size_t)k * plane;
+    if (std::all_of(mk, mk + plane, [](uint8_t v) { return v == 0; })) continue;
+    std::vector<uint8_t>& m = pec_plane_mask(c, k);
+    for (int j = 0; j < d.ny; ++j)
+      for (int i = 0; i < d.nx; ++i) m[(size_t)j * c->px + i] |= mk[(size_t)j * d.nx + i];
+  }
   return YEE_OK;
 }
 
@@ -856,8 +887,8 @@ yee_status yee_reset(yee_ctx* c, void* stream) {
   if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
   hipStream_t s = (hipStream_t)stream;
   const auto& d = c->d;
-  // state: both field sets, psi, series, dft (one contiguous run) -- zeroed
-  const size_t state_end = c->dft.off + align256(std::max<size_t>(c->dft.bytes, 1));
+  // state: both field sets, psi, series, dft, status flags (one contiguous run) -- zeroed
+  const size_t state_end = c->stat.off + align256(c->stat.bytes);
   HIP_TRY(hipMemsetAsync(c->ws, 0, state_end, s));
   yee_status st = upload_materials_impl(c, s);
   if (st) return st;
@@ -918,7 +949,13 @@ yee_status yee_set_field(yee_ctx* c, int32_t comp, const double* host, void* str
   } else if (d.precision == YEE_F32) {
     host_to_storage<float>(host, buf, d, c->px, 1.0f);
   } else {
-    // round from double directly to fp16 (nearest even) after exact scaling
+    // round from double directly to fp16 (nearest even) after exact scaling;
+    // a finite value beyond the format's range is refused (NaN and infinities
+    // are stored as given and reported by yee_status_flags)
+    for (size_t q = 0; q < (size_t)d.nz * d.ny * d.nx; ++q)
+      if (std::isfinite(host[q]) && std::fabs(host[q] * (double)enc) > 65504.0)
+        return fail(YEE_EOVERFLOW, "component %d: |value x 2^%d| = %g exceeds the fp16 range (65504)", comp,
+                    d.fp16_exp[comp], std::fabs(host[q] * (double)enc));
     _Float16* o = reinterpret_cast<_Float16*>(buf.data());
     for (size_t k = 0; k < (size_t)d.nz; ++k)
       for (size_t j = 0; j < (size_t)d.ny; ++j)
@@ -1025,6 +1062,148 @@ yee_status yee_read_dft(yee_ctx* c, double* re, double* im, void* stream) {
   return YEE_OK;
 }
 
+static_assert(YEE_FLAG_NONFINITE == yee::kFlagNonFinite && YEE_FLAG_OVERFLOW == yee::kFlagOverflow,
+              "status flag bits of the ABI and the kernels differ");
+
+yee_status yee_status_flags(yee_ctx* c, uint32_t* flags, void* stream) {
+  if (!c || !flags) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  hipStream_t s = (hipStream_t)stream;
+  // folding checks the probe samples not yet in the DFT
+  yee_status st = fold_dft(c, s);
+  if (st) return st;
+  const int kind = c->d.precision == YEE_F64 ? 0 : c->d.precision == YEE_F32 ? 1 : 2;
+  const size_t nfld = 6 * c->comp_bytes / 16;
+  // the probe ring and the DFT accumulators (256-byte aligned, the gap zero)
+  const size_t ndbl = (c->dft.off + c->dft.bytes - c->series.off) / 16;
+  const size_t words = std::max(nfld, ndbl);
+  const int blocks = (int)std::min<size_t>(2048, std::max<size_t>(1, (words + 255) / 256));
+  uint32_t* dflags = reinterpret_cast<uint32_t*>(c->ws + c->stat.off);
+  hipLaunchKernelGGL(yee::status_scan_kernel, dim3(blocks), dim3(256), 0, s,
+                     reinterpret_cast<const uint4*>(c->ws + c->fields[c->cur].off), nfld, kind,
+                     reinterpret_cast<const uint4*>(c->ws + c->series.off), ndbl, dflags);
+  HIP_TRY(hipGetLastError());
+  uint32_t f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, dflags, sizeof f, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *flags = f;
+  if (f & YEE_FLAG_OVERFLOW)
+    return fail(YEE_EOVERFLOW, "a field sample overflowed FP16 storage by step %lld", (long long)c->n);
+  if (f & YEE_FLAG_NONFINITE) return fail(YEE_ENUMERIC, "a non-finite value by step %lld", (long long)c->n);
+  return YEE_OK;
+}
+
+namespace {
+
+constexpr int64_t kStateMagic = 0x3154415453454559LL;   // "YEESTAT1"
+constexpr int kStateWords = 32;                         // header: 32 int64 (256 bytes)
+constexpr int kStateShapeWords = 22;                    // words that must match on load
+
+struct StateLayout {
+  size_t fields, pse, psh, series, dft, stat, total;
+};
+
+StateLayout state_layout(const yee_ctx* c) {
+  StateLayout L{};
+  size_t off = kStateWords * sizeof(int64_t);
+  auto take = [&](size_t& at, size_t bytes) {
+    at = off;
+    off += align256(bytes);
+  };
+  take(L.fields, 6 * c->comp_bytes);
+  take(L.pse, c->psi_e[0].bytes);
+  take(L.psh, c->psi_h[0].bytes);
+  take(L.series, c->series.bytes);
+  take(L.dft, c->dft.bytes);
+  take(L.stat, c->stat.bytes);
+  L.total = off;
+  return L;
+}
+
+// Header words: 0..21 describe the shape of the state, 24 and 25 the step
+// and fold counters.
+void state_words(const yee_ctx* c, int64_t w[kStateWords]) {
+  const auto& d = c->d;
+  std::fill(w, w + kStateWords, int64_t(0));
+  w[0] = kStateMagic;
+  w[1] = YEE_API_VERSION;
+  w[2] = d.nx; w[3] = d.ny; w[4] = d.nz;
+  w[5] = c->px;
+  w[6] = d.precision;
+  for (int q = 0; q < 3; ++q) w[7 + q] = d.cpml_cells[q];
+  for (int q = 0; q < 6; ++q) w[10 + q] = d.precision == YEE_F16S ? d.fp16_exp[q] : 0;
+  w[16] = (int64_t)c->probes.size();
+  w[17] = (int64_t)c->freqs.size();
+  w[18] = d.series_len;
+  w[19] = (int64_t)c->comp_bytes;
+  w[20] = (int64_t)c->psi_e[0].bytes;
+  w[21] = (int64_t)state_layout(c).total;
+  w[24] = c->n;
+  w[25] = c->folded;
+}
+
+}  // namespace
+
+yee_status yee_state_bytes(const yee_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  *bytes = (int64_t)state_layout(c).total;
+  return YEE_OK;
+}
+
+yee_status yee_save_state(yee_ctx* c, void* dst, int64_t bytes, void* stream) {
+  if (!c || !dst) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  const StateLayout L = state_layout(c);
+  if (bytes < (int64_t)L.total) return fail(YEE_ENOMEM, "state needs %zu bytes, got %lld", L.total, (long long)bytes);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* o = static_cast<unsigned char*>(dst);
+  yee::StateHeader h{};
+  state_words(c, h.w);
+  hipLaunchKernelGGL(yee::state_header_kernel, dim3(1), dim3(64), 0, s, h, reinterpret_cast<int64_t*>(o));
+  HIP_TRY(hipGetLastError());
+  const struct { size_t to; const Region& from; size_t n; } parts[] = {
+      {L.fields, c->fields[c->cur], 6 * c->comp_bytes}, {L.pse, c->psi_e[c->pecur], c->psi_e[0].bytes},
+      {L.psh, c->psi_h[c->cur], c->psi_h[0].bytes},      {L.series, c->series, c->series.bytes},
+      {L.dft, c->dft, c->dft.bytes},                     {L.stat, c->stat, c->stat.bytes}};
+  for (const auto& p : parts)
+    if (p.n) HIP_TRY(hipMemcpyAsync(o + p.to, c->ws + p.from.off, p.n, hipMemcpyDeviceToDevice, s));
+  return YEE_OK;
+}
+
+yee_status yee_load_state(yee_ctx* c, const void* src, int64_t bytes, void* stream) {
+  if (!c || !src) return fail(YEE_EINVAL, "NULL argument");
+  if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
+  if (c->in_batch) return fail(YEE_ESTATE, "context is admitted to a batch");
+  const StateLayout L = state_layout(c);
+  if (bytes < (int64_t)L.total) return fail(YEE_ENOMEM, "state needs %zu bytes, got %lld", L.total, (long long)bytes);
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned char* in = static_cast<const unsigned char*>(src);
+  int64_t got[kStateWords], want[kStateWords];
+  HIP_TRY(hipMemcpyAsync(got, in, sizeof got, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  state_words(c, want);
+  if (got[0] != kStateMagic) return fail(YEE_EINVAL, "not a saved state (bad magic)");
+  for (int q = 1; q < kStateShapeWords; ++q)
+    if (got[q] != want[q])
+      return fail(YEE_EINVAL, "state was saved from a context of another shape (header word %d: %lld, here %lld)", q,
+                  (long long)got[q], (long long)want[q]);
+  const int64_t n = got[24], folded = got[25];
+  if (n < 0 || folded < 0 || folded > n || n - folded > c->d.series_len)
+    return fail(YEE_EINVAL, "corrupt state header (steps %lld, folded %lld)", (long long)n, (long long)folded);
+  const struct { Region& to; size_t from; size_t n; } parts[] = {
+      {c->fields[0], L.fields, 6 * c->comp_bytes}, {c->psi_e[0], L.pse, c->psi_e[0].bytes},
+      {c->psi_h[0], L.psh, c->psi_h[0].bytes},      {c->series, L.series, c->series.bytes},
+      {c->dft, L.dft, c->dft.bytes},                {c->stat, L.stat, c->stat.bytes}};
+  for (const auto& p : parts)
+    if (p.n) HIP_TRY(hipMemcpyAsync(c->ws + p.to.off, in + p.from, p.n, hipMemcpyDeviceToDevice, s));
+  c->cur = 0;
+  c->pecur = 0;
+  c->n = n;
+  c->folded = folded;
+  return YEE_OK;
+}
+
 yee_status yee_sparams(int32_t n_probes, int32_t n_freq, const double* dft_ref_re, const double* dft_ref_im,
                        const double* dft_dut_re, const double* dft_dut_im, int32_t n_ports,
                        const int32_t* port_off, const int32_t* port_probe, const double* port_weight,
@@ -1090,6 +1269,8 @@ yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps
 
 void yee_batch_destroy(yee_batch* b) {
   if (!b) return;
+  for (auto& sl : b->slots)
+    if (sl.used && sl.ctx) sl.ctx->in_batch = false;
   for (int i = 0; i < 2; ++i) {
     if (b->staged[i]) {
       (void)hipEventSynchronize(b->staged[i]);
@@ -1164,6 +1345,7 @@ yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* s
     sl.n_end = c->n + n_steps;
     sl.bytes = c->ws_bytes;
     sl.ty = batch_tile_rows(c);
+    c->in_batch = true;
     b->in_use += sl.bytes;
     *slot = q;
     return YEE_OK;
@@ -1268,6 +1450,7 @@ yee_status yee_batch_release(yee_batch* b, int32_t slot) {
   auto& sl = b->slots[slot];
   if (!sl.used) return fail(YEE_ESTATE, "slot %d is free", slot);
   b->in_use -= sl.bytes;
+  sl.ctx->in_batch = false;
   sl = yee_batch::Slot{};
   return YEE_OK;
 }

@@ -10,9 +10,12 @@ replayed from a HIP graph) the server
     grids stay within it (a request is always admitted when nothing runs).
     The cell cap bounds how many grids share the device, so a large request
     is not slowed by many concurrent ones while small ones still batch.
-Field state stays resident on the device for the life of a request.  The
-plain alternative, :func:`serve_one_at_a_time`, solves requests first come
-first served with one ``yee_step`` call each.
+Field state stays resident on the device for the life of a request.  A
+request may carry initial fields.  When it finishes, the run's health is
+checked (``yee_status_flags``: a non-finite value, an FP16 overflow); a
+failing request gets ``status`` and ``error`` set and does not disturb the
+others.  The plain alternative, :func:`serve_one_at_a_time`, solves requests
+first come first served with one ``yee_step`` call each.
 """
 from __future__ import annotations
 
@@ -46,10 +49,29 @@ class Request:
     series: Optional[np.ndarray] = None
     dft: Optional[np.ndarray] = None
     fields: dict = field(default_factory=dict)
+    init: Optional[dict] = None               # component -> initial field [nx, ny, nz]
+    status: int = 0                           # 0, or YEE_ENUMERIC / YEE_EOVERFLOW
+    error: Optional[str] = None
+
+    @property
+    def failed(self) -> bool:
+        return self.status != 0
 
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+
+def _set_initial(req: Request, solver: YeeSolver):
+    for comp, arr in (req.init or {}).items():
+        solver.set_field(comp, arr)
+
+
+def _check_health(req: Request, solver: YeeSolver):
+    st, flags, msg = solver.status()
+    if st:
+        req.status = st
+        req.error = f"{_lib.STATUS_NAMES.get(st, st)} (flags {flags:#x}): {msg}"
 
 
 class BatchServer:
@@ -77,6 +99,7 @@ class BatchServer:
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
 
     def _collect(self, req: Request, solver: YeeSolver, t0: float):
+        _check_health(req, solver)
         if req.wl.probes:
             req.series = solver.series(solver.steps_done - req.wl.steps + 1, req.wl.steps) \
                 if req.wl.steps <= solver.desc.series_len else None
@@ -103,6 +126,7 @@ class BatchServer:
                     break
                 solver = YeeSolver(req.wl, device=str(self.device),
                                    series_len=max(self.K, req.wl.steps if req.wl.probes else 1))
+                _set_initial(req, solver)
                 slot = C.c_int32()
                 st = lib.yee_batch_admit(self.batch, solver.ctx, int(req.wl.steps), C.byref(slot))
                 if st == -6:              # YEE_EAGAIN: wait for a slot or for memory
@@ -160,8 +184,10 @@ def serve_one_at_a_time(requests: List[Request], device: str = "cuda:0", keep_fi
             time.sleep(req.arrival - now)
         req.admitted = time.perf_counter() - t0
         solver = YeeSolver(req.wl, device=device, series_len=max(1, req.wl.steps))
+        _set_initial(req, solver)
         solver.step(req.wl.steps)
         torch.cuda.current_stream().synchronize()
+        _check_health(req, solver)
         if req.wl.probes:
             req.series = solver.series(1, req.wl.steps)
             req.dft = solver.dft()

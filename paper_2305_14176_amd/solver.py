@@ -87,6 +87,9 @@ class YeeSolver:
         for k, mask in wl.pec_planes:
             m = np.ascontiguousarray(mask, np.uint8)
             _lib.check(lib.yee_add_pec_plane(ctx, int(k), _ptr(m, C.c_uint8)), "yee_add_pec_plane")
+        if wl.pec_volume is not None:
+            v = np.ascontiguousarray(np.transpose(np.asarray(wl.pec_volume, np.uint8), (2, 1, 0)))
+            _lib.check(lib.yee_set_pec_mask(ctx, _ptr(v, C.c_uint8)), "yee_set_pec_mask")
         for s in wl.sources:
             t0, tau = s.times(self.dt)
             sd = _lib.SourceDesc(s.comp, s.i, s.j, s.k, _lib.WAVEFORMS[s.kind], s.amp, t0, tau, s.f0)
@@ -175,6 +178,35 @@ class YeeSolver:
             _lib.check(self.lib.yee_read_dft(self.ctx, _ptr(re, C.c_double), _ptr(im, C.c_double), self._s()),
                        "yee_read_dft")
         return re + 1j * im
+
+    # -- health and checkpoints ------------------------------------------------
+    def status(self):
+        """(status, flags) of yee_status_flags: status 0, YEE_ENUMERIC (-5) or
+        YEE_EOVERFLOW (-7), with a message for the latter two; never raises for them."""
+        f = C.c_uint32()
+        st = self.lib.yee_status_flags(self.ctx, C.byref(f), self._s())
+        if st not in (0, -5, -7):
+            _lib.check(st, "yee_status_flags")
+        msg = self.lib.yee_last_error().decode(errors="replace") if st else ""
+        return st, f.value, msg
+
+    def state_bytes(self) -> int:
+        v = C.c_int64()
+        _lib.check(self.lib.yee_state_bytes(self.ctx, C.byref(v)), "yee_state_bytes")
+        return v.value
+
+    def save_state(self, out=None):
+        """Device copy of the run's state (a uint8 tensor of state_bytes())."""
+        n = self.state_bytes()
+        if out is None:
+            out = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        _lib.check(self.lib.yee_save_state(self.ctx, C.c_void_p(out.data_ptr()), int(out.numel()), self._s()),
+                   "yee_save_state")
+        return out
+
+    def load_state(self, state):
+        _lib.check(self.lib.yee_load_state(self.ctx, C.c_void_p(state.data_ptr()), int(state.numel()), self._s()),
+                   "yee_load_state")
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -91,6 +91,7 @@ class Workload:
     nsy: int = 1
     nsz: int = 1
     pec_planes: List[Tuple[int, np.ndarray]] = field(default_factory=list)  # (k, mask[ny, nx])
+    pec_volume: Optional[np.ndarray] = None   # uint8 [nx, ny, nz]: bit 0 Ex, 1 Ey, 2 Ez held at zero
     sources: List[SourceSpec] = field(default_factory=list)
     probes: List[Tuple[int, int, int, int]] = field(default_factory=list)   # (comp, i, j, k)
     freqs: np.ndarray = field(default_factory=lambda: np.zeros(0))
@@ -115,7 +116,7 @@ class Workload:
 
     def pec_component_masks(self):
         """PEC planes as boolean arrays of the E components' Yee shapes."""
-        if not self.pec_planes:
+        if not self.pec_planes and self.pec_volume is None:
             return None
         nx, ny, nz = self.nx, self.ny, self.nz
         out = {"Ex": np.zeros((nx, ny + 1, nz + 1), bool),
@@ -126,6 +127,11 @@ class Workload:
             out["Ex"][:nx, :ny, k] |= (mt & 1) != 0
             out["Ey"][:nx, :ny, k] |= (mt & 2) != 0
             out["Ez"][:nx, :ny, k] |= (mt & 4) != 0
+        if self.pec_volume is not None:
+            v = np.asarray(self.pec_volume)
+            out["Ex"][:nx, :ny, :nz] |= (v & 1) != 0
+            out["Ey"][:nx, :ny, :nz] |= (v & 2) != 0
+            out["Ez"][:nx, :ny, :nz] |= (v & 4) != 0
         return out
 
     @property
@@ -232,7 +238,13 @@ def fp16_substrate(nx: int = 512, ny: int = 512, nz: int = 256, steps: int = 200
     starts.append(k_top)
     seg_z = _segments(nz, starts)
     eps = np.array([1.0, perm[0], perm[1], perm[2], 1.0])
+    # FP16 storage scales (reading R17): E is stored as fp16(E * 2^12), H as
+    # fp16(H * 2^21).  With a source of amplitude 1 V/m the fields stay below
+    # 65504 / 2^12 = 16 V/m, and the far fields, down to ~1e-8 V/m, stay in
+    # fp16's normal range (2^-14 / 2^12 = 1.5e-8) instead of its subnormals;
+    # 2^9 is about eta0 * 1.36, so H * 2^21 spans the range E * 2^12 does.
     wl = Workload(f"fp16_substrate_{nx}x{ny}x{nz}", nx, ny, nz, 0.5e-3, 0.5e-3, 0.5e-3, precision="f16",
+                  fp16_exp=(12, 12, 12, 21, 21, 21),
                   cpml_cells=(cpml, cpml, cpml), seg_x=np.zeros(nx, np.int32), seg_y=np.zeros(ny, np.int32),
                   seg_z=seg_z, eps_blk=eps, sig_blk=np.zeros(5), nsx=1, nsy=1, nsz=5, steps=steps)
     mask = np.zeros((ny, nx), np.uint8)
@@ -394,12 +406,20 @@ def adjoint_case(seed: int, nx: int = 26, ny: int = 22, nz: int = 20, steps: int
 def random_initial_fields(wl: Workload, seed: int, h_scale: float = 1.0 / 377.0):
     """Random E^0, H^{-1/2} on the stored samples (i < nx, j < ny, k < nz), with
     the PEC-wall E samples (tangential on the faces) and the wall-normal H
-    samples set to 0.  Arrays have shape (nx, ny, nz), index order (i, j, k)."""
+    samples set to 0.  Arrays have shape (nx, ny, nz), index order (i, j, k).
+
+    E is standard normal and H is h_scale times standard normal.  For FP16
+    storage both are scaled by min(1, 2^(10 - s_E)), s_E the largest E
+    exponent: white noise of that size peaks near 8 sigma in E and 13 sigma
+    (of its initial H spread) in H over the first steps, which stays about a
+    factor 4 inside the fp16 range 65504 / 2^s for exponents with
+    s_H - s_E = 9."""
     rng = rng_for(seed)
     nx, ny, nz = wl.nx, wl.ny, wl.nz
-    f = {c: rng.standard_normal((nx, ny, nz)) for c in ("Ex", "Ey", "Ez")}
+    scale = min(1.0, 2.0 ** (10 - max(wl.fp16_exp[:3]))) if wl.precision == "f16" else 1.0
+    f = {c: scale * rng.standard_normal((nx, ny, nz)) for c in ("Ex", "Ey", "Ez")}
     for c in ("Hx", "Hy", "Hz"):
-        f[c] = h_scale * rng.standard_normal((nx, ny, nz))
+        f[c] = scale * h_scale * rng.standard_normal((nx, ny, nz))
     f["Ex"][:, 0, :] = 0; f["Ex"][:, :, 0] = 0
     f["Ey"][0, :, :] = 0; f["Ey"][:, :, 0] = 0
     f["Ez"][0, :, :] = 0; f["Ez"][:, 0, :] = 0

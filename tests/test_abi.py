@@ -114,6 +114,48 @@ def test_configuration_errors_before_device_work():
     lib.yee_destroy(ctx)
 
 
+def test_state_status_and_mask_error_paths():
+    """Status, checkpoint and volume-mask calls: argument and state errors."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    d = _desc(n=(16, 12, 10))
+    ctx = C.c_void_p()
+    assert lib.yee_create(C.byref(d), C.byref(ctx)) == 0
+    flags = C.c_uint32(99)
+    nb = C.c_int64()
+    assert lib.yee_status_flags(None, C.byref(flags), None) == -1
+    assert lib.yee_status_flags(ctx, None, None) == -1
+    assert lib.yee_status_flags(ctx, C.byref(flags), None) == -4        # no workspace
+    assert lib.yee_state_bytes(ctx, None) == -1
+    assert lib.yee_state_bytes(ctx, C.byref(nb)) == -4
+    buf = C.c_void_p(4096)                                               # never dereferenced: rejected first
+    assert lib.yee_save_state(ctx, None, 1 << 20, None) == -1
+    assert lib.yee_save_state(ctx, buf, 1 << 20, None) == -4
+    assert lib.yee_load_state(None, buf, 1 << 20, None) == -1
+    assert lib.yee_load_state(ctx, buf, 1 << 20, None) == -4
+    u8 = lambda a: a.ctypes.data_as(C.POINTER(C.c_uint8))
+    vol = np.zeros((10, 12, 16), np.uint8)
+    assert lib.yee_set_pec_mask(ctx, None) == -1
+    bad = vol.copy(); bad[3, 4, 5] = 8
+    assert lib.yee_set_pec_mask(ctx, u8(bad)) == -1                    # bit 3 is not a component
+    fp0 = C.c_int64()
+    assert lib.yee_footprint(ctx, C.byref(fp0)) == 0
+    vol[0, 2, 3] = 4                                                     # Ez of plane 0 (inside the box)
+    vol[4, :, 7] = 1
+    vol[9, 5, :] = 3
+    assert lib.yee_set_pec_mask(ctx, u8(vol)) == 0
+    fp1 = C.c_int64()
+    assert lib.yee_footprint(ctx, C.byref(fp1)) == 0
+    assert fp1.value > fp0.value                                         # three plane masks
+    plane = np.zeros((12, 16), np.uint8); plane[1, 1] = 2
+    assert lib.yee_add_pec_plane(ctx, 4, u8(plane)) == 0                 # merged into plane 4
+    fp2 = C.c_int64()
+    assert lib.yee_footprint(ctx, C.byref(fp2)) == 0
+    assert fp2.value == fp1.value
+    lib.yee_destroy(ctx)
+
+
 def test_time_step_matches_courant_definition():
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("libyee.so not built")

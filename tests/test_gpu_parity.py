@@ -6,7 +6,10 @@ vector, each final field component):
   * FP64 mode  : 1e-12  (only rounding order and FMA contraction differ);
   * FP32 mode  : 1e-5   against the FP64 oracle (after the pulse has left a
                   CPML grid: three times the oracle's own FP32-storage drift);
-  * FP16 storage: 1e-3  against the oracle emulating FP16 storage.
+  * FP16 storage: 1e-3  against the oracle emulating FP16 storage, over runs
+                  short enough that the two take the same rounding decisions
+                  almost everywhere (the long FP16 run is gated in
+                  test_gpu_golden.py against the size of the storage error).
 """
 import sys
 
@@ -179,27 +182,6 @@ def test_fp16_storage_few_steps(solver_cls, steps):
     wl = W.fp16_substrate(64, 64, 40, steps=steps, cpml=6)
     s, sim = _run_both(solver_cls, wl, steps, init_seed=31)
     _check_fields(s, sim, TOL["f16"])
-
-
-def test_fp16_storage_substrate_long_run(solver_cls):
-    """FP16 storage with a PEC strip mask over 500 steps.
-
-    Over many steps the storage rounding noise of two runs decorrelates as soon
-    as one rounding decision differs, so the error against either oracle grows
-    like a random walk of fp16 roundings: about sqrt(N) u with u = 2^-11.  The
-    run is gated at 4 sqrt(N) u and both errors are reported."""
-    wl = W.fp16_substrate(64, 64, 40, steps=500, cpml=6)
-    s, sim = _run_both(solver_cls, wl, wl.steps)
-    bound = 4.0 * np.sqrt(wl.steps) * 2.0 ** -11
-    got = s.series()
-    e16 = [rel_l2(got[:, p], sim.series_array()[:, p]) for p in range(len(wl.probes))]
-    sim64 = oracle_from_workload(wl, storage="f64")
-    sim64.run(wl.steps)
-    e64 = [rel_l2(got[:, p], sim64.series_array()[:, p]) for p in range(len(wl.probes))]
-    _say(f"[gpu] fp16 storage, {wl.steps} steps: max probe rel L2 vs fp16-emulating oracle {max(e16):.3e}, "
-         f"vs pure FP64 oracle {max(e64):.3e} (bound {bound:.3e})")
-    assert max(e16) <= bound and max(e64) <= bound
-    assert min(np.abs(got[:, p]).max() for p in range(len(wl.probes))) > 1e-4   # the pulse arrived
 
 
 def test_series_ring_and_dft_chunking(solver_cls):

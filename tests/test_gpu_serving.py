@@ -139,3 +139,38 @@ def test_active_cell_cap_queues_and_keeps_results():
         np.testing.assert_array_equal(by_id[rid].series, a.series, err_msg=f"series of request {rid}")
         np.testing.assert_array_equal(by_id[rid].fields["Ez"], a.fields["Ez"])
     srv.close()
+
+
+def test_failed_request_leaves_the_others_untouched():
+    """A NaN poked into one request's initial field fails that request only
+    (YEE_ENUMERIC from the health check at retirement); every other request of
+    the batch equals its run alone bitwise."""
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    specs = [(32, 40, 401, 0.0), (48, 33, 402, 0.0), (64, 37, 403, 0.0), (32, 29, 404, 0.0)]
+    keep = ("Ez", "Hy")
+    _say("[gpu] serving: failing request")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(specs), keep_fields=keep)}
+    assert not any(r.failed for r in alone.values())
+    reqs = _requests(specs)
+    bad = reqs[1]
+    ez = np.zeros((bad.wl.nx, bad.wl.ny, bad.wl.nz))
+    ez[bad.wl.nx // 2, bad.wl.ny // 2, bad.wl.nz // 3] = np.nan
+    bad.init = {"Ez": ez}
+    srv = BatchServer(max_slots=4, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep)
+    done = {r.rid: r for r in srv.serve(reqs)}
+    srv.close()
+    assert done[1].failed and done[1].status == -5, (done[1].status, done[1].error)
+    assert "YEE_ENUMERIC" in done[1].error
+    for rid in (0, 2, 3):
+        b, a = done[rid], alone[rid]
+        assert not b.failed, b.error
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+    # the same request alone fails the same way
+    solo = serve_one_at_a_time([_requests(specs[1:2])[0]], keep_fields=())
+    assert not solo[0].failed
+    poked = _requests(specs[1:2])[0]
+    poked.init = {"Ez": ez}
+    assert serve_one_at_a_time([poked])[0].status == -5
