@@ -71,9 +71,10 @@ def cpu_baseline(wl, budget_s=15.0, max_steps=5):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": wl.cells * n / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+    return {"value": wl.cells * n / dt / 1e6, "unit": "Mcell-updates/s", "cores": 1, "host_cores": os.cpu_count(),
+            "kind": "oracle",
             "sample": f"{n} steps of the same {wl.nx}x{wl.ny}x{wl.nz} workload after 1 untimed step "
-                      f"(numpy FP64, single-threaded elementwise), {dt:.1f} s"}
+                      f"(numpy FP64, single-threaded elementwise: 1 of {os.cpu_count()} host cores), {dt:.1f} s"}
 
 
 def serving_benchmark(n_requests=64, loads=(0.8, 1.2), seed=4, steps_per_replay=32, max_slots=32,
@@ -192,6 +193,70 @@ def precision_benchmark(steps=100, warmup=10):
         solver.close()
         del solver
         torch.cuda.empty_cache()
+    return out
+
+
+def precision_errors():
+    """Error of each output against the FP64 oracle, from the oracle results
+    stored under tests/golden/ (written by tests/golden/make_golden.py):
+    FP32 on the 256^3 CPML workload over its 1000 steps, and FP16 storage on the
+    128 x 128 x 64 layered substrate over 2000 steps (with the error of the
+    oracle's own FP16-storage emulation beside it)."""
+    import numpy as np
+    from paper_2305_14176_amd import workloads as W
+    from paper_2305_14176_amd.solver import YeeSolver
+    comps = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+
+    def rel(x, r):
+        x, r = np.asarray(x), np.asarray(r)
+        return float(np.linalg.norm((x - r).ravel()) / np.linalg.norm(r.ravel()))
+
+    def sample(s, pts):
+        return {c: s.field(c)[pts[:, 0], pts[:, 1], pts[:, 2]] for c in comps}
+
+    out = {}
+    g = np.load(os.path.join(ROOT, "tests", "golden", "cpml_block_lattice_256_1000steps.npz"))
+    steps = int(g["steps"])
+    wl = W.cpml_block_lattice(n=256, steps=steps)
+    s = YeeSolver(wl, device="cuda:0", series_len=steps)
+    fields, done = {}, 0
+    for m in [int(v) for v in g["marks"]]:
+        s.step(m - done)
+        done = m
+        got = sample(s, g["points"])
+        rms = {c: float(g[f"norm_{c}_300"]) / np.sqrt(wl.cells) for c in comps}
+        fields[m] = {c: {"sampled_rel_l2": round(rel(got[c], g[f"field_{c}_{m}"]), 9),
+                         "worst_element_over_rms_at_300": float(np.abs(got[c] - g[f"field_{c}_{m}"]).max() / rms[c])}
+                     for c in comps}
+    ser, dft = s.series(1, steps), s.dft()
+    out[f"{wl.name}_fp32_{steps}_steps"] = {
+        "series_rel_l2_max": max(rel(ser[:, p], g["series"][:, p]) for p in range(len(wl.probes))),
+        "dft_rel_l2_max": max(rel(dft[p], g["dft"][p]) for p in range(len(wl.probes))),
+        "fields_by_step": fields, "points": int(len(g["points"])), "reference": "FP64 oracle"}
+    s.close()
+    g = np.load(os.path.join(ROOT, "tests", "golden", "fp16_substrate_128x128x64_2000steps.npz"))
+    steps = int(g["steps"])
+    wl = W.fp16_substrate(128, 128, 64, steps=steps)
+    s = YeeSolver(wl, device="cuda:0", series_len=steps)
+    curve, done = {}, 0
+    for m in [int(v) for v in g["marks"]]:
+        s.step(m - done)
+        done = m
+        got = sample(s, g["points"])
+        curve[m] = {c: {"gpu": round(rel(got[c], g[f"f64_{c}_{m}"]), 6),
+                        "oracle_fp16_emulation": round(rel(g[f"f16_{c}_{m}"], g[f"f64_{c}_{m}"]), 6)}
+                    for c in comps}
+    ser, dft = s.series(1, steps), s.dft()
+    npr = len(wl.probes)
+    out[f"fp16_substrate_128x128x64_{steps}_steps"] = {
+        "series_rel_l2_max": {"gpu": max(rel(ser[:, p], g["series_f64"][:, p]) for p in range(npr)),
+                              "oracle_fp16_emulation": max(rel(g["series_f16"][:, p], g["series_f64"][:, p])
+                                                           for p in range(npr))},
+        "dft_rel_l2_max": {"gpu": max(rel(dft[p], g["dft_f64"][p]) for p in range(npr)),
+                           "oracle_fp16_emulation": max(rel(g["dft_f16"][p], g["dft_f64"][p]) for p in range(npr))},
+        "fields_sampled_rel_l2_by_step": curve, "points": int(len(g["points"])),
+        "reference": "FP64 oracle"}
+    s.close()
     return out
 
 
@@ -387,9 +452,11 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
         R.if_cube(small, chirps=[0])
         dt = time.perf_counter() - t0
         n = cpu_rays * sc.n_pairs * r.n_samples
-        out["cpu_baseline"] = {"value": round(n / dt, 1), "unit": "terms/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": round(n / dt, 1), "unit": "terms/s", "cores": 1,
+                               "host_cores": os.cpu_count(), "kind": "oracle",
                                "sample": f"the first {cpu_rays} rays, chirp 0, all {sc.n_pairs} pairs and "
-                                         f"{r.n_samples} samples (numpy FP64, single-threaded), {dt:.1f} s"}
+                                         f"{r.n_samples} samples (numpy FP64, single-threaded: 1 of "
+                                         f"{os.cpu_count()} host cores), {dt:.1f} s"}
     return out
 
 
@@ -403,7 +470,7 @@ def main():
     ap.add_argument("--chunk-planes", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
-    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-requests", type=int, default=512)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient measurement")
     ap.add_argument("--no-sparams", action="store_true", help="skip the S-parameter measurement")
     ap.add_argument("--no-precisions", action="store_true", help="skip the FP16-storage and FP64 configurations")
@@ -499,6 +566,7 @@ def main():
     }
     if not args.no_precisions:
         out["precision_modes"] = precision_benchmark()
+        out["precision_modes"]["error_vs_fp64_oracle"] = precision_errors()
     if not args.no_if_synthesis:
         out["if_synthesis"] = if_synthesis_benchmark(reps=args.if_reps, cpu=not args.no_cpu_baseline)
     if not args.no_adjoint:
