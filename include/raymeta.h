@@ -134,6 +134,25 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
                        const float* weights, int32_t chirp0, int32_t chirp_count, float* s,
                        void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
+/* The IF cube of rmd_if_cube (same arguments, checks, method and output,
+ * bitwise) for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, allocation-free serving loops, harnesses that
+ * forbid hipMalloc.  The workspace is a static device array of
+ * RMD_STATIC_SCRATCH_BYTES that each GPU holds from the library's first use
+ * until the process ends; nothing is allocated or freed per call.  Sizes
+ * whose rmd_workspace_bytes() exceeds it return RMD_EINVAL (use rmd_if_cube
+ * with a caller workspace).  Every call on one GPU shares that GPU's array,
+ * so calls that overlap in time on one GPU (different streams, or different
+ * threads without ordering) race and give wrong results; calls queued on one
+ * stream are ordered and safe.  Nothing in the array has to start at zero
+ * (every word a call reads it first writes).  The first call on each device
+ * looks up the array's device address (hipGetSymbolAddress); make it outside
+ * graph capture. */
+#define RMD_STATIC_SCRATCH_BYTES (64ll << 20)
+rmd_status rmd_if_cube_static(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
+                              const float* weights, int32_t chirp0, int32_t chirp_count, float* s,
+                              hipStream_t stream);
+
 /* The same IF cube with the sum over rays evaluated term by term: the arguments,
  * checks and output are those of rmd_if_cube.  Phases are formed in float64 and
  * reduced modulo one cycle; the phasors are float32, split into fp16 high and

@@ -30,6 +30,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "raymeta.h"
@@ -932,6 +933,34 @@ const TapPoly& tap_poly() {
     return tp;
 }
 
+// Workspace of rmd_if_cube_static: a file-scope device array (each GPU the
+// library runs on holds its own copy for the life of the process).  Host code
+// must not pass the array's name to a kernel or a copy (on the host it is a
+// stand-in, not a device address): static_scratch() looks up the device
+// address of the current device's copy once and keeps it.
+static __device__ __align__(256) unsigned char scratch[RMD_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+rmd_status static_scratch(void** out) {
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RMD_EINVAL, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(RMD_EHIP, "hipGetSymbolAddress(scratch) gave NULL");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return RMD_OK;
+}
+
 rmd::SynthArgs synth_args(const rmd_scene* sc) {
     rmd::SynthArgs a{};
     a.mesh_tri_off = sc->mesh_tri_off;
@@ -1093,6 +1122,23 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
         if (e != hipSuccess) return hip_fail(e, "IF cube launch");
     }
     return RMD_OK;
+}
+
+rmd_status rmd_if_cube_static(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
+                              const float* weights, int32_t chirp0, int32_t chirp_count, float* s,
+                              hipStream_t stream) {
+    int64_t need = 0;
+    rmd_status st = rmd_workspace_bytes(scene, radar, n_pairs, chirp_count, &need);
+    if (st != RMD_OK) return st;
+    if (need > RMD_STATIC_SCRATCH_BYTES)
+        return fail(RMD_EINVAL, "rmd_if_cube_static: these sizes need " + std::to_string(need) +
+                                    " bytes of workspace, the static scratch holds " +
+                                    std::to_string((long long)RMD_STATIC_SCRATCH_BYTES));
+    void* ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != RMD_OK) return st;
+    return rmd_if_cube(scene, radar, n_pairs, pairs, weights, chirp0, chirp_count, s, ws, RMD_STATIC_SCRATCH_BYTES,
+                       stream);
 }
 
 rmd_status rmd_if_cube_direct(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,

@@ -26,7 +26,8 @@ SPAN_ANY, SPAN_NONE, SPAN_ALL = 0, 1, 2
 
 # Every symbol include/raymeta.h declares (checked by the CPU test suite).
 EXPORTED = ("rmd_api_version", "rmd_last_error", "rmd_check_scene", "rmd_workspace_bytes", "rmd_if_cube",
-            "rmd_if_cube_direct", "rmd_range_doppler", "rmd_span_weights")
+            "rmd_if_cube_static", "rmd_if_cube_direct", "rmd_range_doppler", "rmd_span_weights")
+STATIC_SCRATCH_BYTES = 64 << 20   # RMD_STATIC_SCRATCH_BYTES
 # Evaluation of the sum over rays: "spread" (type-1 non-uniform FFT,
 # rmd_if_cube) or "direct" (term by term on the matrix cores, rmd_if_cube_direct).
 METHODS = {"spread": "rmd_if_cube", "direct": "rmd_if_cube_direct"}
@@ -76,6 +77,8 @@ def load():
                          C.c_int64, P], C.c_int32),
         "rmd_if_cube_direct": ([C.POINTER(Scene), C.POINTER(Radar), C.c_int32, P, P, C.c_int32, C.c_int32, P, P,
                                 C.c_int64, P], C.c_int32),
+        "rmd_if_cube_static": ([C.POINTER(Scene), C.POINTER(Radar), C.c_int32, P, P, C.c_int32, C.c_int32, P, P],
+                               C.c_int32),
         "rmd_range_doppler": ([P, P, C.c_int32, C.c_int32, C.c_int32, P], C.c_int32),
         "rmd_span_weights": ([C.POINTER(Scene), P, C.POINTER(SpanRule), P, P, P], C.c_int32),
     }

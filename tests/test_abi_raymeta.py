@@ -135,6 +135,22 @@ def test_if_cube_rejects_before_launch():
     assert lib.rmd_if_cube(C.byref(sc), C.byref(r0), 2, p, None, 0, 4, p, p, need.value, None) == -1
 
 
+def test_static_scratch_entry_point_rejects_sizes_beyond_its_array():
+    """rmd_if_cube_static refuses, before any device call, sizes whose
+    workspace exceeds the static array (and bad scene descriptors)."""
+    lib = RM.load()
+    p = C.c_void_p(4096)
+    r = _radar(n_chirps=16, n_samples=1024)
+    sc = _fake_scene(n_rays=1 << 20)
+    need = C.c_int64()
+    assert lib.rmd_workspace_bytes(C.byref(sc), C.byref(r), 8, 16, C.byref(need)) == 0
+    assert need.value > RM.STATIC_SCRATCH_BYTES
+    assert lib.rmd_if_cube_static(C.byref(sc), C.byref(r), 8, p, None, 0, 16, p, None) == -1
+    assert b"static scratch" in lib.rmd_last_error()
+    assert lib.rmd_if_cube_static(C.byref(_fake_scene(n_rays=0)), C.byref(r), 8, p, None, 0, 16, p, None) == -1
+    assert lib.rmd_if_cube_static(None, C.byref(r), 8, p, None, 0, 16, p, None) == -1
+
+
 @pytest.mark.parametrize("fn", ["rmd_if_cube", "rmd_if_cube_direct"])
 def test_both_methods_share_the_checks(fn):
     """Both IF entry points reject the same arguments before any launch."""
