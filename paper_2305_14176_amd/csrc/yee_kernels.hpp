@@ -298,6 +298,19 @@ __device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const
   buf_st<VecT<T, V>>(v, r, vo, so);
 }
 
+template <class T, class C, int V>
+__device__ __forceinline__ void decode_row(const VecT<T, V>& v, C (&out)[V], float dec) {
+#pragma unroll
+  for (int e = 0; e < V; ++e) out[e] = Conv<T, C>::ld(v.v[e], dec);
+}
+
+// Planes the field prefetch of the fused step runs ahead: two for FP16
+// storage with two samples per lane (a wave's loads are then 4 bytes per lane,
+// half the bytes in flight of FP32, and the raw values wait packed in one
+// register per component), one otherwise (no room in the register budget).
+template <class T, int V>
+constexpr int prefetch_depth() { return (sizeof(T) == 2 && V == 2) ? 2 : 1; }
+
 // ---------------------------------------------------------------------------
 // The fused step: planes [k0, k1) of y-tile ytile of one grid (k1 - k0 <= kz).  Waves beyond
 // (ty + 1) * wpr (spare waves of a fixed-size workgroup) take part in the
@@ -310,10 +323,13 @@ __device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const
 // planes, layers) are scalar branches.
 //
 // Per plane k the registers hold E^n(k), E^n(k+1), H^{n-1/2}(k), H^{n+1/2}(k-1)
-// and the H-side psi of plane k.  E^n(k+2), H^{n-1/2}(k+1) are prefetched at
-// the top of the iteration, after the small loads the E half waits for (E-side
-// psi and coefficients of plane k): gfx9 counts vector memory operations in
-// one in-order counter, so a wait never covers the prefetch.  The H-side psi of
+// and the H-side psi of plane k.  With a prefetch depth D (prefetch_depth),
+// E^n(k+1+D), H^{n-1/2}(k+D) and the row above at k+D are loaded at the top of
+// the iteration into a ring of D raw (storage-format) register sets, after the
+// small loads the E half waits for (E-side psi and coefficients of plane k):
+// gfx9 counts vector memory operations in one in-order counter, so a wait
+// never covers a later prefetch.  The set loaded D - 1 iterations earlier is
+// decoded into the window at the end of the iteration.  The H-side psi of
 // plane k+1 is loaded once plane k's has been consumed.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOut = 0x80000000u;
@@ -450,6 +466,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     ld_row<T, C, V>(rin, vrow, so + cs_b, out[1], a.dec[1]);
     ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[2]);
   };
+  auto load_E_raw = [&](int k, VecT<T, V> (&out)[3]) {
+    const uint32_t so = (uint32_t)k * plane_b;
+    out[0] = buf_ld<VecT<T, V>>(rin, vrow, so);
+    out[1] = buf_ld<VecT<T, V>>(rin, vrow, so + cs_b);
+    out[2] = buf_ld<VecT<T, V>>(rin, vrow, so + 2 * cs_b);
+  };
   // Hy of the halo row is not needed; its load is still issued (with every
   // lane out of range), so that every wave issues the same prefetch
   const uint32_t vrow_hy = halo ? kOut : vrow;
@@ -459,11 +481,24 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     ld_row<T, C, V>(rin, vrow_hy, so + cs_b, out[1], a.dec[4]);
     ld_row<T, C, V>(rin, vrow, so + 2 * cs_b, out[2], a.dec[5]);
   };
+  auto load_H_raw = [&](int k, VecT<T, V> (&out)[3]) {
+    const uint32_t so = 3 * cs_b + (uint32_t)k * plane_b;
+    out[0] = buf_ld<VecT<T, V>>(rin, vrow, so);
+    out[1] = buf_ld<VecT<T, V>>(rin, vrow_hy, so + cs_b);
+    out[2] = buf_ld<VecT<T, V>>(rin, vrow, so + 2 * cs_b);
+  };
   auto load_top = [&](int k, C (&tz)[V], C (&tx)[V]) {
     if (top_ok) {
       const uint32_t so = (uint32_t)k * plane_b;
       ld_row<T, C, V>(rin, vtop, so + 2 * cs_b, tz, a.dec[2]);
       ld_row<T, C, V>(rin, vtop, so, tx, a.dec[0]);
+    }
+  };
+  auto load_top_raw = [&](int k, VecT<T, V> (&out)[2]) {
+    if (top_ok) {
+      const uint32_t so = (uint32_t)k * plane_b;
+      out[0] = buf_ld<VecT<T, V>>(rin, vtop, so + 2 * cs_b);
+      out[1] = buf_ld<VecT<T, V>>(rin, vtop, so);
     }
   };
   C ph[6][V];   // H-side psi of the current plane
@@ -489,8 +524,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   };
 
   // ---- prologue: plane kstart ----
-  C e0[3][V], e1[3][V], e2[3][V], h0[3][V], h1[3][V];
-  C hxp[V], hyp[V], tz0[V], tx0[V], tz1[V], tx1[V];
+  constexpr int D = prefetch_depth<T, V>();
+  C e0[3][V], e1[3][V], h0[3][V];
+  C hxp[V], hyp[V], tz0[V], tx0[V];
+  VecT<T, V> qe[D][3], qh[D][3], qt[D][2];   // prefetch ring (storage format)
   C pe[6][V];
   Coef2<C> cf[V];
   int cf_blk = -1;   // z block offset the coefficients in cf belong to
@@ -498,12 +535,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
 #pragma unroll
   for (int e = 0; e < V; ++e) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { e0[c][e] = C(0); e1[c][e] = C(0); e2[c][e] = C(0); h0[c][e] = C(0); h1[c][e] = C(0); }
+    for (int c = 0; c < 3; ++c) { e0[c][e] = C(0); e1[c][e] = C(0); h0[c][e] = C(0); }
 #pragma unroll
     for (int u = 0; u < 6; ++u) { ph[u][e] = C(0); pe[u][e] = C(0); }
-    hxp[e] = C(0); hyp[e] = C(0); tz0[e] = C(0); tx0[e] = C(0); tz1[e] = C(0); tx1[e] = C(0);
+    hxp[e] = C(0); hyp[e] = C(0); tz0[e] = C(0); tx0[e] = C(0);
     pm[e] = 0u;
     cf[e].ca = C(0); cf[e].cb = C(0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { qe[d][c].v[e] = T(0); qh[d][c].v[e] = T(0); }
+      qt[d][0].v[e] = T(0);
+      qt[d][1].v[e] = T(0);
+    }
   }
   // Wave roles.  own: a row j0 .. j0+ty-1 inside the grid; halo: row j0-1
   // (its H is recomputed; it also loads the row above the tile); spare: a row
@@ -518,6 +562,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
     load_E(kstart + 1, e1);
     load_H(kstart, h0);
     load_top(kstart, tz0, tx0);
+    if constexpr (D > 1) {
+      // the set the first iteration decodes: E^n(kstart+2), H and the row above at kstart+1
+      const bool ahead = kstart + 1 < k1;
+      load_E_raw(ahead ? kstart + 2 : nz, qe[D - 1]);
+      load_H_raw(ahead ? kstart + 1 : nz, qh[D - 1]);
+      if (halo) load_top_raw(ahead ? kstart + 1 : nz, qt[D - 1]);
+    }
   } else if (!dummy) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -532,11 +583,15 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
   auto march = [&](auto role) {
     constexpr int R = decltype(role)::value;
     constexpr bool OWN = R == 0, HALO = R == 1;
-    for (int k = kstart; k < k1; ++k) {
+    // one plane; the prefetch goes into ring set S, the window advances from
+    // set (S + 1) % D (loaded D - 1 iterations earlier)
+    auto iter = [&](const int k, auto slot) __attribute__((always_inline)) {
+      constexpr int S = decltype(slot)::value;
+      constexpr int SN = (S + 1) % D;
       if constexpr (R == 2) {
         __syncthreads();
         __syncthreads();
-        continue;
+        return;
       } else {
       const int kq = k - kstart;
       const bool upd = OWN && k >= k0;      // uniform: this wave updates E and stores at plane k
@@ -580,13 +635,13 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         }
       }
       __builtin_amdgcn_sched_barrier(0);
-      // ---- 2. prefetch E^n(k+2), H^{n-1/2}(k+1) and the row above at k+1 ----
-      // (after the last plane: the zero plane, read once per chunk)
+      // ---- 2. prefetch E^n(k+1+D), H^{n-1/2}(k+D) and the row above at k+D ----
+      // (planes no iteration of the chunk will use: the zero plane)
       {
-        const int kn = more ? k + 1 : nz;
-        load_E(more ? k + 2 : nz, e2);
-        load_H(kn, h1);
-        if constexpr (HALO) load_top(kn, tz1, tx1);
+        const bool ahead = k + D < k1;
+        load_E_raw(ahead ? k + 1 + D : nz, qe[S]);
+        load_H_raw(ahead ? k + D : nz, qh[S]);
+        if constexpr (HALO) load_top_raw(ahead ? k + D : nz, qt[S]);
       }
       __builtin_amdgcn_sched_barrier(0);
 
@@ -859,19 +914,35 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
       }
 
       // ---- 8. advance the register window ----
-#pragma unroll
-      for (int e = 0; e < V; ++e) {
-        hxp[e] = hx[e];
-        hyp[e] = hy[e];
-        tz0[e] = tz1[e];
-        tx0[e] = tx1[e];
+      {
+        C e2[3][V], h1[3][V];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          e0[c][e] = e1[c][e];
-          e1[c][e] = e2[c][e];
-          h0[c][e] = h1[c][e];
+          decode_row<T, C, V>(qe[SN][c], e2[c], a.dec[c]);
+          decode_row<T, C, V>(qh[SN][c], h1[c], a.dec[3 + c]);
+        }
+        if constexpr (HALO) {
+          decode_row<T, C, V>(qt[SN][0], tz0, a.dec[2]);
+          decode_row<T, C, V>(qt[SN][1], tx0, a.dec[0]);
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          hxp[e] = hx[e];
+          hyp[e] = hy[e];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            e0[c][e] = e1[c][e];
+            e1[c][e] = e2[c][e];
+            h0[c][e] = h1[c][e];
+          }
         }
       }
+      }
+    };
+    for (int k = kstart; k < k1; k += D) {
+      iter(k, Role<0>{});
+      if constexpr (D > 1) {
+        if (k + 1 < k1) iter(k + 1, Role<1>{});
       }
     }
   };

@@ -624,6 +624,70 @@ size_t batch_lds_bytes() {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+
+// The mask of z-plane k ([ny][px] bytes), added (all clear) on first use.
+std::vector<uint8_t>& pec_plane_mask(yee_ctx* c, int k) {
+  auto it = std::find(c->pec_k.begin(), c->pec_k.end(), k);
+  if (it != c->pec_k.end()) return c->pec_masks[(size_t)(it - c->pec_k.begin())];
+  c->pec_k.push_back(k);
+  c->pec_masks.emplace_back((size_t)c->d.ny * c->px, (uint8_t)0);
+  return c->pec_masks.back();
+}
+
+}  // namespace
+
+namespace {
+
+constexpr int64_t kStateMagic = 0x3154415453454559LL;   // "YEESTAT1"
+constexpr int kStateWords = 32;                         // header: 32 int64 (256 bytes)
+constexpr int kStateShapeWords = 22;                    // words that must match on load
+
+struct StateLayout {
+  size_t fields, pse, psh, series, dft, stat, total;
+};
+
+StateLayout state_layout(const yee_ctx* c) {
+  StateLayout L{};
+  size_t off = kStateWords * sizeof(int64_t);
+  auto take = [&](size_t& at, size_t bytes) {
+    at = off;
+    off += align256(bytes);
+  };
+  take(L.fields, 6 * c->comp_bytes);
+  take(L.pse, c->psi_e[0].bytes);
+  take(L.psh, c->psi_h[0].bytes);
+  take(L.series, c->series.bytes);
+  take(L.dft, c->dft.bytes);
+  take(L.stat, c->stat.bytes);
+  L.total = off;
+  return L;
+}
+
+// Header words: 0..21 describe the shape of the state, 24 and 25 the step
+// and fold counters.
+void state_words(const yee_ctx* c, int64_t w[kStateWords]) {
+  const auto& d = c->d;
+  std::fill(w, w + kStateWords, int64_t(0));
+  w[0] = kStateMagic;
+  w[1] = YEE_API_VERSION;
+  w[2] = d.nx; w[3] = d.ny; w[4] = d.nz;
+  w[5] = c->px;
+  w[6] = d.precision;
+  for (int q = 0; q < 3; ++q) w[7 + q] = d.cpml_cells[q];
+  for (int q = 0; q < 6; ++q) w[10 + q] = d.precision == YEE_F16S ? d.fp16_exp[q] : 0;
+  w[16] = (int64_t)c->probes.size();
+  w[17] = (int64_t)c->freqs.size();
+  w[18] = d.series_len;
+  w[19] = (int64_t)c->comp_bytes;
+  w[20] = (int64_t)c->psi_e[0].bytes;
+  w[21] = (int64_t)state_layout(c).total;
+  w[24] = c->n;
+  w[25] = c->folded;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* yee_last_error(void) { return g_err.c_str(); }
@@ -730,18 +794,6 @@ yee_status yee_upload_materials(yee_ctx* c, void* stream) {
   return upload_materials_impl(c, (hipStream_t)stream);
 }
 
-namespace {
-
-// The mask of z-plane k ([ny][px] bytes), added (all clear) on first use.
-std::vector<uint8_t>& pec_plane_mask(yee_ctx* c, int k) {
-  auto it = std::find(c->pec_k.begin(), c->pec_k.end(), k);
-  if (it != c->pec_k.end()) return c->pec_masks[(size_t)(it - c->pec_k.begin())];
-  c->pec_k.push_back(k);
-  c->pec_masks.emplace_back((size_t)c->d.ny * c->px, (uint8_t)0);
-  return c->pec_masks.back();
-}
-
-}  // namespace
 
 yee_status yee_add_pec_plane(yee_ctx* c, int32_t k, const uint8_t* mask) {
   if (!c || !mask) return fail(YEE_EINVAL, "NULL argument");
@@ -1093,56 +1145,6 @@ yee_status yee_status_flags(yee_ctx* c, uint32_t* flags, void* stream) {
   return YEE_OK;
 }
 
-namespace {
-
-constexpr int64_t kStateMagic = 0x3154415453454559LL;   // "YEESTAT1"
-constexpr int kStateWords = 32;                         // header: 32 int64 (256 bytes)
-constexpr int kStateShapeWords = 22;                    // words that must match on load
-
-struct StateLayout {
-  size_t fields, pse, psh, series, dft, stat, total;
-};
-
-StateLayout state_layout(const yee_ctx* c) {
-  StateLayout L{};
-  size_t off = kStateWords * sizeof(int64_t);
-  auto take = [&](size_t& at, size_t bytes) {
-    at = off;
-    off += align256(bytes);
-  };
-  take(L.fields, 6 * c->comp_bytes);
-  take(L.pse, c->psi_e[0].bytes);
-  take(L.psh, c->psi_h[0].bytes);
-  take(L.series, c->series.bytes);
-  take(L.dft, c->dft.bytes);
-  take(L.stat, c->stat.bytes);
-  L.total = off;
-  return L;
-}
-
-// Header words: 0..21 describe the shape of the state, 24 and 25 the step
-// and fold counters.
-void state_words(const yee_ctx* c, int64_t w[kStateWords]) {
-  const auto& d = c->d;
-  std::fill(w, w + kStateWords, int64_t(0));
-  w[0] = kStateMagic;
-  w[1] = YEE_API_VERSION;
-  w[2] = d.nx; w[3] = d.ny; w[4] = d.nz;
-  w[5] = c->px;
-  w[6] = d.precision;
-  for (int q = 0; q < 3; ++q) w[7 + q] = d.cpml_cells[q];
-  for (int q = 0; q < 6; ++q) w[10 + q] = d.precision == YEE_F16S ? d.fp16_exp[q] : 0;
-  w[16] = (int64_t)c->probes.size();
-  w[17] = (int64_t)c->freqs.size();
-  w[18] = d.series_len;
-  w[19] = (int64_t)c->comp_bytes;
-  w[20] = (int64_t)c->psi_e[0].bytes;
-  w[21] = (int64_t)state_layout(c).total;
-  w[24] = c->n;
-  w[25] = c->folded;
-}
-
-}  // namespace
 
 yee_status yee_state_bytes(const yee_ctx* c, int64_t* bytes) {
   if (!c || !bytes) return fail(YEE_EINVAL, "NULL argument");
