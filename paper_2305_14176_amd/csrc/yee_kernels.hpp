@@ -31,6 +31,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace yee {
@@ -155,6 +157,18 @@ struct alignas(sizeof(T) * V) VecT {
 template <class T, class C>
 __device__ __forceinline__ C to_storage(C v, float enc, float dec) {
   return Conv<T, C>::ld(Conv<T, C>::st(v, enc), dec);
+}
+// The same, also handing back the storage bits for FP16 storage (stored as
+// they are: encoding the decoded value again would give the same bits).  With
+// T == C the caller stores the value itself and bits is left alone.
+template <class T, class C>
+__device__ __forceinline__ C to_storage(C v, float enc, float dec, T& bits) {
+  if constexpr (std::is_same<T, C>::value) {
+    return v;
+  } else {
+    bits = Conv<T, C>::st(v, enc);
+    return Conv<T, C>::ld(bits, dec);
+  }
 }
 
 // Source waveform in FP64: w(t) = -2u exp(-u^2) or sin(2 pi f0 (t - t0)) exp(-u^2).
@@ -658,8 +672,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
 
       // ---- 4. H half step at plane k ----
       C hx[V], hy[V], hz[V];
+      VecT<T, V> sh[3];   // H^{n+1/2}(k) in storage format
 #pragma unroll
-      for (int e = 0; e < V; ++e) { hx[e] = C(0); hy[e] = C(0); hz[e] = C(0); }
+      for (int e = 0; e < V; ++e) {
+        hx[e] = C(0); hy[e] = C(0); hz[e] = C(0);
+        sh[0].v[e] = T(0); sh[1].v[e] = T(0); sh[2].v[e] = T(0);
+      }
       if (OWN || row_ok) {
         C exu[V], ezu[V], eyr[V], ezr[V];
         lds_get<C, V>(myE + 3 * RS, exu);           // row j+1
@@ -706,9 +724,10 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         }
 #pragma unroll
         for (int e = 0; e < V; ++e) {
-          hx[e] = to_storage<T, C>(h_new(h0[0][e], dEz_dy[e], dEy_dz[e], dtm), a.enc[3], a.dec[3]);
-          hy[e] = HALO ? C(0) : to_storage<T, C>(h_new(h0[1][e], dEx_dz[e], dEz_dx[e], dtm), a.enc[4], a.dec[4]);
-          hz[e] = to_storage<T, C>(h_new(h0[2][e], dEy_dx[e], dEx_dy[e], dtm), a.enc[5], a.dec[5]);
+          hx[e] = to_storage<T, C>(h_new(h0[0][e], dEz_dy[e], dEy_dz[e], dtm), a.enc[3], a.dec[3], sh[0].v[e]);
+          hy[e] = HALO ? C(0)
+                       : to_storage<T, C>(h_new(h0[1][e], dEx_dz[e], dEz_dx[e], dtm), a.enc[4], a.dec[4], sh[1].v[e]);
+          hz[e] = to_storage<T, C>(h_new(h0[2][e], dEy_dx[e], dEx_dy[e], dtm), a.enc[5], a.dec[5], sh[2].v[e]);
         }
         // new H-side psi of the own rows
         if (upd) {
@@ -752,8 +771,12 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
       // ---- 7. E half step at plane k and stores ----
       if constexpr (OWN) {
         C exo[V], eyo[V], ezo[V];
+        VecT<T, V> se[3];   // E^{n+1}(k) in storage format
 #pragma unroll
-        for (int e = 0; e < V; ++e) { exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e]; }
+        for (int e = 0; e < V; ++e) {
+          exo[e] = e0[0][e]; eyo[e] = e0[1][e]; ezo[e] = e0[2][e];
+          se[0].v[e] = T(0); se[1].v[e] = T(0); se[2].v[e] = T(0);
+        }
         uint8_t flags = 0;
         if (upd) {
           C hxd[V], hzd[V], hyl[V], hzl[V];
@@ -881,21 +904,30 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           }
 #pragma unroll
           for (int e = 0; e < V; ++e) {
-            exo[e] = to_storage<T, C>(exo[e], a.enc[0], a.dec[0]);
-            eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1]);
-            ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2]);
+            exo[e] = to_storage<T, C>(exo[e], a.enc[0], a.dec[0], se[0].v[e]);
+            eyo[e] = to_storage<T, C>(eyo[e], a.enc[1], a.dec[1], se[1].v[e]);
+            ezo[e] = to_storage<T, C>(ezo[e], a.enc[2], a.dec[2], se[2].v[e]);
           }
         }
         // The field stores are issued at every plane; below the chunk (the
         // warm-up plane, which updates nothing) every lane is out of range.
         const uint32_t vst = upd ? vrow : kOut;
         const uint32_t so = (uint32_t)k * plane_b;
-        st_row<T, C, V>(rout, vst, so, exo, a.enc[0]);
-        st_row<T, C, V>(rout, vst, so + cs_b, eyo, a.enc[1]);
-        st_row<T, C, V>(rout, vst, so + 2 * cs_b, ezo, a.enc[2]);
-        st_row<T, C, V>(rout, vst, so + 3 * cs_b, hx, a.enc[3]);
-        st_row<T, C, V>(rout, vst, so + 4 * cs_b, hy, a.enc[4]);
-        st_row<T, C, V>(rout, vst, so + 5 * cs_b, hz, a.enc[5]);
+        if constexpr (std::is_same<T, C>::value) {
+          st_row<T, C, V>(rout, vst, so, exo, a.enc[0]);
+          st_row<T, C, V>(rout, vst, so + cs_b, eyo, a.enc[1]);
+          st_row<T, C, V>(rout, vst, so + 2 * cs_b, ezo, a.enc[2]);
+          st_row<T, C, V>(rout, vst, so + 3 * cs_b, hx, a.enc[3]);
+          st_row<T, C, V>(rout, vst, so + 4 * cs_b, hy, a.enc[4]);
+          st_row<T, C, V>(rout, vst, so + 5 * cs_b, hz, a.enc[5]);
+        } else {
+          buf_st<VecT<T, V>>(se[0], rout, vst, so);
+          buf_st<VecT<T, V>>(se[1], rout, vst, so + cs_b);
+          buf_st<VecT<T, V>>(se[2], rout, vst, so + 2 * cs_b);
+          buf_st<VecT<T, V>>(sh[0], rout, vst, so + 3 * cs_b);
+          buf_st<VecT<T, V>>(sh[1], rout, vst, so + 4 * cs_b);
+          buf_st<VecT<T, V>>(sh[2], rout, vst, so + 5 * cs_b);
+        }
         if (flags & 2) {
           for (int p = 0; p < a.nprobe; ++p) {
             const int4 pr = a.probe[p];

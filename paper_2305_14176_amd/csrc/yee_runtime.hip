@@ -421,6 +421,11 @@ yee_status fold_dft(yee_ctx* c, hipStream_t s) {
 }
 
 constexpr int kMinChunk = 8;   // fewest planes per chunk of the automatic launch above 2^20 cells
+// most planes per chunk of the automatic launch: where one round would take
+// longer chunks (one workgroup per CU), several rounds of 64-plane chunks run
+// faster (512 x 512 x 256 per step: FP16 storage 0.673 -> 0.620 ms, FP32
+// 0.884 -> 0.825 ms)
+constexpr int kMaxChunk = 64;
 
 // Workgroups of the step kernel that fit one CU at once.
 template <class T, class C, int V>
@@ -574,7 +579,7 @@ void default_launch(yee_ctx* c) {
       const int slots = step_slots(c, threads, step_lds_bytes(c, c->ty, c->V, d.nz));
       const int ny_tiles = (d.ny + c->ty - 1) / c->ty;
       const int chunks = std::max(1, slots / ny_tiles);
-      c->kz = std::min(d.nz, std::max(min_chunk, (d.nz + chunks - 1) / chunks));
+      c->kz = std::min({d.nz, kMaxChunk, std::max(min_chunk, (d.nz + chunks - 1) / chunks)});
     }
     // keep the LDS rows and z tables within the device's per-workgroup limit
     if (c->ty == 1 || step_lds_bytes(c, c->ty, c->V, c->kz) <= c->lds_limit) break;
