@@ -109,6 +109,11 @@ struct StepArgs {
   int32_t ty, kz, wpr, ny_tiles, ntiles;  // rows per tile, planes per chunk, waves per row
   uint32_t psi_bytes;       // bytes of one psi region (E side; each H-side set is as large)
   uint32_t coef_bytes;      // bytes of the (Ca, Cb) table
+  // E^{n+1} of a box of cells (adjoint history; kernels instantiated with it):
+  // component c of cell (i, j, k) at hist[c * hstride + ((k - k0) * by + j - j0) * bx + i - i0]
+  T* hist;
+  uint64_t hstride;
+  int32_t hbox[6];          // i0, i1, j0, j1, k0, k1
 };
 
 // ---------------------------------------------------------------------------
@@ -348,7 +353,7 @@ constexpr int prefetch_depth() { return (sizeof(T) == 2 && V == 2) ? 2 : 1; }
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOut = 0x80000000u;
 
-template <class T, class C, int V>
+template <class T, class C, int V, bool HIST = false>
 __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int k0,
                                           const int k1, unsigned char* smem_raw) {
   const int wpr = a.wpr;
@@ -928,6 +933,29 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           buf_st<VecT<T, V>>(sh[1], rout, vst, so + 4 * cs_b);
           buf_st<VecT<T, V>>(sh[2], rout, vst, so + 5 * cs_b);
         }
+        if constexpr (HIST) {
+          // E^{n+1} of the box cells of this row and plane (adjoint history)
+          if (upd && j >= a.hbox[2] && j < a.hbox[3] && k >= a.hbox[4] && k < a.hbox[5]) {
+            const int hbx = a.hbox[1] - a.hbox[0], hby = a.hbox[3] - a.hbox[2];
+            T* hp = a.hist + ((size_t)(k - a.hbox[4]) * hby + (j - a.hbox[2])) * hbx;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+              const int i = xl + e;
+              if (i >= a.hbox[0] && i < a.hbox[1]) {
+                const size_t h = (size_t)(i - a.hbox[0]);
+                if constexpr (std::is_same<T, C>::value) {
+                  hp[h] = exo[e];
+                  hp[a.hstride + h] = eyo[e];
+                  hp[2 * a.hstride + h] = ezo[e];
+                } else {
+                  hp[h] = se[0].v[e];
+                  hp[a.hstride + h] = se[1].v[e];
+                  hp[2 * a.hstride + h] = se[2].v[e];
+                }
+              }
+            }
+          }
+        }
         if (flags & 2) {
           for (int p = 0; p < a.nprobe; ++p) {
             const int4 pr = a.probe[p];
@@ -994,7 +1022,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
 template <class C, int V>
 constexpr int step_waves_per_eu() { return (sizeof(C) == 4 && V == 1) ? 6 : 1; }
 
-template <class T, class C, int V>
+template <class T, class C, int V, bool HIST = false>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 step_kernel(const StepArgs<T, C> a) {
@@ -1006,7 +1034,7 @@ step_kernel(const StepArgs<T, C> a) {
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= a.ntiles) return;
   const int k0 = (t / a.ny_tiles) * a.kz;
-  step_tile<T, C, V>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
+  step_tile<T, C, V, HIST>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
 }
 
 // ---------------------------------------------------------------------------

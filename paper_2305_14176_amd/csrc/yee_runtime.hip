@@ -330,35 +330,57 @@ yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool reco
   return a;
 }
 
+// E^{n+1} of a box written by the step itself (adjoint history): the box
+// {i0, i1, j0, j1, k0, k1}, the destination of component 0 and the component
+// stride in elements.
+struct HistOut {
+  const int32_t* box;
+  void* dst;
+  uint64_t stride;
+};
+
 template <class T, class C, int V>
-yee_status launch_step(yee_ctx* c, hipStream_t s, bool record) {
+yee_status launch_step(yee_ctx* c, hipStream_t s, bool record, const HistOut* hist) {
   using namespace yee;
-  const StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz, record);
+  StepArgs<T, C> a = fill_args<T, C>(c, V, c->ty, c->kz, record);
   const int grid = ((a.ntiles + 7) / 8) * 8;
   const int waves = (c->ty + 1) * a.wpr;
   if (waves > max_block_waves(V))
     return fail(YEE_EINVAL, "tile of %d rows x %d waves per row exceeds %d waves", c->ty, a.wpr, max_block_waves(V));
   const size_t lds = step_lds_bytes(c, c->ty, V, c->kz);
   if (lds > c->lds_limit) return fail(YEE_EINVAL, "tile of %d rows needs %zu bytes of LDS (limit %zu)", c->ty, lds, c->lds_limit);
+  if constexpr (std::is_same<T, C>::value) {
+    if (hist) {
+      a.hist = static_cast<T*>(hist->dst);
+      a.hstride = hist->stride;
+      for (int q = 0; q < 6; ++q) a.hbox[q] = hist->box[q];
+      hipLaunchKernelGGL((step_kernel<T, C, V, true>), dim3(grid), dim3(kWave * waves), lds, s, a);
+      HIP_TRY(hipGetLastError());
+      return YEE_OK;
+    }
+  }
   hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
   HIP_TRY(hipGetLastError());
   return YEE_OK;
 }
 
 template <class T, class C>
-yee_status launch_step_v(yee_ctx* c, hipStream_t s, bool record) {
+yee_status launch_step_v(yee_ctx* c, hipStream_t s, bool record, const HistOut* hist) {
   switch (c->V) {
-    case 1: return launch_step<T, C, 1>(c, s, record);
-    case 2: return launch_step<T, C, 2>(c, s, record);
-    default: return launch_step<T, C, 4>(c, s, record);
+    case 1: return launch_step<T, C, 1>(c, s, record, hist);
+    case 2: return launch_step<T, C, 2>(c, s, record, hist);
+    default: return launch_step<T, C, 4>(c, s, record, hist);
   }
 }
 
-yee_status launch_one_step(yee_ctx* c, hipStream_t s, bool record = true) {
+// One single step; hist (FP64 and FP32 contexts only) also writes E^{n+1} of a box.
+yee_status launch_one_step(yee_ctx* c, hipStream_t s, bool record = true, const HistOut* hist = nullptr) {
   switch (c->d.precision) {
-    case YEE_F64: return launch_step_v<double, double>(c, s, record);
-    case YEE_F32: return launch_step_v<float, float>(c, s, record);
-    default: return launch_step_v<_Float16, float>(c, s, record);
+    case YEE_F64: return launch_step_v<double, double>(c, s, record, hist);
+    case YEE_F32: return launch_step_v<float, float>(c, s, record, hist);
+    default:
+      if (hist) return fail(YEE_EINVAL, "box history is written for FP64 and FP32 contexts only");
+      return launch_step_v<_Float16, float>(c, s, record, nullptr);
   }
 }
 
@@ -1545,6 +1567,19 @@ yee_status adj_checkpoint(yee_adjoint* A, int q, bool save, hipStream_t s) {
   return YEE_OK;
 }
 
+// Destination of entry m of history slot `slot` (component 0; components hs apart).
+void* adj_hist_entry(yee_adjoint* A, int slot, int m) {
+  const size_t hs = A->nbox;
+  return A->ws + A->hist.off + ((size_t)slot * (A->K + 1) + m) * 3 * hs * A->c->csize;
+}
+
+// One forward step of the context that also writes E^{n+1} of the box into
+// entry m of history slot `slot` (no separate copy kernel).
+yee_status adj_step_store(yee_adjoint* A, int slot, int m, bool record, hipStream_t s) {
+  const HistOut h{A->box, adj_hist_entry(A, slot, m), (uint64_t)A->nbox};
+  return launch_one_step(A->c, s, record, &h);
+}
+
 // E of the box cells at the current step into entry m of history slot `slot`.
 yee_status adj_store(yee_adjoint* A, int slot, int m, hipStream_t s) {
   yee_ctx* c = A->c;
@@ -1755,10 +1790,9 @@ yee_status yee_adjoint_forward(yee_adjoint* A, double* objective, void* stream) 
     if ((st = adj_checkpoint(A, seg, true, s))) return st;
     if (keep && (st = adj_store(A, slot, 0, s))) return st;
     for (int64_t n = n0; n < n1; ++n) {
-      if ((st = launch_one_step(c, s))) return st;
+      if ((st = keep ? adj_step_store(A, slot, (int)(n + 1 - n0), true, s) : launch_one_step(c, s))) return st;
       c->n += 1;
       c->cur ^= 1;
-      if (keep && (st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       if (c->n - gathered >= d.series_len) {
         if ((st = adj_gather(A, gathered, c->n - gathered, s))) return st;
         gathered = c->n;
@@ -1852,10 +1886,9 @@ yee_status yee_adjoint_backward(yee_adjoint* A, double* grad, void* stream) {
       if ((st = adj_checkpoint(A, seg, false, s))) return st;
       if ((st = adj_store(A, slot, 0, s))) return st;
       for (int64_t n = n0; n < n1; ++n) {
-        if ((st = launch_one_step(c, s, false))) return st;
+        if ((st = adj_step_store(A, slot, (int)(n + 1 - n0), false, s))) return st;
         c->n += 1;
         c->cur ^= 1;
-        if ((st = adj_store(A, slot, (int)(c->n - n0), s))) return st;
       }
       A->slot_seg[slot] = seg;
     }
