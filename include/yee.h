@@ -286,6 +286,20 @@ yee_status yee_set_time_blocking(yee_ctx* ctx, int32_t steps_per_sweep, int32_t 
 yee_status yee_launch_info(const yee_ctx* ctx, int32_t* steps_per_sweep, int32_t* tile_rows, int32_t* chunk_planes,
                            int32_t* samples_per_lane);
 
+/* Debug: tile-ownership check.  With a count buffer set, every single step
+ * of yee_step (two-step sweeps are not taken meanwhile) adds one, with an
+ * atomic, to the count of each element of the output field set it stores:
+ * component c (0..5) of sample (i, j, k) at
+ *     counts[c * comp_stride + (k * ny + j) * row_pitch + i].
+ * After one step every stored sample (i < nx, j < ny, k < nz) must count
+ * exactly one (it belongs to exactly one tile); padding columns i >= nx may
+ * count one (vector stores of a lane's last samples, zeros), and the zero
+ * plane k = nz none.  The caller owns the buffer (uint32, at least
+ * 6 * comp_stride elements, zeroed by the caller); NULL switches counting
+ * off.  Much slower than a plain step: for small test grids. */
+yee_status yee_debug_layout(const yee_ctx* ctx, int64_t* comp_stride, int32_t* row_pitch);
+yee_status yee_debug_set_write_counts(yee_ctx* ctx, uint32_t* device_counts, int64_t n_elems);
+
 /* ------------------------------------------------------------------------
  * Batched stepper for serving many grids (continuous batching).
  *

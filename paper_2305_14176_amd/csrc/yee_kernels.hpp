@@ -114,6 +114,10 @@ struct StepArgs {
   T* hist;
   uint64_t hstride;
   int32_t hbox[6];          // i0, i1, j0, j1, k0, k1
+  // debug (kernels instantiated with it): one count per stored element of the
+  // output field set, component c at wcount + c * cstride, incremented by
+  // every store of that element (tile ownership: exactly one per step)
+  uint32_t* wcount;
 };
 
 // ---------------------------------------------------------------------------
@@ -353,7 +357,11 @@ constexpr int prefetch_depth() { return (sizeof(T) == 2 && V == 2) ? 2 : 1; }
 // ---------------------------------------------------------------------------
 constexpr uint32_t kOut = 0x80000000u;
 
-template <class T, class C, int V, bool HIST = false>
+// Extra work of a step_kernel instantiation: none, the adjoint box history,
+// or the debug write counts.
+enum StepExtra { kPlain = 0, kHistory = 1, kWriteCount = 2 };
+
+template <class T, class C, int V, int EXTRA = kPlain>
 __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int k0,
                                           const int k1, unsigned char* smem_raw) {
   const int wpr = a.wpr;
@@ -933,7 +941,16 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           buf_st<VecT<T, V>>(sh[1], rout, vst, so + 4 * cs_b);
           buf_st<VecT<T, V>>(sh[2], rout, vst, so + 5 * cs_b);
         }
-        if constexpr (HIST) {
+        if constexpr (EXTRA == kWriteCount) {
+          if (vst != kOut) {
+            const uint32_t o = vst / (uint32_t)sizeof(T) + (uint32_t)k * plane;
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+#pragma unroll
+              for (int c = 0; c < 6; ++c) atomicAdd(a.wcount + (size_t)c * a.cstride + o + e, 1u);
+          }
+        }
+        if constexpr (EXTRA == kHistory) {
           // E^{n+1} of the box cells of this row and plane (adjoint history)
           if (upd && j >= a.hbox[2] && j < a.hbox[3] && k >= a.hbox[4] && k < a.hbox[5]) {
             const int hbx = a.hbox[1] - a.hbox[0], hby = a.hbox[3] - a.hbox[2];
@@ -1022,7 +1039,7 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
 template <class C, int V>
 constexpr int step_waves_per_eu() { return (sizeof(C) == 4 && V == 1) ? 6 : 1; }
 
-template <class T, class C, int V, bool HIST = false>
+template <class T, class C, int V, int EXTRA = kPlain>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 step_kernel(const StepArgs<T, C> a) {
@@ -1034,7 +1051,7 @@ step_kernel(const StepArgs<T, C> a) {
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= a.ntiles) return;
   const int k0 = (t / a.ny_tiles) * a.kz;
-  step_tile<T, C, V, HIST>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
+  step_tile<T, C, V, EXTRA>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
 }
 
 // ---------------------------------------------------------------------------

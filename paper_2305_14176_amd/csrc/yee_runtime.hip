@@ -108,6 +108,7 @@ struct yee_ctx {
   // updated in place by a single step and ping-ponged by a sweep (pecur)
   int cur = 0, pecur = 0;
   bool in_batch = false;   // admitted to a batch (yee_load_state refuses)
+  uint32_t* dbg_count = nullptr;   // debug write counts (single steps count their stores)
 };
 
 struct yee_batch {
@@ -354,10 +355,16 @@ yee_status launch_step(yee_ctx* c, hipStream_t s, bool record, const HistOut* hi
       a.hist = static_cast<T*>(hist->dst);
       a.hstride = hist->stride;
       for (int q = 0; q < 6; ++q) a.hbox[q] = hist->box[q];
-      hipLaunchKernelGGL((step_kernel<T, C, V, true>), dim3(grid), dim3(kWave * waves), lds, s, a);
+      hipLaunchKernelGGL((step_kernel<T, C, V, kHistory>), dim3(grid), dim3(kWave * waves), lds, s, a);
       HIP_TRY(hipGetLastError());
       return YEE_OK;
     }
+  }
+  if (c->dbg_count) {
+    a.wcount = c->dbg_count;
+    hipLaunchKernelGGL((step_kernel<T, C, V, kWriteCount>), dim3(grid), dim3(kWave * waves), lds, s, a);
+    HIP_TRY(hipGetLastError());
+    return YEE_OK;
   }
   hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
   HIP_TRY(hipGetLastError());
@@ -961,6 +968,22 @@ yee_status yee_launch_info(const yee_ctx* c, int32_t* steps_per_sweep, int32_t* 
   return YEE_OK;
 }
 
+yee_status yee_debug_layout(const yee_ctx* c, int64_t* comp_stride, int32_t* row_pitch) {
+  if (!c || !comp_stride || !row_pitch) return fail(YEE_EINVAL, "NULL argument");
+  *comp_stride = (int64_t)(c->comp_bytes / c->tsize);
+  *row_pitch = c->px;
+  return YEE_OK;
+}
+
+yee_status yee_debug_set_write_counts(yee_ctx* c, uint32_t* device_counts, int64_t n_elems) {
+  if (!c) return fail(YEE_EINVAL, "NULL context");
+  if (device_counts && n_elems < 6 * (int64_t)(c->comp_bytes / c->tsize))
+    return fail(YEE_ENOMEM, "write counts need %lld elements, got %lld", (long long)(6 * (c->comp_bytes / c->tsize)),
+                (long long)n_elems);
+  c->dbg_count = device_counts;
+  return YEE_OK;
+}
+
 yee_status yee_reset(yee_ctx* c, void* stream) {
   if (!c) return fail(YEE_EINVAL, "NULL context");
   if (!c->bound) return fail(YEE_ESTATE, "no workspace bound");
@@ -1056,7 +1079,7 @@ yee_status yee_step(yee_ctx* c, int64_t n_steps, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   yee_status st = YEE_OK;
   for (int64_t left = n_steps; left > 0;) {
-    const int k = (c->tb_ok && left >= 2) ? 2 : 1;
+    const int k = (c->tb_ok && left >= 2 && !c->dbg_count) ? 2 : 1;
     // the probe ring holds series_len steps: fold before a launch would
     // overwrite samples not yet in the DFT
     if (c->n + k - c->folded > c->d.series_len && (st = fold_dft(c, s))) return st;

@@ -14,8 +14,22 @@ Field state stays resident on the device for the life of a request.  A
 request may carry initial fields.  When it finishes, the run's health is
 checked (``yee_status_flags``: a non-finite value, an FP16 overflow); a
 failing request gets ``status`` and ``error`` set and does not disturb the
-others.  The plain alternative, :func:`serve_one_at_a_time`, solves requests
-first come first served with one ``yee_step`` call each.
+others.
+
+Between replays the server also
+  * cancels requests (``cancel(rid)``, or a ``deadline`` in seconds after
+    arrival that has passed): a running one is retired at once and its slot
+    freed, a waiting one is dropped;
+  * every ``checkpoint_every`` replays, saves the state of each running
+    request (``yee_save_state``) into a device buffer of its own;
+  * after a device reset (simulated from the host by destroying the batch and
+    every in-flight context, ``reset_after_replays``), re-queues the
+    in-flight requests at the front of the queue; each resumes from its last
+    checkpoint (``yee_load_state``), or from the start if it has none.  A
+    resumed request's fields and probe series equal those of an
+    uninterrupted run bitwise.
+The plain alternative, :func:`serve_one_at_a_time`, solves requests first
+come first served with one ``yee_step`` call each.
 """
 from __future__ import annotations
 
@@ -52,6 +66,10 @@ class Request:
     init: Optional[dict] = None               # component -> initial field [nx, ny, nz]
     status: int = 0                           # 0, or YEE_ENUMERIC / YEE_EOVERFLOW
     error: Optional[str] = None
+    deadline: Optional[float] = None          # seconds after arrival; cancelled once passed
+    cancelled: bool = False
+    requeued: int = 0                         # times re-queued after a device reset
+    _resume: Optional[tuple] = field(default=None, repr=False)   # (state tensor, steps done)
 
     @property
     def failed(self) -> bool:
@@ -76,24 +94,37 @@ def _check_health(req: Request, solver: YeeSolver):
 
 class BatchServer:
     def __init__(self, max_slots: int = 32, hbm_budget: int = 4 << 30, steps_per_replay: int = 64,
-                 device: str = "cuda:0", keep_fields=(), max_active_cells: Optional[int] = DEFAULT_ACTIVE_CELLS):
+                 device: str = "cuda:0", keep_fields=(), max_active_cells: Optional[int] = DEFAULT_ACTIVE_CELLS,
+                 checkpoint_every: int = 0):
         import torch
         self.torch = torch
         self.lib = _lib.load()
         self.device = torch.device(device)
         self.K = int(steps_per_replay)
         self.keep_fields = tuple(keep_fields)
+        self.max_slots = int(max_slots)
+        self.hbm_budget = int(hbm_budget)
+        self.max_active_cells = max_active_cells
+        self.checkpoint_every = int(checkpoint_every)
+        self.replays = 0
+        self.resets = 0
+        self._cancel = set()
+        self.batch = None
+        self._make_batch()
+
+    def _make_batch(self):
         b = C.c_void_p()
-        _lib.check(self.lib.yee_batch_create(int(max_slots), int(hbm_budget), self.K, C.byref(b)), "yee_batch_create")
+        _lib.check(self.lib.yee_batch_create(self.max_slots, self.hbm_budget, self.K, C.byref(b)), "yee_batch_create")
         self.batch = b
         nb = C.c_int64()
-        _lib.check(self.lib.yee_batch_footprint(int(max_slots), C.byref(nb)), "yee_batch_footprint")
-        self.table = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        _lib.check(self.lib.yee_batch_footprint(self.max_slots, C.byref(nb)), "yee_batch_footprint")
+        self.table = self.torch.empty(nb.value + 256, dtype=self.torch.uint8, device=self.device)
         base = (self.table.data_ptr() + 255) & ~255
         _lib.check(self.lib.yee_batch_bind_workspace(b, C.c_void_p(base), nb.value), "yee_batch_bind_workspace")
-        self.max_slots = int(max_slots)
-        self.max_active_cells = max_active_cells
-        self.replays = 0
+
+    def cancel(self, rid: int):
+        """Cancel request `rid` at the next replay boundary (running or waiting)."""
+        self._cancel.add(rid)
 
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
@@ -108,8 +139,23 @@ class BatchServer:
             req.fields[c] = solver.field(c)
         req.finished = time.perf_counter() - t0
 
-    def serve(self, requests: List[Request], t0: Optional[float] = None) -> List[Request]:
-        """Serve requests with the given arrival offsets (seconds from t0)."""
+    def _due(self, req: Request, now: float) -> bool:
+        return req.rid in self._cancel or (req.deadline is not None and now > req.arrival + req.deadline)
+
+    def _retire_cancelled(self, req: Request, now: float, done: List[Request]):
+        req.cancelled = True
+        req.error = "cancelled" if req.rid in self._cancel else f"deadline of {req.deadline} s passed"
+        req.finished = now
+        req._resume = None
+        done.append(req)
+
+    def serve(self, requests: List[Request], t0: Optional[float] = None,
+              reset_after_replays: Optional[int] = None) -> List[Request]:
+        """Serve requests with the given arrival offsets (seconds from t0).
+
+        reset_after_replays: simulate a device reset after that many replays
+        (the batch and every in-flight context are destroyed; see the module
+        documentation)."""
         lib = self.lib
         t0 = time.perf_counter() if t0 is None else t0
         waiting = sorted(requests, key=lambda r: r.arrival)
@@ -117,6 +163,17 @@ class BatchServer:
         done: List[Request] = []
         while waiting or running:
             now = time.perf_counter() - t0
+            # cancellations and deadlines (a boundary between replays)
+            for slot in [q for q, (r, _) in running.items() if self._due(r, now)]:
+                req, solver = running.pop(slot)
+                _lib.check(lib.yee_batch_release(self.batch, slot), "yee_batch_release")
+                solver.close()
+                self._retire_cancelled(req, now, done)
+            for req in [r for r in waiting if self._due(r, now)]:
+                waiting.remove(req)
+                self._retire_cancelled(req, now, done)
+            if not waiting and not running:
+                break
             # admit arrived requests while slots, budget and the cell cap allow
             active = sum(r.wl.cells for r, _ in running.values())
             while waiting and waiting[0].arrival <= now:
@@ -126,9 +183,15 @@ class BatchServer:
                     break
                 solver = YeeSolver(req.wl, device=str(self.device),
                                    series_len=max(self.K, req.wl.steps if req.wl.probes else 1))
-                _set_initial(req, solver)
+                left = req.wl.steps
+                if req._resume is not None:
+                    state, done_steps = req._resume
+                    solver.load_state(state)
+                    left = req.wl.steps - done_steps
+                else:
+                    _set_initial(req, solver)
                 slot = C.c_int32()
-                st = lib.yee_batch_admit(self.batch, solver.ctx, int(req.wl.steps), C.byref(slot))
+                st = lib.yee_batch_admit(self.batch, solver.ctx, int(left), C.byref(slot))
                 if st == -6:              # YEE_EAGAIN: wait for a slot or for memory
                     solver.close()
                     if not running:
@@ -136,7 +199,8 @@ class BatchServer:
                                            f"HBM budget even with nothing else admitted")
                     break
                 _lib.check(st, "yee_batch_admit")
-                req.admitted = time.perf_counter() - t0
+                if req.admitted is None:
+                    req.admitted = time.perf_counter() - t0
                 running[slot.value] = (req, solver)
                 active += req.wl.cells
                 waiting.pop(0)
@@ -157,7 +221,27 @@ class BatchServer:
                 self._collect(req, solver, t0)
                 _lib.check(lib.yee_batch_release(self.batch, slot), "yee_batch_release")
                 solver.close()
+                req._resume = None
                 done.append(req)
+            if self.checkpoint_every and self.replays % self.checkpoint_every == 0:
+                for req, solver in running.values():
+                    buf_t = req._resume[0] if req._resume is not None else None
+                    state = solver.save_state(buf_t)
+                    req._resume = (state, solver.steps_done)
+            if reset_after_replays is not None and self.replays == reset_after_replays:
+                # simulated device reset: everything in flight is lost except
+                # the saved states; the requests go back to the front of the queue
+                self.torch.cuda.current_stream(self.device).synchronize()
+                lost = [r for r, _ in running.values()]
+                self.close()
+                for _, solver in running.values():
+                    solver.close()
+                running = {}
+                self._make_batch()
+                self.resets += 1
+                for req in lost:
+                    req.requeued += 1
+                waiting = sorted(lost, key=lambda r: r.arrival) + waiting
         return done
 
     def close(self):

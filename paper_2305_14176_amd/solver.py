@@ -26,9 +26,15 @@ def _ptr(a: np.ndarray, ctype):
 class YeeSolver:
     """A configured, bound and reset context for one workload on one device."""
 
+    # byte the guard bands of a debug workspace are filled with
+    GUARD_BYTE = 0xA5
+
     def __init__(self, wl: Workload, device: str = "cuda:0", series_len: Optional[int] = None,
                  tile_rows: int = 0, chunk_planes: int = 0, samples_per_lane: int = 0, stream=None,
-                 steps_per_sweep: int = 0, sweep_rows: int = 0, sweep_planes: int = 0):
+                 steps_per_sweep: int = 0, sweep_rows: int = 0, sweep_planes: int = 0, guard_bytes: int = 0):
+        """guard_bytes > 0 (debug): the workspace gets guard bands of at least
+        that many bytes on both sides, filled with GUARD_BYTE; check_guards()
+        tells whether any kernel wrote outside the footprint."""
         import torch
         self.torch = torch
         self.lib = _lib.load()
@@ -61,10 +67,15 @@ class YeeSolver:
         nbytes = C.c_int64()
         _lib.check(self.lib.yee_footprint(ctx, C.byref(nbytes)), "yee_footprint")
         self.footprint = nbytes.value
+        g = int(guard_bytes)
         with torch.cuda.device(self.device):
-            self.workspace = torch.empty(self.footprint + 256, dtype=torch.uint8, device=self.device)
+            self.workspace = torch.empty(self.footprint + 256 + 2 * g, dtype=torch.uint8, device=self.device)
+            if g:
+                self.workspace.fill_(self.GUARD_BYTE)
         base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
+        aligned = (base + g + 255) & ~255
+        self._ws_off = aligned - base
+        self.guard_bytes = g
         _lib.check(self.lib.yee_bind_workspace(ctx, C.c_void_p(aligned), self.footprint), "yee_bind_workspace")
         if tile_rows or chunk_planes or samples_per_lane:
             _lib.check(self.lib.yee_set_launch(ctx, tile_rows, chunk_planes, samples_per_lane), "yee_set_launch")
@@ -178,6 +189,35 @@ class YeeSolver:
             _lib.check(self.lib.yee_read_dft(self.ctx, _ptr(re, C.c_double), _ptr(im, C.c_double), self._s()),
                        "yee_read_dft")
         return re + 1j * im
+
+    # -- debug checks ------------------------------------------------------------
+    def check_guards(self) -> bool:
+        """True if both guard bands still hold GUARD_BYTE (needs guard_bytes > 0)."""
+        if not self.guard_bytes:
+            raise RuntimeError("no guard bands: create the solver with guard_bytes > 0")
+        self.torch.cuda.synchronize(self.device)
+        lo = self.workspace[:self._ws_off]
+        hi = self.workspace[self._ws_off + self.footprint:]
+        return bool((lo == self.GUARD_BYTE).all().item() and (hi == self.GUARD_BYTE).all().item())
+
+    def write_counts(self, steps: int = 1) -> np.ndarray:
+        """Debug: run `steps` single steps counting every store of the output
+        field set; returns counts as [6][nz + 1][ny][row_pitch] (uint32)."""
+        stride, pitch = C.c_int64(), C.c_int32()
+        _lib.check(self.lib.yee_debug_layout(self.ctx, C.byref(stride), C.byref(pitch)), "yee_debug_layout")
+        n = 6 * stride.value
+        counts = self.torch.zeros(n, dtype=self.torch.int32, device=self.device)
+        _lib.check(self.lib.yee_debug_set_write_counts(self.ctx, C.c_void_p(counts.data_ptr()), n),
+                   "yee_debug_set_write_counts")
+        try:
+            self.step(steps)
+            self.torch.cuda.synchronize(self.device)
+        finally:
+            self.lib.yee_debug_set_write_counts(self.ctx, None, 0)
+        wl = self.wl
+        per = (wl.nz + 1) * wl.ny * pitch.value
+        host = counts.cpu().numpy().view(np.uint32).reshape(6, stride.value)
+        return host[:, :per].reshape(6, wl.nz + 1, wl.ny, pitch.value)
 
     # -- health and checkpoints ------------------------------------------------
     def status(self):

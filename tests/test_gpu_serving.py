@@ -174,3 +174,51 @@ def test_failed_request_leaves_the_others_untouched():
     poked = _requests(specs[1:2])[0]
     poked.init = {"Ez": ez}
     assert serve_one_at_a_time([poked])[0].status == -5
+
+
+def test_cancel_and_deadline():
+    """A request cancelled by id and one whose deadline passes are retired at a
+    replay boundary (slot freed); the others finish as if alone."""
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    specs = [(32, 60, 501, 0.0), (48, 400, 502, 0.0), (64, 400, 503, 0.0), (32, 45, 504, 0.0)]
+    keep = ("Ez",)
+    _say("[gpu] serving: cancel and deadline")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests([specs[0], specs[3]]), keep_fields=keep)}
+    reqs = _requests(specs)
+    reqs[2].deadline = 0.0                       # passed at the first boundary after arrival
+    srv = BatchServer(max_slots=4, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep)
+    srv.cancel(1)
+    done = {r.rid: r for r in srv.serve(reqs)}
+    info = (C.c_int32(), C.c_int64())
+    srv.lib.yee_batch_info(srv.batch, C.byref(info[0]), C.byref(info[1]))
+    assert info[0].value == 0 and info[1].value == 0           # every slot and byte released
+    srv.close()
+    assert done[1].cancelled and done[2].cancelled
+    assert "cancelled" in done[1].error and "deadline" in done[2].error
+    for rid, a in ((0, alone[0]), (3, alone[1])):
+        assert not done[rid].cancelled and not done[rid].failed
+        np.testing.assert_array_equal(done[rid].series, a.series)
+        np.testing.assert_array_equal(done[rid].fields["Ez"], a.fields["Ez"])
+
+
+def test_device_reset_requeues_from_checkpoints():
+    """A simulated device reset (the batch and every in-flight context
+    destroyed from the host) re-queues the running requests; each resumes from
+    its last checkpoint and ends bitwise equal to its run alone."""
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    specs = [(32, 90, 601, 0.0), (48, 75, 602, 0.0), (64, 70, 603, 0.0), (32, 20, 604, 0.0)]
+    keep = ("Ez", "Hx")
+    _say("[gpu] serving: device reset")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(specs), keep_fields=keep)}
+    srv = BatchServer(max_slots=4, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep, checkpoint_every=3)
+    done = {r.rid: r for r in srv.serve(_requests(specs), reset_after_replays=5)}
+    srv.close()
+    assert srv.resets == 1
+    assert sum(r.requeued for r in done.values()) >= 3      # every request longer than 40 steps was in flight
+    for rid, a in alone.items():
+        b = done[rid]
+        assert not b.failed and not b.cancelled
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
