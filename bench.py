@@ -290,22 +290,29 @@ def adjoint_benchmark(checkpoint_every=64):
         prob.solver.step(prob.n_steps)
         torch.cuda.synchronize()
         t4 = time.perf_counter()
-        res = (t1 - t0, t2 - t1, t4 - t3, g.numel(), prob.run.footprint, prob.n_steps)
+        res = (t1 - t0, t2 - t1, t4 - t3, g.numel(), prob.run.footprint, prob.n_steps, prob.run.history_segments)
         prob.close()
         return res
 
-    fwd, bwd, plain, nbox, ws, n_steps = timed(1)
+    # the default schedule: checkpoints every K steps, the newest segments'
+    # E histories kept within the default history budget, the older
+    # segments recomputed from their checkpoints
+    fwd, bwd, plain, nbox, ws, n_steps, kept = timed(None)
+    segments = -(-n_steps // checkpoint_every)
     out = {"workload": f"{wl.name}: design [{d0},{d1})^3, {n_steps} steps, {len(wl.probes)} Ez probes, "
                        f"checkpoint every {checkpoint_every}",
            "dtype": "f32 fields, f64 gradient",
+           "schedule": f"{segments} segments: E history kept from the forward run for the newest {kept}, "
+                       f"{segments - kept} recomputed from their checkpoints",
            "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
            "gradient_ms": round((fwd + bwd) * 1e3, 2), "plain_forward_ms": round(plain * 1e3, 2),
            "gradient_over_plain": round((fwd + bwd) / plain, 3),
            "design_cells": nbox, "workspace_bytes": ws}
-    fwd, bwd, plain, _, ws, _ = timed(0)
-    out["all_history_kept"] = {"forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
-                               "gradient_ms": round((fwd + bwd) * 1e3, 2),
-                               "gradient_over_plain": round((fwd + bwd) / plain, 3), "workspace_bytes": ws}
+    for name, h in (("one_history_kept", 1), ("all_history_kept", 0)):
+        fwd, bwd, plain, _, ws, _, _ = timed(h)
+        out[name] = {"forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
+                     "gradient_ms": round((fwd + bwd) * 1e3, 2),
+                     "gradient_over_plain": round((fwd + bwd) / plain, 3), "workspace_bytes": ws}
     return out
 
 
@@ -314,6 +321,9 @@ FP16_MFMA_PEAK_TFLOPS = 2500.0    # published MI355X dense fp16 matrix peak
 FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply-add, four real multiply-adds
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak
 SPREAD_FLOPS_PER_RAY_BLOCK = 2 * 44 + 16 + 16   # per (ray, pair, chirp): 44 FMAs (8 taps), 16 mul, 16 grid adds
+SPREAD_ATOMICS_PER_RAY_BLOCK = 16   # 64-bit LDS integer atomics per (ray, pair, chirp): 8 taps x (re, im)
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz; one 64-bit atomic moves 8 bytes
+LDS_ATOMIC64_PEAK_PER_S = 256 * 2.4e9 * 128 / 8
 
 
 def sparams_benchmark():
@@ -428,17 +438,25 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
                      "traffic": None, "algorithmic_flops_per_launch": ray_blocks * SPREAD_FLOPS_PER_RAY_BLOCK,
                      "flops_counted": "per ray, pair and chirp: 8 kernel values (44 FMAs), 16 multiplies, 16 grid "
                                       "additions; the FP64 antenna legs, conversions and atomics are not counted",
+                     "lds_atomic_bound": {
+                         "achieved_per_s": round(ray_blocks * SPREAD_ATOMICS_PER_RAY_BLOCK / (ms / 1e3), 1),
+                         "peak_per_s": LDS_ATOMIC64_PEAK_PER_S,
+                         "frac": round(ray_blocks * SPREAD_ATOMICS_PER_RAY_BLOCK / (ms / 1e3)
+                                       / LDS_ATOMIC64_PEAK_PER_S, 4),
+                         "basis": "16 64-bit integer LDS atomics per ray, pair and chirp against 128 B per clock "
+                                  "per CU of LDS bandwidth (8 B per atomic, no bank conflicts)"},
                      "kernel": "rmd::spread_kernel (timed with rmd::geometry_kernel and rmd::finish_kernel: "
                                "one IF cube)",
                      "kernel_ms_avg": round(ms, 3)},
         "direct": {
             "method": "direct: fp16 hi/lo split MFMA products (rmd_if_cube_direct)",
             "value": round(terms / (ms_d / 1e3), 1), "unit": "terms/s", "ms_per_cube": round(ms_d, 3),
-            "roofline": {"bound": "mfma", "achieved": round(tflops_d, 2), "peak": FP32_MFMA_PEAK_TFLOPS,
-                         "unit": "TFLOP/s", "frac": round(tflops_d / FP32_MFMA_PEAK_TFLOPS, 4),
-                         "peak_basis": "dense FP32 matrix peak: the result has FP32-class accuracy",
-                         "fp16_matrix_tflops": round(3 * tflops_d, 2),
-                         "fp16_matrix_frac": round(3 * tflops_d / FP16_MFMA_PEAK_TFLOPS, 4),
+            "roofline": {"bound": "mfma", "achieved": round(3 * tflops_d, 2), "peak": FP16_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(3 * tflops_d / FP16_MFMA_PEAK_TFLOPS, 4),
+                         "peak_basis": "dense fp16 matrix peak, the type the products execute in: three fp16 "
+                                       "MFMA products (hi x hi, hi x lo, lo x hi) per FP32-class term",
+                         "fp32_class_tflops": round(tflops_d, 2),
+                         "frac_of_fp32_matrix_peak": round(tflops_d / FP32_MFMA_PEAK_TFLOPS, 4),
                          "traffic": None, "algorithmic_flops_per_launch": terms * FLOPS_PER_TERM,
                          "kernel": "rmd::synth_kernel (timed with rmd::geometry_kernel and rmd::reduce_kernel: "
                                    "one IF cube)",

@@ -54,16 +54,30 @@ def design_workload(wl: Workload, box: Sequence[int]) -> Tuple[Workload, np.ndar
     return out, (kk * nsy + jj) * nsx + ii
 
 
+# Device memory the default schedule may spend on kept E histories (bytes).
+DEFAULT_HISTORY_BUDGET = 2 << 30
+
+
+def history_segments_for(n_steps: int, checkpoint_every: int, box_cells: int, elem_bytes: int,
+                         budget: int = DEFAULT_HISTORY_BUDGET) -> int:
+    """The newest segments whose E histories fit in `budget` bytes (at least one:
+    the segment the backward run starts with), each (K + 1) x 3 x box cells."""
+    segments = -(-int(n_steps) // int(checkpoint_every))
+    per_segment = (int(checkpoint_every) + 1) * 3 * int(box_cells) * int(elem_bytes)
+    return max(1, min(segments, int(budget) // per_segment))
+
+
 class AdjointRun:
     """One forward run with checkpoints and its reverse-time gradient.
 
     ``history_segments``: how many of the newest segments keep the E history
-    of the box from the forward run (1: checkpoint-recompute; 0: all, and the
-    backward run recomputes nothing, for (K + 1) x 3 x box cells of memory per
-    segment)."""
+    of the box from the forward run (1: every other segment is recomputed from
+    its checkpoint; 0: all, and the backward run recomputes nothing), for
+    (K + 1) x 3 x box cells of memory per segment.  None: as many as fit in
+    DEFAULT_HISTORY_BUDGET bytes, the older segments recomputed."""
 
     def __init__(self, solver: YeeSolver, n_steps: int, box: Sequence[int], checkpoint_every: int = 64,
-                 history_segments: int = 1):
+                 history_segments: int = None):
         self.solver = solver
         self.lib = solver.lib
         self.box = tuple(int(v) for v in box)
@@ -74,6 +88,11 @@ class AdjointRun:
         _lib.check(self.lib.yee_adjoint_create(solver.ctx, self.n_steps, int(checkpoint_every), b, C.byref(h)),
                    "yee_adjoint_create")
         self.handle = h
+        if history_segments is None:
+            cells = self.shape[0] * self.shape[1] * self.shape[2]
+            elem = 8 if solver.wl.precision == "f64" else 4
+            history_segments = history_segments_for(self.n_steps, checkpoint_every, cells, elem)
+        self.history_segments = int(history_segments)
         if history_segments != 1:
             _lib.check(self.lib.yee_adjoint_set_history(h, int(history_segments)), "yee_adjoint_set_history")
         nb = C.c_int64()
@@ -115,7 +134,7 @@ class DesignProblem:
     """A workload whose box cells carry free eps_r values (the design)."""
 
     def __init__(self, wl: Workload, box: Sequence[int], n_steps: int = None, checkpoint_every: int = 64,
-                 device: str = "cuda:0", history_segments: int = 1):
+                 device: str = "cuda:0", history_segments: int = None):
         self.wl, self.block = design_workload(wl, box)
         self.box = tuple(int(v) for v in box)
         self.n_steps = int(wl.steps if n_steps is None else n_steps)

@@ -43,7 +43,7 @@ def _gpu_gradient(wl, box, ckpt, init=None):
     if init is not None:
         for c, a in init.items():
             s.set_field(c, a)
-    run = AdjointRun(s, wl.steps, box, checkpoint_every=ckpt)
+    run = AdjointRun(s, wl.steps, box, checkpoint_every=ckpt, history_segments=1)
     j = run.forward()
     g = run.backward().cpu().numpy()
     run.close()
@@ -94,7 +94,7 @@ def test_gradient_matches_finite_differences_small():
     wl = _case("f64", "e", seed=12, steps=120)
     box = BOX_IN
     _say(f"[gpu] adjoint FD {wl.name}")
-    prob = DesignProblem(wl, box, checkpoint_every=32)
+    prob = DesignProblem(wl, box, checkpoint_every=32, history_segments=1)
     eps0 = prob.initial_design
     prob.forward(eps0)
     g = prob.gradient().cpu().numpy()
@@ -166,7 +166,7 @@ def test_autograd_function_returns_the_library_gradient():
     wl = _case("f32", "e", seed=13, steps=100)
     box = BOX_IN
     _say(f"[gpu] adjoint autograd {wl.name}")
-    prob = DesignProblem(wl, box, checkpoint_every=32)
+    prob = DesignProblem(wl, box, checkpoint_every=32, history_segments=1)
     rng = np.random.default_rng(5)
     design = prob.initial_design + rng.uniform(0, 0.5, prob.block.shape)
     eps = torch.tensor(design, dtype=torch.float64, device="cuda", requires_grad=True)
@@ -201,7 +201,7 @@ def test_adjoint_leaves_context_as_plain_steps():
     # a probe ring shorter than the run and the checkpoint interval
     a = YeeSolver(wl, series_len=20)
     b = YeeSolver(wl, series_len=20)
-    run = AdjointRun(a, wl.steps, BOX_IN, checkpoint_every=32)
+    run = AdjointRun(a, wl.steps, BOX_IN, checkpoint_every=32, history_segments=1)
     run.forward()
     g1 = run.backward().cpu().numpy()
     g2 = run.backward().cpu().numpy()
