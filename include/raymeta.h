@@ -99,8 +99,11 @@ rmd_status rmd_check_scene(const rmd_scene* scene, int32_t n_chirps, void* works
 /* Bytes of device workspace rmd_if_cube and rmd_if_cube_direct need for these
  * sizes (one size serves both).  Chirps are processed in batches of up to 16
  * whose per-ray geometry (7 float64 per ray and chirp: inner path length,
- * first and last hit point) fits in 1 GiB; the workspace holds one batch's
- * geometry, every hit resolved to its triangle's vertex indices and
+ * first and last hit point) fits in 1 GiB; the workspace holds the geometry
+ * of one batch, or of two when there are several (the next batch's geometry
+ * is built on a library-owned helper stream of the device while the current
+ * batch is synthesised; events join it back into the caller's stream),
+ * every hit resolved to its triangle's vertex indices and
  * barycentric coordinates (20 bytes per hit, once per call), and the batch's
  * per-partition results (rmd_if_cube: a grid of M
  * complex64 cells per ray partition, pair and chirp, M the smallest power of

@@ -853,6 +853,7 @@ int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
 struct Plan {
     int batch, parts, rays_per_part, grid_log2;
     int64_t geo_bytes, rec_bytes, partial_bytes, grid_bytes, deconv_bytes, total_bytes;
+    int geo_sets;   // geometry buffers: 2 when there are several batches (the next one is built meanwhile)
 };
 
 Plan plan(int n_rays, int64_t n_hits, int n_pairs, int chirp_count, int n_samples) {
@@ -874,7 +875,8 @@ Plan plan(int n_rays, int64_t n_hits, int n_pairs, int chirp_count, int n_sample
     p.partial_bytes = (int64_t)p.parts * blocks * n_samples * (int64_t)sizeof(float2);
     p.grid_bytes = round256((int64_t)p.parts * blocks * (int64_t(1) << p.grid_log2) * (int64_t)sizeof(float2));
     p.deconv_bytes = round256((int64_t)n_samples * (int64_t)sizeof(double)) + 256;   // + the max-weight word
-    p.total_bytes = p.geo_bytes + p.rec_bytes + std::max(p.partial_bytes, p.grid_bytes + p.deconv_bytes);
+    p.geo_sets = chirp_count > p.batch ? 2 : 1;
+    p.total_bytes = p.geo_sets * p.geo_bytes + p.rec_bytes + std::max(p.partial_bytes, p.grid_bytes + p.deconv_bytes);
     return p;
 }
 
@@ -1046,10 +1048,11 @@ rmd_status cube_setup(const rmd_scene* scene, const rmd_radar* radar, int32_t n_
     a.pairs = pairs;
     a.weights = weights;
     a.geo = static_cast<double*>(workspace);
-    a.hit_rec = reinterpret_cast<int4*>(static_cast<char*>(workspace) + p.geo_bytes);
-    a.hit_rec_v = reinterpret_cast<float*>(static_cast<char*>(workspace) + p.geo_bytes +
+    const int64_t geo_all = p.geo_sets * p.geo_bytes;
+    a.hit_rec = reinterpret_cast<int4*>(static_cast<char*>(workspace) + geo_all);
+    a.hit_rec_v = reinterpret_cast<float*>(static_cast<char*>(workspace) + geo_all +
                                            round256(scene->n_hits * (int64_t)sizeof(int4)));
-    a.partial = reinterpret_cast<float2*>(static_cast<char*>(workspace) + p.geo_bytes + p.rec_bytes);
+    a.partial = reinterpret_cast<float2*>(static_cast<char*>(workspace) + geo_all + p.rec_bytes);
     a.n_pairs = n_pairs;
     a.n_samples = radar->n_samples;
     a.n_parts = p.parts;
@@ -1058,6 +1061,102 @@ rmd_status cube_setup(const rmd_scene* scene, const rmd_radar* radar, int32_t n_
     const double mu = radar->bandwidth / radar->t_chirp;               // Eq. 3
     a.cyc_per_m = radar->f_c / rmd::kC0;
     a.step_per_m = mu / (rmd::kC0 * radar->f_s);
+    return RMD_OK;
+}
+
+// Helper stream of the current device (created once, default priority): the
+// geometry of the next chirp batch is built on it while the current batch is
+// synthesised on the caller's stream.
+rmd_status helper_stream(hipStream_t* out) {
+    static std::mutex mu;
+    static hipStream_t streams[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(RMD_EINVAL, "device index beyond the helper stream table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    *out = streams[dev];
+    return RMD_OK;
+}
+
+// The chirp batches of one IF cube: geometry_kernel of batch b into geometry
+// set b mod geo_sets, then work(args, nb, c0) on `stream` (the batch's
+// synthesis).  With two sets, batch b + 1's geometry runs on the helper stream
+// while batch b is synthesised; events order each geometry after the
+// synthesis that last read its set, and each synthesis after its geometry, so
+// the helper stream's work is joined back into `stream` (also under graph
+// capture).  The results are those of the serial order.
+template <class Work>
+rmd_status run_batches(const Plan& p, rmd::SynthArgs a, int32_t chirp0, int32_t chirp_count, int n_rays,
+                       hipStream_t stream, Work&& work) {
+    char* geo0 = reinterpret_cast<char*>(a.geo);
+    auto geometry = [&](int b, hipStream_t st) {
+        rmd::SynthArgs g = a;
+        const int c0 = b * p.batch;
+        g.chirp0 = chirp0 + c0;
+        g.chirp_count = std::min(p.batch, chirp_count - c0);
+        g.geo = reinterpret_cast<double*>(geo0 + (size_t)(b % p.geo_sets) * p.geo_bytes);
+        hipLaunchKernelGGL(rmd::geometry_kernel, dim3((n_rays + 255) / 256, g.chirp_count), dim3(256), 0, st, g);
+    };
+    auto batch_args = [&](int b) {
+        rmd::SynthArgs w = a;
+        const int c0 = b * p.batch;
+        w.chirp0 = chirp0 + c0;
+        w.chirp_count = std::min(p.batch, chirp_count - c0);
+        w.geo = reinterpret_cast<double*>(geo0 + (size_t)(b % p.geo_sets) * p.geo_bytes);
+        return w;
+    };
+    const int nbatch = (chirp_count + p.batch - 1) / p.batch;
+    if (p.geo_sets == 1) {
+        for (int b = 0; b < nbatch; ++b) {
+            geometry(b, stream);
+            const rmd::SynthArgs w = batch_args(b);
+            work(w, w.chirp_count, b * p.batch);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "IF cube launch");
+        }
+        return RMD_OK;
+    }
+    hipStream_t s2 = nullptr;
+    rmd_status st = helper_stream(&s2);
+    if (st != RMD_OK) return st;
+    hipEvent_t ev[5] = {};   // start, geometry done (per set), synthesis done (per set)
+    for (auto& x : ev) {
+        hipError_t e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (auto& y : ev)
+                if (y) (void)hipEventDestroy(y);
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
+    }
+    hipEvent_t* geo_done = ev + 1;
+    hipEvent_t* work_done = ev + 3;
+    hipError_t e = hipEventRecord(ev[0], stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, ev[0], 0);      // after everything queued before the call
+    if (e == hipSuccess) {
+        geometry(0, s2);
+        e = hipEventRecord(geo_done[0], s2);
+    }
+    for (int b = 0; b < nbatch && e == hipSuccess; ++b) {
+        e = hipStreamWaitEvent(stream, geo_done[b & 1], 0);
+        if (e != hipSuccess) break;
+        const rmd::SynthArgs w = batch_args(b);
+        work(w, w.chirp_count, b * p.batch);
+        e = hipEventRecord(work_done[b & 1], stream);
+        if (e != hipSuccess || b + 1 >= nbatch) break;
+        // set (b + 1) % 2 was last read by batch b - 1
+        if (b >= 1) e = hipStreamWaitEvent(s2, work_done[(b + 1) & 1], 0);
+        if (e != hipSuccess) break;
+        geometry(b + 1, s2);
+        e = hipEventRecord(geo_done[(b + 1) & 1], s2);
+    }
+    if (e == hipSuccess) e = hipGetLastError();
+    for (auto& x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "IF cube launch");
     return RMD_OK;
 }
 
@@ -1087,7 +1186,7 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     const int M = 1 << p.grid_log2;
     a.grid_log2 = p.grid_log2;
     a.center = radar->n_samples / 2;
-    char* tail = static_cast<char*>(workspace) + p.geo_bytes + p.rec_bytes + p.grid_bytes;
+    char* tail = static_cast<char*>(workspace) + p.geo_sets * p.geo_bytes + p.rec_bytes + p.grid_bytes;
     auto* wmax = reinterpret_cast<unsigned*>(tail);
     auto* deconv = reinterpret_cast<double*>(tail + 256);
     a.deconv = deconv;
@@ -1106,22 +1205,17 @@ rmd_status rmd_if_cube(const rmd_scene* scene, const rmd_radar* radar, int32_t n
     const size_t spread_lds =
         (size_t)rmd::kGridCopies * (2 * (M + rmd::kTaps) + 1) * sizeof(unsigned long long);
     const size_t finish_lds = (size_t)(M / 2 + M) * sizeof(double2);
-    // Chirp batches: geometry of the batch, then the spreading and the
-    // transform of the batch (the partition count is the same for every
-    // batch: a shorter last batch uses part of the buffers).
-    for (int c0 = 0; c0 < chirp_count; c0 += p.batch) {
-        const int nb = std::min(p.batch, chirp_count - c0);
-        a.chirp0 = chirp0 + c0;
-        a.chirp_count = nb;
-        hipLaunchKernelGGL(rmd::geometry_kernel, dim3((scene->n_rays + 255) / 256, nb), dim3(256), 0, stream, a);
-        const dim3 grid((unsigned)((int64_t)n_pairs * nb * p.parts));
-        hipLaunchKernelGGL(rmd::spread_kernel, grid, dim3(rmd::kThreads), spread_lds, stream, a);
-        hipLaunchKernelGGL(rmd::finish_kernel, dim3((unsigned)(n_pairs * nb)), dim3(rmd::kFinishThreads), finish_lds,
-                           stream, a, reinterpret_cast<float2*>(s), chirp_count, c0);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "IF cube launch");
-    }
-    return RMD_OK;
+    // Chirp batches: the spreading and the transform of each batch after its
+    // geometry (the partition count is the same for every batch: a shorter
+    // last batch uses part of the buffers).
+    return run_batches(p, a, chirp0, chirp_count, scene->n_rays, stream,
+                       [&](const rmd::SynthArgs& w, int nb, int c0) {
+                           const dim3 grid((unsigned)((int64_t)n_pairs * nb * p.parts));
+                           hipLaunchKernelGGL(rmd::spread_kernel, grid, dim3(rmd::kThreads), spread_lds, stream, w);
+                           hipLaunchKernelGGL(rmd::finish_kernel, dim3((unsigned)(n_pairs * nb)),
+                                              dim3(rmd::kFinishThreads), finish_lds, stream, w,
+                                              reinterpret_cast<float2*>(s), chirp_count, c0);
+                       });
 }
 
 rmd_status rmd_if_cube_static(const rmd_scene* scene, const rmd_radar* radar, int32_t n_pairs, const double* pairs,
@@ -1151,23 +1245,18 @@ rmd_status rmd_if_cube_direct(const rmd_scene* scene, const rmd_radar* radar, in
     if (st != RMD_OK) return st;
     st = resolve_hits(a, stream);
     if (st != RMD_OK) return st;
-    // Chirp batches: geometry of the batch, then the synthesis and the
-    // partition sums of the batch.
-    for (int c0 = 0; c0 < chirp_count; c0 += p.batch) {
-        const int nb = std::min(p.batch, chirp_count - c0);
-        a.chirp0 = chirp0 + c0;
-        a.chirp_count = nb;
-        hipLaunchKernelGGL(rmd::geometry_kernel, dim3((scene->n_rays + 255) / 256, nb), dim3(256), 0, stream, a);
-        const dim3 grid((unsigned)((int64_t)n_pairs * a.n_passes * nb * p.parts));
-        hipLaunchKernelGGL(rmd::synth_kernel, grid, dim3(rmd::kThreads), 0, stream, a);
-        const int64_t count = (int64_t)n_pairs * nb * radar->n_samples;
-        hipLaunchKernelGGL(rmd::reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
-                           a.partial, reinterpret_cast<float2*>(s), n_pairs, nb, radar->n_samples, p.parts,
-                           chirp_count, c0);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "IF cube launch");
-    }
-    return RMD_OK;
+    // Chirp batches: the synthesis and the partition sums of each batch after
+    // its geometry.
+    const int n_samples = radar->n_samples;
+    return run_batches(p, a, chirp0, chirp_count, scene->n_rays, stream,
+                       [&](const rmd::SynthArgs& w, int nb, int c0) {
+                           const dim3 grid((unsigned)((int64_t)n_pairs * w.n_passes * nb * p.parts));
+                           hipLaunchKernelGGL(rmd::synth_kernel, grid, dim3(rmd::kThreads), 0, stream, w);
+                           const int64_t count = (int64_t)n_pairs * nb * n_samples;
+                           hipLaunchKernelGGL(rmd::reduce_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                                              stream, w.partial, reinterpret_cast<float2*>(s), n_pairs, nb, n_samples,
+                                              p.parts, chirp_count, c0);
+                       });
 }
 
 rmd_status rmd_range_doppler(const float* s, float* S, int32_t n_pairs, int32_t n_chirps, int32_t n_samples,

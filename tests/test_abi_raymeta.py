@@ -49,7 +49,8 @@ def _r256(b):
 
 def _plan(n_rays, n_pairs, chirps, n_samples, n_hits=None):
     """The documented work plan: chirp batches of at most 16 whose per-ray
-    geometry (7 doubles per ray and chirp) fits in 1 GiB; ray partitions so
+    geometry (7 doubles per ray and chirp) fits in 1 GiB, two such geometry
+    buffers when there is more than one batch; ray partitions so
     that about 8192 workgroups run per batch, each wave keeping >= 4 groups
     of 64 rays (256-ray granules); the hits' resolved records (16 + 4 bytes
     per hit); then room for either method's partition
@@ -63,7 +64,7 @@ def _plan(n_rays, n_pairs, chirps, n_samples, n_hits=None):
     rpp = -(-n_rays // np_)
     rpp = -(-rpp // 256) * 256
     parts = -(-n_rays // rpp)
-    geo = _r256(n_rays * 56 * batch)
+    geo = _r256(n_rays * 56 * batch) * (2 if chirps > batch else 1)
     n_hits = int(n_rays * 1.75) if n_hits is None else n_hits
     rec = _r256(n_hits * 16) + _r256(n_hits * 4)
     M = 64
