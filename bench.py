@@ -486,6 +486,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid side (256 is the benchmark workload)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--chunk-planes", type=int, default=0)
+    ap.add_argument("--steps-per-sweep", type=int, default=0,
+                    help="0 automatic (single steps at 256^3), 1 single steps, 2 two-step sweeps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving sweep")
     ap.add_argument("--serving-requests", type=int, default=512)
@@ -518,7 +520,7 @@ def main():
     wl = W.cpml_block_lattice(n=args.n, steps=args.steps)
     if args.profile_run:
         solver = YeeSolver(wl, device="cuda:0", series_len=1000, tile_rows=args.tile_rows,
-                           chunk_planes=args.chunk_planes)
+                           chunk_planes=args.chunk_planes, steps_per_sweep=args.steps_per_sweep)
         solver.step(args.steps)
         src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
@@ -529,7 +531,8 @@ def main():
                           "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
     solver = YeeSolver(wl, device="cuda:0", series_len=max(1000, args.steps),
-                       tile_rows=args.tile_rows, chunk_planes=args.chunk_planes)
+                       tile_rows=args.tile_rows, chunk_planes=args.chunk_planes, steps_per_sweep=args.steps_per_sweep)
+    launch = solver.launch_info()
     stream = torch.cuda.current_stream()
     solver.step(args.warmup)
     torch.cuda.synchronize()
@@ -551,7 +554,7 @@ def main():
     value = cells * args.steps / (ms / 1e3) / 1e6
     alg, fields_b, psi_b = algorithmic_bytes_per_step(wl)
     achieved = alg / (ms_per_step / 1e3) / 1e9
-    traffic = load_traffic()
+    traffic = load_traffic() if launch["steps_per_sweep"] == 1 else None
 
     out = {
         "metric": "Mcell-updates/s (FP32 Yee step, 256^3, CPML 10); serving p50/p99 in 'serving'",
@@ -569,14 +572,16 @@ def main():
         "config": {"workload": wl.name, "cells": cells, "cpml_cells": list(wl.cpml_cells),
                    "materials": "8^3-cell block lattice, eps_r~U[1,10), sigma~U[0,0.1)",
                    "probes": len(wl.probes), "dft_freqs": len(wl.freqs),
-                   "tile_rows": args.tile_rows or "auto", "chunk_planes": args.chunk_planes or "auto",
+                   "tile_rows": launch["tile_rows"], "chunk_planes": launch["chunk_planes"],
+                   "steps_per_sweep": launch["steps_per_sweep"],
                    "parallelism": "single GPU"},
         "hbm_gbs_algorithmic": round(achieved, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg,
-                     "kernel": "yee::step_kernel (fused H + E + CPML step)",
+                     "kernel": ("yee::tb_kernel (two fused steps per sweep; per step)" if launch["steps_per_sweep"] == 2
+                                else "yee::step_kernel (fused H + E + CPML step)"),
                      "kernel_ms_avg": round(ms_per_step, 5),
                      "copy_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
