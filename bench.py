@@ -498,6 +498,10 @@ def main():
     ap.add_argument("--if-only", action="store_true",
                     help="run only the ray-meta-data IF measurement and print its JSON object")
     ap.add_argument("--if-reps", type=int, default=5)
+    ap.add_argument("--precision-only", action="store_true",
+                    help="run only the FP16-storage and FP64 timings and print their JSON object")
+    ap.add_argument("--profile-workload", choices=("cpml256", "fp16sub"), default="cpml256",
+                    help="workload of --profile-run: the 256^3 FP32 one or the 512x512x256 FP16-storage substrate")
     ap.add_argument("--profile-run", action="store_true",
                     help="counter-collection driver: a few untimed steps, then a plain device copy of "
                          "COPY_MIB MiB (the known-size kernel the HBM counters are scaled by)")
@@ -517,8 +521,14 @@ def main():
                                                                  cpu=not args.no_cpu_baseline)}))
         return
 
+    if args.precision_only:
+        print(json.dumps({"precision_modes": precision_benchmark()}))
+        return
+
     wl = W.cpml_block_lattice(n=args.n, steps=args.steps)
     if args.profile_run:
+        if args.profile_workload == "fp16sub":
+            wl = W.fp16_substrate(steps=args.steps)
         solver = YeeSolver(wl, device="cuda:0", series_len=1000, tile_rows=args.tile_rows,
                            chunk_planes=args.chunk_planes, steps_per_sweep=args.steps_per_sweep)
         solver.step(args.steps)
@@ -526,8 +536,9 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": wl.name, "steps": args.steps,
-                          "algorithmic_bytes_per_step": algorithmic_bytes_per_step(wl)[0],
+        eb = 2 if wl.precision == "f16" else 4
+        print(json.dumps({"profile_run": wl.name, "steps": args.steps, "launch": solver.launch_info(),
+                          "algorithmic_bytes_per_step": algorithmic_bytes_per_step(wl, elem_bytes=eb)[0],
                           "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
         return
     solver = YeeSolver(wl, device="cuda:0", series_len=max(1000, args.steps),
