@@ -54,8 +54,10 @@ def design_workload(wl: Workload, box: Sequence[int]) -> Tuple[Workload, np.ndar
     return out, (kk * nsy + jj) * nsx + ii
 
 
-# Device memory the default schedule may spend on kept E histories (bytes).
-DEFAULT_HISTORY_BUDGET = 2 << 30
+# Device memory the default schedule may spend on kept E histories (bytes):
+# a small share of a 288 GB device (the 128^3 design problem's 16 segments of
+# 64 steps need 3.3 GB).
+DEFAULT_HISTORY_BUDGET = 4 << 30
 
 
 def history_segments_for(n_steps: int, checkpoint_every: int, box_cells: int, elem_bytes: int,
