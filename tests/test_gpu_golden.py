@@ -5,14 +5,19 @@ The expected values under ``tests/golden/`` were written by
 seeded input generators.
 
 * 256^3 FP32, 10-cell CPML, 16 probes, 64 DFT frequencies, 1000 steps (the
-  full-size FP32 workload): every probe series and every probe's DFT vector
-  to 1e-5 relative L2; every component at 8192 seeded positions plus the
-  probe cells, element by element, at step 300 (the pulse inside the grid)
-  and at step 1000 (most of it gone through the CPML): |got - ref| <= 1e-4
-  of the component's RMS over the whole grid at step 300 (FP32 storage
-  rounds each value to 2^-24 relative; over 1000 steps that walks to a few
-  1e-6 of the local amplitude, and local amplitudes stay within a few tens of
-  the RMS), and at step 300 also 1e-5 relative L2 over the sampled set.
+  full-size FP32 workload), in single steps and in two-step sweeps: every
+  probe series and every probe's DFT vector to 1e-5 relative L2 (measured
+  2.5e-6 and 1.7e-6); every component at 8192 seeded positions plus the
+  probe cells at step 300 (the pulse inside the grid) and at step 1000 (most
+  of it gone through the CPML), to 1e-5 relative L2 over the sampled set
+  (measured at most 6.2e-6 and 3.7e-6) and element by element to
+  |got - ref| <= 4 n 2^-24 A, A the component's largest sampled value at
+  step 300.  The element bound is the error model of an FP32 run: per step
+  each value is stored once in FP32 and updated with FP32 coefficients (Ca,
+  Cb, the inverse cell size), each at most 2^-24 relative from the oracle's
+  FP64 values; in a stable scheme these errors add at most linearly over n
+  steps.  Measured: 0.20 of the bound at step 300 (Ex, 1.45e-5 A), 0.02 at
+  step 1000.  The errors are written to gpurun_out/golden256_errors_*.json.
 
 * FP16 storage, layered substrate at 128 x 128 x 64, 2000 steps: the
   oracle's FP16 emulation (FP64 arithmetic, each stored value rounded to
@@ -51,6 +56,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden")
 ROOT = os.path.dirname(HERE)
 COMPS = ("Ex", "Ey", "Ez", "Hx", "Hy", "Hz")
+ELEMENT_UNITS = 4    # FP32 roundings per value and step in the element bound of the 256^3 run
 
 
 def _say(msg):
@@ -88,27 +94,47 @@ def test_cpml_lattice_256_fp32_full_run(solver_cls, steps_per_sweep):
     pts = g["points"]
     ncell = wl.nx * wl.ny * wl.nz
     rms300 = {c: float(g[f"norm_{c}_300"]) / np.sqrt(ncell) for c in COMPS}
+    amp300 = {c: float(np.abs(g[f"field_{c}_300"]).max()) for c in COMPS}
+    rec = {"workload": "cpml_block_lattice 256^3 FP32, CPML 10, 1000 steps", "steps_per_sweep": steps_per_sweep,
+           "fields": {}}
+    failures = []
     done = 0
     for m in marks:
         s.step(m - done)
         done = m
         got = _sample(s, pts)
-        worst = {}
+        row = {}
         for c in COMPS:
             ref = g[f"field_{c}_{m}"]
             d = np.abs(got[c] - ref)
-            worst[c] = float(d.max() / rms300[c])
-            assert d.max() <= 1e-4 * rms300[c], (m, c, worst[c])
-            if m == 300:
-                assert rel_l2(got[c], ref) <= 1e-5, (m, c, rel_l2(got[c], ref))
-        _say(f"[gpu]   step {m}: worst element error / RMS at step 300: "
-             + " ".join(f"{c} {v:.1e}" for c, v in worst.items()))
+            bound = ELEMENT_UNITS * m * 2.0 ** -24 * amp300[c]
+            row[c] = {"max_err_over_bound": float(d.max() / bound),
+                      "max_err_over_rms300": float(d.max() / rms300[c]),
+                      "max_err_over_max_ref": float(d.max() / np.abs(ref).max()),
+                      "rel_l2": float(rel_l2(got[c], ref))}
+            if d.max() > bound:
+                failures.append((m, c, "element", row[c]))
+            if row[c]["rel_l2"] > 1e-5:
+                failures.append((m, c, "rel_l2", row[c]))
+        rec["fields"][m] = row
+        _say(f"[gpu]   step {m}: worst element error / bound: "
+             + " ".join(f"{c} {row[c]['max_err_over_bound']:.2f}" for c in COMPS)
+             + "; relative L2: " + " ".join(f"{c} {row[c]['rel_l2']:.1e}" for c in COMPS))
     got_series, got_dft = s.series(1, steps), s.dft()
-    es = [rel_l2(got_series[:, p], g["series"][:, p]) for p in range(len(wl.probes))]
-    ed = [rel_l2(got_dft[p], g["dft"][p]) for p in range(len(wl.probes))]
+    es = [float(rel_l2(got_series[:, p], g["series"][:, p])) for p in range(len(wl.probes))]
+    ed = [float(rel_l2(got_dft[p], g["dft"][p])) for p in range(len(wl.probes))]
+    rec["series_rel_l2"], rec["dft_rel_l2"] = es, ed
     _say(f"[gpu]   worst probe series {max(es):.2e}, worst DFT {max(ed):.2e}")
-    assert max(es) <= 1e-5 and max(ed) <= 1e-5, (es, ed)
-    assert min(np.abs(g["series"]).max(axis=0)) > 1e-3      # the pulse reached every probe
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, f"golden256_errors_sweep{steps_per_sweep}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    if max(es) > 1e-5 or max(ed) > 1e-5:
+        failures.append(("series/dft", max(es), max(ed)))
+    assert not failures, failures
+    # the pulse reached every probe: in the oracle's run each probe peaks
+    # between steps 636 and 972, at 3.7e-5 to 2.5e-4
+    assert min(np.abs(g["series"]).max(axis=0)) > 1e-5
 
 
 def test_fp16_substrate_2000_steps_error_curve(solver_cls):
