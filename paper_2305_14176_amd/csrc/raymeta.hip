@@ -117,9 +117,26 @@ struct SynthArgs {
     float tap_odd[kTaps / 2][kTapDeg / 2];        // O_t coefficients
 };
 
-__device__ inline double dist3(double ax, double ay, double az, double bx, double by, double bz) {
+// sqrt(x) for finite x >= 0 from the hardware reciprocal square root: one
+// Newton step on y = 1/sqrt(x), then one correction of the root s = x y,
+// s + (y / 2)(x - s^2) (Markstein's method): each step doubles the correct
+// bits, so from the instruction's 2^-20 or better the result is within a few
+// ulp, against about 25 instructions for a correctly rounded root.  The
+// antenna legs (tens of metres at 257 carrier cycles per metre) need about
+// 1e-13 relative, and so do the inner paths.  x = 0 gives 0.
+__device__ inline double sqrt_leg(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hy = 0.5 * y;
+    y = fma(hy, fma(-x, y * y, 1.0), y);
+    const double sr = x * y;
+    const double r = fma(-sr, sr, x);
+    const double out = fma(0.5 * y, r, sr);
+    return x == 0.0 ? 0.0 : out;
+}
+
+__device__ inline double leg3(double ax, double ay, double az, double bx, double by, double bz) {
     const double dx = ax - bx, dy = ay - by, dz = az - bz;
-    return sqrt(dx * dx + dy * dy + dz * dz);
+    return sqrt_leg(dx * dx + dy * dy + dz * dz);
 }
 
 // Eq. 6 for hit k on the snapshot `v` (n_verts x 3); false if any index of
@@ -227,7 +244,7 @@ __global__ void geometry_kernel(SynthArgs a) {
                 if (k0 + c == b) {
                     fx = x; fy = y; fz = z;
                 } else {
-                    inner += dist3(x, y, z, lx, ly, lz);
+                    inner += leg3(x, y, z, lx, ly, lz);
                 }
                 lx = x; ly = y; lz = z;
             }
@@ -279,8 +296,8 @@ struct Phases {
 __device__ inline Phases ray_phases(const SynthArgs& a, const Geo& g, const double* __restrict__ pq) {
     Phases p{0.0, 0.0, 0.0f};
     if (!(g.inner >= 0.0) || g.w == 0.0f) return p;
-    const double len = g.inner + dist3(g.fx, g.fy, g.fz, pq[0], pq[1], pq[2]) +
-                       dist3(g.lx, g.ly, g.lz, pq[3], pq[4], pq[5]);
+    const double len = g.inner + leg3(g.fx, g.fy, g.fz, pq[0], pq[1], pq[2]) +
+                       leg3(g.lx, g.ly, g.lz, pq[3], pq[4], pq[5]);
     const double ph = len * a.cyc_per_m;              // f_c tau
     const double th = len * a.step_per_m;             // mu tau / f_s
     p.phi = ph - floor(ph);
