@@ -308,8 +308,10 @@ yee_status yee_debug_set_write_counts(yee_ctx* ctx, uint32_t* device_counts, int
  * Requests are admitted and retired between replays, so requests that arrive
  * while others run join the next replay as slots and memory free up.  The
  * update of each grid is the same operation as yee_step() (results do not
- * depend on batching).  Admitted contexts must be FP32 with nx <= 256 and, if
- * they have probes, series_len >= steps_per_replay.
+ * depend on batching).  A batch takes contexts of one storage precision
+ * (yee_batch_set_precision; FP32 unless set): FP32 and FP64 with nx <= 256,
+ * FP16 storage with nx <= 512.  Contexts with probes need
+ * series_len >= steps_per_replay.
  *
  * The caller owns the batch's device descriptor table (yee_batch_footprint()
  * bytes, handed over with yee_batch_bind_workspace()) as well as every
@@ -320,6 +322,10 @@ typedef struct yee_batch yee_batch;
 yee_status yee_batch_footprint(int32_t max_slots, int64_t* bytes);
 /* hbm_budget: sum of admitted context footprints allowed at one time (bytes). */
 yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps_per_replay, yee_batch** out);
+/* The storage precision (yee_precision) of the contexts the batch admits;
+ * set before yee_batch_bind_workspace (YEE_ESTATE after it, YEE_EINVAL for an
+ * unknown value).  The footprint does not depend on it. */
+yee_status yee_batch_set_precision(yee_batch* batch, int32_t precision);
 void yee_batch_destroy(yee_batch* batch);
 yee_status yee_batch_bind_workspace(yee_batch* batch, void* device_ptr, int64_t bytes);
 /* Admit a bound context for n_steps more steps.  YEE_EAGAIN: no free slot or

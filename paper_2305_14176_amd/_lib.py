@@ -28,7 +28,7 @@ EXPORTED = (
     "yee_set_field", "yee_step", "yee_steps_done", "yee_read_field", "yee_read_series",
     "yee_read_dft", "yee_status_flags", "yee_state_bytes", "yee_save_state", "yee_load_state", "yee_sparams", "yee_set_launch", "yee_set_time_blocking", "yee_launch_info",
     "yee_debug_layout", "yee_debug_set_write_counts",
-    "yee_batch_footprint", "yee_batch_create", "yee_batch_destroy",
+    "yee_batch_footprint", "yee_batch_create", "yee_batch_set_precision", "yee_batch_destroy",
     "yee_batch_bind_workspace", "yee_batch_admit", "yee_batch_run", "yee_batch_poll", "yee_batch_release",
     "yee_batch_info", "yee_adjoint_create", "yee_adjoint_destroy", "yee_adjoint_footprint",
     "yee_adjoint_bind_workspace", "yee_adjoint_forward", "yee_adjoint_backward", "yee_adjoint_set_history",
@@ -113,6 +113,7 @@ def load():
         "yee_debug_set_write_counts": (I32, [VP, VP, I64]),
         "yee_batch_footprint": (I32, [I32, P(I64)]),
         "yee_batch_create": (I32, [I32, I64, I32, P(VP)]),
+        "yee_batch_set_precision": (I32, [VP, I32]),
         "yee_batch_destroy": (None, [VP]),
         "yee_batch_bind_workspace": (I32, [VP, VP, I64]),
         "yee_batch_admit": (I32, [VP, VP, I64, P(I32)]),

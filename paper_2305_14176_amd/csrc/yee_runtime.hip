@@ -113,6 +113,7 @@ struct yee_ctx {
 
 struct yee_batch {
   int32_t max_slots = 0;
+  int32_t prec = YEE_F32;  // storage precision of every admitted context
   int64_t budget = 0;      // bytes of admitted context workspaces
   int32_t K = 0;           // steps per replay
   int32_t grid = 0;        // workgroups of the batched launch
@@ -628,8 +629,9 @@ void host_to_storage(const double* in, std::vector<unsigned char>& out, const ye
 }
 
 // ---------------------------------------------------------------------------
-// Batched stepper (serving): FP32 contexts with rows of at most 256 samples
-// (one sample per lane) share one fixed-size launch.
+// Batched stepper (serving): contexts of one storage precision share one
+// fixed-size launch: FP32 and FP64 at one sample per lane (rows of at most
+// 256 samples), FP16 storage at two (rows of at most 512: 4-byte row loads).
 // ---------------------------------------------------------------------------
 #ifndef YEE_BATCH_WAVES
 #define YEE_BATCH_WAVES 12
@@ -637,18 +639,27 @@ void host_to_storage(const double* in, std::vector<unsigned char>& out, const ye
 constexpr int kBatchBlockWaves = YEE_BATCH_WAVES;  // waves per workgroup of the batched launch
 constexpr int kBatchMaxChunk = 32;    // most planes per z-chunk of a batched grid
 constexpr int kBatchMinChunk = 2;     // fewest: with few requests running, short marches keep a step short
-using BatchDesc = yee::SlotDesc<float, float>;
+int batch_V(int prec) { return prec == YEE_F16S ? 2 : 1; }
 
-int batch_tile_rows(const yee_ctx* c) {
-  const int wpr = waves_per_row(c->d.nx, 1);
+// bytes of one slot descriptor in the device table (the largest of the
+// precisions, so the table's size does not depend on the precision)
+size_t batch_desc_bytes() {
+  return std::max({sizeof(yee::SlotDesc<float, float>), sizeof(yee::SlotDesc<_Float16, float>),
+                   sizeof(yee::SlotDesc<double, double>)});
+}
+
+int batch_tile_rows(const yee_ctx* c, int V) {
+  const int wpr = waves_per_row(c->d.nx, V);
   return std::max(1, std::min(c->d.ny, kBatchBlockWaves / wpr - 1));
 }
 
-size_t batch_lds_bytes() {
+size_t batch_lds_bytes(int prec) {
+  const int V = batch_V(prec);
+  const size_t csize = prec == YEE_F64 ? sizeof(double) : sizeof(float);
   size_t m = 0;
   for (int wpr = 1; wpr <= 4; ++wpr) {
     const int ty = std::max(1, kBatchBlockWaves / wpr - 1);
-    m = std::max(m, yee::step_lds_bytes_for(ty, wpr, 1, kBatchMaxChunk, sizeof(float)));
+    m = std::max(m, yee::step_lds_bytes_for(ty, wpr, V, kBatchMaxChunk, csize));
   }
   return m;
 }
@@ -1298,7 +1309,7 @@ yee_status yee_sparams(int32_t n_probes, int32_t n_freq, const double* dft_ref_r
 // ---------------------------------------------------------------------------
 yee_status yee_batch_footprint(int32_t max_slots, int64_t* bytes) {
   if (max_slots < 1 || !bytes) return fail(YEE_EINVAL, "max_slots must be >= 1");
-  *bytes = (int64_t)(256 + align256((size_t)max_slots * sizeof(BatchDesc)));
+  *bytes = (int64_t)(256 + align256((size_t)max_slots * batch_desc_bytes()));
   return YEE_OK;
 }
 
@@ -1314,8 +1325,18 @@ yee_status yee_batch_create(int32_t max_slots, int64_t hbm_budget, int32_t steps
   b->budget = hbm_budget;
   b->K = steps_per_replay;
   b->slots.resize(max_slots);
-  b->lds = batch_lds_bytes();
+  b->lds = batch_lds_bytes(b->prec);
   *out = b;
+  return YEE_OK;
+}
+
+yee_status yee_batch_set_precision(yee_batch* b, int32_t precision) {
+  if (!b) return fail(YEE_EINVAL, "NULL batch");
+  if (precision != YEE_F64 && precision != YEE_F32 && precision != YEE_F16S)
+    return fail(YEE_EINVAL, "unknown precision %d", precision);
+  if (b->bound) return fail(YEE_ESTATE, "the precision is set before yee_batch_bind_workspace");
+  b->prec = precision;
+  b->lds = batch_lds_bytes(precision);
   return YEE_OK;
 }
 
@@ -1346,10 +1367,15 @@ yee_status yee_batch_bind_workspace(yee_batch* b, void* dev, int64_t bytes) {
   HIP_TRY(hipGetDevice(&dev_id));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
   // the persistent launch: as many workgroups as are resident at once
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, yee::batch_step_kernel<float, float, 1>,
-                                                       yee::kWave * kBatchBlockWaves, b->lds));
+  const int bt = yee::kWave * kBatchBlockWaves;
+  if (b->prec == YEE_F16S)
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, yee::batch_step_kernel<_Float16, float, 2>, bt, b->lds));
+  else if (b->prec == YEE_F64)
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, yee::batch_step_kernel<double, double, 1>, bt, b->lds));
+  else
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, yee::batch_step_kernel<float, float, 1>, bt, b->lds));
   b->grid = std::max(8, std::max(1, per_cu) * cus);
-  b->staging_bytes = 256 + (size_t)b->max_slots * sizeof(BatchDesc);
+  b->staging_bytes = 256 + (size_t)b->max_slots * batch_desc_bytes();
   for (int i = 0; i < 2; ++i) {
     if (!b->staging[i]) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b->staging[i]), b->staging_bytes, 0));
     if (!b->staged[i]) HIP_TRY(hipEventCreateWithFlags(&b->staged[i], hipEventDisableTiming));
@@ -1382,8 +1408,12 @@ yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* s
   if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
   if (!c->bound) return fail(YEE_ESTATE, "context workspace not bound");
   if (n_steps < 1) return fail(YEE_EINVAL, "n_steps must be >= 1");
-  if (c->d.precision != YEE_F32) return fail(YEE_EINVAL, "the batched stepper runs FP32 contexts");
-  if (c->d.nx > 4 * yee::kWave) return fail(YEE_EINVAL, "the batched stepper takes rows of at most %d samples", 4 * yee::kWave);
+  if (c->d.precision != b->prec)
+    return fail(YEE_EINVAL, "the batch runs contexts of precision %d (yee_batch_set_precision), this one is %d", b->prec,
+                (int)c->d.precision);
+  const int bV = batch_V(b->prec);
+  if (c->d.nx > 4 * yee::kWave * bV)
+    return fail(YEE_EINVAL, "the batched stepper takes rows of at most %d samples", 4 * yee::kWave * bV);
   if (!c->probes.empty() && c->d.series_len < b->K)
     return fail(YEE_EINVAL, "probe ring (%d) shorter than the steps per replay (%d)", c->d.series_len, b->K);
   for (auto& sl : b->slots)
@@ -1396,7 +1426,7 @@ yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* s
     sl.ctx = c;
     sl.n_end = c->n + n_steps;
     sl.bytes = c->ws_bytes;
-    sl.ty = batch_tile_rows(c);
+    sl.ty = batch_tile_rows(c, bV);
     c->in_batch = true;
     b->in_use += sl.bytes;
     *slot = q;
@@ -1405,10 +1435,15 @@ yee_status yee_batch_admit(yee_batch* b, yee_ctx* c, int64_t n_steps, int32_t* s
   return fail(YEE_EAGAIN, "no free slot");
 }
 
-yee_status yee_batch_run(yee_batch* b, void* stream) {
-  if (!b) return fail(YEE_EINVAL, "NULL batch");
-  if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// One replay of a batch whose contexts store T and compute in C, V samples
+// per lane (see yee_batch_run).
+template <class T, class C, int V>
+yee_status batch_run_t(yee_batch* b, hipStream_t s) {
+  using BatchDesc = yee::SlotDesc<T, C>;
   // The device table is rewritten by a copy on `stream`, behind the replays
   // already queued there, so the host runs ahead of the device; only the host
   // image used two runs ago must have been copied out.
@@ -1433,12 +1468,12 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
     yee_ctx* c = sl.ctx;
     BatchDesc& d = desc[nact++];
     sl.kz = std::min(c->d.nz, kz_all);
-    d.a = fill_args<float, float>(c, 1, sl.ty, sl.kz);
+    d.a = fill_args<T, C>(c, V, sl.ty, sl.kz);
     // set[0] holds the state at the start of the replay (the context's current buffers)
-    d.set[0] = reinterpret_cast<const float*>(c->ws + c->fields[c->cur].off);
-    d.set[1] = reinterpret_cast<const float*>(c->ws + c->fields[c->cur ^ 1].off);
-    d.psh[0] = reinterpret_cast<float*>(c->ws + c->psi_h[c->cur].off);
-    d.psh[1] = reinterpret_cast<float*>(c->ws + c->psi_h[c->cur ^ 1].off);
+    d.set[0] = reinterpret_cast<const T*>(c->ws + c->fields[c->cur].off);
+    d.set[1] = reinterpret_cast<const T*>(c->ws + c->fields[c->cur ^ 1].off);
+    d.psh[0] = reinterpret_cast<C*>(c->ws + c->psi_h[c->cur].off);
+    d.psh[1] = reinterpret_cast<C*>(c->ws + c->psi_h[c->cur ^ 1].off);
     d.base_n = c->n;
     d.n_end = sl.n_end;
     d.series_len = c->d.series_len;
@@ -1461,7 +1496,7 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
     if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     for (int q = 0; q < b->K; ++q)
-      hipLaunchKernelGGL((yee::batch_step_kernel<float, float, 1>), dim3(b->grid), dim3(yee::kWave * kBatchBlockWaves),
+      hipLaunchKernelGGL((yee::batch_step_kernel<T, C, V>), dim3(b->grid), dim3(yee::kWave * kBatchBlockWaves),
                          b->lds, b->capture, dslots, dhdr, q);
     hipGraph_t g = nullptr;
     hipError_t e1 = hipStreamEndCapture(b->capture, &g);
@@ -1481,6 +1516,19 @@ yee_status yee_batch_run(yee_batch* b, void* stream) {
     if (st) return st;
   }
   return YEE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+yee_status yee_batch_run(yee_batch* b, void* stream) {
+  if (!b) return fail(YEE_EINVAL, "NULL batch");
+  if (!b->bound) return fail(YEE_ESTATE, "batch workspace not bound");
+  hipStream_t s = (hipStream_t)stream;
+  if (b->prec == YEE_F16S) return batch_run_t<_Float16, float, 2>(b, s);
+  if (b->prec == YEE_F64) return batch_run_t<double, double, 1>(b, s);
+  return batch_run_t<float, float, 1>(b, s);
 }
 
 yee_status yee_batch_poll(yee_batch* b, int32_t* done, int32_t cap, int32_t* n_done) {

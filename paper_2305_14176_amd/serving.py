@@ -64,7 +64,7 @@ class Request:
     dft: Optional[np.ndarray] = None
     fields: dict = field(default_factory=dict)
     init: Optional[dict] = None               # component -> initial field [nx, ny, nz]
-    status: int = 0                           # 0, or YEE_ENUMERIC / YEE_EOVERFLOW
+    status: int = 0                           # 0, or YEE_ENUMERIC / YEE_EOVERFLOW, YEE_EINVAL (precision)
     error: Optional[str] = None
     deadline: Optional[float] = None          # seconds after arrival; cancelled once passed
     cancelled: bool = False
@@ -95,7 +95,9 @@ def _check_health(req: Request, solver: YeeSolver):
 class BatchServer:
     def __init__(self, max_slots: int = 32, hbm_budget: int = 4 << 30, steps_per_replay: int = 64,
                  device: str = "cuda:0", keep_fields=(), max_active_cells: Optional[int] = DEFAULT_ACTIVE_CELLS,
-                 checkpoint_every: int = 0):
+                 checkpoint_every: int = 0, precision: str = "f32"):
+        """precision: storage precision of every request this server takes
+        ("f32", "f64" or "f16"); a request of another precision fails."""
         import torch
         self.torch = torch
         self.lib = _lib.load()
@@ -106,6 +108,9 @@ class BatchServer:
         self.hbm_budget = int(hbm_budget)
         self.max_active_cells = max_active_cells
         self.checkpoint_every = int(checkpoint_every)
+        if precision not in _lib.PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_lib.PRECISIONS)}")
+        self.precision = precision
         self.replays = 0
         self.resets = 0
         self._cancel = set()
@@ -116,6 +121,7 @@ class BatchServer:
         b = C.c_void_p()
         _lib.check(self.lib.yee_batch_create(self.max_slots, self.hbm_budget, self.K, C.byref(b)), "yee_batch_create")
         self.batch = b
+        _lib.check(self.lib.yee_batch_set_precision(b, _lib.PRECISIONS[self.precision]), "yee_batch_set_precision")
         nb = C.c_int64()
         _lib.check(self.lib.yee_batch_footprint(self.max_slots, C.byref(nb)), "yee_batch_footprint")
         self.table = self.torch.empty(nb.value + 256, dtype=self.torch.uint8, device=self.device)
@@ -178,6 +184,14 @@ class BatchServer:
             active = sum(r.wl.cells for r, _ in running.values())
             while waiting and waiting[0].arrival <= now:
                 req = waiting[0]
+                if req.wl.precision != self.precision:
+                    # the batch takes one storage precision: this request fails alone
+                    waiting.pop(0)
+                    req.status = -1
+                    req.error = f"YEE_EINVAL: precision {req.wl.precision}, the server runs {self.precision}"
+                    req.finished = now
+                    done.append(req)
+                    continue
                 if (self.max_active_cells is not None and running
                         and active + req.wl.cells > self.max_active_cells):
                     break

@@ -135,6 +135,10 @@ static void yee_paths() {
   CHECK(yee_batch_footprint(0, &tb) == YEE_EINVAL);
   yee_batch* b = nullptr;
   CHECK(yee_batch_create(8, int64_t(1) << 30, 16, &b) == YEE_OK && b != nullptr);
+  CHECK(yee_batch_set_precision(b, 9) == YEE_EINVAL);
+  CHECK(yee_batch_set_precision(nullptr, YEE_F32) == YEE_EINVAL);
+  CHECK(yee_batch_set_precision(b, YEE_F16S) == YEE_OK);
+  CHECK(yee_batch_set_precision(b, YEE_F32) == YEE_OK);
   int32_t slot = -1;
   yee_grid_desc d = desc(32, 32, 32, YEE_F32, 4);
   CHECK(yee_create(&d, &c) == YEE_OK);

@@ -191,3 +191,23 @@ def test_workloads_are_seeded_and_consistent():
     for (_, i, j, k) in ad.probes:
         assert not (12 <= i < 28 and 12 <= j < 28 and 12 <= k < 28)
 
+
+
+def test_batch_precision_before_binding():
+    """yee_batch_set_precision: unknown values and a NULL batch are refused, the
+    three precisions are accepted before the table is bound (host only)."""
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libyee.so not built")
+    lib = _lib.load()
+    b = C.c_void_p()
+    assert lib.yee_batch_create(4, 1 << 30, 8, C.byref(b)) == 0
+    try:
+        assert lib.yee_batch_set_precision(None, 1) == -1
+        for bad in (-1, 3, 7):
+            assert lib.yee_batch_set_precision(b, bad) == -1, bad
+        for p in ("f64", "f16", "f32"):
+            assert lib.yee_batch_set_precision(b, _lib.PRECISIONS[p]) == 0, p
+        n1 = C.c_int64()
+        assert lib.yee_batch_footprint(4, C.byref(n1)) == 0 and n1.value > 256
+    finally:
+        lib.yee_batch_destroy(b)

@@ -222,3 +222,47 @@ def test_device_reset_requeues_from_checkpoints():
         assert rel_l2(b.dft, a.dft) <= 1e-13
         for c in keep:
             np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+
+
+def _requests_prec(specs, precision):
+    import dataclasses
+    from paper_2305_14176_amd.serving import Request
+    out = []
+    for rid, (side, steps, seed, arrival) in enumerate(specs):
+        wl = dataclasses.replace(W.serving_request(seed, side=side, steps=steps), precision=precision,
+                                 fp16_exp=(12, 12, 12, 21, 21, 21))
+        out.append(Request(wl, arrival=arrival, rid=rid))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f16", "f64"])
+def test_batched_other_precisions_equal_alone(precision):
+    """A batch of FP16-storage (two samples per lane) or FP64 contexts: each
+    request bitwise equal to the same request stepped alone, with admissions
+    mid-run; a request of another precision fails alone."""
+    import torch
+    from paper_2305_14176_amd import _lib
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    assert torch.cuda.is_available()
+    specs = [(32, 40, 301, 0.0), (96, 23, 302, 0.0), (64, 31, 303, 0.0), (48, 17, 304, 0.0), (128, 12, 305, 0.0)]
+    keep = ("Ex", "Ez", "Hy")
+    _say(f"[gpu] serving {precision}: alone")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests_prec(specs, precision), keep_fields=keep)}
+    _say(f"[gpu] serving {precision}: batched")
+    srv = BatchServer(max_slots=2, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep, precision=precision)
+    reqs = _requests_prec(specs, precision)
+    other = _requests_prec([(32, 9, 306, 0.0)], "f32")[0]
+    other.rid = 99
+    mixed = {r.rid: r for r in srv.serve(reqs + [other])}
+    assert srv.replays > 3
+    assert mixed[99].failed and mixed[99].status == -1, (mixed[99].status, mixed[99].error)
+    for rid, a in alone.items():
+        b = mixed[rid]
+        assert not a.failed and not b.failed, (rid, a.error, b.error)
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13, (rid, rel_l2(b.dft, a.dft))
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+    # the precision is fixed once the table is bound
+    assert srv.lib.yee_batch_set_precision(srv.batch, _lib.PRECISIONS["f32"]) == -4     # YEE_ESTATE
+    srv.close()
