@@ -79,7 +79,11 @@ struct AdjArgs {
   const double* yrow_e;     // adj_e: probe samples whose E seeds the next reverse step needs (or null)
 };
 
-constexpr int kAdjBX = 64, kAdjBY = 4;  // threads per workgroup along x, y
+// Threads per workgroup along x, y: two waves of 32 samples of 2 rows each
+// (one plane).  At 128^3 the reverse run of 1024 steps took 55.9 ms against
+// 61.1 ms with 64 x 4 and 71.0 ms with 64 x 8; 16-wide or one-row shapes
+// were slower still.
+constexpr int kAdjBX = 32, kAdjBY = 4;
 
 // Seed of probed sample d: w * (sum of the samples of the probes on it).
 __device__ __forceinline__ double inj_seed(const InjDev& d, const int4* probe, int nprobe, const double* yrow) {
