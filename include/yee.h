@@ -336,6 +336,9 @@ yee_status yee_batch_admit(yee_batch* batch, yee_ctx* ctx, int64_t n_steps, int3
  * table is rewritten by a copy on the same stream, behind them): successive
  * runs of one batch must use one stream.  Probe DFTs are folded after it. */
 yee_status yee_batch_run(yee_batch* batch, void* stream);
+/* yee_step may also advance an admitted context between replays, on the
+ * batch's stream (for instance a lone request in its own launch shape): the
+ * next replay continues from the context's current step. */
 /* Slots whose requested steps are all taken (up to cap written to done). */
 yee_status yee_batch_poll(yee_batch* batch, int32_t* done, int32_t cap, int32_t* n_done);
 /* Retire a slot (its context stays valid; read results before or after). */

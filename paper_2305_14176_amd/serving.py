@@ -95,9 +95,12 @@ def _check_health(req: Request, solver: YeeSolver):
 class BatchServer:
     def __init__(self, max_slots: int = 32, hbm_budget: int = 4 << 30, steps_per_replay: int = 64,
                  device: str = "cuda:0", keep_fields=(), max_active_cells: Optional[int] = DEFAULT_ACTIVE_CELLS,
-                 checkpoint_every: int = 0, precision: str = "f32"):
+                 checkpoint_every: int = 0, precision: str = "f32", solo: bool = True):
         """precision: storage precision of every request this server takes
-        ("f32", "f64" or "f16"); a request of another precision fails."""
+        ("f32", "f64" or "f16"); a request of another precision fails.
+        solo: while a single request runs, step it with yee_step in its own
+        launch shape (the batch picks it up again from its current step when
+        others join); its results are the same bits."""
         import torch
         self.torch = torch
         self.lib = _lib.load()
@@ -111,6 +114,8 @@ class BatchServer:
         if precision not in _lib.PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(_lib.PRECISIONS)}")
         self.precision = precision
+        self.solo = bool(solo)
+        self.solo_runs = 0                # replays taken by a lone request with yee_step
         self.replays = 0
         self.resets = 0
         self._cancel = set()
@@ -222,7 +227,13 @@ class BatchServer:
                 # nothing to run: wait for the next arrival
                 time.sleep(max(0.0, min(0.001, waiting[0].arrival - now)))
                 continue
-            _lib.check(lib.yee_batch_run(self.batch, self._stream()), "yee_batch_run")
+            if self.solo and len(running) == 1:
+                # a lone request: its own launch shape is faster than the batch's
+                (req, solver), = running.values()
+                solver.step(min(self.K, req.wl.steps - solver.steps_done))
+                self.solo_runs += 1
+            else:
+                _lib.check(lib.yee_batch_run(self.batch, self._stream()), "yee_batch_run")
             self.replays += 1
             ndone = C.c_int32()
             buf = (C.c_int32 * self.max_slots)()

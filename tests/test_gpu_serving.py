@@ -266,3 +266,26 @@ def test_batched_other_precisions_equal_alone(precision):
     # the precision is fixed once the table is bound
     assert srv.lib.yee_batch_set_precision(srv.batch, _lib.PRECISIONS["f32"]) == -4     # YEE_ESTATE
     srv.close()
+
+
+def test_lone_requests_run_solo_and_match_alone():
+    """Three requests start together in the batch; once the two short ones
+    are done the long one runs alone with yee_step in its own launch shape
+    (solo), continuing from the batch's last step.  A late request runs
+    alone or joins.  Every request's results are the same bits as
+    one-at-a-time."""
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    specs = [(96, 200, 401, 0.0), (64, 24, 402, 0.0), (48, 40, 403, 0.0), (32, 30, 404, 0.05)]
+    keep = ("Ez", "Hy")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(specs), keep_fields=keep)}
+    srv = BatchServer(max_slots=4, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep)
+    mixed = {r.rid: r for r in srv.serve(_requests(specs))}
+    _say(f"[gpu] serving solo: {srv.solo_runs} of {srv.replays} replays solo")
+    assert srv.solo_runs > 0 and srv.replays > srv.solo_runs
+    for rid, a in alone.items():
+        b = mixed[rid]
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13, (rid, rel_l2(b.dft, a.dft))
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+    srv.close()
