@@ -29,7 +29,15 @@ What is computed (the paper is silent on all of it; textbook definitions):
 * Optional storage emulation: each stored component is rounded once per step
   (H after the H update, E after the E update and the source injection), as
   x <- fp16_RNE(x 2^s) 2^-s (FP16 storage) or x <- fp32_RNE(x) (FP32
-  storage); the arithmetic stays FP64.
+  storage).
+* Arithmetic: FP64 by default.  With arith="f32" every stored array (fields,
+  CPML auxiliaries), the material coefficients and the CPML profiles are
+  float32 and every operation of the step is a float32 operation (numpy keeps
+  float32 when a Python float meets a float32 array); sources are evaluated
+  in FP64 and added in float32, probes and the DFT stay FP64.  This is the
+  arithmetic of the FP32 and FP16-storage modes of the device path, with the
+  textbook operation order (no fused multiply-adds), so the two differ in
+  the last bit of some results.
 """
 from __future__ import annotations
 
@@ -203,13 +211,16 @@ class Simulation:
     cpml : CpmlParams (cells = 0 for a plain PEC box).
     storage : "f64", "f16" (FP16-storage emulation with exponents fp16_exp
         for Ex, Ey, Ez, Hx, Hy, Hz) or "f32" (FP32-storage emulation).
+    arith : "f64" or "f32" (the dtype of every array and operation; see the
+        module documentation).
     """
 
     def __init__(self, nx, ny, nz, dx, dy=None, dz=None, courant=0.99,
                  eps_r=1.0, sigma=0.0, pec: Optional[Dict[str, np.ndarray]] = None,
                  cpml: Optional[CpmlParams] = None,
                  sources: Sequence[Source] = (), probes: Sequence[Probe] = (),
-                 storage: str = "f64", fp16_exp=(0, 0, 0, 9, 9, 9), dt: Optional[float] = None):
+                 storage: str = "f64", fp16_exp=(0, 0, 0, 9, 9, 9), dt: Optional[float] = None,
+                 arith: str = "f64"):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.dx = float(dx)
         self.dy = float(dx if dy is None else dy)
@@ -217,6 +228,10 @@ class Simulation:
         self.dt = float(time_step(self.dx, self.dy, self.dz, courant) if dt is None else dt)
         self.cpml = cpml if cpml is not None else CpmlParams()
         self.storage = storage
+        if arith not in ("f64", "f32"):
+            raise ValueError("arith must be 'f64' or 'f32'")
+        self.arith = arith
+        f = self.dtype = np.float32 if arith == "f32" else np.float64
         self.fp16_exp = tuple(int(s) for s in fp16_exp)
         self.sources: List[Source] = list(sources)
         self.probes: List[Probe] = list(probes)
@@ -241,29 +256,30 @@ class Simulation:
                 m = np.asarray(pec[c], dtype=bool)
                 ca[m] = 0.0
                 cb[m] = 0.0
-            self.Ca[c], self.Cb[c] = ca, cb
+            self.Ca[c], self.Cb[c] = ca.astype(f), cb.astype(f)
 
         # CPML profiles per axis: E side (integer positions), H side (half-integer).
         p = self.cpml
         self.pe, self.ph = {}, {}
         for ax, n, d, L in zip("xyz", (self.nx, self.ny, self.nz), (self.dx, self.dy, self.dz),
                                cpml_cells(p)):
-            self.pe[ax] = cpml_profile(n, d, self.dt, p, half=False, L=L)
-            self.ph[ax] = cpml_profile(n, d, self.dt, p, half=True, L=L)
+            self.pe[ax] = tuple(v.astype(f) for v in cpml_profile(n, d, self.dt, p, half=False, L=L))
+            self.ph[ax] = tuple(v.astype(f) for v in cpml_profile(n, d, self.dt, p, half=True, L=L))
 
-        self.E = {c: np.zeros(yee_shape(c, *cells)) for c in E_COMPONENTS}
-        self.H = {c: np.zeros(yee_shape(c, *cells)) for c in H_COMPONENTS}
+        self.E = {c: np.zeros(yee_shape(c, *cells), dtype=f) for c in E_COMPONENTS}
+        self.H = {c: np.zeros(yee_shape(c, *cells), dtype=f) for c in H_COMPONENTS}
         # psi arrays, named by (component, derivative axis); full size, zero
         # wherever a = 0 (outside the layer).
         nx_, ny_, nz_ = cells
-        self.psi = {
-            "Hxy": np.zeros((nx_ + 1, ny_, nz_)), "Hxz": np.zeros((nx_ + 1, ny_, nz_)),
-            "Hyz": np.zeros((nx_, ny_ + 1, nz_)), "Hyx": np.zeros((nx_, ny_ + 1, nz_)),
-            "Hzx": np.zeros((nx_, ny_, nz_ + 1)), "Hzy": np.zeros((nx_, ny_, nz_ + 1)),
-            "Exy": np.zeros((nx_, ny_ - 1, nz_ - 1)), "Exz": np.zeros((nx_, ny_ - 1, nz_ - 1)),
-            "Eyz": np.zeros((nx_ - 1, ny_, nz_ - 1)), "Eyx": np.zeros((nx_ - 1, ny_, nz_ - 1)),
-            "Ezx": np.zeros((nx_ - 1, ny_ - 1, nz_)), "Ezy": np.zeros((nx_ - 1, ny_ - 1, nz_)),
+        shapes = {
+            "Hxy": (nx_ + 1, ny_, nz_), "Hxz": (nx_ + 1, ny_, nz_),
+            "Hyz": (nx_, ny_ + 1, nz_), "Hyx": (nx_, ny_ + 1, nz_),
+            "Hzx": (nx_, ny_, nz_ + 1), "Hzy": (nx_, ny_, nz_ + 1),
+            "Exy": (nx_, ny_ - 1, nz_ - 1), "Exz": (nx_, ny_ - 1, nz_ - 1),
+            "Eyz": (nx_ - 1, ny_, nz_ - 1), "Eyx": (nx_ - 1, ny_, nz_ - 1),
+            "Ezx": (nx_ - 1, ny_ - 1, nz_), "Ezy": (nx_ - 1, ny_ - 1, nz_),
         }
+        self.psi = {k: np.zeros(v, dtype=f) for k, v in shapes.items()}
         self.series: List[List[float]] = [[] for _ in self.probes]
         self.dft = [np.zeros(len(pr.freqs) if pr.freqs is not None else 0, dtype=np.complex128)
                     for pr in self.probes]
@@ -278,10 +294,10 @@ class Simulation:
 
     def _store(self, comp_index, x):
         if self.storage == "f16":
-            return round_fp16_scaled(x, self.fp16_exp[comp_index])
-        if self.storage == "f32":
-            return round_fp32(x)
-        return x
+            x = round_fp16_scaled(x, self.fp16_exp[comp_index])
+        elif self.storage == "f32":
+            x = round_fp32(x)
+        return np.asarray(x, dtype=self.dtype)
 
     def set_fields(self, **arrays):
         """Set initial components (E^0 or H^{-1/2}); stored values are rounded

@@ -4,14 +4,14 @@ import numpy as np
 from oracle.yee import CpmlParams, Probe, Simulation, Source
 
 
-def oracle_from_workload(wl, initial=None, storage=None, dt=None):
+def oracle_from_workload(wl, initial=None, storage=None, dt=None, arith="f64"):
     eps, sig = wl.cell_materials()
     cp = CpmlParams(cells=tuple(wl.cpml_cells), m=wl.cpml_m, sigma_max=wl.cpml_sigma_max,
                     kappa_max=wl.cpml_kappa_max, alpha_max=wl.cpml_alpha_max)
     sim = Simulation(wl.nx, wl.ny, wl.nz, wl.dx, wl.dy, wl.dz, courant=wl.courant, eps_r=eps, sigma=sig,
                      pec=wl.pec_component_masks(), cpml=cp,
                      storage=storage or ("f16" if wl.precision == "f16" else "f64"),
-                     fp16_exp=wl.fp16_exp, dt=dt)
+                     fp16_exp=wl.fp16_exp, dt=dt, arith=arith)
     srcs = []
     for s in wl.sources:
         t0, tau = s.times(sim.dt)

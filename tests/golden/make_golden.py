@@ -9,6 +9,8 @@ sample of stored positions (plus the positions themselves) at a few steps.
                                                    # (about 90 minutes on one core)
     python tests/golden/make_golden.py fp16sub     # 128 x 128 x 64 substrate, 2000 steps, oracle
                                                    # emulating FP16 storage and the plain FP64 oracle
+    python tests/golden/make_golden.py fp16sub_f32 # the same substrate, FP16 storage with FP32
+                                                   # arithmetic (about 6 minutes)
 """
 import os
 import sys
@@ -35,8 +37,8 @@ def sample_points(wl, count, seed):
     return np.concatenate([extra, pts]).astype(np.int32)
 
 
-def run(wl, storage, steps, pts, marks=()):
-    sim = oracle_from_workload(wl, storage=storage)
+def run(wl, storage, steps, pts, marks=(), arith="f64"):
+    sim = oracle_from_workload(wl, storage=storage, arith=arith)
     t0 = time.time()
     out = {}
     for n in range(1, steps + 1):
@@ -101,5 +103,19 @@ def fp16sub():
     print({k: (float(np.max(v)) if np.ndim(v) else float(v)) for k, v in rec.items()})
 
 
+def fp16sub_f32():
+    # the substrate of fp16sub (same sample positions and marks), FP16 storage
+    # rounding the results of FP32 arithmetic, as the device path computes
+    steps = 2000
+    wl = W.fp16_substrate(128, 128, 64, steps=steps)
+    pts = sample_points(wl, 4096, seed=3003)
+    marks = (500, 1000, 1500)
+    sim, out = run(wl, "f16", steps, pts, marks, arith="f32")
+    fields = {f"f16a32_{c}_{n}": out[n][c].astype(np.float32) for n in sorted(out) for c in COMPS}
+    np.savez_compressed(os.path.join(HERE, "fp16_substrate_128x128x64_2000steps_f32arith.npz"),
+                        steps=steps, marks=np.array(sorted(out)), points=pts, series=sim.series_array(),
+                        dft=np.array(sim.dft), **fields)
+
+
 if __name__ == "__main__":
-    {"cpml256": cpml256, "fp16sub": fp16sub}[sys.argv[1]]()
+    {"cpml256": cpml256, "fp16sub": fp16sub, "fp16sub_f32": fp16sub_f32}[sys.argv[1]]()

@@ -633,3 +633,68 @@ def test_fp16_rounding_rules():
     r = round_fp16_scaled(x, 9)
     assert np.all(np.abs(r - x) <= 2.0 ** -11 * np.abs(x) + 2.0 ** -25 * 2.0 ** -9)
     assert round_fp16_scaled(3.0 * 2.0 ** -9, 9) == 3.0 * 2.0 ** -9   # exact scale
+
+
+# ---------------------------------------------------------------------------
+# FP32 arithmetic mode: the same step in float32
+# ---------------------------------------------------------------------------
+
+def _lossy_cpml_pair(storage, fp16_exp=(0, 0, 0, 9, 9, 9)):
+    rng = np.random.default_rng(11)
+    nx, ny, nz = 14, 12, 16
+    eps = rng.uniform(1, 6, (nx, ny, nz))
+    sig = rng.uniform(0, 0.3, (nx, ny, nz))
+    cp = CpmlParams(cells=(3, 3, 4), m=3.0, kappa_max=3.0, alpha_max=0.05)
+    sims = []
+    for arith in ("f64", "f32"):
+        sim = Simulation(nx, ny, nz, 1e-3, eps_r=eps, sigma=sig, cpml=cp, storage=storage if arith == "f32" else "f64",
+                         fp16_exp=fp16_exp, arith=arith)
+        sim.sources = [Source(2, 7, 6, 8, "mod_gauss", 1.0, 8 * sim.dt, 3 * sim.dt, 40e9)]
+        sim.probes = [Probe(2, 5, 4, 6, np.array([30e9, 45e9]))]
+        sim.series, sim.dft = [[]], [np.zeros(2, complex)]
+        _random_fields(sim, np.random.default_rng(5), scale_h=1.0 / 377.0)
+        sims.append(sim)
+    return sims
+
+
+def test_fp32_arithmetic_follows_the_fp64_step():
+    """arith="f32": every array stays float32 (no operation widens it), and 60
+    steps of a lossy grid with CPML in all three axes, a source and a probe
+    agree with the FP64 oracle to FP32 accuracy: each component and psi
+    array to 1e-5 relative L2 (one step rounds at 2^-24; the growth over 60
+    steps stays far below 1e-5), the probe series and DFT too.  A term
+    computed in FP64 or dropped would break the dtype or the agreement."""
+    s64, s32 = _lossy_cpml_pair("f64")
+    for _ in range(60):
+        s64.step()
+        s32.step()
+    for c in COMPONENTS:
+        a32, a64 = s32.component(c), s64.component(c)
+        assert a32.dtype == np.float32, c
+        assert np.linalg.norm(a32 - a64) <= 1e-5 * np.linalg.norm(a64), c
+    for k in s64.psi:
+        assert s32.psi[k].dtype == np.float32, k
+        n = np.linalg.norm(s64.psi[k])
+        assert np.linalg.norm(s32.psi[k] - s64.psi[k]) <= 1e-5 * n + 1e-30, k
+    a, b = s32.series_array(), s64.series_array()
+    assert np.linalg.norm(a - b) <= 1e-5 * np.linalg.norm(b)
+    assert np.linalg.norm(s32.dft[0] - s64.dft[0]) <= 1e-5 * np.linalg.norm(s64.dft[0])
+
+
+def test_fp16_storage_with_fp32_arithmetic_stores_fp16_values():
+    """storage="f16" with arith="f32": every stored field value times 2^s is
+    an fp16 number (the rounding happens on the FP32 result), the psi arrays
+    stay unrounded float32, and the run tracks FP64 within the fp16 storage
+    error (2^-11 relative per value)."""
+    exps = (4, 4, 4, 12, 12, 12)
+    s64, s16 = _lossy_cpml_pair("f16", fp16_exp=exps)
+    for _ in range(30):
+        s64.step()
+        s16.step()
+    for ci, c in enumerate(COMPONENTS):
+        x = s16.component(c).astype(np.float64) * 2.0 ** exps[ci]
+        assert np.array_equal(x.astype(np.float16).astype(np.float64), x), c
+        a64 = s64.component(c)
+        assert np.linalg.norm(s16.component(c) - a64) <= 4e-3 * np.linalg.norm(a64), c   # measured 1.1e-3 to 1.3e-3
+    assert any(not np.array_equal(v.astype(np.float16).astype(np.float32), v)
+               for v in s16.psi.values() if np.any(v))
