@@ -332,7 +332,7 @@ FP32_MFMA_PEAK_TFLOPS = 157.3     # published MI355X dense FP32 matrix peak
 FP16_MFMA_PEAK_TFLOPS = 2500.0    # published MI355X dense fp16 matrix peak
 FLOPS_PER_TERM = 8                # per (ray, sample): a complex multiply-add, four real multiply-adds
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # published MI355X FP32 vector peak
-SPREAD_FLOPS_PER_RAY_BLOCK = 2 * 44 + 16 + 16   # per (ray, pair, chirp): 44 FMAs (8 taps), 16 mul, 16 grid adds
+SPREAD_FLOPS_PER_RAY_BLOCK = 2 * 36 + 16 + 16   # per (ray, pair, chirp): 36 FMAs (8 taps), 16 mul, 16 grid adds
 SPREAD_ATOMICS_PER_RAY_BLOCK = 16   # 64-bit LDS integer atomics per (ray, pair, chirp): 8 taps x (re, im)
 # LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz; one 64-bit atomic moves 8 bytes
 LDS_ATOMIC64_PEAK_PER_S = 256 * 2.4e9 * 128 / 8
@@ -448,7 +448,7 @@ def if_synthesis_benchmark(reps=5, cpu=True, cpu_rays=1 << 15):
                      "peak_basis": "published FP32 vector peak (packed FMA); built without packed FP32, the issue "
                                    "limit is half of it",
                      "traffic": None, "algorithmic_flops_per_launch": ray_blocks * SPREAD_FLOPS_PER_RAY_BLOCK,
-                     "flops_counted": "per ray, pair and chirp: 8 kernel values (44 FMAs), 16 multiplies, 16 grid "
+                     "flops_counted": "per ray, pair and chirp: 8 kernel values (36 FMAs), 16 multiplies, 16 grid "
                                       "additions; the FP64 antenna legs, conversions and atomics are not counted",
                      "lds_atomic_bound": {
                          "achieved_per_s": round(ray_blocks * SPREAD_ATOMICS_PER_RAY_BLOCK / (ms / 1e3), 1),
