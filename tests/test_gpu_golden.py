@@ -17,7 +17,8 @@ seeded input generators.
   Cb, the inverse cell size), each at most 2^-24 relative from the oracle's
   FP64 values; in a stable scheme these errors add at most linearly over n
   steps.  Measured: 0.20 of the bound at step 300 (Ex, 1.45e-5 A), 0.02 at
-  step 1000.  The errors are written to gpurun_out/golden256_errors_*.json.
+  step 1000.  The errors are written as JSON to the run's output folder
+  (golden256_errors_*.json).
 
 * FP16 storage, layered substrate at 128 x 128 x 64, 2000 steps: the
   oracle's FP16 emulation (FP64 arithmetic, each stored value rounded to
@@ -46,7 +47,8 @@ seeded input generators.
   a 1e-3 match between two FP16 runs is out of reach over a long run.  The
   GPU is gated against it like against the other emulation (within 2.5
   times the storage error).
-  The measured curve is written to gpurun_out/fp16_error_curve.json.
+  The measured curve is written as JSON to the run's output folder
+  (fp16_error_curve.json).
 """
 import json
 import os
