@@ -249,8 +249,11 @@ struct Raw<2> {
   static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
     return U{__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0)};
   }
-  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b16(v.x, r, vo, so, 0);
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so, bool nt) {
+    if (nt)
+      __builtin_amdgcn_raw_buffer_store_b16(v.x, r, vo, so, 2);
+    else
+      __builtin_amdgcn_raw_buffer_store_b16(v.x, r, vo, so, 0);
   }
 };
 template <>
@@ -259,8 +262,11 @@ struct Raw<4> {
   static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
     return U{__builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0)};
   }
-  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b32(v.x, r, vo, so, 0);
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so, bool nt) {
+    if (nt)
+      __builtin_amdgcn_raw_buffer_store_b32(v.x, r, vo, so, 2);
+    else
+      __builtin_amdgcn_raw_buffer_store_b32(v.x, r, vo, so, 0);
   }
 };
 template <>
@@ -269,8 +275,11 @@ struct Raw<8> {
   static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
     return U{__builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0)};
   }
-  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b64(v.x, r, vo, so, 0);
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so, bool nt) {
+    if (nt)
+      __builtin_amdgcn_raw_buffer_store_b64(v.x, r, vo, so, 2);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(v.x, r, vo, so, 0);
   }
 };
 template <>
@@ -279,8 +288,11 @@ struct Raw<16> {
   static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
     return U{__builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0)};
   }
-  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 0);
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so, bool nt) {
+    if (nt)
+      __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 2);
+    else
+      __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 0);
   }
 };
 template <>
@@ -289,9 +301,9 @@ struct Raw<32> {
   static __device__ __forceinline__ U ld(rsrc_t r, uint32_t vo, uint32_t so) {
     return U{__builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0), __builtin_amdgcn_raw_buffer_load_b128(r, vo + 16, so, 0)};
   }
-  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so) {
-    __builtin_amdgcn_raw_buffer_store_b128(v.x, r, vo, so, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(v.y, r, vo + 16, so, 0);
+  static __device__ __forceinline__ void st(U v, rsrc_t r, uint32_t vo, uint32_t so, bool nt) {
+    Raw<16>::st(Raw<16>::U{v.x}, r, vo, so, nt);
+    Raw<16>::st(Raw<16>::U{v.y}, r, vo + 16, so, nt);
   }
 };
 
@@ -300,10 +312,12 @@ __device__ __forceinline__ X buf_ld(rsrc_t r, uint32_t vo, uint32_t so) {
   using R = Raw<sizeof(X)>;
   return __builtin_bit_cast(X, R::ld(r, vo, so));
 }
+// Cache policy of a store: nt marks it non-temporal (streamed past the
+// last-level cache); a compile-time choice, so each kernel has one store path.
 template <class X>
-__device__ __forceinline__ void buf_st(const X& v, rsrc_t r, uint32_t vo, uint32_t so) {
+__device__ __forceinline__ void buf_st(const X& v, rsrc_t r, uint32_t vo, uint32_t so, bool nt = false) {
   using R = Raw<sizeof(X)>;
-  R::st(__builtin_bit_cast(typename R::U, v), r, vo, so);
+  R::st(__builtin_bit_cast(typename R::U, v), r, vo, so, nt);
 }
 
 template <class T, class C, int V>
@@ -314,11 +328,12 @@ __device__ __forceinline__ void ld_row(rsrc_t r, uint32_t vo, uint32_t so, C (&o
 }
 
 template <class T, class C, int V>
-__device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const C (&in)[V], float enc) {
+__device__ __forceinline__ void st_row(rsrc_t r, uint32_t vo, uint32_t so, const C (&in)[V], float enc,
+                                       bool nt = false) {
   VecT<T, V> v;
 #pragma unroll
   for (int e = 0; e < V; ++e) v.v[e] = Conv<T, C>::st(in[e], enc);
-  buf_st<VecT<T, V>>(v, r, vo, so);
+  buf_st<VecT<T, V>>(v, r, vo, so, nt);
 }
 
 template <class T, class C, int V>
@@ -358,14 +373,16 @@ constexpr int prefetch_depth() { return (sizeof(T) == 2 && V == 2) ? 2 : 1; }
 constexpr uint32_t kOut = 0x80000000u;
 
 // Extra work of a step_kernel instantiation: none, the adjoint box history,
-// or the debug write counts.
-enum StepExtra { kPlain = 0, kHistory = 1, kWriteCount = 2 };
+// or the debug write counts; kStream is the plain step with its field and
+// CPML stores streamed past the last-level cache (non-temporal).
+enum StepExtra { kPlain = 0, kHistory = 1, kWriteCount = 2, kStream = 3 };
 
 template <class T, class C, int V, int EXTRA = kPlain>
 __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int ytile, const int k0,
                                           const int k1, unsigned char* smem_raw) {
   const int wpr = a.wpr;
   const int ty = a.ty;
+  constexpr bool nt = EXTRA == kStream;
   const int RL = wpr * kWave * V;
   const int RS = RL + 2 * V;
   const int nk1 = a.kz + 1;
@@ -747,19 +764,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           if (iny) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{ph[PHXY][e], ph[PHZY][e]}, rpsi, vxc + e * 2 * CB, phout + yso(k, PHXY));
+              buf_st<Pair<C>>(Pair<C>{ph[PHXY][e], ph[PHZY][e]}, rpsi, vxc + e * 2 * CB, phout + yso(k, PHXY), nt);
             }
           }
           if (inz) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{ph[PHXZ][e], ph[PHYZ][e]}, rpsi, vxc + e * 2 * CB, phout + zso(k, PHXZ));
+              buf_st<Pair<C>>(Pair<C>{ph[PHXZ][e], ph[PHYZ][e]}, rpsi, vxc + e * 2 * CB, phout + zso(k, PHXZ), nt);
             }
           }
           if (wave_inx && lane_inx) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{ph[PHYX][e], ph[PHZX][e]}, rpsi, vxs[e], phout + xso(k, PHYX));
+              buf_st<Pair<C>>(Pair<C>{ph[PHYX][e], ph[PHZX][e]}, rpsi, vxs[e], phout + xso(k, PHYX), nt);
             }
           }
         }
@@ -883,19 +900,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
           if (iny) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{pe[PEXY][e], pe[PEZY][e]}, rpsi, vxc + e * 2 * CB, yso(k, PEXY));
+              buf_st<Pair<C>>(Pair<C>{pe[PEXY][e], pe[PEZY][e]}, rpsi, vxc + e * 2 * CB, yso(k, PEXY), nt);
             }
           }
           if (inz) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{pe[PEXZ][e], pe[PEYZ][e]}, rpsi, vxc + e * 2 * CB, zso(k, PEXZ));
+              buf_st<Pair<C>>(Pair<C>{pe[PEXZ][e], pe[PEYZ][e]}, rpsi, vxc + e * 2 * CB, zso(k, PEXZ), nt);
             }
           }
           if (wave_inx && lane_inx) {
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-              buf_st<Pair<C>>(Pair<C>{pe[PEYX][e], pe[PEZX][e]}, rpsi, vxs[e], xso(k, PEYX));
+              buf_st<Pair<C>>(Pair<C>{pe[PEYX][e], pe[PEZX][e]}, rpsi, vxs[e], xso(k, PEYX), nt);
             }
           }
           flags = tfl[r * nk1 + kq];
@@ -927,19 +944,19 @@ __device__ __forceinline__ void step_tile(const StepArgs<T, C>& a, const int yti
         const uint32_t vst = upd ? vrow : kOut;
         const uint32_t so = (uint32_t)k * plane_b;
         if constexpr (std::is_same<T, C>::value) {
-          st_row<T, C, V>(rout, vst, so, exo, a.enc[0]);
-          st_row<T, C, V>(rout, vst, so + cs_b, eyo, a.enc[1]);
-          st_row<T, C, V>(rout, vst, so + 2 * cs_b, ezo, a.enc[2]);
-          st_row<T, C, V>(rout, vst, so + 3 * cs_b, hx, a.enc[3]);
-          st_row<T, C, V>(rout, vst, so + 4 * cs_b, hy, a.enc[4]);
-          st_row<T, C, V>(rout, vst, so + 5 * cs_b, hz, a.enc[5]);
+          st_row<T, C, V>(rout, vst, so, exo, a.enc[0], nt);
+          st_row<T, C, V>(rout, vst, so + cs_b, eyo, a.enc[1], nt);
+          st_row<T, C, V>(rout, vst, so + 2 * cs_b, ezo, a.enc[2], nt);
+          st_row<T, C, V>(rout, vst, so + 3 * cs_b, hx, a.enc[3], nt);
+          st_row<T, C, V>(rout, vst, so + 4 * cs_b, hy, a.enc[4], nt);
+          st_row<T, C, V>(rout, vst, so + 5 * cs_b, hz, a.enc[5], nt);
         } else {
-          buf_st<VecT<T, V>>(se[0], rout, vst, so);
-          buf_st<VecT<T, V>>(se[1], rout, vst, so + cs_b);
-          buf_st<VecT<T, V>>(se[2], rout, vst, so + 2 * cs_b);
-          buf_st<VecT<T, V>>(sh[0], rout, vst, so + 3 * cs_b);
-          buf_st<VecT<T, V>>(sh[1], rout, vst, so + 4 * cs_b);
-          buf_st<VecT<T, V>>(sh[2], rout, vst, so + 5 * cs_b);
+          buf_st<VecT<T, V>>(se[0], rout, vst, so, nt);
+          buf_st<VecT<T, V>>(se[1], rout, vst, so + cs_b, nt);
+          buf_st<VecT<T, V>>(se[2], rout, vst, so + 2 * cs_b, nt);
+          buf_st<VecT<T, V>>(sh[0], rout, vst, so + 3 * cs_b, nt);
+          buf_st<VecT<T, V>>(sh[1], rout, vst, so + 4 * cs_b, nt);
+          buf_st<VecT<T, V>>(sh[2], rout, vst, so + 5 * cs_b, nt);
         }
         if constexpr (EXTRA == kWriteCount) {
           if (vst != kOut) {

@@ -276,6 +276,15 @@ size_t step_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
 // launch shape (V samples per lane, ty rows per tile, kz planes per chunk).
 // record = false: the step writes no probe samples (recomputation of steps
 // already recorded).
+// Cache policy of the field and CPML stores of a step with component arrays
+// of comp_bytes each: streamed past the 256 MB last-level cache
+// (non-temporal) when the step's field traffic -- 6 arrays read, 6 written --
+// exceeds it. The written set is then evicted before the next step reads it,
+// and caching it only displaces the reads; when it fits, the next step reads
+// it from there and streaming the stores loses that.
+constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
+inline bool stream_stores(size_t comp_bytes) { return 12 * comp_bytes > kLastLevelCacheBytes; }
+
 template <class T, class C>
 yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool record = true) {
   using namespace yee;
@@ -367,7 +376,10 @@ yee_status launch_step(yee_ctx* c, hipStream_t s, bool record, const HistOut* hi
     HIP_TRY(hipGetLastError());
     return YEE_OK;
   }
-  hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
+  if (stream_stores(c->comp_bytes))
+    hipLaunchKernelGGL((step_kernel<T, C, V, kStream>), dim3(grid), dim3(kWave * waves), lds, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<T, C, V>), dim3(grid), dim3(kWave * waves), lds, s, a);
   HIP_TRY(hipGetLastError());
   return YEE_OK;
 }
@@ -414,7 +426,11 @@ yee_status launch_tb(yee_ctx* c, hipStream_t s, bool record) {
   if (lds > c->lds_limit) return fail(YEE_EINVAL, "two-step tile needs %zu bytes of LDS (limit %zu)", lds, c->lds_limit);
   if (c->tb_ty < 1 || c->tb_ty > tb_max_rows(V, WPR))
     return fail(YEE_EINVAL, "two-step tile of %d rows exceeds the workgroup", c->tb_ty);
-  hipLaunchKernelGGL((tb_kernel<T, C, V, WPR>), dim3(grid), dim3(kWave * WPR * (c->tb_ty + 3)), lds, s, a);
+  const dim3 block(kWave * WPR * (c->tb_ty + 3));
+  if (stream_stores(c->comp_bytes))
+    hipLaunchKernelGGL((tb_kernel<T, C, V, WPR, true>), dim3(grid), block, lds, s, a);
+  else
+    hipLaunchKernelGGL((tb_kernel<T, C, V, WPR>), dim3(grid), block, lds, s, a);
   HIP_TRY(hipGetLastError());
   return YEE_OK;
 }

@@ -86,12 +86,15 @@ __device__ __forceinline__ void ld_pair_f32(rsrc_t r, uint32_t vo, uint32_t so, 
   a0 = __builtin_bit_cast(float, v0);
   a1 = __builtin_bit_cast(float, v1);
 }
-__device__ __forceinline__ void st_pair_f32(rsrc_t r, uint32_t vo, uint32_t so, float a0, float a1) {
+__device__ __forceinline__ void st_pair_f32(rsrc_t r, uint32_t vo, uint32_t so, float a0, float a1, bool nt) {
   // (opaque: otherwise the two values are gathered through scratch memory)
   u32x2 v;
   v.x = __builtin_bit_cast(unsigned int, opaque(a0));
   v.y = __builtin_bit_cast(unsigned int, opaque(a1));
-  __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
+  if (nt)
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 2);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, so, 0);
 }
 
 // LDS bytes of one two-step workgroup: ty rows per tile, V samples per lane,
@@ -131,12 +134,13 @@ struct TbRole {
   static constexpr int value = N;
 };
 
-template <class T, class C, int V, int WPR>
+template <class T, class C, int V, int WPR, bool NT>
 __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile, const int k0, const int k1,
                                         unsigned char* smem) {
   static_assert(sizeof(C) == 4, "two-step sweeps compute in FP32");
   constexpr int RL = kWave * V * WPR;     // samples per row (WPR waves of 64 V)
   const int ty = a.ty;
+  constexpr bool nt = NT;   // stores streamed past the last-level cache
   const int NR = ty + 4, NW = ty + 3;
   const int nx = a.nx, ny = a.ny, nz = a.nz, px = a.px;
   const int Lx = a.L[0], Ly = a.L[1], Lz = a.L[2];
@@ -283,7 +287,7 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
   };
   auto st_pair = [&](uint32_t off, const C (&i0)[V], const C (&i1)[V]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) st_pair_f32(rpsi, vxc + e * 2 * CB, off, i0[e], i1[e]);
+    for (int e = 0; e < V; ++e) st_pair_f32(rpsi, vxc + e * 2 * CB, off, i0[e], i1[e], nt);
   };
   auto ld_xpair = [&](uint32_t off, C (&o0)[V], C (&o1)[V]) __attribute__((always_inline)) {
 #pragma unroll
@@ -291,7 +295,7 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
   };
   auto st_xpair = [&](uint32_t off, const C (&i0)[V], const C (&i1)[V]) __attribute__((always_inline)) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) st_pair_f32(rpsi, vxs[e], off, i0[e], i1[e]);
+    for (int e = 0; e < V; ++e) st_pair_f32(rpsi, vxs[e], off, i0[e], i1[e], nt);
   };
   // auxiliaries of plane k at region base `rb` (H side: (XY, ZY), (XZ, YZ), (YX, ZX))
   struct Aux {
@@ -752,12 +756,12 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
         // where nothing is owned), so each iteration issues the same operations
         const uint32_t vst = doD ? vrow : kOut;
         const uint32_t so = (uint32_t)(p >= 1 ? p - 1 : 0) * plane_b;
-        st_row<T, C, V>(rout, vst, so, eD[0], a.enc[0]);
-        st_row<T, C, V>(rout, vst, so + cs_b, eD[1], a.enc[1]);
-        st_row<T, C, V>(rout, vst, so + 2 * cs_b, eD[2], a.enc[2]);
-        st_row<T, C, V>(rout, vst, so + 3 * cs_b, hC[0], a.enc[3]);
-        st_row<T, C, V>(rout, vst, so + 4 * cs_b, hC[1], a.enc[4]);
-        st_row<T, C, V>(rout, vst, so + 5 * cs_b, hC[2], a.enc[5]);
+        st_row<T, C, V>(rout, vst, so, eD[0], a.enc[0], nt);
+        st_row<T, C, V>(rout, vst, so + cs_b, eD[1], a.enc[1], nt);
+        st_row<T, C, V>(rout, vst, so + 2 * cs_b, eD[2], a.enc[2], nt);
+        st_row<T, C, V>(rout, vst, so + 3 * cs_b, hC[0], a.enc[3], nt);
+        st_row<T, C, V>(rout, vst, so + 4 * cs_b, hC[1], a.enc[4], nt);
+        st_row<T, C, V>(rout, vst, so + 5 * cs_b, hC[2], a.enc[5], nt);
       }
 
       // ---- publish E^n(p+1) for the next stage A; advance the window ----
@@ -795,7 +799,7 @@ __device__ __forceinline__ void tb_tile(const StepArgs<T, C>& a, const int ytile
 // up to 168 VGPRs).
 __host__ __device__ constexpr int tb_block_waves(int V) { return V >= 4 ? 12 : 16; }
 
-template <class T, class C, int V, int WPR>
+template <class T, class C, int V, int WPR, bool NT = false>
 __global__ void __launch_bounds__(kWave * tb_block_waves(V))
 tb_kernel(const StepArgs<T, C> a) {
   extern __shared__ unsigned char smem_raw[];
@@ -805,7 +809,7 @@ tb_kernel(const StepArgs<T, C> a) {
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= a.ntiles) return;
   const int k0 = (t / a.ny_tiles) * a.kz;
-  tb_tile<T, C, V, WPR>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
+  tb_tile<T, C, V, WPR, NT>(a, t % a.ny_tiles, k0, min(a.nz, k0 + a.kz), smem_raw);
 }
 
 }  // namespace yee
