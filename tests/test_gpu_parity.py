@@ -174,6 +174,17 @@ def test_cpml_lattice_full_size_fp32_few_steps(solver_cls):
     _check_probes(s, sim, TOL["f32"], 3)
 
 
+def test_fp64_streamed_stores_few_steps(solver_cls):
+    """160^3 in FP64: the twelve component arrays a step reads and writes
+    (33 MB each) exceed the 256 MB last-level cache, so the step runs with its
+    stores streamed past it; 3 steps from a random state with CPML, probes and
+    the DFT, against the FP64 oracle."""
+    wl = W.cpml_block_lattice(n=160, steps=3, precision="f64", nprobes=4, nfreq=8)
+    s, sim = _run_both(solver_cls, wl, 3, init_seed=23)
+    _check_fields(s, sim, TOL["f64"])
+    _check_probes(s, sim, TOL["f64"], 3)
+
+
 @pytest.mark.parametrize("steps", [1, 10])
 def test_fp16_storage_few_steps(solver_cls, steps):
     """FP16 storage, few steps from a common random state: the GPU and the
