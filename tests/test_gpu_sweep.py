@@ -108,6 +108,20 @@ def test_two_step_sweep_fp16_storage_bitwise(solver_cls):
     _check_bitwise(one, two, 10)
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_two_step_sweep_streamed_stores_bitwise(solver_cls, precision):
+    """Grids whose fields exceed the 256 MB last-level cache (256^3 FP32;
+    256 x 256 x 192 with FP16 storage): the single steps and the sweeps both
+    stream their stores past it.  5 steps (two sweeps, then a single step) from
+    a random state, bitwise."""
+    if precision == "f32":
+        wl = W.cpml_block_lattice(n=256, steps=5)
+    else:
+        wl = W.fp16_substrate(256, 256, 192, steps=5, cpml=8)
+    (one, two), _ = _pair(solver_cls, wl, 5, init_seed=13)
+    _check_bitwise(one, two, 5)
+
+
 @pytest.mark.parametrize("shape,cpml", [((150, 26, 31), (8, 6, 5)), ((256, 18, 25), (10, 4, 6))])
 def test_two_step_sweep_against_oracle(solver_cls, shape, cpml):
     steps = 14
