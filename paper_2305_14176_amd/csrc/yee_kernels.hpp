@@ -1092,7 +1092,7 @@ struct SlotDesc {
   int32_t pad[2];
 };
 
-template <class T, class C, int V>
+template <class T, class C, int V, int EXTRA = kPlain>
 __global__ void __launch_bounds__(kWave * max_block_waves(V))
 __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<C, V>())))
 batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __restrict__ hdr, const int q) {
@@ -1113,7 +1113,7 @@ batch_step_kernel(const SlotDesc<T, C>* __restrict__ slots, const int32_t* __res
       a.series_slot = (int32_t)(n % slots[s].series_len);
       const int tl = t - slots[s].tile0;
       const int kb = (tl / a.ny_tiles) * a.kz;
-      step_tile<T, C, V>(a, tl % a.ny_tiles, kb, min(a.nz, kb + a.kz), smem_raw);
+      step_tile<T, C, V, EXTRA>(a, tl % a.ny_tiles, kb, min(a.nz, kb + a.kz), smem_raw);
     }
     __syncthreads();  // the next tile reuses the LDS
   }

@@ -130,9 +130,11 @@ struct yee_batch {
   };
   std::vector<Slot> slots;
   int64_t in_use = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  hipStream_t capture = nullptr;       // private stream the replay graph is captured on
+  // replay graphs, captured on first use: [0] cached stores, [1] stores
+  // streamed past the last-level cache (active slots' fields exceed it)
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipStream_t capture = nullptr;       // private stream the replay graphs are captured on
   // host images of the descriptor table (pinned, used in turn; the event of
   // each marks the end of the copy that last read it)
   unsigned char* staging[2] = {nullptr, nullptr};
@@ -1369,8 +1371,10 @@ void yee_batch_destroy(yee_batch* b) {
     }
     if (b->staging[i]) (void)hipHostFree(b->staging[i]);
   }
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int i = 0; i < 2; ++i) {
+    if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+    if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+  }
   if (b->capture) (void)hipStreamDestroy(b->capture);
   delete b;
 }
@@ -1472,6 +1476,7 @@ yee_status batch_run_t(yee_batch* b, hipStream_t s) {
   std::memset(stg, 0, b->staging_bytes);
   BatchDesc* desc = reinterpret_cast<BatchDesc*>(stg + hdr_bytes);
   int32_t nact = 0, tiles = 0;
+  size_t comp_total = 0;
   std::vector<int32_t> order;
   // planes per chunk for this replay: the fewest (kBatchMinChunk ..
   // kBatchMaxChunk) that spread the (y-tile, plane) units of every active slot
@@ -1497,6 +1502,7 @@ yee_status batch_run_t(yee_batch* b, hipStream_t s) {
     d.series_len = c->d.series_len;
     d.tile0 = tiles;
     tiles += d.a.ntiles;
+    comp_total += c->comp_bytes;
     order.push_back(q);
   }
   if (nact == 0) return YEE_OK;
@@ -1506,23 +1512,32 @@ yee_status batch_run_t(yee_batch* b, hipStream_t s) {
   HIP_TRY(hipEventRecord(b->staged[sb], s));
   b->staged_used[sb] = true;
   b->runs += 1;
-  if (!b->exec) {
-    // capture K launches once; they read the descriptor table from device memory
+  // the replay steps every active slot: their fields share the cache
+  const int nt = stream_stores(comp_total) ? 1 : 0;
+  if (!b->exec[nt]) {
+    // capture K launches once per store policy; they read the descriptor
+    // table from device memory
     const BatchDesc* dslots = reinterpret_cast<const BatchDesc*>(b->ws + hdr_bytes);
     const int32_t* dhdr = reinterpret_cast<const int32_t*>(b->ws);
     // (captured on a private stream: the caller's may be the legacy null stream)
     if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    for (int q = 0; q < b->K; ++q)
-      hipLaunchKernelGGL((yee::batch_step_kernel<T, C, V>), dim3(b->grid), dim3(yee::kWave * kBatchBlockWaves),
-                         b->lds, b->capture, dslots, dhdr, q);
+    const dim3 block(yee::kWave * kBatchBlockWaves);
+    for (int q = 0; q < b->K; ++q) {
+      if (nt)
+        hipLaunchKernelGGL((yee::batch_step_kernel<T, C, V, yee::kStream>), dim3(b->grid), block, b->lds, b->capture,
+                           dslots, dhdr, q);
+      else
+        hipLaunchKernelGGL((yee::batch_step_kernel<T, C, V>), dim3(b->grid), block, b->lds, b->capture, dslots, dhdr,
+                           q);
+    }
     hipGraph_t g = nullptr;
     hipError_t e1 = hipStreamEndCapture(b->capture, &g);
     if (e1 != hipSuccess) return fail(YEE_EHIP, "graph capture failed: %s", hipGetErrorString(e1));
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph[nt] = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec[nt], b->graph[nt], nullptr, nullptr, 0));
   }
-  HIP_TRY(hipGraphLaunch(b->exec, s));
+  HIP_TRY(hipGraphLaunch(b->exec[nt], s));
   // host bookkeeping: every included slot advanced min(K, remaining) steps
   for (int32_t q : order) {
     auto& sl = b->slots[q];
