@@ -281,11 +281,13 @@ size_t step_lds_bytes(const yee_ctx* c, int ty, int V, int kz) {
 // Cache policy of the field and CPML stores of a step with component arrays
 // of comp_bytes each: streamed past the 256 MB last-level cache
 // (non-temporal) when the step's field traffic -- 6 arrays read, 6 written --
-// exceeds it. The written set is then evicted before the next step reads it,
+// takes more than 7/8 of it (the rest holds the CPML auxiliaries and the
+// tables). The written set is then evicted before the next step reads it,
 // and caching it only displaces the reads; when it fits, the next step reads
-// it from there and streaming the stores loses that.
+// it from there and streaming the stores loses that.  Measured crossover:
+// cached stores win at 194 MiB of fields, streamed ones from 238 MiB.
 constexpr size_t kLastLevelCacheBytes = size_t(256) << 20;
-inline bool stream_stores(size_t comp_bytes) { return 12 * comp_bytes > kLastLevelCacheBytes; }
+inline bool stream_stores(size_t comp_bytes) { return 12 * comp_bytes > kLastLevelCacheBytes / 8 * 7; }
 
 template <class T, class C>
 yee::StepArgs<T, C> fill_args(const yee_ctx* c, int V, int ty, int kz, bool record = true) {
