@@ -59,6 +59,31 @@ def test_batched_results_equal_alone():
     srv.close()
 
 
+def test_batched_streamed_replays_equal_alone():
+    """Slots whose fields together exceed the last-level cache (two 160^3
+    grids: 396 MB of field traffic per step) take the replay graph with
+    streamed stores; with one 128^3 grid left (101 MB) the batch goes back to
+    the cached graph.  Every request gives the bits it gives alone."""
+    import torch
+    from paper_2305_14176_amd.serving import BatchServer, serve_one_at_a_time
+    assert torch.cuda.is_available()
+    keep = ("Ex", "Hz")
+    specs = [(160, 20, 111, 0.0), (160, 27, 112, 0.0), (128, 45, 113, 0.0)]
+    _say("[gpu] serving: streamed replays, alone")
+    alone = {r.rid: r for r in serve_one_at_a_time(_requests(specs), keep_fields=keep)}
+    _say("[gpu] serving: streamed replays, batched")
+    srv = BatchServer(max_slots=3, hbm_budget=1 << 30, steps_per_replay=8, keep_fields=keep, solo=False)
+    mixed = {r.rid: r for r in srv.serve(_requests(specs))}
+    assert srv.solo_runs == 0 and srv.replays > 3
+    for rid in alone:
+        a, b = alone[rid], mixed[rid]
+        np.testing.assert_array_equal(b.series, a.series, err_msg=f"series of request {rid}")
+        assert rel_l2(b.dft, a.dft) <= 1e-13, (rid, rel_l2(b.dft, a.dft))
+        for c in keep:
+            np.testing.assert_array_equal(b.fields[c], a.fields[c], err_msg=f"{c} of request {rid}")
+    srv.close()
+
+
 def test_batched_request_matches_oracle():
     from paper_2305_14176_amd.serving import BatchServer
     reqs = _requests([(48, 60, 201, 0.0), (32, 25, 202, 0.0)])
